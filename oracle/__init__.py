@@ -1,0 +1,216 @@
+"""Reference (oracle) renderer -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the bench's CPU-baseline leg
+may import this package.  The renderer library and its Python binding never
+import, load or call anything here, and this package imports nothing from
+them.
+
+Contents:
+* ``liboracle.so`` (``oracle.c``): FP64 per-pixel renderer, FP64 geometry,
+  FP32 mirror of the integer decisions (culling, tile rectangles, depth keys).
+* ``tile_lists``: per-tile (depth, index) order via ``numpy.lexsort``.
+* ``grad``: FP64 dense formulation in plain PyTorch CPU ops whose autograd
+  gives the exact derivative with every discrete decision frozen.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+# field order of or_geometry_f64's output rows
+GEOM_FIELDS = ("u", "v", "a", "b", "c", "conA", "conB", "conC", "o", "r", "g", "b_", "X", "Y", "Z")
+
+_lib = None
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("rank", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("num_packets", ctypes.c_int32), ("num_contexts", ctypes.c_int32),
+                ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
+                ("color", ctypes.c_void_p), ("temporal", ctypes.c_void_p),
+                ("packet_layer", ctypes.c_void_p), ("cluster_affine", ctypes.c_void_p)]
+
+
+class _Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("near_z", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        src = os.path.join(HERE, "oracle.c")
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.or_exp_f32.restype = ctypes.c_float
+        L.or_exp_f32.argtypes = [ctypes.c_float]
+        L.or_mirror_f32.restype = ctypes.c_int
+        L.or_geometry_f64.restype = ctypes.c_int
+        L.or_render.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class _Pinned:
+    """Keeps the numpy arrays referenced by a ctypes struct alive."""
+
+    def __init__(self, scene, cam):
+        self.arrs = dict(mean=_f32(scene.mean), log_scale=_f32(scene.log_scale),
+                         quat=_f32(scene.quat), opacity_logit=_f32(scene.opacity_logit),
+                         color=_f32(scene.color), temporal=_f32(scene.temporal),
+                         packet_layer=np.ascontiguousarray(scene.packet_layer, dtype=np.uint16))
+        aff = None
+        if scene.cluster_affine is not None:
+            aff = _f32(scene.cluster_affine)
+            self.arrs["cluster_affine"] = aff
+        ptr = lambda k: self.arrs[k].ctypes.data if k in self.arrs else None  # noqa: E731
+        n = scene.mean.shape[1]
+        self.scene = _Scene(n, scene.rank, scene.sh_degree, scene.num_clusters * scene.num_contexts,
+                            scene.num_contexts, ptr("mean"), ptr("log_scale"), ptr("quat"),
+                            ptr("opacity_logit"), ptr("color"), ptr("temporal"),
+                            ptr("packet_layer"), ptr("cluster_affine"))
+        c = _Camera()
+        R = _f32(cam.R_cw).reshape(9)
+        t = _f32(cam.t_cw).reshape(3)
+        for k in range(9):
+            c.R[k] = float(R[k])
+        for k in range(3):
+            c.t[k] = float(t[k])
+        c.fx, c.fy, c.cx, c.cy = cam.fx, cam.fy, cam.cx, cam.cy
+        c.near_z = cam.near
+        c.width, c.height = cam.width, cam.height
+        self.cam = c
+
+
+def exp_f32(x: float) -> np.float32:
+    return np.float32(lib().or_exp_f32(ctypes.c_float(x)))
+
+
+def geometry_f64(scene, cam, basis) -> dict:
+    """Per-Gaussian FP64 projection: dict of [N] float64 arrays (GEOM_FIELDS)."""
+    pin = _Pinned(scene, cam)
+    n = scene.mean.shape[1]
+    out = np.zeros((len(GEOM_FIELDS), max(n, 1)), dtype=np.float64)
+    b = _f32(basis) if len(basis) else np.zeros(1, np.float32)
+    rc = lib().or_geometry_f64(ctypes.byref(pin.scene), ctypes.byref(pin.cam),
+                               b.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 0
+    return {k: out[j, :n] for j, k in enumerate(GEOM_FIELDS)}
+
+
+def mirror_f32(scene, cam, basis, tile_w: int = 16, tile_h: int = 16) -> dict:
+    """FP32 integer decisions: depth z32 (+ its uint32 bits), u, v, a, b, c,
+    tile rectangle [x0, y0, x1, y1) and validity."""
+    pin = _Pinned(scene, cam)
+    n = scene.mean.shape[1]
+    f = np.zeros((6, max(n, 1)), dtype=np.float32)
+    r = np.zeros((4, max(n, 1)), dtype=np.int32)
+    v = np.zeros(max(n, 1), dtype=np.int32)
+    b = _f32(basis) if len(basis) else np.zeros(1, np.float32)
+    rc = lib().or_mirror_f32(ctypes.byref(pin.scene), ctypes.byref(pin.cam),
+                             b.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(tile_w),
+                             ctypes.c_int(tile_h), f.ctypes.data_as(ctypes.c_void_p),
+                             r.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError("tile sizes must be powers of two")
+    z32 = f[0, :n].copy()
+    return dict(z32=z32, zbits=z32.view(np.uint32), u=f[1, :n].copy(), v=f[2, :n].copy(),
+                a=f[3, :n].copy(), b=f[4, :n].copy(), c=f[5, :n].copy(),
+                rect=r[:, :n].copy(), valid=v[:n].astype(bool), tile_w=tile_w, tile_h=tile_h)
+
+
+def tile_lists(mirror: dict, width: int, height: int, present=None):
+    """Per-tile Gaussian lists in the order (tile id, depth bits, index).
+
+    Returns (ranges [tiles][2] int64 half-open into ids, ids [M] int64,
+    keys [M] uint64 = tile << 32 | depth bits).  ``present`` (bool [N])
+    restricts the lists to a subset.  The order is numpy.lexsort's, i.e. a
+    stable sort on the three keys."""
+    tw, th = mirror["tile_w"], mirror["tile_h"]
+    tiles_x = (width + tw - 1) // tw
+    tiles_y = (height + th - 1) // th
+    rect = mirror["rect"].astype(np.int64)
+    ok = mirror["valid"].copy()
+    if present is not None:
+        ok &= present
+    nx = np.clip(rect[2] - rect[0], 0, None)
+    ny = np.clip(rect[3] - rect[1], 0, None)
+    cnt = np.where(ok, nx * ny, 0)
+    total = int(cnt.sum())
+    ids = np.repeat(np.arange(cnt.size, dtype=np.int64), cnt)
+    start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    k = np.arange(total, dtype=np.int64) - start
+    nxr = np.repeat(np.maximum(nx, 1), cnt)
+    tx = np.repeat(rect[0], cnt) + k % nxr
+    ty = np.repeat(rect[1], cnt) + k // nxr
+    tile = ty * tiles_x + tx
+    zb = mirror["zbits"].astype(np.int64)[ids]
+    order = np.lexsort((ids, zb, tile))
+    tile, ids, zb = tile[order], ids[order], zb[order]
+    counts = np.bincount(tile, minlength=tiles_x * tiles_y)
+    ends = np.cumsum(counts)
+    ranges = np.stack([ends - counts, ends], axis=1)
+    keys = (tile.astype(np.uint64) << np.uint64(32)) | zb.astype(np.uint64)
+    return ranges, ids, keys
+
+
+def render(scene, cam, basis, codes, background, pixels=None) -> dict:
+    """FP64 render.  ``pixels``: None (all, row-major) or int array [K][2] of
+    (x, y).  Returns image [W][K][3] (or [W][H][Wd][3] when pixels is None),
+    tfinal, budget, ncomp with matching leading shapes."""
+    pin = _Pinned(scene, cam)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    W = codes.shape[0]
+    assert codes.shape[1] == scene.num_clusters * scene.num_contexts
+    if pixels is None:
+        npix = cam.width * cam.height
+        pix = None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        npix = pix.shape[0]
+    image = np.zeros((W, npix, 3), dtype=np.float64)
+    tfinal = np.zeros((W, npix), dtype=np.float64)
+    budget = np.zeros((W, npix), dtype=np.float64)
+    ncomp = np.zeros((W, npix), dtype=np.int32)
+    bg = _f32(background)
+    b = _f32(basis) if len(basis) else np.zeros(1, np.float32)
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    rc = lib().or_render(ctypes.byref(pin.scene), ctypes.byref(pin.cam), vp(b), ctypes.c_int(W),
+                         vp(codes), vp(bg), ctypes.c_int64(npix),
+                         vp(pix) if pix is not None else None, vp(image), vp(tfinal), vp(budget),
+                         vp(ncomp))
+    if rc != 0:
+        raise MemoryError("oracle render failed")
+    if pixels is None:
+        H, Wd = cam.height, cam.width
+        return dict(image=image.reshape(W, H, Wd, 3), tfinal=tfinal.reshape(W, H, Wd),
+                    budget=budget.reshape(W, H, Wd), ncomp=ncomp.reshape(W, H, Wd))
+    return dict(image=image, tfinal=tfinal, budget=budget, ncomp=ncomp)
+
+
+def psnr(image, reference) -> np.ndarray:
+    """PSNR per state with peak 1: 10 log10(1 / max(MSE, 1e-10)), MSE over
+    every pixel and channel."""
+    d = np.asarray(image, np.float64) - np.asarray(reference, np.float64)[None]
+    mse = (d * d).reshape(d.shape[0], -1).mean(axis=1)
+    return 10.0 * np.log10(1.0 / np.maximum(mse, 1e-10))
+
+
+def present_mask(scene, codes_row) -> np.ndarray:
+    """bool [N]: Gaussian present under one state's codes (layer < code)."""
+    pl = scene.packet_layer.astype(np.int64)
+    return (pl & 3) < np.asarray(codes_row, np.int64)[pl >> 2]

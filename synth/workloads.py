@@ -1,0 +1,302 @@
+"""Synthetic dynamic Gaussian scenes, cameras and delivery-state codes.
+
+Every array is drawn from ``numpy.random.default_rng(SeedSequence([2606,
+workload_index, stream]))`` with stream 0 = scene, 1 = delivery states,
+2 = parameter perturbation, 3 = finite-difference subscene.  Values are drawn in
+float64 and stored as float32; both the oracle and the GPU path read the
+float32 values.
+
+Layouts (component-major structure of arrays, ``[k][N]``):
+
+* ``mean [3][N]``        canonical means (the paper's mu-bar in Eq. (1), Sec. 3)
+* ``log_scale [3][N]``   per-axis log standard deviations
+* ``quat [4][N]``        rotation quaternion (w, x, y, z)
+* ``opacity_logit [N]``
+* ``color [3][N]`` (RGB) or ``[12][N]`` (degree-1 spherical harmonics,
+  coefficient-major: row index = coef*3 + channel)
+* ``temporal [3R][N]``   per-Gaussian temporal coefficients q_{i,r} of Eq. (1),
+  row index = r*3 + axis
+* ``packet_layer [N]``   uint16 ``(packet << 2) | layer`` with
+  ``packet = cluster * K + context``
+
+Delivery states are ``codes [W][P]`` uint8: 0 = packet absent, d+1 = prefix
+depth d (layers 0..d delivered).  A Gaussian of layer l in packet p is present
+in state w iff ``l < codes[w][p]``.  The prefix encoding is dependency-closed
+by construction (Sec. 4: dependencies are enforced before masks are formed;
+Sec. 3: one base and three refinement groups per cluster).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+from typing import Optional
+
+import numpy as np
+
+
+@dataclass
+class SceneArrays:
+    mean: np.ndarray
+    log_scale: np.ndarray
+    quat: np.ndarray
+    opacity_logit: np.ndarray
+    color: np.ndarray
+    temporal: np.ndarray
+    packet_layer: np.ndarray
+    num_clusters: int
+    num_contexts: int
+    rank: int
+    sh_degree: int
+    cluster_affine: Optional[np.ndarray] = None  # [C][12] row-major 3x4, None = identity
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[1])
+
+    @property
+    def num_packets(self) -> int:
+        return self.num_clusters * self.num_contexts
+
+
+@dataclass
+class CameraArrays:
+    R_cw: np.ndarray  # float32 [3][3], world -> camera rotation (rows: right, down, forward)
+    t_cw: np.ndarray  # float32 [3]
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    near: float = 0.01
+
+
+@dataclass
+class Workload:
+    name: str
+    index: int
+    scene: SceneArrays
+    camera: CameraArrays
+    codes: np.ndarray  # uint8 [W][P]
+    basis: np.ndarray  # float32 [R]
+    t: float
+    background: np.ndarray  # float32 [3]
+    batch: int = 0  # states per launch when the workload is swept in batches (0 = all)
+    total_states: int = 0  # states in the full sweep (0 = codes.shape[0])
+
+
+# name -> recipe.  ``index`` is the workload's seed index.
+WORKLOADS = {
+    # 4,096 Gaussians, 8 clusters x 4 contexts, 1 layer, 128x128, 16 states.
+    "g4k_128px_16states": dict(index=1, n=4096, clusters=8, contexts=4, layers=1,
+                               width=128, height=128, states=16, color="rgb",
+                               masks=("bernoulli", 0.7, 0.7)),
+    # 250,000 Gaussians, 32x32x4 packets/layers, 800x800, 64 states (forward only).
+    "g250k_800px_64states": dict(index=2, n=250_000, clusters=32, contexts=32, layers=4,
+                                 width=800, height=800, states=64, color="sh1",
+                                 masks=("present_depth", 0.3, 1.0)),
+    # 2.7M Gaussians, 64x64x4, 1920x1080, 256 states with present fractions 5%..100%.
+    "g2700k_1080p_256states": dict(index=3, n=2_700_000, clusters=64, contexts=64, layers=4,
+                                   width=1920, height=1080, states=256, color="sh1",
+                                   masks=("binomial_ramp", 0.05, 1.0)),
+    # 250,000 Gaussians, 1280x720, 8 states; forward + L1 loss + backward.
+    "g250k_720p_8states_fwdbwd": dict(index=4, n=250_000, clusters=32, contexts=32, layers=4,
+                                      width=1280, height=720, states=8, color="sh1",
+                                      masks=("present_depth", 0.3, 1.0)),
+    # 1M Gaussians, 64x16, 960x540, 32,768 states swept in batches of 512 (PSNR only).
+    "g1m_540p_32768states_psnr": dict(index=5, n=1_000_000, clusters=64, contexts=16, layers=1,
+                                      width=960, height=540, states=512, color="sh1",
+                                      masks=("bernoulli_uniform", 0.2, 1.0),
+                                      batch=512, total_states=32768),
+}
+
+
+def _rng(index: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([2606, index, stream]))
+
+
+def variance_split(points: np.ndarray, num_leaves: int) -> np.ndarray:
+    """Deterministic variance split (Sec. 3): recursively halve the point set
+    at the median of its largest-variance axis (ties by index) until
+    ``num_leaves`` leaves (a power of two) remain; leaves are numbered in
+    depth-first order.  ``points`` is (N, 3)."""
+    n = points.shape[0]
+    if num_leaves & (num_leaves - 1):
+        raise ValueError("num_leaves must be a power of two")
+    labels = np.zeros(n, dtype=np.int64)
+    stack = [(np.arange(n), 0, num_leaves)]
+    while stack:
+        idx, first, count = stack.pop()
+        if count == 1 or idx.size == 0:
+            labels[idx] = first
+            continue
+        pts = points[idx]
+        axis = int(np.argmax(pts.var(axis=0))) if idx.size > 1 else 0
+        order = np.lexsort((idx, pts[:, axis]))
+        srt = idx[order]
+        half = srt.size // 2
+        stack.append((srt[half:], first + count // 2, count // 2))
+        stack.append((srt[:half], first, count // 2))
+    return labels
+
+
+def make_scene(n: int, clusters: int, contexts: int, layers: int, color: str,
+               rank: int = 2, index: int = 0, stream: int = 0) -> SceneArrays:
+    """Draw a scene: means U[-1,1]^3, log-scales N(-3,0.3), unit quaternions
+    from normalised N(0,1)^4, opacity logits N(0,1), RGB U[0,1] or SH-1
+    coefficients N(0,0.2), temporal coefficients N(0,0.05), uniform contexts,
+    uniform layers 0..layers-1."""
+    rng = _rng(index, stream)
+    mean = rng.uniform(-1.0, 1.0, size=(n, 3))
+    log_scale = rng.normal(-3.0, 0.3, size=(n, 3))
+    q = rng.normal(0.0, 1.0, size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    logit = rng.normal(0.0, 1.0, size=n)
+    if color == "rgb":
+        col = rng.uniform(0.0, 1.0, size=(n, 3))
+        sh_degree = 0
+    elif color == "sh1":
+        col = rng.normal(0.0, 0.2, size=(n, 12))
+        sh_degree = 1
+    else:
+        raise ValueError(color)
+    temporal = rng.normal(0.0, 0.05, size=(n, 3 * rank))
+    context = rng.integers(0, contexts, size=n)
+    layer = rng.integers(0, layers, size=n) if layers > 1 else np.zeros(n, dtype=np.int64)
+
+    mean32 = np.ascontiguousarray(mean.T, dtype=np.float32)
+    cluster = variance_split(mean32.T.astype(np.float64), clusters)
+    packet = cluster * contexts + context
+    packet_layer = ((packet << 2) | layer).astype(np.uint16)
+    return SceneArrays(
+        mean=mean32,
+        log_scale=np.ascontiguousarray(log_scale.T, dtype=np.float32),
+        quat=np.ascontiguousarray(q.T, dtype=np.float32),
+        opacity_logit=np.ascontiguousarray(logit, dtype=np.float32),
+        color=np.ascontiguousarray(col.T, dtype=np.float32),
+        temporal=np.ascontiguousarray(temporal.T, dtype=np.float32),
+        packet_layer=packet_layer,
+        num_clusters=clusters,
+        num_contexts=contexts,
+        rank=rank,
+        sh_degree=sh_degree,
+    )
+
+
+def ring_camera(width: int, height: int, theta: float = 0.0, radius: float = 3.0,
+                fov_x_deg: float = 60.0, near: float = 0.01) -> CameraArrays:
+    """Pinhole camera on a ring of the given radius around the origin, looking
+    at the origin with world up +y; OpenCV frame (x right, y down, z forward).
+    Rows of R_cw are (right, down, forward); t_cw = -R_cw C."""
+    centre = np.array([radius * math.sin(theta), 0.0, -radius * math.cos(theta)])
+    fwd = -centre / np.linalg.norm(centre)
+    up = np.array([0.0, 1.0, 0.0])
+    right = np.cross(fwd, up)
+    right /= np.linalg.norm(right)
+    down = np.cross(fwd, right)
+    R = np.stack([right, down, fwd])
+    t = -R @ centre
+    f = (width / 2.0) / math.tan(math.radians(fov_x_deg) / 2.0)
+    return CameraArrays(R_cw=R.astype(np.float32), t_cw=t.astype(np.float32),
+                        fx=float(np.float32(f)), fy=float(np.float32(f)),
+                        cx=float(np.float32(width / 2.0)), cy=float(np.float32(height / 2.0)),
+                        width=int(width), height=int(height), near=float(np.float32(near)))
+
+
+def make_camera(width: int, height: int, **kw) -> CameraArrays:
+    return ring_camera(width, height, **kw)
+
+
+def make_codes(kind: str, lo: float, hi: float, num_states: int, num_packets: int,
+               layers: int, index: int = 0, stream: int = 1) -> np.ndarray:
+    """Delivery-state codes [W][P] uint8.
+
+    * ``bernoulli``: each packet present with probability ``lo`` (layer 0 only).
+    * ``bernoulli_uniform``: per state p_w ~ U[lo, hi], packets ~ Bernoulli(p_w).
+    * ``present_depth``: per state p_w ~ U[lo, hi], packets ~ Bernoulli(p_w),
+      prefix depth ~ UniformInt{0..layers-1}.
+    * ``binomial_ramp``: present fraction f_w rising linearly from lo to hi over
+      the states; per packet the number of kept layers ~ Binomial(layers, f_w).
+    """
+    rng = _rng(index, stream)
+    W, P = num_states, num_packets
+    if kind == "bernoulli":
+        codes = (rng.random((W, P)) < lo).astype(np.uint8)
+    elif kind == "bernoulli_uniform":
+        p = rng.uniform(lo, hi, size=W)
+        codes = (rng.random((W, P)) < p[:, None]).astype(np.uint8)
+    elif kind == "present_depth":
+        p = rng.uniform(lo, hi, size=W)
+        present = rng.random((W, P)) < p[:, None]
+        depth = rng.integers(0, layers, size=(W, P))
+        codes = np.where(present, depth + 1, 0).astype(np.uint8)
+    elif kind == "binomial_ramp":
+        f = lo + (hi - lo) * np.arange(W) / max(W - 1, 1)
+        codes = rng.binomial(layers, f[:, None], size=(W, P)).astype(np.uint8)
+    else:
+        raise ValueError(kind)
+    return np.ascontiguousarray(codes)
+
+
+def temporal_basis(t: float, rank: int) -> np.ndarray:
+    """Synthetic shared temporal basis b_{t,r} = t^r, r = 1..R (the learned
+    basis of Eq. (1) is replaced by monomials; t = 0 gives a static scene)."""
+    return np.array([t ** (r + 1) for r in range(rank)], dtype=np.float32)
+
+
+def perturb_scene(scene: SceneArrays, sigma: float = 0.01, index: int = 0,
+                  stream: int = 2) -> SceneArrays:
+    """Add N(0, sigma) to every learned parameter array (draw order: mean,
+    log_scale, quat, opacity_logit, color, temporal)."""
+    rng = _rng(index, stream)
+
+    def noisy(a):
+        return (a.astype(np.float64) + rng.normal(0.0, sigma, size=a.shape)).astype(np.float32)
+
+    return replace(scene, mean=noisy(scene.mean), log_scale=noisy(scene.log_scale),
+                   quat=noisy(scene.quat), opacity_logit=noisy(scene.opacity_logit),
+                   color=noisy(scene.color), temporal=noisy(scene.temporal))
+
+
+def permute_gaussians(scene: SceneArrays, perm: np.ndarray) -> SceneArrays:
+    """Reorder the storage of the Gaussians (perm[k] = old index of new k)."""
+    take = lambda a: np.ascontiguousarray(a[..., perm])  # noqa: E731
+    return replace(scene, mean=take(scene.mean), log_scale=take(scene.log_scale),
+                   quat=take(scene.quat), opacity_logit=take(scene.opacity_logit),
+                   color=take(scene.color), temporal=take(scene.temporal),
+                   packet_layer=take(scene.packet_layer))
+
+
+def subscene(n: int = 256, width: int = 64, height: int = 64, states: int = 8,
+             log_scale_mean: float = -3.0, index: int = 4, stream: int = 3,
+             background=(0.25, 0.5, 0.75)) -> Workload:
+    """Small scene with the 250k-Gaussian training workload's distributions
+    (SH-1 colour, 4 layers, 32x32 packets) for finite-difference checks."""
+    scene = make_scene(n, 32, 32, 4, "sh1", index=index, stream=stream)
+    if log_scale_mean != -3.0:
+        scene = replace(scene, log_scale=(scene.log_scale + np.float32(log_scale_mean + 3.0)))
+    cam = ring_camera(width, height)
+    codes = make_codes("present_depth", 0.3, 1.0, states, scene.num_packets, 4,
+                       index=index, stream=stream + 10)
+    return Workload(name=f"sub{n}_{width}x{height}", index=index, scene=scene, camera=cam,
+                    codes=codes, basis=temporal_basis(0.5, scene.rank), t=0.5,
+                    background=np.asarray(background, dtype=np.float32))
+
+
+def make_workload(name: str, background=(0.0, 0.0, 0.0), t: float = 0.5,
+                  n: Optional[int] = None, states: Optional[int] = None) -> Workload:
+    """Build a named workload.  ``n``/``states`` override the sizes (smaller
+    instances of the same recipe for tests)."""
+    r = WORKLOADS[name]
+    idx = r["index"]
+    nn = r["n"] if n is None else n
+    scene = make_scene(nn, r["clusters"], r["contexts"], r["layers"], r["color"], index=idx)
+    cam = ring_camera(r["width"], r["height"])
+    W = r["states"] if states is None else states
+    kind, lo, hi = r["masks"]
+    codes = make_codes(kind, lo, hi, W, scene.num_packets, r["layers"], index=idx)
+    return Workload(name=name, index=idx, scene=scene, camera=cam, codes=codes,
+                    basis=temporal_basis(t, scene.rank), t=t,
+                    background=np.asarray(background, dtype=np.float32),
+                    batch=r.get("batch", 0), total_states=r.get("total_states", 0))
