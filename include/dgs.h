@@ -1,0 +1,238 @@
+/*
+ * dgs.h -- C ABI of the batched partial-delivery Gaussian renderer for
+ * AMD MI355X (gfx950).
+ *
+ * The library renders one dynamic Gaussian scene (Sec. 3 of the paper:
+ * clustered Gaussians, Eq. (1) affine + low-rank temporal motion, one base and
+ * three refinement groups per cluster) under many incomplete delivery states
+ * at once (Sec. 6: states of shape [W, N, .] rasterised in one call, FP32
+ * rasterisation, batched evaluation bit-equivalent to serial evaluation).  A
+ * delivery state is a cluster/context packet mask with a delivered prefix
+ * depth, formed after dependency enforcement (Sec. 4).
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are HIP device pointers; "host" are host
+ *    pointers.  The caller owns all memory: scene, codes, images, gradients
+ *    and the workspace.  The library allocates nothing on the render path.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Every call except
+ *    dgs_count_instances and dgs_check is asynchronous on that stream:
+ *    device buffers must stay valid until the stream's work completes.
+ *  - Return value: a dgs_status.  Arguments are validated before any HIP call;
+ *    on failure nothing is launched and dgs_last_error() (thread-local)
+ *    describes the problem.  No exception crosses the ABI and nothing aborts.
+ *  - Floating point: FP32 throughout the device path.  Depth keys, culling
+ *    and tile rectangles follow a fixed FP32 operation order, so binning and
+ *    sort keys are reproducible bit for bit; a state's image is bit-identical
+ *    whether it is rendered alone (dgs_render_per_state) or batched
+ *    (dgs_render), with either tile shape.
+ */
+#ifndef DGS_H
+#define DGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGS_ABI_VERSION 1
+
+typedef enum {
+  DGS_OK = 0,
+  DGS_ERR_INVALID_ARG = 1, /* bad pointer, size or shape; nothing launched */
+  DGS_ERR_WORKSPACE = 2,   /* workspace smaller than dgs_workspace_bytes() */
+  DGS_ERR_OVERFLOW = 3,    /* tile instances exceeded the capacity (dgs_check) */
+  DGS_ERR_HIP = 4,         /* a HIP runtime call failed (message in dgs_last_error) */
+  DGS_ERR_UNSUPPORTED = 5  /* tuning outside the compiled variants */
+} dgs_status;
+
+/*
+ * Scene: structure of arrays, FP32, component-major [k][n] (row k holds
+ * component k of every Gaussian).  All pointers are device pointers.
+ *   mean          [3][n]   canonical means (mu-bar of Eq. (1))
+ *   log_scale     [3][n]   per-axis log standard deviation
+ *   quat          [4][n]   rotation quaternion (w, x, y, z), any non-zero norm
+ *   opacity_logit [n]      opacity = sigmoid(logit)
+ *   color         [3][n]   RGB (sh_degree 0) or [12][n] degree-1 real SH,
+ *                          row = coefficient * 3 + channel (sh_degree 1)
+ *   temporal      [3*rank][n]  per-Gaussian temporal coefficients q_{i,r} of
+ *                          Eq. (1), row = r * 3 + axis
+ *   packet_layer  [n]      (packet << 2) | layer, packet = cluster * K + context,
+ *                          layer 0..3 (base + three refinements, Sec. 3)
+ *   cluster_affine [C][12] per-cluster 3x4 affine A_{c,t} of Eq. (1) at the
+ *                          render time, row-major, or NULL for the identity
+ * Limits: n >= 0; rank 0..4; sh_degree 0 or 1; 1 <= C*K <= 16384.
+ */
+typedef struct {
+  int32_t n;
+  int32_t rank;
+  int32_t sh_degree;
+  int32_t num_clusters;
+  int32_t num_contexts;
+  const float *mean;
+  const float *log_scale;
+  const float *quat;
+  const float *opacity_logit;
+  const float *color;
+  const float *temporal;
+  const uint16_t *packet_layer;
+  const float *cluster_affine;
+} dgs_scene;
+
+/* Pinhole camera (host struct): world -> camera rotation R_cw (row-major) and
+ * translation t_cw; OpenCV frame (x right, y down, z forward); focal lengths
+ * and principal point in pixels; pixel (x, y) has its centre at (x+0.5, y+0.5).
+ * Gaussians with camera depth <= near_z are culled.  1 <= width, height <= 16384. */
+typedef struct {
+  float R_cw[9];
+  float t_cw[3];
+  float fx, fy, cx, cy, near_z;
+  int32_t width, height;
+} dgs_camera;
+
+/* Delivery states.  codes: device [num_states][C*K] uint8; code 0 = packet
+ * absent, d+1 = prefix depth d (layers 0..d delivered).  Gaussian (packet p,
+ * layer l) is present in state w iff l < codes[w][p]; codes above 4 act as 4.
+ * basis: host b_r(t) for r < rank (the shared temporal basis of Eq. (1) at
+ * the render time).  background: host RGB composited behind every pixel. */
+typedef struct {
+  int32_t num_states;
+  const uint8_t *codes;
+  float basis[4];
+  float background[3];
+} dgs_states;
+
+/* Launch shape.  tile_w x tile_h in {16x16, 32x8} (0,0 = 16x16);
+ * states_per_group in {1,2,4,8,16,32} (0 = 16): states composited together
+ * by one workgroup, sharing each splat's alpha evaluation. */
+typedef struct {
+  int32_t tile_w;
+  int32_t tile_h;
+  int32_t states_per_group;
+  int32_t flags; /* reserved, must be 0 */
+} dgs_tuning;
+
+/* Parameter gradients, device pointers with the scene's shapes; overwritten. */
+typedef struct {
+  float *mean;
+  float *log_scale;
+  float *quat;
+  float *opacity_logit;
+  float *color;
+  float *temporal;
+} dgs_scene_grad;
+
+int dgs_abi_version(void);
+const char *dgs_status_string(int status);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *dgs_last_error(void);
+
+/*
+ * Bytes of device workspace needed by the calls below for a scene of n
+ * Gaussians and num_packets = C*K packets seen by `cam` with tuning `tun`,
+ * at most max_states states per call, and room for instance_capacity
+ * (tile, Gaussian) instances.  Returns 0 on invalid arguments.
+ * The workspace is caller-owned device memory, at least 256-byte aligned.
+ */
+size_t dgs_workspace_bytes(int32_t n, int32_t num_packets, const dgs_camera *cam,
+                           const dgs_tuning *tun, int32_t max_states,
+                           int64_t instance_capacity);
+
+/*
+ * Projects every Gaussian (masks ignored) and counts its tile instances; the
+ * total is the capacity a render of any subset of the scene needs.
+ * SYNCHRONISES the stream and writes the count to *instances (host).
+ * ws may be sized with instance_capacity = 0.
+ */
+int dgs_count_instances(const dgs_scene *scene, const dgs_camera *cam,
+                        const dgs_states *states, const dgs_tuning *tun, void *ws,
+                        size_t ws_bytes, int64_t *instances, void *stream);
+
+/*
+ * Batched render (the hot path).  Deformation (Eq. (1)) and projection of all
+ * Gaussians, tile binning and the (tile, depth, index) sort run once; then
+ * every state is composited front to back from the shared per-tile lists,
+ * skipping Gaussians its codes do not deliver.
+ *   image  device [W][height][width][3] FP32, colour + T_final * background
+ *   tfinal device [W][height][width] transmittance after the last
+ *          composited Gaussian, or NULL
+ * instance_capacity: as passed to dgs_workspace_bytes; if the scene needs
+ * more instances the output is undefined and dgs_check reports
+ * DGS_ERR_OVERFLOW.  Work on the stream only: safe to capture in a HIP graph.
+ * The workspace keeps the sorted lists for a following dgs_backward.
+ */
+int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+               const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t instance_capacity,
+               float *image, float *tfinal, void *stream);
+
+/*
+ * Plain per-state render (baseline): for each state in turn, compacts the
+ * delivered Gaussians, projects, bins, sorts and composites only them.
+ * Same outputs, bit-identical to dgs_render's.  tun->states_per_group is
+ * ignored.  instance_capacity from dgs_count_instances covers every state.
+ */
+int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam,
+                         const dgs_states *states, const dgs_tuning *tun, void *ws,
+                         size_t ws_bytes, int64_t instance_capacity, float *image,
+                         float *tfinal, void *stream);
+
+/*
+ * Batched render reduced on device to one PSNR per state against `reference`
+ * (device [height][width][3]): PSNR = 10 log10(1 / max(MSE, 1e-10)), MSE over
+ * every pixel and channel, accumulated from per-tile FP32 partial sums in
+ * FP64.  No image is written.  psnr: device [W] FP32.
+ */
+int dgs_render_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                    const dgs_tuning *tun, void *ws, size_t ws_bytes,
+                    int64_t instance_capacity, const float *reference, float *psnr,
+                    void *stream);
+
+/*
+ * Backward of dgs_render.  Must follow a dgs_render with the same arguments
+ * and the same, untouched workspace (its sorted lists are reused; per tile the
+ * compositing is recomputed front to back, no per-pixel lists are stored).
+ *   image      device [W][H][Wd][3]: the forward's output
+ *   grad_image device [W][H][Wd][3]: dL/d image
+ *   grad       parameter gradients summed over all states (overwritten).
+ * Gradients are accumulated with FP32 atomics: not bitwise reproducible.
+ * tun->states_per_group above 8 is clamped to 8 here.
+ */
+int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                 const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t instance_capacity,
+                 const float *image, const float *grad_image, const dgs_scene_grad *grad,
+                 void *stream);
+
+/*
+ * SYNCHRONISES the stream, then reports the instance count of the last
+ * binning in ws (*instances, may be NULL) and DGS_ERR_OVERFLOW if it exceeded
+ * the capacity that call was given; also returns DGS_ERR_HIP for a pending
+ * asynchronous HIP error.
+ */
+int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream);
+
+/*
+ * Byte offsets, inside a workspace laid out for the given sizes, of the
+ * intermediate results a render leaves behind (for inspection and tests):
+ *   rec0/rec1/rec2  float4 [n] per Gaussian: (u, v, opacity, packet_layer
+ *                   bits), (conic A, B, C, FP32 camera depth), (r, g, b, 0);
+ *                   only Gaussians that entered the last binning are written
+ *   rect            uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16), half-open tiles
+ *   ranges          uint2 [tiles]: [start, end) of each tile's list
+ *   sorted_ids      u32 [capacity]: Gaussian ids in (tile, depth, id) order
+ * Returns DGS_OK or DGS_ERR_INVALID_ARG.  Host-only; launches nothing.
+ */
+typedef struct {
+  uint64_t rec0, rec1, rec2, rect, ranges, sorted_ids;
+  int32_t tiles_x, tiles_y;
+} dgs_workspace_view;
+
+int dgs_workspace_sections(int32_t n, int32_t num_packets, const dgs_camera *cam,
+                           const dgs_tuning *tun, int32_t max_states, int64_t instance_capacity,
+                           dgs_workspace_view *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGS_H */

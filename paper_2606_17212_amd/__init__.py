@@ -1,0 +1,10 @@
+"""Batched partial-delivery Gaussian splatting on AMD MI355X (gfx950).
+
+Renders one dynamic Gaussian scene (clustered Gaussians with affine +
+low-rank temporal motion, one base and three refinement layers per cluster)
+under many incomplete delivery states in one batched launch, forward and
+backward, through the hand-written HIP kernels of ``libdgs.so``.
+"""
+
+from .render import Camera, GaussianScene, Renderer, RenderFunction, render  # noqa: F401
+from ._abi import DgsError, lib  # noqa: F401

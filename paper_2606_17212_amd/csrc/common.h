@@ -1,0 +1,145 @@
+// Shared definitions of the HIP renderer library (device helpers, kernel
+// parameter blocks, workspace layout).  Internal to libdgs.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dgs {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;         // every kernel runs 256-thread workgroups (4 waves)
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTStop = 1e-4f;
+constexpr float kQCut = 11.1f;      // >= 2 ln 255: outside the rectangle alpha < 1/255
+constexpr float kDilation = 0.3f;
+constexpr float kShC0 = 0.28209479177387814f;
+constexpr float kShC1 = 0.4886025119029199f;
+
+// Scene parameters passed by value to kernels.
+struct SceneArgs {
+  int n, rank, sh_degree, num_contexts, num_packets;
+  const float *mean, *log_scale, *quat, *opacity_logit, *color, *temporal;
+  const uint16_t *packet_layer;
+  const float *affine;
+  float basis[4];
+};
+
+struct CamArgs {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, near_z;
+  int width, height;
+  float campos[3];  // camera centre in world space (-R^T t)
+};
+
+struct TileArgs {
+  int tile_w, tile_h, tiles_x, tiles_y;
+};
+
+// Device-side counters at the start of the workspace.
+struct Header {
+  unsigned long long instances;   // tile instances of the last binning
+  unsigned long long capacity;    // capacity that binning was given
+  unsigned int overflow;          // 1 if instances > capacity
+  unsigned int n_active;          // Gaussians entering the last binning
+  unsigned int pad[10];
+};
+
+// Workspace layout (byte offsets, each 256-aligned).
+struct Layout {
+  size_t header;
+  size_t rec0, rec1, rec2;   // float4 [n] each: (u, v, o, packet_layer bits), (A, B, C, depth), (r, g, b, 0)
+  size_t rect;               // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16)
+  size_t dkey0, dkey1, dval0, dval1;  // depth sort ping-pong [n]
+  size_t cnt;                // u32 [n]: instance counts, then offsets (sorted order)
+  size_t present;            // u32 [n]: per-state compaction flags / list
+  size_t part;               // u64 scan partials
+  size_t tkey0, tkey1, tval0, tval1;  // tile sort ping-pong [cap]
+  size_t hist;               // u32 radix histograms
+  size_t ranges;             // uint2 [tiles]
+  size_t grad2d;             // f32 [9][n]
+  size_t visbits;            // u32 [max_states][P*4]
+  size_t psnr_part;          // f32 [max_states][tiles]
+  size_t total;
+  int64_t n, cap, tiles, max_states, P;
+  int64_t sort_blocks;       // blocks of the largest radix pass
+  int64_t scan_parts;        // entries of the partials buffer
+};
+
+constexpr int kSortIpt = 16;
+constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per radix workgroup
+constexpr int kScanTile = kBlock * 16;        // 4096 values per scan workgroup
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline Layout make_layout(int64_t n, int64_t P, int64_t tiles, int64_t max_states, int64_t cap) {
+  Layout L{};
+  L.n = n; L.cap = cap; L.tiles = tiles; L.max_states = max_states; L.P = P;
+  int64_t nn = n > 0 ? n : 1;
+  int64_t cc = cap > 0 ? cap : 1;
+  int64_t big = nn > cc ? nn : cc;
+  L.sort_blocks = ceil_div(big, kSortTile);
+  int64_t hist_entries = 256 * L.sort_blocks;
+  int64_t scan_max = hist_entries > nn ? hist_entries : nn;
+  L.scan_parts = ceil_div(scan_max, kScanTile) + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.header = take(sizeof(Header));
+  L.rec0 = take(16 * nn);
+  L.rec1 = take(16 * nn);
+  L.rec2 = take(16 * nn);
+  L.rect = take(8 * nn);
+  L.dkey0 = take(4 * nn);
+  L.dkey1 = take(4 * nn);
+  L.dval0 = take(4 * nn);
+  L.dval1 = take(4 * nn);
+  L.cnt = take(4 * nn);
+  L.present = take(4 * nn);
+  L.part = take(8 * L.scan_parts);
+  L.tkey0 = take(4 * cc);
+  L.tkey1 = take(4 * cc);
+  L.tval0 = take(4 * cc);
+  L.tval1 = take(4 * cc);
+  L.hist = take(4 * hist_entries);
+  L.ranges = take(8 * (tiles > 0 ? tiles : 1));
+  L.grad2d = take(4 * 9 * nn);
+  L.visbits = take(4 * (max_states > 0 ? max_states : 1) * P * 4);
+  L.psnr_part = take(4 * (max_states > 0 ? max_states : 1) * (tiles > 0 ? tiles : 1));
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+inline T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ inline unsigned long long lanemask_lt() {
+  unsigned lane = __lane_id();
+  return (1ull << lane) - 1ull;
+}
+
+__device__ inline unsigned long long lanemask_gt() {
+  unsigned lane = __lane_id();
+  return lane == 63 ? 0ull : (~0ull << (lane + 1));
+}
+
+template <typename T>
+__device__ inline T wave_incl_scan(T x) {
+  const unsigned lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d, kWave);
+    if (lane >= (unsigned)d) x += y;
+  }
+  return x;
+}
+
+}  // namespace dgs

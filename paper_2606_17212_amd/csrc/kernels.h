@@ -1,0 +1,77 @@
+// Host-side launchers of the renderer's kernels (internal to libdgs.so).
+#pragma once
+
+#include "common.h"
+
+namespace dgs {
+
+// geometry.hip
+void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
+                     const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
+                     uint2 *rect, uint32_t *dkey, uint32_t *dval, hipStream_t st);
+void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,
+                         float *g_ls, float *g_quat, float *g_logit, float *g_color, float *g_temporal,
+                         hipStream_t st);
+
+// sort.hip: exclusive scan of u32 values (total written as u64 when non-null)
+// and stable LSD radix sort of (u32 key, u32 value) pairs.
+void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, unsigned long long *parts,
+                     unsigned long long *total, hipStream_t st);
+// Sorts bits [begin_bit, end_bit) of the keys.  Count = *count_dev clamped to
+// max_count when count_dev is non-null, else max_count.  Ping-pongs between
+// (k0,v0) and (k1,v1); returns 0 if the result is in (k0,v0), 1 otherwise.
+int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const void *count_dev,
+                      int count_is_u64, int64_t max_count, int begin_bit, int end_bit, uint32_t *hist,
+                      unsigned long long *parts, hipStream_t st);
+
+// binning.hip
+void launch_clear_header(Header *h, unsigned long long capacity, hipStream_t st);
+void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+                  int grid_n, uint32_t *cnt, hipStream_t st);
+void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, const uint32_t *cnt,
+                 const unsigned *n_active, int grid_n, int tiles_x, Header *h, uint32_t *tkey,
+                 uint32_t *tval, hipStream_t st);
+void launch_ranges(const uint32_t *tkey, const Header *h, int64_t cap, int tiles, uint2 *ranges,
+                   hipStream_t st);
+void launch_visbits(const uint8_t *codes, int num_states, int P, int S, uint32_t *visbits,
+                    hipStream_t st);
+void launch_present_flags(const uint8_t *codes_row, const uint16_t *packet_layer, int n, int P,
+                          uint32_t *flags, hipStream_t st);
+void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, uint32_t *list,
+                            const unsigned long long *total, Header *h, hipStream_t st);
+void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+
+// composite.hip
+struct CompositeArgs {
+  const float4 *rec0, *rec1, *rec2;
+  const uint32_t *vals;        // sorted Gaussian ids
+  const uint2 *ranges;         // per tile [start, end)
+  const uint32_t *visbits;     // [groups][P*4] state bits, or null (every entry visible, S = 1)
+  int P4;                      // P * 4
+  int num_states, width, height, tiles_x, tiles_y, groups;
+  float bg[3];
+  float *image;                // [W][H][Wd][3]
+  float *tfinal;               // [W][H][Wd] or null
+  const float *reference;      // [H][Wd][3] (PSNR mode)
+  float *psnr_part;            // [W][tiles] (PSNR mode)
+  int state_offset;            // first state index of this launch's images
+};
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int psnr_mode,
+                     hipStream_t st);
+void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int64_t pixels,
+                          float *psnr, hipStream_t st);
+
+struct CompositeBwdArgs {
+  const float4 *rec0, *rec1, *rec2;
+  const uint32_t *vals;
+  const uint2 *ranges;
+  const uint32_t *visbits;
+  int P4;
+  int num_states, width, height, tiles_x, tiles_y, groups;
+  const float *image, *grad_image;
+  float *g2d;                  // [9][n]
+  int n;
+};
+int launch_composite_bwd(const CompositeBwdArgs &a, int S, int tile_w, int tile_h, hipStream_t st);
+
+}  // namespace dgs

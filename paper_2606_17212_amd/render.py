@@ -1,0 +1,316 @@
+"""Python binding of the renderer: device tensors in, device tensors out.
+
+PyTorch provides device memory and the stream; every step of the render runs
+in the HIP kernels of ``libdgs.so`` through the C ABI (``_abi``).  The
+binding marshals arguments and sizes the caller-owned workspace.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _abi
+
+PARAMS = ("mean", "log_scale", "quat", "opacity_logit", "color", "temporal")
+
+
+@dataclass
+class GaussianScene:
+    """Scene on the device (FP32 component-major arrays, see include/dgs.h)."""
+    mean: torch.Tensor
+    log_scale: torch.Tensor
+    quat: torch.Tensor
+    opacity_logit: torch.Tensor
+    color: torch.Tensor
+    temporal: torch.Tensor
+    packet_layer: torch.Tensor  # int16 storage of the uint16 (packet << 2) | layer
+    num_clusters: int
+    num_contexts: int
+    rank: int
+    sh_degree: int
+    cluster_affine: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[1])
+
+    @property
+    def num_packets(self) -> int:
+        return self.num_clusters * self.num_contexts
+
+    @staticmethod
+    def from_arrays(a, device="cuda") -> "GaussianScene":
+        """From a host container with numpy fields of the same names."""
+        import numpy as np
+
+        t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(device)  # noqa: E731
+        pl = torch.from_numpy(np.ascontiguousarray(a.packet_layer, dtype=np.uint16).view(np.int16)).to(device)
+        aff = None if a.cluster_affine is None else t(a.cluster_affine)
+        return GaussianScene(t(a.mean), t(a.log_scale), t(a.quat), t(a.opacity_logit), t(a.color),
+                             t(a.temporal), pl, a.num_clusters, a.num_contexts, a.rank, a.sh_degree, aff)
+
+    def with_params(self, **p) -> "GaussianScene":
+        d = dict(self.__dict__)
+        d.update(p)
+        return GaussianScene(**d)
+
+
+@dataclass
+class Camera:
+    R_cw: Sequence[float]  # 9 floats, row-major
+    t_cw: Sequence[float]
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    near: float = 0.01
+
+    @staticmethod
+    def from_arrays(c) -> "Camera":
+        import numpy as np
+        return Camera([float(x) for x in np.asarray(c.R_cw, np.float32).reshape(9)],
+                      [float(x) for x in np.asarray(c.t_cw, np.float32).reshape(3)],
+                      c.fx, c.fy, c.cx, c.cy, c.width, c.height, c.near)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, dtype, device):
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+
+
+def _c_scene(s: GaussianScene, params=None) -> _abi.Scene:
+    p = params or {k: getattr(s, k) for k in PARAMS}
+    dev = p["mean"].device
+    for k in PARAMS:
+        _check_tensor(p[k], k, torch.float32, dev)
+    _check_tensor(s.packet_layer, "packet_layer", torch.int16, dev)
+    n = s.n
+    shapes = dict(mean=(3, n), log_scale=(3, n), quat=(4, n), opacity_logit=(n,),
+                  color=((3 if s.sh_degree == 0 else 12), n), temporal=(3 * s.rank, n))
+    for k, shp in shapes.items():
+        if tuple(p[k].shape) != shp:
+            raise ValueError(f"{k} has shape {tuple(p[k].shape)}, expected {shp}")
+    return _abi.Scene(n, s.rank, s.sh_degree, s.num_clusters, s.num_contexts, _ptr(p["mean"]),
+                      _ptr(p["log_scale"]), _ptr(p["quat"]), _ptr(p["opacity_logit"]), _ptr(p["color"]),
+                      _ptr(p["temporal"]), _ptr(s.packet_layer), _ptr(s.cluster_affine))
+
+
+def _c_camera(c: Camera) -> _abi.Camera:
+    cc = _abi.Camera()
+    for k in range(9):
+        cc.R_cw[k] = float(c.R_cw[k])
+    for k in range(3):
+        cc.t_cw[k] = float(c.t_cw[k])
+    cc.fx, cc.fy, cc.cx, cc.cy, cc.near_z = c.fx, c.fy, c.cx, c.cy, c.near
+    cc.width, cc.height = int(c.width), int(c.height)
+    return cc
+
+
+def _c_states(codes: Optional[torch.Tensor], basis, background, num_states=None) -> _abi.States:
+    st = _abi.States()
+    st.num_states = int(codes.shape[0]) if codes is not None else int(num_states or 0)
+    st.codes = _ptr(codes)
+    b = list(basis) + [0.0] * (4 - len(basis))
+    for k in range(4):
+        st.basis[k] = float(b[k])
+    for k in range(3):
+        st.background[k] = float(background[k])
+    return st
+
+
+class Renderer:
+    """Owns the device workspace and the launch shape.
+
+    ``plan`` counts the scene's tile instances (one synchronisation) and sizes
+    the workspace; ``render`` and friends are then asynchronous on the
+    current stream.  ``slack`` over-provisions the instance capacity so a
+    scene whose parameters change (training) rarely needs a new plan;
+    ``check()`` reports an overflow.
+    """
+
+    def __init__(self, device="cuda", tile=(16, 16), states_per_group=16, slack=1.25):
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.tuning = _abi.Tuning(int(tile[0]), int(tile[1]), int(states_per_group), 0)
+        self.slack = float(slack)
+        self.ws = None
+        self.ws_bytes = 0
+        self.capacity = 0
+        self.max_states = 0
+        self.generation = 0  # bumps whenever the workspace's sorted lists change
+        self._key = None
+
+    # ---------------------------------------------------------------- planning
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _ensure_ws(self, nbytes):
+        if self.ws is None or self.ws_bytes < nbytes:
+            # 256-byte aligned device buffer (torch's caching allocator aligns to 512)
+            self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            self.ws_bytes = int(nbytes)
+
+    def workspace_bytes(self, scene: GaussianScene, camera: Camera, max_states: int, capacity: int) -> int:
+        b = _abi.lib().dgs_workspace_bytes(scene.n, scene.num_packets, ctypes.byref(_c_camera(camera)),
+                                           ctypes.byref(self.tuning), int(max_states), int(capacity))
+        if b == 0:
+            raise ValueError("invalid arguments for dgs_workspace_bytes")
+        return int(b)
+
+    def count_instances(self, scene: GaussianScene, camera: Camera, basis, params=None) -> int:
+        L = _abi.lib()
+        cam = _c_camera(camera)
+        self._ensure_ws(self.workspace_bytes(scene, camera, 0, 0))
+        m = ctypes.c_int64(0)
+        st = _c_states(None, basis, (0, 0, 0))
+        _abi.check(L.dgs_count_instances(ctypes.byref(_c_scene(scene, params)), ctypes.byref(cam),
+                                         ctypes.byref(st), ctypes.byref(self.tuning), _ptr(self.ws),
+                                         self.ws_bytes, ctypes.byref(m), self._stream()))
+        self.generation += 1
+        return int(m.value)
+
+    def plan(self, scene: GaussianScene, camera: Camera, basis, max_states: int, params=None) -> int:
+        m = self.count_instances(scene, camera, basis, params)
+        cap = max(int(m * self.slack) + 1024, 1024)
+        cap = min(cap, 0xFFFFFFFF)
+        self.capacity = cap
+        self.max_states = int(max_states)
+        self._ensure_ws(self.workspace_bytes(scene, camera, max_states, cap))
+        self._key = (scene.n, camera.width, camera.height)
+        return m
+
+    def _need_plan(self, scene, camera, basis, W, params=None):
+        if self._key != (scene.n, camera.width, camera.height) or W > self.max_states or self.capacity == 0:
+            self.plan(scene, camera, basis, max(W, self.max_states), params)
+
+    def sections(self, scene: GaussianScene, camera: Camera, num_states: int) -> dict:
+        """Intermediate results of the last render (synchronises): per-Gaussian
+        records and rectangles, per-tile ranges and the sorted ids."""
+        v = _abi.WorkspaceView()
+        _abi.check(_abi.lib().dgs_workspace_sections(
+            scene.n, scene.num_packets, ctypes.byref(_c_camera(camera)), ctypes.byref(self.tuning),
+            int(num_states), self.capacity, ctypes.byref(v)))
+        torch.cuda.synchronize(self.device)
+        n, tiles = scene.n, v.tiles_x * v.tiles_y
+
+        def sl(off, count, dtype, width):
+            nbytes = count * width * torch.tensor([], dtype=dtype).element_size()
+            return self.ws[off:off + nbytes].view(dtype).reshape(count, width).cpu()
+
+        return dict(rec0=sl(v.rec0, n, torch.float32, 4), rec1=sl(v.rec1, n, torch.float32, 4),
+                    rec2=sl(v.rec2, n, torch.float32, 4), rect=sl(v.rect, n, torch.int32, 2),
+                    ranges=sl(v.ranges, tiles, torch.int32, 2),
+                    sorted_ids=sl(v.sorted_ids, self.capacity, torch.int32, 1).reshape(-1),
+                    tiles_x=v.tiles_x, tiles_y=v.tiles_y)
+
+    def check(self) -> int:
+        """Synchronise and return the last binning's instance count; raises
+        DgsError on overflow."""
+        m = ctypes.c_int64(0)
+        _abi.check(_abi.lib().dgs_check(_ptr(self.ws), self.ws_bytes, ctypes.byref(m), self._stream()))
+        return int(m.value)
+
+    # ------------------------------------------------------------------ calls
+    def _codes(self, codes, scene):
+        _check_tensor(codes, "codes", torch.uint8, self.device)
+        if codes.dim() != 2 or codes.shape[1] != scene.num_packets:
+            raise ValueError(f"codes must be [W, {scene.num_packets}]")
+
+    def render(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis, background=(0, 0, 0),
+               tfinal: bool = False, params=None, per_state: bool = False, out=None):
+        """Images [W, H, Wd, 3] (and T_final [W, H, Wd] when ``tfinal``)."""
+        self._codes(codes, scene)
+        W = int(codes.shape[0])
+        self._need_plan(scene, camera, basis, W, params)
+        img = out if out is not None else torch.empty((W, camera.height, camera.width, 3),
+                                                      dtype=torch.float32, device=self.device)
+        tf = torch.empty((W, camera.height, camera.width), dtype=torch.float32,
+                         device=self.device) if tfinal else None
+        fn = _abi.lib().dgs_render_per_state if per_state else _abi.lib().dgs_render
+        _abi.check(fn(ctypes.byref(_c_scene(scene, params)), ctypes.byref(_c_camera(camera)),
+                      ctypes.byref(_c_states(codes, basis, background)), ctypes.byref(self.tuning),
+                      _ptr(self.ws), self.ws_bytes, self.capacity, _ptr(img), _ptr(tf), self._stream()))
+        self.generation += 1
+        return (img, tf) if tfinal else img
+
+    def render_psnr(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
+                    reference: torch.Tensor, background=(0, 0, 0), out=None):
+        """PSNR [W] of each state against ``reference`` [H, Wd, 3]."""
+        self._codes(codes, scene)
+        _check_tensor(reference, "reference", torch.float32, self.device)
+        W = int(codes.shape[0])
+        self._need_plan(scene, camera, basis, W)
+        ps = out if out is not None else torch.empty((W,), dtype=torch.float32, device=self.device)
+        _abi.check(_abi.lib().dgs_render_psnr(
+            ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(codes, basis, background)), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(reference), _ptr(ps), self._stream()))
+        self.generation += 1
+        return ps
+
+    def backward(self, scene: GaussianScene, camera: Camera, codes, basis, background, image, grad_image,
+                 params=None):
+        """Parameter gradients (dict of tensors) for dL/d image; the workspace
+        must still hold this render's lists (see ``RenderFunction``)."""
+        p = params or {k: getattr(scene, k) for k in PARAMS}
+        grads = {k: torch.empty_like(p[k]) for k in PARAMS}
+        g = _abi.SceneGrad(*[_ptr(grads[k]) for k in PARAMS])
+        image = image.contiguous()
+        grad_image = grad_image.contiguous()
+        _abi.check(_abi.lib().dgs_backward(
+            ctypes.byref(_c_scene(scene, p)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(codes, basis, background)), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(image), _ptr(grad_image), ctypes.byref(g), self._stream()))
+        return grads
+
+
+class RenderFunction(torch.autograd.Function):
+    """Differentiable batched render: gradients for the six parameter tensors.
+
+    The backward replays each tile's compositing from the forward's sorted
+    lists.  If the renderer's workspace was reused by another call in between,
+    the lists are rebuilt first (one extra forward)."""
+
+    @staticmethod
+    def forward(ctx, renderer, scene, camera, codes, basis, background, *params):
+        p = dict(zip(PARAMS, params))
+        img = renderer.render(scene, camera, codes, basis, background, params=p)
+        ctx.renderer, ctx.scene, ctx.camera = renderer, scene, camera
+        ctx.codes, ctx.basis, ctx.background = codes, basis, background
+        ctx.generation = renderer.generation
+        ctx.save_for_backward(img, *params)
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        img, *params = ctx.saved_tensors
+        p = dict(zip(PARAMS, params))
+        r = ctx.renderer
+        if r.generation != ctx.generation:
+            r.render(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, params=p)
+        g = r.backward(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, img, grad_image, params=p)
+        return (None, None, None, None, None, None) + tuple(g[k] for k in PARAMS)
+
+
+def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
+           background=(0, 0, 0)):
+    """Differentiable render of every state in ``codes`` -> [W, H, Wd, 3]."""
+    params = [getattr(scene, k) for k in PARAMS]
+    return RenderFunction.apply(renderer, scene, camera, codes, tuple(float(b) for b in basis),
+                                tuple(float(x) for x in background), *params)

@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol ``include/dgs.h`` declares, sizes workspaces, and rejects bad
+arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2606_17212_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libdgs.so not built (run __graft_entry__.build())")
+    return _abi, _abi.lib()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "dgs.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*(dgs_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    abi, L = _lib()
+    decl = _declared()
+    assert len(decl) >= 11
+    assert sorted(abi.EXPORTS) == decl
+    for name in decl:
+        assert hasattr(L, name), name
+    assert L.dgs_abi_version() == 1
+    assert L.dgs_status_string(3) == b"instance capacity exceeded"
+
+
+def _cam(abi, w=128, h=96):
+    c = abi.Camera()
+    for k in range(9):
+        c.R_cw[k] = 1.0 if k in (0, 4, 8) else 0.0
+    c.t_cw[2] = 3.0
+    c.fx = c.fy = 100.0
+    c.cx, c.cy, c.near_z = w / 2, h / 2, 0.01
+    c.width, c.height = w, h
+    return c
+
+
+def test_workspace_bytes_and_sections():
+    abi, L = _lib()
+    cam = _cam(abi)
+    tun = abi.Tuning(16, 16, 16, 0)
+    b0 = L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 0)
+    b1 = L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 100000)
+    assert 0 < b0 < b1
+    bad = abi.Tuning(8, 8, 16, 0)
+    assert L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(bad), 16, 0) == 0
+    assert L.dgs_workspace_bytes(-1, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 0) == 0
+    v = abi.WorkspaceView()
+    assert L.dgs_workspace_sections(1000, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 100000,
+                                    ctypes.byref(v)) == 0
+    assert (v.tiles_x, v.tiles_y) == (8, 6)
+    offs = [v.rec0, v.rec1, v.rec2, v.rect, v.ranges, v.sorted_ids]
+    assert all(o % 256 == 0 and o < b1 for o in offs)
+    tun2 = abi.Tuning(32, 8, 16, 0)
+    assert L.dgs_workspace_sections(1000, 32, ctypes.byref(cam), ctypes.byref(tun2), 16, 100000,
+                                    ctypes.byref(v)) == 0
+    assert (v.tiles_x, v.tiles_y) == (4, 12)
+
+
+def test_invalid_arguments_rejected_before_any_launch():
+    abi, L = _lib()
+    cam = _cam(abi)
+    tun = abi.Tuning(16, 16, 16, 0)
+    st = abi.States()
+    st.num_states = 1
+    st.codes = 4096  # never dereferenced: validation fails first
+    sc = abi.Scene(10, 2, 0, 2, 2, *([4096] * 8))
+    ws = ctypes.c_void_p(1 << 20)
+    # scene NULL
+    assert L.dgs_render(None, ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), ws, 1 << 30, 0,
+                        ctypes.c_void_p(4096), None, None) == 1
+    assert b"scene" in L.dgs_last_error()
+    # rank out of range
+    bad = abi.Scene(10, 7, 0, 2, 2, *([4096] * 8))
+    assert L.dgs_render(ctypes.byref(bad), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), ws,
+                        1 << 30, 0, ctypes.c_void_p(4096), None, None) == 1
+    # unsupported tile
+    t8 = abi.Tuning(8, 8, 16, 0)
+    assert L.dgs_render(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(t8), ws,
+                        1 << 30, 0, ctypes.c_void_p(4096), None, None) == 5
+    # workspace too small
+    assert L.dgs_render(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), ws, 16,
+                        0, ctypes.c_void_p(4096), None, None) == 2
+    # misaligned workspace
+    assert L.dgs_render(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun),
+                        ctypes.c_void_p((1 << 20) + 4), 1 << 30, 0, ctypes.c_void_p(4096), None, None) == 1
+    # capacity beyond 32-bit offsets
+    assert L.dgs_render(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), ws,
+                        1 << 30, 1 << 33, ctypes.c_void_p(4096), None, None) == 1
+    # camera size
+    c0 = _cam(abi, 0, 10)
+    assert L.dgs_render(ctypes.byref(sc), ctypes.byref(c0), ctypes.byref(st), ctypes.byref(tun), ws,
+                        1 << 30, 0, ctypes.c_void_p(4096), None, None) == 1
+    # missing image / grads
+    assert L.dgs_render(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), ws,
+                        1 << 30, 0, None, None, None) == 1
+    g = abi.SceneGrad(None, None, None, None, None, None)
+    assert L.dgs_backward(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), ws,
+                          1 << 30, 0, ctypes.c_void_p(4096), ctypes.c_void_p(4096), ctypes.byref(g),
+                          None) == 1
+
+
+def test_python_binding_validates_tensors():
+    import torch
+
+    import paper_2606_17212_amd as dgs
+    from paper_2606_17212_amd.render import _c_scene
+    sc = dgs.GaussianScene(torch.zeros(3, 5), torch.zeros(3, 5), torch.zeros(4, 5), torch.zeros(5),
+                           torch.zeros(3, 5), torch.zeros(6, 5), torch.zeros(5, dtype=torch.int16),
+                           2, 2, 2, 0)
+    _c_scene(sc)  # shapes and dtypes fine (host tensors: pointers are only marshalled)
+    with pytest.raises(ValueError):
+        _c_scene(sc.with_params(color=torch.zeros(12, 5)))
+    with pytest.raises(TypeError):
+        _c_scene(sc.with_params(mean=torch.zeros(3, 5, dtype=torch.float64)))

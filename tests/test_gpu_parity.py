@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+Bars: tile rectangles, depth keys and per-tile sorted lists bit-exact with the
+oracle's FP32 mirror; images within 1e-4 absolute of the FP64 oracle plus its
+ambiguity budget (alphas within 0.1% of 1/255, transmittance near 1e-4);
+batched == per-state == any group size == either tile shape, bit for bit.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+BG = (0.25, 0.5, 0.75)
+TOL = 1e-4
+
+
+def _dgs():
+    import paper_2606_17212_amd as dgs
+    return dgs
+
+
+def on_device(w):
+    dgs = _dgs()
+    dev = torch.device("cuda:0")
+    return (dgs.GaussianScene.from_arrays(w.scene, dev), dgs.Camera.from_arrays(w.camera),
+            torch.from_numpy(np.ascontiguousarray(w.codes)).to(dev))
+
+
+def image_excess(gpu_img, ref):
+    """max over pixels of (|gpu - oracle| - budget), per state/pixel/channel."""
+    d = np.abs(gpu_img.astype(np.float64) - ref["image"]).max(-1)
+    return d - ref["budget"]
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.make_workload("g4k_128px_16states", background=BG)
+    ref = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background)
+    return w, ref
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_geometry_keys_rects_and_lists_bit_exact(tiny, tile):
+    dgs = _dgs()
+    w, _ = tiny
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer(tile=tile)
+    r.render(scene, cam, codes, w.basis, BG)
+    assert r.check() > 0
+    sec = r.sections(scene, cam, codes.shape[0])
+    m = oracle.mirror_f32(w.scene, w.camera, w.basis, *tile)
+    valid = m["valid"]
+    zb = sec["rec1"][:, 3].numpy().view(np.uint32)
+    assert np.array_equal(zb[valid], m["zbits"][valid])
+    rect = sec["rect"].numpy().view(np.uint32)
+    x0, y0 = rect[:, 0] & 0xFFFF, rect[:, 0] >> 16
+    x1, y1 = rect[:, 1] & 0xFFFF, rect[:, 1] >> 16
+    gr = np.stack([x0, y0, x1, y1]).astype(np.int64)
+    assert np.array_equal(gr[:, valid], m["rect"][:, valid].astype(np.int64))
+    ranges, ids, _ = oracle.tile_lists(m, w.camera.width, w.camera.height)
+    granges = sec["ranges"].numpy().astype(np.int64)
+    nonempty = ranges[:, 1] > ranges[:, 0]
+    assert np.array_equal(granges[nonempty], ranges[nonempty])
+    assert np.all(granges[~nonempty, 1] == granges[~nonempty, 0])
+    M = ids.size
+    assert np.array_equal(sec["sorted_ids"].numpy()[:M].astype(np.int64), ids)
+    # FP32 projection against the FP64 definition
+    g = oracle.geometry_f64(w.scene, w.camera, w.basis)
+    rec0, rec1, rec2 = sec["rec0"].numpy(), sec["rec1"].numpy(), sec["rec2"].numpy()
+    assert np.max(np.abs(rec0[valid, 0] - g["u"][valid])) < 2e-4
+    assert np.max(np.abs(rec0[valid, 1] - g["v"][valid])) < 2e-4
+    assert np.max(np.abs(rec0[valid, 2] / g["o"][valid] - 1)) < 1e-5
+    for j, k in enumerate(("conA", "conB", "conC")):
+        scale = np.maximum(np.abs(g["conA"]), np.abs(g["conC"]))[valid]
+        assert np.max(np.abs(rec1[valid, j] - g[k][valid]) / scale) < 2e-5
+    col = np.stack([g["r"], g["g"], g["b_"]], 1)[valid]
+    assert np.max(np.abs(rec2[valid, :3] - col)) < 2e-6
+
+
+@pytest.mark.parametrize("tile,S", [((16, 16), 16), ((32, 8), 4), ((16, 16), 1)])
+def test_images_match_oracle(tiny, tile, S):
+    dgs = _dgs()
+    w, ref = tiny
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer(tile=tile, states_per_group=S)
+    img, tf = r.render(scene, cam, codes, w.basis, BG, tfinal=True)
+    r.check()
+    ex = image_excess(img.cpu().numpy(), ref)
+    assert ex.max() <= TOL, f"max excess {ex.max():.3g} at {np.unravel_index(ex.argmax(), ex.shape)}"
+    tfe = np.abs(tf.cpu().numpy() - ref["tfinal"])
+    amb = ref["budget"] > 0
+    assert tfe[~amb].max() <= 1e-5
+
+
+def test_batched_equals_per_state_and_any_launch_shape(tiny):
+    dgs = _dgs()
+    w, _ = tiny
+    scene, cam, codes = on_device(w)
+    base = dgs.Renderer(tile=(16, 16), states_per_group=16)
+    ref_img, ref_tf = base.render(scene, cam, codes, w.basis, BG, tfinal=True)
+    ps_img, ps_tf = base.render(scene, cam, codes, w.basis, BG, tfinal=True, per_state=True)
+    base.check()
+    assert torch.equal(ps_img, ref_img) and torch.equal(ps_tf, ref_tf)
+    for tile in ((16, 16), (32, 8)):
+        for S in (1, 2, 4, 8, 16, 32):
+            r = dgs.Renderer(tile=tile, states_per_group=S)
+            img = r.render(scene, cam, codes, w.basis, BG)
+            assert torch.equal(img, ref_img), (tile, S)
+    # repeat-run determinism
+    assert torch.equal(base.render(scene, cam, codes, w.basis, BG), ref_img)
+
+
+def test_state_permutation_and_masks(tiny):
+    dgs = _dgs()
+    w, _ = tiny
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer()
+    img = r.render(scene, cam, codes, w.basis, BG)
+    perm = torch.randperm(codes.shape[0], generator=torch.Generator().manual_seed(0)).to(codes.device)
+    img_p = r.render(scene, cam, codes[perm].contiguous(), w.basis, BG)
+    assert torch.equal(img_p, img[perm])
+    empty = torch.zeros_like(codes[:3])
+    e = r.render(scene, cam, empty, w.basis, BG)
+    assert torch.equal(e, torch.tensor(BG, dtype=torch.float32, device=e.device).expand_as(e))
+    full = torch.full_like(codes[:2], 4)
+    one = torch.ones_like(codes[:2])  # this scene has only layer 0: code 1 delivers everything
+    assert torch.equal(r.render(scene, cam, full, w.basis, BG), r.render(scene, cam, one, w.basis, BG))
+
+
+def test_storage_permutation_invariance(tiny):
+    dgs = _dgs()
+    w, _ = tiny
+    m = oracle.mirror_f32(w.scene, w.camera, w.basis)
+    # random storage order, except that Gaussians with equal depth keys keep
+    # their relative order (equal keys are ordered by storage index)
+    perm = np.random.default_rng(4).permutation(w.scene.n)
+    newpos = np.empty_like(perm)
+    newpos[perm] = np.arange(perm.size)
+    zb = m["zbits"]
+    for key in np.unique(zb[np.unique(zb, return_counts=True)[1][np.searchsorted(np.unique(zb), zb)] > 1]):
+        members = np.nonzero(zb == key)[0]
+        newpos[members] = np.sort(newpos[members])
+    perm = np.empty_like(newpos)
+    perm[newpos] = np.arange(newpos.size)
+    scene, cam, codes = on_device(w)
+    w2 = synth.Workload(**{**w.__dict__, "scene": synth.permute_gaussians(w.scene, perm)})
+    scene2, _, _ = on_device(w2)
+    r = dgs.Renderer()
+    a = r.render(scene, cam, codes, w.basis, BG)
+    b = r.render(scene2, cam, codes, w.basis, BG)
+    assert torch.equal(a, b)
+
+
+def test_ragged_sizes_and_edge_cases():
+    dgs = _dgs()
+    sc = synth.make_scene(1537, 4, 4, 4, "sh1", index=9)
+    cam = synth.ring_camera(100, 75)
+    codes = synth.make_codes("present_depth", 0.3, 1.0, 5, sc.num_packets, 4, index=9)
+    w = synth.Workload("ragged", 9, sc, cam, codes, synth.temporal_basis(0.5, 2), 0.5,
+                       np.array(BG, np.float32))
+    ref = oracle.render(sc, cam, w.basis, codes, w.background)
+    scene, dcam, dcodes = on_device(w)
+    for tile in ((16, 16), (32, 8)):
+        r = dgs.Renderer(tile=tile, states_per_group=4)
+        img = r.render(scene, dcam, dcodes, w.basis, BG)
+        r.check()
+        assert image_excess(img.cpu().numpy(), ref).max() <= TOL
+        ps = r.render(scene, dcam, dcodes, w.basis, BG, per_state=True)
+        assert torch.equal(ps, img)
+    # no states: nothing to do; one state
+    r = dgs.Renderer()
+    one = r.render(scene, dcam, dcodes[:1].contiguous(), w.basis, BG)
+    assert one.shape == (1, 75, 100, 3)
+    assert image_excess(one.cpu().numpy(), {k: v[:1] for k, v in ref.items()}).max() <= TOL
+
+
+def test_camera_inside_and_behind():
+    """Gaussians behind the camera and on the near plane are culled; the
+    camera sits inside the cloud."""
+    dgs = _dgs()
+    sc = synth.make_scene(3000, 4, 2, 1, "rgb", index=10)
+    cam = synth.ring_camera(96, 64, radius=0.5)
+    codes = synth.make_codes("bernoulli", 0.8, 0.8, 3, sc.num_packets, 1, index=10)
+    w = synth.Workload("inside", 10, sc, cam, codes, synth.temporal_basis(0.5, 2), 0.5,
+                       np.array(BG, np.float32))
+    ref = oracle.render(sc, cam, w.basis, codes, w.background)
+    scene, dcam, dcodes = on_device(w)
+    r = dgs.Renderer()
+    img = r.render(scene, dcam, dcodes, w.basis, BG)
+    r.check()
+    assert image_excess(img.cpu().numpy(), ref).max() <= TOL
+
+
+def test_overflow_is_reported_and_safe(tiny):
+    dgs = _dgs()
+    w, _ = tiny
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer()
+    r.plan(scene, cam, w.basis, codes.shape[0])
+    r.capacity = 100  # far below the scene's instances; the workspace stays large enough
+    img = r.render(scene, cam, codes, w.basis, BG)
+    with pytest.raises(dgs.DgsError) as e:
+        r.check()
+    assert e.value.status == 3
+    assert torch.equal(img, torch.tensor(BG, dtype=torch.float32, device=img.device).expand_as(img))
+
+
+def test_psnr_reduction(tiny):
+    dgs = _dgs()
+    w, ref = tiny
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer()
+    full = torch.ones_like(codes[:1])
+    reference = r.render(scene, cam, full, w.basis, BG)[0].contiguous()
+    img = r.render(scene, cam, codes, w.basis, BG)
+    ps = r.render_psnr(scene, cam, codes, w.basis, reference, BG).cpu().numpy()
+    host = oracle.psnr(img.cpu().numpy(), reference.cpu().numpy())
+    assert np.max(np.abs(ps - host)) <= 1e-4 * np.maximum(1.0, np.abs(host)).max()
+    ref_full = oracle.render(w.scene, w.camera, w.basis, np.ones_like(w.codes[:1]), w.background)
+    orc = oracle.psnr(ref["image"], ref_full["image"][0])
+    assert np.max(np.abs(ps - orc)) <= 0.05
+
+
+def test_full_size_250k_800px_sampled_pixels():
+    """The 250k-Gaussian, 800x800, 64-state workload in the bench's launch
+    shape: sorted lists bit-exact at full size, sampled pixels of every state
+    against the oracle, and per-state == batched for a few states."""
+    dgs = _dgs()
+    w = synth.make_workload("g250k_800px_64states", background=BG)
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer(tile=(16, 16), states_per_group=16)
+    img = r.render(scene, cam, codes, w.basis, BG)
+    M = r.check()
+    sec = r.sections(scene, cam, codes.shape[0])
+    m = oracle.mirror_f32(w.scene, w.camera, w.basis)
+    ranges, ids, _ = oracle.tile_lists(m, w.camera.width, w.camera.height)
+    assert M == ids.size
+    assert np.array_equal(sec["sorted_ids"].numpy()[:M].astype(np.int64), ids)
+    rng = np.random.default_rng(12)
+    pix = np.concatenate([rng.integers(0, 800, size=(96, 2)),
+                          rng.integers(300, 500, size=(96, 2))])  # more in the dense centre
+    ref = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
+    got = img.cpu().numpy()[:, pix[:, 1], pix[:, 0], :]
+    ex = np.abs(got.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
+    assert ex.max() <= TOL, f"excess {ex.max():.3g}"
+    sub = codes[[0, 17, 63]].contiguous()
+    ps = r.render(scene, cam, sub, w.basis, BG, per_state=True)
+    assert torch.equal(ps, img[[0, 17, 63]])
