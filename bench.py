@@ -1,0 +1,237 @@
+"""Batched partial-delivery render benchmark (one MI355X).
+
+Step = one pass of the whole hot path over one batch of synthetic input:
+deformation + projection of every Gaussian, depth sort, tile binning and
+per-tile lists (dgs_bin), then masked compositing of every delivery state
+(dgs_composite).  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line: batched delivery-states/s (value), the plain per-state
+render timed as synchronized serial evaluation, fwd+bwd ms/iter on the
+250k-Gaussian 720p 8-state training workload, the compositing kernel's
+roofline, and the oracle's CPU rate on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "delivery-states rendered/s batched vs per-state; fwd+bwd ms/iter @250k G"
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+# Algorithmic FLOPs (an FMA counts 2) per unit of compositing work:
+FLOPS_PER_ALPHA = 14       # dx, dy, quadratic form (8), scale, exp, x opacity, cap
+FLOPS_PER_BLEND = 8        # T*alpha, 3 FMA colour, T - T*alpha
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="g250k_800px_64states")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--states-per-group", type=int, default=16)
+    ap.add_argument("--no-per-state", action="store_true")
+    ap.add_argument("--no-fwdbwd", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported in this build "
+              "(states shard across GPUs with no exchange in the forward; see DESIGN.md)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2606_17212_amd as dgs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    w = synth.make_workload(args.workload)
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(w.codes).to(dev)
+    W = int(codes.shape[0])
+    bg = tuple(float(x) for x in w.background)
+    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group)
+    M = r.plan(scene, cam, w.basis, W)
+    log(f"[bench] {args.workload}: N={scene.n} {cam.width}x{cam.height} W={W} instances={M}")
+    img = torch.empty((W, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+
+    def step():
+        r.bin(scene, cam, w.basis)
+        r.composite(scene, cam, codes, w.basis, bg, out=img)
+
+    for _ in range(args.warmup):
+        step()
+    r.check()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(st)
+    for k in range(args.steps):
+        ev[k][0].record(st)
+        r.bin(scene, cam, w.basis)
+        ev[k][1].record(st)
+        r.composite(scene, cam, codes, w.basis, bg, out=img)
+        ev[k][2].record(st)
+    t_end.record(st)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    bin_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    comp_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    ms_step = total_ms / args.steps
+    value = W * args.steps / (total_ms / 1e3)
+    r.check()
+    log(f"[bench] batched: {ms_step:.3f} ms/step (bin {bin_ms:.3f}, composite {comp_ms:.3f}) -> {value:.1f} states/s")
+
+    # algorithmic work of one composite launch
+    alpha_evals, blends = r.composite_stats(scene, cam, codes, w.basis)
+    flops = FLOPS_PER_ALPHA * alpha_evals + FLOPS_PER_BLEND * blends
+    achieved = flops / (comp_ms / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "k_composite<16,16,16,0>" if (tw, th, args.states_per_group) == (16, 16, 16) else
+                f"k_composite<{args.states_per_group},{tw},{th},0>",
+                "kernel_ms": round(comp_ms, 4), "alpha_evals": alpha_evals, "blends": blends,
+                "flops_per_launch": flops}
+    log(f"[bench] composite work: {alpha_evals} alpha evals, {blends} blends -> {achieved:.2f} TFLOP/s")
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "states/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "gaussians": scene.n, "width": cam.width,
+                      "height": cam.height, "states": W, "clusters": w.scene.num_clusters,
+                      "contexts": w.scene.num_contexts, "tile": f"{tw}x{th}",
+                      "states_per_group": args.states_per_group, "instances": M},
+           "batched": {"bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4)}}
+
+    if not args.no_per_state:
+        # plain per-state render, synchronized after every state
+        one = torch.empty((1, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+        for k in range(min(4, W)):
+            r.render(scene, cam, codes[k:k + 1], w.basis, bg, per_state=True, out=one)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(W):
+            r.render(scene, cam, codes[k:k + 1], w.basis, bg, per_state=True, out=one)
+            torch.cuda.synchronize()
+        ps_s = time.perf_counter() - t0
+        r.check()
+        same = bool(torch.equal(one[0], img[W - 1]))
+        ps_rate = W / ps_s
+        out["per_state"] = {"value": round(ps_rate, 2), "unit": "states/s", "ms_per_state": round(1e3 * ps_s / W, 4),
+                            "bit_identical_to_batched": same}
+        out["speedup_batched_vs_per_state"] = round(value / ps_rate, 3)
+        log(f"[bench] per-state: {1e3 * ps_s / W:.3f} ms/state -> {ps_rate:.1f} states/s; identical={same}")
+
+    out["roofline"] = roofline
+
+    if not args.no_fwdbwd:
+        out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, np, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def fwd_bwd(dgs, synth, torch, np, dev, args):
+    """Forward + L1 loss + backward to the six parameter tensors on the
+    250k-Gaussian 1280x720 8-state workload; the target is the full-delivery
+    render of the scene with parameters perturbed by N(0, 0.01)."""
+    name = "g250k_720p_8states_fwdbwd"
+    w = synth.make_workload(name)
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(w.codes).to(dev)
+    bg = tuple(float(x) for x in w.background)
+    r = dgs.Renderer(dev, tile=(16, 16), states_per_group=8)
+    pert = dgs.GaussianScene.from_arrays(synth.perturb_scene(w.scene, 0.01, index=w.index), dev)
+    full = torch.full((1, w.scene.num_packets), 4, dtype=torch.uint8, device=dev)
+    target = r.render(pert, cam, full, w.basis, bg)[0].clone()
+    r.plan(scene, cam, w.basis, codes.shape[0])
+    from paper_2606_17212_amd.render import PARAMS
+    params = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    sc = scene.with_params(**params)
+
+    def it():
+        for p in params.values():
+            p.grad = None
+        img = dgs.render(r, sc, cam, codes, w.basis, bg)
+        loss = (img - target).abs().mean()
+        loss.backward()
+        return loss
+
+    for _ in range(3):
+        it()
+    r.check()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    iters = max(5, args.steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(iters):
+        e0.record(st)
+        loss = it()
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    r.check()
+    finite = all(bool(torch.isfinite(p.grad).all()) for p in params.values())
+    log(f"[bench] fwd+bwd {name}: median {np.median(times):.3f} ms/iter, loss {float(loss):.5f}")
+    return {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
+            "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
+            "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+
+
+def cpu_baseline(w, np, seconds):
+    """The oracle (plain FP64 C, OpenMP over pixels) on a bounded random pixel
+    sample of the same workload, every state; scaled to full-frame states/s."""
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    H, Wd = w.camera.height, w.camera.width
+    rng = np.random.default_rng(2606)
+    probe = np.stack([rng.integers(0, Wd, 64), rng.integers(0, H, 64)], 1)
+    t0 = time.perf_counter()
+    oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=probe)
+    per_px = (time.perf_counter() - t0) / 64
+    k = int(min(H * Wd, max(256, seconds / max(per_px, 1e-9))))
+    pix = np.stack([rng.integers(0, Wd, k), rng.integers(0, H, k)], 1)
+    t0 = time.perf_counter()
+    oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
+    dt = time.perf_counter() - t0
+    W = w.codes.shape[0]
+    rate = W * (k / (H * Wd)) / dt
+    log(f"[bench] cpu oracle: {k} px x {W} states in {dt:.2f} s on {cores} threads -> {rate:.4g} states/s")
+    return {"value": rate, "unit": "states/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} uniformly random pixels of {Wd}x{H}, all {W} states, {dt:.1f} s; "
+                      "rate scaled by (sampled pixels / frame pixels)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

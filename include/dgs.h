@@ -167,6 +167,42 @@ int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *
                float *image, float *tfinal, void *stream);
 
 /*
+ * The two halves of dgs_render.  dgs_bin runs the shared part -- deformation,
+ * projection, depth sort, tile binning and the per-tile lists -- for the
+ * scene and camera (states->codes is not read; basis is).  dgs_composite then
+ * composites every state in `states` from those lists; it may be called any
+ * number of times after one dgs_bin (e.g. a sweep over many state batches of
+ * one scene and time), with the same scene, camera, tuning, workspace and
+ * capacity.  Outputs as for dgs_render.
+ */
+int dgs_bin(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+            const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t instance_capacity,
+            void *stream);
+int dgs_composite(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                  const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t instance_capacity,
+                  float *image, float *tfinal, void *stream);
+
+/*
+ * PSNR of every state against `reference` from the lists of the last dgs_bin
+ * (as dgs_render_psnr, without the binning).
+ */
+int dgs_composite_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                       const dgs_tuning *tun, void *ws, size_t ws_bytes,
+                       int64_t instance_capacity, const float *reference, float *psnr,
+                       void *stream);
+
+/*
+ * Work counters of dgs_composite for the same arguments, nothing rendered:
+ * counters (device, 2 x u64, overwritten) = { alpha evaluations: (pixel,
+ * list entry, state group) triples where some delivered state of the group is
+ * still compositing that pixel, blends: (pixel, state, Gaussian) triples
+ * composited, i.e. present Gaussians with alpha >= 1/255 before the stop }.
+ */
+int dgs_composite_stats(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                        const dgs_tuning *tun, void *ws, size_t ws_bytes,
+                        int64_t instance_capacity, unsigned long long *counters, void *stream);
+
+/*
  * Plain per-state render (baseline): for each state in turn, compacts the
  * delivered Gaussians, projects, bins, sorts and composites only them.
  * Same outputs, bit-identical to dgs_render's.  tun->states_per_group is

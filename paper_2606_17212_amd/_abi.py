@@ -19,7 +19,8 @@ DGS_ERR_OVERFLOW = 3
 EXPORTS = (
     "dgs_abi_version", "dgs_status_string", "dgs_last_error", "dgs_workspace_bytes",
     "dgs_count_instances", "dgs_render", "dgs_render_per_state", "dgs_render_psnr",
-    "dgs_backward", "dgs_check", "dgs_workspace_sections",
+    "dgs_backward", "dgs_check", "dgs_workspace_sections", "dgs_bin", "dgs_composite",
+    "dgs_composite_psnr", "dgs_composite_stats",
 )
 
 
@@ -93,6 +94,14 @@ def lib():
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = common + [i64, vp, vp, vp]
+    L.dgs_bin.restype = ctypes.c_int
+    L.dgs_bin.argtypes = common + [i64, vp]
+    L.dgs_composite.restype = ctypes.c_int
+    L.dgs_composite.argtypes = common + [i64, vp, vp, vp]
+    L.dgs_composite_psnr.restype = ctypes.c_int
+    L.dgs_composite_psnr.argtypes = common + [i64, vp, vp, vp]
+    L.dgs_composite_stats.restype = ctypes.c_int
+    L.dgs_composite_stats.argtypes = common + [i64, vp, vp]
     L.dgs_render_psnr.restype = ctypes.c_int
     L.dgs_render_psnr.argtypes = common + [i64, vp, vp, vp]
     L.dgs_backward.restype = ctypes.c_int

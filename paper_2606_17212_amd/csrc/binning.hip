@@ -169,4 +169,10 @@ void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st) {
   k_fill_f32<<<(unsigned)ceil_div(n, kBlock), kBlock, 0, st>>>(p, n, v);
 }
 
+__global__ void k_fill_u64(unsigned long long *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+void launch_fill_u64(unsigned long long *p, int n, hipStream_t st) { k_fill_u64<<<1, 64, 0, st>>>(p, n); }
+
 }  // namespace dgs

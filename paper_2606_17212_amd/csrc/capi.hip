@@ -295,6 +295,81 @@ int dgs_count_instances(const dgs_scene *scene, const dgs_camera *cam, const dgs
   return DGS_OK;
 }
 
+int dgs_bin(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states, const dgs_tuning *tun,
+            void *ws, size_t ws_bytes, int64_t cap, void *stream) {
+  g_err.clear();
+  Call cl;
+  int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 0, &cl);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Header *h = at<Header>(ws, cl.L.header);
+  launch_clear_header(h, (unsigned long long)cap, st);
+  project_and_count(cl, ws, false, st);
+  emit_and_sort(cl, ws, false, cap, st);
+  return hip_check("bin launch");
+}
+
+namespace {
+
+// Masked compositing of every state from the lists of the last dgs_bin.
+// mode 0: images, 1: PSNR partials + finalisation, 2: work counters.
+int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                   const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, int mode, float *image,
+                   float *tfinal, const float *reference, float *psnr, unsigned long long *counters,
+                   void *stream) {
+  Call cl;
+  int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl);
+  if (rc) return rc;
+  const int W = states->num_states;
+  if (mode == 0 && W > 0 && !image) return fail(DGS_ERR_INVALID_ARG, "image is NULL");
+  if (mode == 1 && W > 0 && (!reference || !psnr)) return fail(DGS_ERR_INVALID_ARG, "reference / psnr is NULL");
+  if (mode == 2 && !counters) return fail(DGS_ERR_INVALID_ARG, "counters is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (mode == 2) launch_fill_u64(counters, 2, st);
+  if (W == 0) return hip_check("composite launch");
+  const int S = group_size(tun, W, 32);
+  const int groups = (W + S - 1) / S;
+  uint32_t *visbits = at<uint32_t>(ws, cl.L.visbits);
+  launch_visbits(states->codes, W, cl.P, S, visbits, st);
+  CompositeArgs a = composite_args(cl, ws, sorted_vals(cl, ws), states, visbits, groups);
+  a.image = image;
+  a.tfinal = tfinal;
+  a.reference = reference;
+  a.psnr_part = at<float>(ws, cl.L.psnr_part);
+  a.counters = counters;
+  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, st))
+    return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
+  if (mode == 1)
+    launch_psnr_finalize(a.psnr_part, W, cl.tiling.tiles, (int64_t)cl.c.width * cl.c.height, psnr, st);
+  return hip_check("composite launch");
+}
+
+}  // namespace
+
+int dgs_composite(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                  const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, float *image, float *tfinal,
+                  void *stream) {
+  g_err.clear();
+  return composite_call(scene, cam, states, tun, ws, ws_bytes, cap, 0, image, tfinal, nullptr, nullptr, nullptr,
+                        stream);
+}
+
+int dgs_composite_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                       const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, const float *reference,
+                       float *psnr, void *stream) {
+  g_err.clear();
+  return composite_call(scene, cam, states, tun, ws, ws_bytes, cap, 1, nullptr, nullptr, reference, psnr, nullptr,
+                        stream);
+}
+
+int dgs_composite_stats(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                        const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap,
+                        unsigned long long *counters, void *stream) {
+  g_err.clear();
+  return composite_call(scene, cam, states, tun, ws, ws_bytes, cap, 2, nullptr, nullptr, nullptr, nullptr,
+                        counters, stream);
+}
+
 int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states, const dgs_tuning *tun,
                void *ws, size_t ws_bytes, int64_t cap, float *image, float *tfinal, void *stream) {
   g_err.clear();
@@ -302,23 +377,9 @@ int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *
   int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl);
   if (rc) return rc;
   if (states->num_states > 0 && !image) return fail(DGS_ERR_INVALID_ARG, "image is NULL");
-  hipStream_t st = (hipStream_t)stream;
-  const int W = states->num_states;
-  if (W == 0) return DGS_OK;
-  Header *h = at<Header>(ws, cl.L.header);
-  launch_clear_header(h, (unsigned long long)cap, st);
-  project_and_count(cl, ws, false, st);
-  const uint32_t *vals = emit_and_sort(cl, ws, false, cap, st);
-  const int S = group_size(tun, W, 32);
-  const int groups = (W + S - 1) / S;
-  uint32_t *visbits = at<uint32_t>(ws, cl.L.visbits);
-  launch_visbits(states->codes, W, cl.P, S, visbits, st);
-  CompositeArgs a = composite_args(cl, ws, vals, states, visbits, groups);
-  a.image = image;
-  a.tfinal = tfinal;
-  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, 0, st))
-    return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
-  return hip_check("render launch");
+  if (states->num_states == 0) return DGS_OK;
+  if ((rc = dgs_bin(scene, cam, states, tun, ws, ws_bytes, cap, stream))) return rc;
+  return dgs_composite(scene, cam, states, tun, ws, ws_bytes, cap, image, tfinal, stream);
 }
 
 int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
@@ -364,22 +425,8 @@ int dgs_render_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_sta
   const int W = states->num_states;
   if (W > 0 && (!reference || !psnr)) return fail(DGS_ERR_INVALID_ARG, "reference / psnr is NULL");
   if (W == 0) return DGS_OK;
-  hipStream_t st = (hipStream_t)stream;
-  Header *h = at<Header>(ws, cl.L.header);
-  launch_clear_header(h, (unsigned long long)cap, st);
-  project_and_count(cl, ws, false, st);
-  const uint32_t *vals = emit_and_sort(cl, ws, false, cap, st);
-  const int S = group_size(tun, W, 32);
-  const int groups = (W + S - 1) / S;
-  uint32_t *visbits = at<uint32_t>(ws, cl.L.visbits);
-  launch_visbits(states->codes, W, cl.P, S, visbits, st);
-  CompositeArgs a = composite_args(cl, ws, vals, states, visbits, groups);
-  a.reference = reference;
-  a.psnr_part = at<float>(ws, cl.L.psnr_part);
-  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, 1, st))
-    return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
-  launch_psnr_finalize(a.psnr_part, W, cl.tiling.tiles, (int64_t)cl.c.width * cl.c.height, psnr, st);
-  return hip_check("render_psnr launch");
+  if ((rc = dgs_bin(scene, cam, states, tun, ws, ws_bytes, cap, stream))) return rc;
+  return dgs_composite_psnr(scene, cam, states, tun, ws, ws_bytes, cap, reference, psnr, stream);
 }
 
 int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states, const dgs_tuning *tun,

@@ -75,6 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
 
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
+  uint32_t n_alpha = 0, n_blend = 0;  // MODE 2 only
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
     int alive = 0;
 #pragma unroll
@@ -99,6 +100,12 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
       const float4 A = s_a[k];
       const uint32_t uv = __builtin_amdgcn_readfirstlane(__float_as_uint(A.w)) & wave_alive;
       if (uv == 0u) continue;
+      if (MODE == 2) {
+        uint32_t lane_alive = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) lane_alive |= (T[s] > 0.0f ? 1u : 0u) << s;
+        n_alpha += (uv & lane_alive) ? 1u : 0u;
+      }
       const float4 B = s_b[k];
       float e;
       const float alpha = splat_alpha_e(A.x, A.y, A.z, B.x, B.y, B.z, fpx, fpy, e);
@@ -106,9 +113,27 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
       const float4 C = s_c[k];
 #pragma unroll
       for (int s = 0; s < S; ++s)
-        if (uv & (1u << s)) blend(T[s], cr[s], cg[s], cb[s], alpha, C.x, C.y, C.z);
+        if (uv & (1u << s)) {
+          if (MODE == 2) n_blend += T[s] > 0.0f ? 1u : 0u;
+          blend(T[s], cr[s], cg[s], cb[s], alpha, C.x, C.y, C.z);
+        }
     }
     __syncthreads();
+  }
+
+  if (MODE == 2) {
+    // work counters: alpha evaluations some live delivered state needs, and blends
+    unsigned long long c0 = n_alpha, c1 = n_blend;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      c0 += __shfl_xor(c0, d, kWave);
+      c1 += __shfl_xor(c1, d, kWave);
+    }
+    if (__lane_id() == 0) {
+      atomicAdd(a.counters, c0);
+      atomicAdd(a.counters + 1, c1);
+    }
+    return;
   }
 
   if (MODE == 0) {
@@ -330,8 +355,10 @@ template <int S, int TW, int TH>
 static void launch_fwd_t(const CompositeArgs &a, int mode, unsigned blocks, hipStream_t st) {
   if (mode == 0)
     k_composite<S, TW, TH, 0><<<blocks, kBlock, 0, st>>>(a);
-  else
+  else if (mode == 1)
     k_composite<S, TW, TH, 1><<<blocks, kBlock, 0, st>>>(a);
+  else
+    k_composite<S, TW, TH, 2><<<blocks, kBlock, 0, st>>>(a);
 }
 
 template <int TW, int TH>
@@ -347,12 +374,12 @@ static int launch_fwd_s(const CompositeArgs &a, int S, int mode, unsigned blocks
   }
 }
 
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int psnr_mode, hipStream_t st) {
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, hipStream_t st) {
   const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.groups;
   if (total <= 0) return 0;
   const unsigned blocks = (unsigned)total;
-  if (tile_w == 16 && tile_h == 16) return launch_fwd_s<16, 16>(a, S, psnr_mode, blocks, st);
-  if (tile_w == 32 && tile_h == 8) return launch_fwd_s<32, 8>(a, S, psnr_mode, blocks, st);
+  if (tile_w == 16 && tile_h == 16) return launch_fwd_s<16, 16>(a, S, mode, blocks, st);
+  if (tile_w == 32 && tile_h == 8) return launch_fwd_s<32, 8>(a, S, mode, blocks, st);
   return 1;
 }
 

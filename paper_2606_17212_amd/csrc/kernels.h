@@ -40,6 +40,7 @@ void launch_present_flags(const uint8_t *codes_row, const uint16_t *packet_layer
 void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, uint32_t *list,
                             const unsigned long long *total, Header *h, hipStream_t st);
 void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+void launch_fill_u64(unsigned long long *p, int n, hipStream_t st);  // zero n <= 64 counters
 
 // composite.hip
 struct CompositeArgs {
@@ -55,9 +56,10 @@ struct CompositeArgs {
   const float *reference;      // [H][Wd][3] (PSNR mode)
   float *psnr_part;            // [W][tiles] (PSNR mode)
   int state_offset;            // first state index of this launch's images
+  unsigned long long *counters;  // [2] (count mode): alpha evaluations, blends
 };
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int psnr_mode,
-                     hipStream_t st);
+// mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, hipStream_t st);
 void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int64_t pixels,
                           float *psnr, hipStream_t st);
 

@@ -249,6 +249,59 @@ class Renderer:
         self.generation += 1
         return (img, tf) if tfinal else img
 
+    def bin(self, scene: GaussianScene, camera: Camera, basis, params=None):
+        """Shared half of a render: projection, depth sort, tile lists."""
+        self._need_plan(scene, camera, basis, self.max_states, params)
+        _abi.check(_abi.lib().dgs_bin(
+            ctypes.byref(_c_scene(scene, params)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(None, basis, (0, 0, 0))), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, self._stream()))
+        self.generation += 1
+
+    def composite(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis, background=(0, 0, 0),
+                  tfinal: bool = False, out=None):
+        """Masked compositing of every state in ``codes`` from the last ``bin``."""
+        self._codes(codes, scene)
+        W = int(codes.shape[0])
+        if W > self.max_states:
+            raise ValueError(f"{W} states > planned {self.max_states}; plan again")
+        img = out if out is not None else torch.empty((W, camera.height, camera.width, 3),
+                                                      dtype=torch.float32, device=self.device)
+        tf = torch.empty((W, camera.height, camera.width), dtype=torch.float32,
+                         device=self.device) if tfinal else None
+        _abi.check(_abi.lib().dgs_composite(
+            ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(codes, basis, background)), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(img), _ptr(tf), self._stream()))
+        return (img, tf) if tfinal else img
+
+    def composite_psnr(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
+                       reference: torch.Tensor, background=(0, 0, 0), out=None):
+        """PSNR [W] from the last ``bin`` (no image written)."""
+        self._codes(codes, scene)
+        _check_tensor(reference, "reference", torch.float32, self.device)
+        W = int(codes.shape[0])
+        if W > self.max_states:
+            raise ValueError(f"{W} states > planned {self.max_states}; plan again")
+        ps = out if out is not None else torch.empty((W,), dtype=torch.float32, device=self.device)
+        _abi.check(_abi.lib().dgs_composite_psnr(
+            ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(codes, basis, background)), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(reference), _ptr(ps), self._stream()))
+        return ps
+
+    def composite_stats(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis):
+        """(alpha evaluations, blends) one ``composite`` of ``codes`` performs
+        after the last ``bin`` (synchronises)."""
+        self._codes(codes, scene)
+        cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
+        _abi.check(_abi.lib().dgs_composite_stats(
+            ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(codes, basis, (0, 0, 0))), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(cnt), self._stream()))
+        c = cnt.cpu().tolist()
+        return int(c[0]), int(c[1])
+
     def render_psnr(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
                     reference: torch.Tensor, background=(0, 0, 0), out=None):
         """PSNR [W] of each state against ``reference`` [H, Wd, 3]."""

@@ -141,8 +141,9 @@ def test_storage_permutation_invariance(tiny):
     newpos = np.empty_like(perm)
     newpos[perm] = np.arange(perm.size)
     zb = m["zbits"]
-    for key in np.unique(zb[np.unique(zb, return_counts=True)[1][np.searchsorted(np.unique(zb), zb)] > 1]):
-        members = np.nonzero(zb == key)[0]
+    _, inv, cnt = np.unique(zb, return_inverse=True, return_counts=True)
+    for grp in np.nonzero(cnt > 1)[0]:
+        members = np.nonzero(inv == grp)[0]
         newpos[members] = np.sort(newpos[members])
     perm = np.empty_like(newpos)
     perm[newpos] = np.arange(newpos.size)
@@ -250,3 +251,26 @@ def test_full_size_250k_800px_sampled_pixels():
     sub = codes[[0, 17, 63]].contiguous()
     ps = r.render(scene, cam, sub, w.basis, BG, per_state=True)
     assert torch.equal(ps, img[[0, 17, 63]])
+
+
+def test_bin_once_composite_many_and_work_counters(tiny):
+    """One binning serves several composite calls (a sweep over state
+    batches); the blend counter equals the oracle's composited-pair count up to
+    ambiguous pixels."""
+    dgs = _dgs()
+    w, ref = tiny
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer(states_per_group=8)
+    full = r.render(scene, cam, codes, w.basis, BG)
+    r.bin(scene, cam, w.basis)
+    a = r.composite(scene, cam, codes[:5].contiguous(), w.basis, BG)
+    b = r.composite(scene, cam, codes[5:].contiguous(), w.basis, BG)
+    assert torch.equal(torch.cat([a, b]), full)
+    alpha_evals, blends = r.composite_stats(scene, cam, codes, w.basis)
+    want = int(ref["ncomp"].sum())
+    amb = int((ref["budget"] > 0).sum())
+    assert abs(blends - want) <= 4 * amb, (blends, want, amb)
+    assert alpha_evals >= blends / codes.shape[0]
+    ps = r.composite_psnr(scene, cam, codes, w.basis, full[0].contiguous(), BG).cpu().numpy()
+    host = oracle.psnr(full.cpu().numpy(), full[0].cpu().numpy())
+    assert np.max(np.abs(ps - host)) <= 1e-3
