@@ -1,0 +1,111 @@
+"""GPU backward vs the oracle's FP64 gradient (autograd of the dense FP64
+formulation with every discrete decision frozen).
+
+Bar, per parameter tensor: ||g - g*|| / ||g*|| <= 1e-3, and elementwise
+|g - g*| <= 1e-3 (|g*| + rms(g*)) outside entries whose Gaussian touches an
+ambiguous pixel (an alpha within 0.1% of 1/255 or T within 0.1% of 1e-4 may
+take either branch in FP32)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.grad as og
+import synth
+
+pytestmark = pytest.mark.gpu
+BG = (0.25, 0.5, 0.75)
+
+
+def _gpu_grads(w, gimg, tile=(16, 16), S=8, pixels_mask=None):
+    import paper_2606_17212_amd as dgs
+    from paper_2606_17212_amd.render import PARAMS
+    dev = torch.device("cuda:0")
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(np.ascontiguousarray(w.codes)).to(dev)
+    r = dgs.Renderer(dev, tile=tile, states_per_group=S)
+    p = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    sc = scene.with_params(**p)
+    img = dgs.render(r, sc, cam, codes, w.basis, BG)
+    g = torch.from_numpy(np.ascontiguousarray(gimg, dtype=np.float32)).to(dev)
+    (img * g).sum().backward()
+    r.check()
+    return {k: p[k].grad.double().cpu().numpy() for k in PARAMS}, img.detach().cpu().numpy()
+
+
+def _compare(got, ref, exclude=None, rel=1e-3):
+    for k in ref:
+        a, b = got[k], ref[k]
+        nb = np.linalg.norm(b)
+        if nb == 0:
+            assert np.linalg.norm(a) <= 1e-6, k
+            continue
+        assert np.linalg.norm(a - b) / nb <= rel, (k, np.linalg.norm(a - b) / nb)
+        rms = np.sqrt(np.mean(b * b))
+        bad = np.abs(a - b) > rel * (np.abs(b) + rms)
+        if exclude is not None:
+            bad &= ~exclude[None, :] if bad.ndim == 2 else ~exclude
+        assert not bad.any(), (k, int(bad.sum()), np.argwhere(bad)[:5])
+
+
+def _ambiguous_gaussians(w, budget_pixels):
+    """Gaussians reaching alpha >= 1/(2*255) at a pixel with a nonzero budget."""
+    n = w.scene.n
+    g = oracle.geometry_f64(w.scene, w.camera, w.basis)
+    out = np.zeros(n, dtype=bool)
+    for (px, py) in budget_pixels:
+        dx, dy = g["u"] - (px + 0.5), g["v"] - (py + 0.5)
+        q = g["conA"] * dx * dx + 2 * g["conB"] * dx * dy + g["conC"] * dy * dy
+        out |= g["o"] * np.exp(-0.5 * q) >= 0.5 / 255
+    return out
+
+
+@pytest.mark.parametrize("log_scale_mean", [-3.0, -1.5])
+def test_gradients_match_fp64_oracle_subscene(log_scale_mean):
+    w = synth.subscene(256, 64, 64, states=8, log_scale_mean=log_scale_mean, background=BG)
+    rng = np.random.default_rng(7)
+    gimg = rng.normal(size=(8, 64, 64, 3))
+    got, img = _gpu_grads(w, gimg)
+    ref_img = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background)
+    assert (np.abs(img - ref_img["image"]).max(-1) - ref_img["budget"]).max() <= 1e-4
+    ref = og.gradients(w.scene, w.camera, w.basis, w.codes, BG, gimg)
+    amb_pix = np.argwhere(ref_img["budget"].max(0) > 0)[:, ::-1]
+    _compare(got, ref, exclude=_ambiguous_gaussians(w, amb_pix))
+
+
+def test_gradients_l1_loss_tile_shapes_agree():
+    """L1 loss against a perturbed-scene target; both tile shapes and group
+    sizes give the same gradients up to atomic-order rounding."""
+    w = synth.subscene(256, 64, 64, states=8, log_scale_mean=-1.5, background=BG)
+    tgt = oracle.render(synth.perturb_scene(w.scene, 0.01, index=4), w.camera, w.basis,
+                        np.full((1, w.scene.num_packets), 4, np.uint8), w.background)["image"][0]
+    ref_img = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background)["image"]
+    gimg = og.l1_loss_grad(ref_img, tgt[None])
+    a, _ = _gpu_grads(w, gimg, tile=(16, 16), S=8)
+    b, _ = _gpu_grads(w, gimg, tile=(32, 8), S=2)
+    for k in a:
+        nb = np.linalg.norm(a[k])
+        assert np.linalg.norm(a[k] - b[k]) <= 1e-5 * max(nb, 1e-12), k
+    ref = og.gradients(w.scene, w.camera, w.basis, w.codes, BG, gimg)
+    _compare(a, ref, exclude=None, rel=2e-3)
+
+
+def test_gradients_full_size_720p_window():
+    """The 250k-Gaussian 1280x720 8-state training workload at full size with
+    dL/dimage non-zero only in a 24x24 window: the Gaussians touching the
+    window get the oracle's gradient, all others exactly zero."""
+    w = synth.make_workload("g250k_720p_8states_fwdbwd", background=BG)
+    W, H, Wd = w.codes.shape[0], w.camera.height, w.camera.width
+    x0, y0 = 620, 350
+    rng = np.random.default_rng(3)
+    gimg = np.zeros((W, H, Wd, 3))
+    gimg[:, y0:y0 + 24, x0:x0 + 24, :] = rng.normal(size=(W, 24, 24, 3))
+    got, _ = _gpu_grads(w, gimg)
+    ys, xs = np.meshgrid(np.arange(y0, y0 + 24), np.arange(x0, x0 + 24), indexing="ij")
+    pix = np.stack([xs.reshape(-1), ys.reshape(-1)], 1)
+    ref = og.gradients(w.scene, w.camera, w.basis, w.codes, BG, gimg[:, y0:y0 + 24, x0:x0 + 24, :], pixels=pix)
+    rpix = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
+    amb = pix[rpix["budget"].max(0) > 0]
+    _compare(got, ref, exclude=_ambiguous_gaussians(w, amb))
