@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
 
 
@@ -149,6 +151,15 @@ def main():
         log(f"[bench] per-state: {1e3 * ps_s / W:.3f} ms/state -> {ps_rate:.1f} states/s; identical={same}")
 
     out["roofline"] = roofline
+
+    if args.copy_mib > 0:
+        # a plain copy kernel of known size, for scaling FETCH_SIZE / WRITE_SIZE counters
+        nbytes = args.copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)

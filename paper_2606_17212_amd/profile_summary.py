@@ -26,3 +26,23 @@ if __name__ == "__main__":
     ap.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
     print(summarize(a.db, a.top))
+
+
+def summarize_pmc(csv_paths, match=None) -> str:
+    """Per-kernel averages of rocprofv3 ``--pmc ... --output-format csv``
+    counter files (``*_counter_collection.csv``)."""
+    import collections
+    import csv
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for p in csv_paths:
+        for row in csv.DictReader(open(p)):
+            name = row["Kernel_Name"]
+            if match and not any(m in name for m in match):
+                continue
+            acc[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    lines = []
+    for name, ctrs in acc.items():
+        lines.append(name)
+        for c, v in sorted(ctrs.items()):
+            lines.append(f"    {c:24s} mean {sum(v) / len(v):16.1f}   dispatches {len(v)}")
+    return "\n".join(lines)
