@@ -250,8 +250,9 @@ int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream);
 /*
  * Byte offsets, inside a workspace laid out for the given sizes, of the
  * intermediate results a render leaves behind (for inspection and tests):
- *   rec0/rec1/rec2  float4 [n] per Gaussian: (u, v, opacity, packet_layer
- *                   bits), (conic A, B, C, FP32 camera depth), (r, g, b, 0);
+ *   rec0/rec1/rec2  float4 [n] per Gaussian: (u, v, log2 opacity,
+ *                   packet_layer bits), (conic A, B, C scaled by -log2(e)/2,
+ *                   -log2(e), -log2(e)/2, FP32 camera depth), (r, g, b, 0);
  *                   only Gaussians that entered the last binning are written
  *   rect            uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16), half-open tiles
  *   ranges          uint2 [tiles]: [start, end) of each tile's list

@@ -104,10 +104,10 @@ void launch_ranges(const uint32_t *tkey, const Header *h, int64_t cap, int tiles
 }
 
 // visbits[g][p*4 + l], bit s set iff layer l of packet p is delivered in
-// state g*S + s (l < code).
+// state order[g*S + s] (l < code).
 __global__ void __launch_bounds__(kBlock)
-k_visbits(const uint8_t *__restrict__ codes, int num_states, int P, int S, int groups,
-          uint32_t *__restrict__ visbits) {
+k_visbits(const uint8_t *__restrict__ codes, const uint32_t *__restrict__ order, int num_states, int P, int S,
+          int groups, uint32_t *__restrict__ visbits) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t P4 = (int64_t)P * 4;
   if (idx >= (int64_t)groups * P4) return;
@@ -116,17 +116,131 @@ k_visbits(const uint8_t *__restrict__ codes, int num_states, int P, int S, int g
   const int p = pl >> 2, l = pl & 3;
   uint32_t bits = 0;
   for (int s = 0; s < S; ++s) {
-    const int w = g * S + s;
-    if (w < num_states && l < (int)codes[(int64_t)w * P + p]) bits |= 1u << s;
+    const int k = g * S + s;
+    if (k >= num_states) break;
+    const int w = order ? (int)order[k] : k;
+    if (l < (int)codes[(int64_t)w * P + p]) bits |= 1u << s;
   }
   visbits[idx] = bits;
 }
 
-void launch_visbits(const uint8_t *codes, int num_states, int P, int S, uint32_t *visbits, hipStream_t st) {
+void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S,
+                    uint32_t *visbits, hipStream_t st) {
   const int groups = (int)ceil_div(num_states, S);
   const int64_t total = (int64_t)groups * P * 4;
   if (total <= 0) return;
-  k_visbits<<<(unsigned)ceil_div(total, kBlock), kBlock, 0, st>>>(codes, num_states, P, S, groups, visbits);
+  k_visbits<<<(unsigned)ceil_div(total, kBlock), kBlock, 0, st>>>(codes, order, num_states, P, S, groups,
+                                                                  visbits);
+}
+
+// Gaussians per (packet, layer) of the binned scene.
+__global__ void __launch_bounds__(kBlock)
+k_plhist(const uint16_t *__restrict__ packet_layer, int n, int P4, uint32_t *__restrict__ hist) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int pl = packet_layer[i];
+  if (pl < P4) atomicAdd(hist + pl, 1u);
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero_u32(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st) {
+  const int P4 = P * 4;
+  k_zero_u32<<<(unsigned)ceil_div(P4, kBlock), kBlock, 0, st>>>(hist, P4);
+  if (n > 0) k_plhist<<<(unsigned)ceil_div(n, kBlock), kBlock, 0, st>>>(packet_layer, n, P4, hist);
+}
+
+// Present count of every state (one workgroup per state) from the
+// (packet, layer) histogram.
+__global__ void __launch_bounds__(kBlock)
+k_state_counts(const uint8_t *__restrict__ codes, const uint32_t *__restrict__ hist, int P,
+               uint32_t *__restrict__ cnt) {
+  const int w = blockIdx.x;
+  uint32_t c = 0;
+  for (int p = threadIdx.x; p < P; p += kBlock) {
+    const int code = codes[(int64_t)w * P + p];
+    const uint4 h = reinterpret_cast<const uint4 *>(hist)[p];
+    c += (code > 0 ? h.x : 0u) + (code > 1 ? h.y : 0u) + (code > 2 ? h.z : 0u) + (code > 3 ? h.w : 0u);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, kWave);
+  __shared__ uint32_t part[4];
+  if (__lane_id() == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[w] = part[0] + part[1] + part[2] + part[3];
+}
+
+// One workgroup: states ordered by increasing present count (ties by index),
+// so that the S states of a group have similar list-walk depths.
+__global__ void __launch_bounds__(1024)
+k_state_rank(const uint32_t *__restrict__ cnt_g, int num_states, uint32_t *__restrict__ order) {
+  extern __shared__ uint32_t cnt[];
+  for (int w = threadIdx.x; w < num_states; w += blockDim.x) cnt[w] = cnt_g[w];
+  __syncthreads();
+  for (int w = threadIdx.x; w < num_states; w += blockDim.x) {
+    const uint32_t cw = cnt[w];
+    int rank = 0;
+    for (int v = 0; v < num_states; ++v) {
+      const uint32_t cv = cnt[v];
+      rank += (cv < cw || (cv == cw && v < w)) ? 1 : 0;
+    }
+    order[rank] = (uint32_t)w;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_iota(uint32_t *p, int n) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
+void launch_state_order(const uint8_t *codes, const uint32_t *hist, int num_states, int P, uint32_t *cnt,
+                        uint32_t *order, hipStream_t st) {
+  if (num_states <= 0) return;
+  if (num_states > kMaxOrderedStates) {  // identity order beyond the LDS-resident ranking
+    k_iota<<<(unsigned)ceil_div(num_states, kBlock), kBlock, 0, st>>>(order, num_states);
+    return;
+  }
+  k_state_counts<<<num_states, kBlock, 0, st>>>(codes, hist, P, cnt);
+  k_state_rank<<<1, 1024, sizeof(uint32_t) * num_states, st>>>(cnt, num_states, order);
+}
+
+// One workgroup: tiles ordered by decreasing list length, bucketed by
+// floor(log2(length + 1)) (order inside a bucket is arbitrary: every work
+// item writes disjoint outputs, so the processing order never changes results).
+__global__ void __launch_bounds__(1024)
+k_tile_order(const uint2 *__restrict__ ranges, int tiles, uint32_t *__restrict__ order) {
+  __shared__ uint32_t bcount[33];
+  __shared__ uint32_t bstart[33];
+  if (threadIdx.x < 33) bcount[threadIdx.x] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    const int b = 32 - __clz(len);  // 0 for empty
+    atomicAdd(&bcount[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int b = 32; b >= 0; --b) {  // heaviest bucket first
+      bstart[b] = acc;
+      acc += bcount[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+    const uint2 r = ranges[t];
+    const int b = 32 - __clz(r.y - r.x);
+    order[atomicAdd(&bstart[b], 1u)] = (uint32_t)t;
+  }
+}
+
+void launch_tile_order(const uint2 *ranges, int tiles, uint32_t *order, hipStream_t st) {
+  if (tiles <= 0) return;
+  k_tile_order<<<1, 1024, 0, st>>>(ranges, tiles, order);
 }
 
 __global__ void __launch_bounds__(kBlock)

@@ -174,8 +174,8 @@ void project_and_count(const Call &cl, void *ws, bool list_mode, hipStream_t st)
   const uint32_t *list = list_mode ? at<uint32_t>(ws, L.present) : nullptr;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
   launch_geometry(cl.s, cl.c, cl.t, list, nact, n, at<float4>(ws, L.rec0), at<float4>(ws, L.rec1),
-                  at<float4>(ws, L.rec2), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey0),
-                  at<uint32_t>(ws, L.dval0), st);
+                  at<float4>(ws, L.rec2), at<uint2>(ws, L.rect), at<uint2>(ws, L.pbox),
+                  at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), st);
   // depth keys: 32 bits, 4 passes -> result back in dkey0/dval0
   launch_radix_sort(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.dkey1),
                     at<uint32_t>(ws, L.dval1), nact, 0, n, 0, 32, at<uint32_t>(ws, L.hist),
@@ -229,8 +229,10 @@ CompositeArgs composite_args(const Call &cl, void *ws, const uint32_t *vals, con
   a.rec0 = at<float4>(ws, cl.L.rec0);
   a.rec1 = at<float4>(ws, cl.L.rec1);
   a.rec2 = at<float4>(ws, cl.L.rec2);
+  a.pbox = at<uint2>(ws, cl.L.pbox);
   a.vals = vals;
   a.ranges = at<uint2>(ws, cl.L.ranges);
+  a.tile_order = at<uint32_t>(ws, cl.L.tile_order);
   a.visbits = visbits;
   a.P4 = cl.P * 4;
   a.num_states = states->num_states;
@@ -306,6 +308,8 @@ int dgs_bin(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *sta
   launch_clear_header(h, (unsigned long long)cap, st);
   project_and_count(cl, ws, false, st);
   emit_and_sort(cl, ws, false, cap, st);
+  launch_plhist(scene->packet_layer, cl.s.n, cl.P, at<uint32_t>(ws, cl.L.plhist), st);
+  launch_tile_order(at<uint2>(ws, cl.L.ranges), cl.tiling.tiles, at<uint32_t>(ws, cl.L.tile_order), st);
   return hip_check("bin launch");
 }
 
@@ -330,8 +334,13 @@ int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_stat
   const int S = group_size(tun, W, 32);
   const int groups = (W + S - 1) / S;
   uint32_t *visbits = at<uint32_t>(ws, cl.L.visbits);
-  launch_visbits(states->codes, W, cl.P, S, visbits, st);
+  uint32_t *order = at<uint32_t>(ws, cl.L.state_order);
+  launch_state_order(states->codes, at<uint32_t>(ws, cl.L.plhist), W, cl.P, at<uint32_t>(ws, cl.L.state_cnt),
+                     order, st);
+  launch_visbits(states->codes, order, W, cl.P, S, visbits, st);
   CompositeArgs a = composite_args(cl, ws, sorted_vals(cl, ws), states, visbits, groups);
+  a.state_order = order;
+  a.launch_states = W;
   a.image = image;
   a.tfinal = tfinal;
   a.reference = reference;
@@ -405,10 +414,12 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
                            at<uint32_t>(ws, cl.L.present), &h->instances, h, st);
     project_and_count(cl, ws, true, st);
     const uint32_t *vals = emit_and_sort(cl, ws, true, cap, st);
+    launch_tile_order(at<uint2>(ws, cl.L.ranges), cl.tiling.tiles, at<uint32_t>(ws, cl.L.tile_order), st);
     CompositeArgs a = composite_args(cl, ws, vals, states, nullptr, 1);
     a.image = image;
     a.tfinal = tfinal;
     a.state_offset = w;
+    a.launch_states = 1;
     if (launch_composite(a, 1, cl.tiling.tw, cl.tiling.th, 0, st))
       return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=1");
   }
@@ -449,11 +460,17 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
     const int S = group_size(tun, W, 8);
     const int groups = (W + S - 1) / S;
     uint32_t *visbits = at<uint32_t>(ws, cl.L.visbits);
-    launch_visbits(states->codes, W, cl.P, S, visbits, st);
+    uint32_t *order = at<uint32_t>(ws, cl.L.state_order);
+    launch_state_order(states->codes, at<uint32_t>(ws, cl.L.plhist), W, cl.P, at<uint32_t>(ws, cl.L.state_cnt),
+                       order, st);
+    launch_visbits(states->codes, order, W, cl.P, S, visbits, st);
     CompositeBwdArgs b{};
+    b.tile_order = at<uint32_t>(ws, cl.L.tile_order);
+    b.state_order = order;
     b.rec0 = at<float4>(ws, cl.L.rec0);
     b.rec1 = at<float4>(ws, cl.L.rec1);
     b.rec2 = at<float4>(ws, cl.L.rec2);
+    b.pbox = at<uint2>(ws, cl.L.pbox);
     b.vals = sorted_vals(cl, ws);
     b.ranges = at<uint2>(ws, cl.L.ranges);
     b.visbits = visbits;

@@ -17,6 +17,12 @@ constexpr float kQCut = 11.1f;      // >= 2 ln 255: outside the rectangle alpha 
 constexpr float kDilation = 0.3f;
 constexpr float kShC0 = 0.28209479177387814f;
 constexpr float kShC1 = 0.4886025119029199f;
+// alpha = min(0.99, 2^q') with q' = A' dx^2 + B' dx dy + C' dy^2 + log2(o), where
+// (A', B', C') = (kConicA A, kConicB B, kConicA C) pre-scale the conic (A, B, C):
+// 2^q' = o exp(-(A dx^2 + 2 B dx dy + C dy^2) / 2).
+constexpr float kConicA = -0.72134752044448170f;  // -log2(e) / 2
+constexpr float kConicB = -1.4426950408889634f;   // -log2(e)
+constexpr float kQSkip = -7.9943534368588578f;    // log2(1/255): alpha < 1/255 <=> q' < kQSkip
 
 // Scene parameters passed by value to kernels.
 struct SceneArgs {
@@ -51,8 +57,9 @@ struct Header {
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
   size_t header;
-  size_t rec0, rec1, rec2;   // float4 [n] each: (u, v, o, packet_layer bits), (A, B, C, depth), (r, g, b, 0)
-  size_t rect;               // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16)
+  size_t rec0, rec1, rec2;   // float4 [n] each: (u, v, log2 o, packet_layer bits), (A', B', C', depth), (r, g, b, 0)
+  size_t rect;               // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16) in tiles
+  size_t pbox;               // uint2 [n]: the same rectangle in pixels
   size_t dkey0, dkey1, dval0, dval1;  // depth sort ping-pong [n]
   size_t cnt;                // u32 [n]: instance counts, then offsets (sorted order)
   size_t present;            // u32 [n]: per-state compaction flags / list
@@ -61,6 +68,10 @@ struct Layout {
   size_t hist;               // u32 radix histograms
   size_t ranges;             // uint2 [tiles]
   size_t grad2d;             // f32 [9][n]
+  size_t plhist;             // u32 [P*4]: Gaussians per (packet, layer)
+  size_t tile_order;         // u32 [tiles]: tiles by decreasing list length
+  size_t state_cnt;          // u32 [max_states]: present Gaussians per state
+  size_t state_order;        // u32 [max_states]: states by increasing present count
   size_t visbits;            // u32 [max_states][P*4]
   size_t psnr_part;          // f32 [max_states][tiles]
   size_t total;
@@ -94,6 +105,7 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles, int64_t max_state
   L.rec1 = take(16 * nn);
   L.rec2 = take(16 * nn);
   L.rect = take(8 * nn);
+  L.pbox = take(8 * nn);
   L.dkey0 = take(4 * nn);
   L.dkey1 = take(4 * nn);
   L.dval0 = take(4 * nn);
@@ -108,6 +120,10 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles, int64_t max_state
   L.hist = take(4 * hist_entries);
   L.ranges = take(8 * (tiles > 0 ? tiles : 1));
   L.grad2d = take(4 * 9 * nn);
+  L.plhist = take(4 * P * 4);
+  L.tile_order = take(4 * (tiles > 0 ? tiles : 1));
+  L.state_cnt = take(4 * (max_states > 0 ? max_states : 1));
+  L.state_order = take(4 * (max_states > 0 ? max_states : 1));
   L.visbits = take(4 * (max_states > 0 ? max_states : 1) * P * 4);
   L.psnr_part = take(4 * (max_states > 0 ? max_states : 1) * (tiles > 0 ? tiles : 1));
   L.total = o;

@@ -2,38 +2,48 @@
 // of per-tile (depth, index)-sorted lists, forward and backward.
 //
 // Work item = (tile, group of S states); one 256-thread workgroup, one pixel
-// per thread.  The tile's list is walked in batches of 256 entries staged in
-// LDS.  The alpha of a splat at a pixel does not depend on the state, so it
-// is evaluated once per (pixel, entry) and applied to every state of the
-// group that has the entry delivered: the delivery bits of an entry are the
-// same for every pixel, so the per-state tests are scalar (wave-uniform)
-// branches, and an entry no state of the wave still needs costs four scalar
-// instructions.  States are independent recurrences held in registers.
+// per thread, each wave owning an 8x8 pixel block of the tile.  The tile's
+// list is walked in batches of 256 entries staged in LDS; the thread that
+// stages an entry also records, per wave, whether the entry's pixel rectangle
+// touches that wave's block and which of the group's states have the entry
+// delivered (one 32-bit word per wave).  The alpha of a splat at a pixel
+// does not depend on the state, so it is evaluated once per (pixel, entry) and
+// applied to every state of the group that has the entry delivered.  The
+// delivery word is wave-uniform, so the per-state tests are scalar branches,
+// and an entry no live state of the wave needs costs one LDS read and a few
+// scalar instructions.
 //
-// Per (pixel, state): alpha = min(0.99, o exp(-q/2)); alpha < 1/255 is
-// skipped; C += T alpha c; T -= T alpha; compositing stops right after the
-// entry that leaves T < 1e-4.  A stopped state keeps -T_final in its T slot,
-// which makes every later update an exact no-op.  The per-state arithmetic
-// is one shared function, so a state's pixels are bit-identical whichever
+// Per (pixel, state): alpha = min(0.99, o exp(-q/2)), evaluated as
+// 2^(q' + log2 o) with a pre-scaled conic; alpha < 1/255 is skipped (tested
+// on the exponent, before the exponential); C += T alpha c; T -= T alpha;
+// compositing stops right after the entry that leaves T < 1e-4.  A stopped
+// state keeps -T_final in its T slot; the clamped product clamp(T alpha)
+// then makes every later update an exact no-op.  The per-state arithmetic is
+// one shared function, so a state's pixels are bit-identical whichever
 // group, tile shape or launch they are composited in.
 #include "common.h"
 #include "kernels.h"
 
 namespace dgs {
 
-__device__ __forceinline__ float splat_alpha_e(float u, float v, float o, float A, float B, float C,
-                                               float px, float py, float &e_out) {
-  const float dx = u - px, dy = v - py;
-  const float q = fmaf(A * dx, dx, fmaf(C * dy, dy, (2.0f * B) * dx * dy));
-  const float e = __builtin_amdgcn_exp2f(q * -0.72134752044448170f);  // e^{-q/2}
-  e_out = e;
-  return fminf(kAlphaMax, o * e);
+// q' = A' dx^2 + B' dx dy + C' dy^2 + log2(o) for p0 = (u, v, log2 o, A'), p1 = (B', C')
+__device__ __forceinline__ float splat_q(const float4 &p0, const float2 &p1, float px, float py) {
+  const float dx = p0.x - px, dy = p0.y - py;
+  float t = p0.w * dx;
+  t = fmaf(p1.x, dy, t);
+  const float q = fmaf(t, dx, p0.z);
+  const float c = p1.y * dy;
+  return fmaf(c, dy, q);
+}
+
+__device__ __forceinline__ float alpha_of(float q) {
+  return fminf(kAlphaMax, __builtin_amdgcn_exp2f(q));
 }
 
 __device__ __forceinline__ void blend(float &T, float &r, float &g, float &b, float alpha, float cr,
                                       float cg, float cb) {
-  const float Tp = fmaxf(T, 0.0f);
-  const float ta = Tp * alpha;
+  // T alpha for a live state (T > 0, T alpha < 1), exactly 0 for a stopped one (T <= 0)
+  const float ta = __builtin_amdgcn_fmed3f(T * alpha, 0.0f, 1.0f);
   r = fmaf(ta, cr, r);
   g = fmaf(ta, cg, g);
   b = fmaf(ta, cb, b);
@@ -41,24 +51,65 @@ __device__ __forceinline__ void blend(float &T, float &r, float &g, float &b, fl
   T = (Tn < kTStop) ? -fabsf(Tn) : Tn;
 }
 
-// Linear workgroup id -> work item, so that consecutive items land on the
-// same XCD (workgroups are dispatched round-robin over the 8 XCDs): the
-// groups of one tile and neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int xcd_item(int L, int total) {
-  const int xcd = L & 7, slot = L >> 3;
-  const int q = total >> 3, rm = total & 7;
-  return xcd * q + (xcd < rm ? xcd : rm) + slot;
+// Workgroup id -> (position in the tile order, state group).  Workgroups are
+// dispatched in id order, round-robin over the 8 XCDs; the mapping keeps all
+// groups of a tile on one XCD (sharing its L2) and starts the heaviest tiles
+// first.  Returns false for the idle workgroups of the last row.
+__device__ __forceinline__ bool work_item(int L, int groups, int tiles, int &k, int &grp) {
+  const int xcd = L & 7, r = L >> 3;
+  grp = r % groups;
+  k = (r / groups) * 8 + xcd;
+  return k < tiles;
+}
+
+__host__ __device__ inline int work_items(int tiles, int groups) { return ((tiles + 7) / 8) * 8 * groups; }
+
+// Origin of wave w's 8x8 block inside a TW x TH tile.
+template <int TW>
+__device__ __forceinline__ int wave_x0(int w) { return (w * 8) % TW; }
+template <int TW>
+__device__ __forceinline__ int wave_y0(int w) { return ((w * 8) / TW) * 8; }
+
+struct Stage {
+  uint32_t vis[4][kBlock];  // per wave: delivery bits of the entry, 0 if it misses the wave's block
+  float4 p0[kBlock];        // u, v, log2 o, A'
+  float2 p1[kBlock];        // B', C'
+  float4 col[kBlock];       // r, g, b, -
+  uint32_t id[kBlock];      // Gaussian id (backward)
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t id, const float4 *rec0,
+                                            const float4 *rec1, const float4 *rec2, const uint2 *pbox,
+                                            const uint32_t *vis, int tpx, int tpy) {
+  const float4 r0 = rec0[id];
+  const float4 r1 = rec1[id];
+  const uint2 pb = pbox[id];
+  const uint32_t vb = vis ? vis[__float_as_uint(r0.w)] : 1u;
+  const int x0 = (int)(pb.x & 0xFFFFu) - tpx, y0 = (int)(pb.x >> 16) - tpy;
+  const int x1 = (int)(pb.y & 0xFFFFu) - tpx, y1 = (int)(pb.y >> 16) - tpy;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int bx = wave_x0<TW>(w), by = wave_y0<TW>(w);
+    const bool hit = x0 < bx + 8 && x1 > bx && y0 < by + 8 && y1 > by;
+    st.vis[w][slot] = hit ? vb : 0u;
+  }
+  st.p0[slot] = make_float4(r0.x, r0.y, r0.z, r1.x);
+  st.p1[slot] = make_float2(r1.y, r1.z);
+  st.col[slot] = rec2[id];
+  st.id[slot] = id;
 }
 
 template <int S, int TW, int TH, int MODE>
 __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
   static_assert(TW * TH == kBlock, "one pixel per thread");
-  const int total = a.tiles_x * a.tiles_y * a.groups;
-  const int item = xcd_item(blockIdx.x, total);
-  const int tile = item / a.groups, grp = item - tile * a.groups;
+  int kpos, grp;
+  if (!work_item(blockIdx.x, a.groups, a.tiles_x * a.tiles_y, kpos, grp)) return;
+  const int tile = (int)a.tile_order[kpos];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int tid = threadIdx.x;
-  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int tpx = tx * TW, tpy = ty * TH;
+  const int px = tpx + wave_x0<TW>(wv) + (lane & 7), py = tpy + wave_y0<TW>(wv) + (lane >> 3);
   const bool inside = px < a.width && py < a.height;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
 
@@ -69,10 +120,7 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
     cr[s] = cg[s] = cb[s] = 0.0f;
   }
 
-  __shared__ float4 s_a[kBlock];  // u, v, o, delivery bits
-  __shared__ float4 s_b[kBlock];  // conic A, B, C, depth
-  __shared__ float4 s_c[kBlock];  // colour
-
+  __shared__ Stage st;
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
   uint32_t n_alpha = 0, n_blend = 0;  // MODE 2 only
@@ -82,23 +130,18 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
     for (int s = 0; s < S; ++s) alive |= T[s] > 0.0f;
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
-    if (e < rg.y) {
-      const uint32_t id = a.vals[e];
-      const float4 r0 = a.rec0[id];
-      const uint32_t vb = vis ? vis[__float_as_uint(r0.w)] : 1u;
-      s_a[tid] = make_float4(r0.x, r0.y, r0.z, __uint_as_float(vb));
-      s_b[tid] = a.rec1[id];
-      s_c[tid] = a.rec2[id];
-    }
+    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, a.pbox, vis, tpx, tpy);
     __syncthreads();
-    uint32_t wave_alive = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-      if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
     const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
+    uint32_t wave_alive = 0;
     for (int k = 0; k < cnt; ++k) {
-      const float4 A = s_a[k];
-      const uint32_t uv = __builtin_amdgcn_readfirstlane(__float_as_uint(A.w)) & wave_alive;
+      if ((k & 63) == 0) {  // states still compositing some pixel of this wave
+        wave_alive = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
+      }
+      const uint32_t uv = __builtin_amdgcn_readfirstlane(st.vis[wv][k]) & wave_alive;
       if (uv == 0u) continue;
       if (MODE == 2) {
         uint32_t lane_alive = 0;
@@ -106,11 +149,10 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
         for (int s = 0; s < S; ++s) lane_alive |= (T[s] > 0.0f ? 1u : 0u) << s;
         n_alpha += (uv & lane_alive) ? 1u : 0u;
       }
-      const float4 B = s_b[k];
-      float e;
-      const float alpha = splat_alpha_e(A.x, A.y, A.z, B.x, B.y, B.z, fpx, fpy, e);
-      if (alpha < kAlphaMin) continue;
-      const float4 C = s_c[k];
+      const float q = splat_q(st.p0[k], st.p1[k], fpx, fpy);
+      if (q < kQSkip) continue;
+      const float alpha = alpha_of(q);
+      const float4 C = st.col[k];
 #pragma unroll
       for (int s = 0; s < S; ++s)
         if (uv & (1u << s)) {
@@ -142,8 +184,9 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
     const int64_t plane = (int64_t)a.width * a.height;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int w = a.state_offset + grp * S + s;
-      if (w >= a.num_states) break;
+      const int slot = grp * S + s;
+      if (slot >= a.launch_states) break;
+      const int w = a.state_offset + (a.state_order ? (int)a.state_order[slot] : slot);
       const float Tf = fabsf(T[s]);
       float *o = a.image + ((int64_t)w * plane + pix) * 3;
       o[0] = fmaf(Tf, a.bg[0], cr[s]);
@@ -159,7 +202,6 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
       const float *rp = a.reference + ((int64_t)py * a.width + px) * 3;
       ref[0] = rp[0]; ref[1] = rp[1]; ref[2] = rp[2];
     }
-    const int lane = __lane_id(), wv = tid >> 6;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       float se = 0.0f;
@@ -175,9 +217,10 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
       if (lane == 0) s_red[wv][s] = se;
     }
     __syncthreads();
-    if (tid < S) {
-      const int w = a.state_offset + grp * S + tid;
-      if (w < a.num_states) {
+    if (tid < S && grp * S + tid < a.launch_states) {
+      const int slot = grp * S + tid;
+      const int w = a.state_offset + (a.state_order ? (int)a.state_order[slot] : slot);
+      {
         const int ntiles = a.tiles_x * a.tiles_y;
         a.psnr_part[(int64_t)w * ntiles + tile] = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
       }
@@ -223,17 +266,18 @@ __device__ __forceinline__ float wave_sum(float x) {
 // which includes T_final * background.  Per state and entry:
 //   dL/dc_k     = g T_k a_k
 //   dL/da_k     = T_k (g . c_k) - (g . rem_k) / (1 - a_k)
-// summed over the group's states, then through a = min(0.99, o e^{-q/2}) to
-// (u, v, A, B, C, o), reduced over the wave and added to the Gaussian's
-// 2D gradient with one atomic per value.
+// summed over the group's states; then, below the 0.99 cap, through
+// a = 2^q' to (u, v, A', B', C', log2 o), reduced over the wave and added to
+// the Gaussian's 2D gradient with one atomic per value.
 template <int S, int TW, int TH>
 __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
-  const int total = a.tiles_x * a.tiles_y * a.groups;
-  const int item = xcd_item(blockIdx.x, total);
-  const int tile = item / a.groups, grp = item - tile * a.groups;
+  int kpos, grp;
+  if (!work_item(blockIdx.x, a.groups, a.tiles_x * a.tiles_y, kpos, grp)) return;
+  const int tile = (int)a.tile_order[kpos];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int tid = threadIdx.x;
-  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int tpx = tx * TW, tpy = ty * TH;
+  const int px = tpx + wave_x0<TW>(wv) + (lane & 7), py = tpy + wave_y0<TW>(wv) + (lane >> 3);
   const bool inside = px < a.width && py < a.height;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const int64_t plane = (int64_t)a.width * a.height;
@@ -242,8 +286,9 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
   float T[S], rr[S], rgn[S], rb[S], gr[S], gg[S], gb[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int w = grp * S + s;
-    const bool ok = inside && w < a.num_states;
+    const int slot = grp * S + s;
+    const bool ok = inside && slot < a.num_states;
+    const int w = ok ? (a.state_order ? (int)a.state_order[slot] : slot) : 0;
     T[s] = ok ? 1.0f : -1.0f;
     rr[s] = rgn[s] = rb[s] = gr[s] = gg[s] = gb[s] = 0.0f;
     if (ok) {
@@ -254,61 +299,52 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
     }
   }
 
-  __shared__ float4 s_a[kBlock];
-  __shared__ float4 s_b[kBlock];
-  __shared__ float4 s_c[kBlock];
-  __shared__ uint32_t s_id[kBlock];
-
+  __shared__ Stage st;
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
-  const int lane = __lane_id();
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
     int alive = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) alive |= T[s] > 0.0f;
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
-    if (e < rg.y) {
-      const uint32_t id = a.vals[e];
-      const float4 r0 = a.rec0[id];
-      const uint32_t vb = vis ? vis[__float_as_uint(r0.w)] : 1u;
-      s_a[tid] = make_float4(r0.x, r0.y, r0.z, __uint_as_float(vb));
-      s_b[tid] = a.rec1[id];
-      s_c[tid] = a.rec2[id];
-      s_id[tid] = id;
-    }
+    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, a.pbox, vis, tpx, tpy);
     __syncthreads();
-    uint32_t wave_alive = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-      if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
     const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
+    uint32_t wave_alive = 0;
     for (int k = 0; k < cnt; ++k) {
-      const float4 A = s_a[k];
-      const uint32_t uv = __builtin_amdgcn_readfirstlane(__float_as_uint(A.w)) & wave_alive;
+      if ((k & 63) == 0) {
+        wave_alive = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
+      }
+      const uint32_t uv = __builtin_amdgcn_readfirstlane(st.vis[wv][k]) & wave_alive;
       if (uv == 0u) continue;
-      const float4 B = s_b[k];
-      float ev;
-      const float alpha = splat_alpha_e(A.x, A.y, A.z, B.x, B.y, B.z, fpx, fpy, ev);
-      const bool hit = alpha >= kAlphaMin;
+      const float4 P0 = st.p0[k];
+      const float2 P1 = st.p1[k];
+      const float q = splat_q(P0, P1, fpx, fpy);
+      const bool hit = q >= kQSkip;
       if (!__ballot(hit)) continue;
-      float d_alpha = 0.0f, dcr = 0.0f, dcg = 0.0f, dcb = 0.0f;
-      float gu = 0.0f, gv = 0.0f, gA = 0.0f, gB = 0.0f, gC = 0.0f, go = 0.0f;
+      float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f;
+      float gu = 0.0f, gv = 0.0f, gA = 0.0f, gB = 0.0f, gC = 0.0f, glo = 0.0f;
       if (hit) {
-        const float4 C = s_c[k];
+        const float alpha = alpha_of(q);
+        const float4 C = st.col[k];
         const float inv1ma = 1.0f / (1.0f - alpha);
+        float d_alpha = 0.0f;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           if (uv & (1u << s)) {
-            const float Tp = fmaxf(T[s], 0.0f);
-            const float ta = Tp * alpha;
+            const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
             rr[s] = fmaf(-ta, C.x, rr[s]);
             rgn[s] = fmaf(-ta, C.y, rgn[s]);
             rb[s] = fmaf(-ta, C.z, rb[s]);
             const float gcol = gr[s] * C.x + gg[s] * C.y + gb[s] * C.z;
             const float grem = gr[s] * rr[s] + gg[s] * rgn[s] + gb[s] * rb[s];
+            const float Tp = fmaxf(T[s], 0.0f);
             const float da = Tp * gcol - grem * inv1ma;
-            d_alpha += (Tp > 0.0f) ? da : 0.0f;
+            d_alpha += (T[s] > 0.0f) ? da : 0.0f;
             dcr = fmaf(gr[s], ta, dcr);
             dcg = fmaf(gg[s], ta, dcg);
             dcb = fmaf(gb[s], ta, dcb);
@@ -316,22 +352,22 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
             T[s] = (Tn < kTStop) ? -fabsf(Tn) : Tn;
           }
         }
-        // alpha = o e when below the cap; the cap passes no gradient
-        if (A.z * ev < kAlphaMax) {
-          const float dpow = d_alpha * alpha;  // d alpha / d power = alpha
-          go = d_alpha * ev;
-          const float dx = A.x - fpx, dy = A.y - fpy;
-          gu = -dpow * (B.x * dx + B.y * dy);
-          gv = -dpow * (B.y * dx + B.z * dy);
-          gA = -0.5f * dpow * dx * dx;
-          gB = -dpow * dx * dy;
-          gC = -0.5f * dpow * dy * dy;
+        // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap passes nothing
+        if (alpha < kAlphaMax) {
+          const float dq = d_alpha * alpha * 0.69314718055994531f;
+          const float dx = P0.x - fpx, dy = P0.y - fpy;
+          gu = dq * (2.0f * P0.w * dx + P1.x * dy);
+          gv = dq * (P1.x * dx + 2.0f * P1.y * dy);
+          gA = dq * dx * dx;
+          gB = dq * dx * dy;
+          gC = dq * dy * dy;
+          glo = dq;
         }
       }
       gu = wave_sum(gu); gv = wave_sum(gv); gA = wave_sum(gA); gB = wave_sum(gB); gC = wave_sum(gC);
-      go = wave_sum(go); dcr = wave_sum(dcr); dcg = wave_sum(dcg); dcb = wave_sum(dcb);
+      glo = wave_sum(glo); dcr = wave_sum(dcr); dcg = wave_sum(dcg); dcb = wave_sum(dcb);
       if (lane == 0) {
-        const uint32_t id = s_id[k];
+        const uint32_t id = st.id[k];
         float *g = a.g2d;
         const int64_t n = a.n;
         unsafeAtomicAdd(g + id, gu);
@@ -339,7 +375,7 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
         unsafeAtomicAdd(g + 2 * n + id, gA);
         unsafeAtomicAdd(g + 3 * n + id, gB);
         unsafeAtomicAdd(g + 4 * n + id, gC);
-        unsafeAtomicAdd(g + 5 * n + id, go);
+        unsafeAtomicAdd(g + 5 * n + id, glo);
         unsafeAtomicAdd(g + 6 * n + id, dcr);
         unsafeAtomicAdd(g + 7 * n + id, dcg);
         unsafeAtomicAdd(g + 8 * n + id, dcb);
@@ -375,7 +411,7 @@ static int launch_fwd_s(const CompositeArgs &a, int S, int mode, unsigned blocks
 }
 
 int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, hipStream_t st) {
-  const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.groups;
+  const int64_t total = work_items(a.tiles_x * a.tiles_y, a.groups);
   if (total <= 0) return 0;
   const unsigned blocks = (unsigned)total;
   if (tile_w == 16 && tile_h == 16) return launch_fwd_s<16, 16>(a, S, mode, blocks, st);
@@ -395,7 +431,7 @@ static int launch_bwd_s(const CompositeBwdArgs &a, int S, unsigned blocks, hipSt
 }
 
 int launch_composite_bwd(const CompositeBwdArgs &a, int S, int tile_w, int tile_h, hipStream_t st) {
-  const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.groups;
+  const int64_t total = work_items(a.tiles_x * a.tiles_y, a.groups);
   if (total <= 0) return 0;
   const unsigned blocks = (unsigned)total;
   if (tile_w == 16 && tile_h == 16) return launch_bwd_s<16, 16>(a, S, blocks, st);

@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kBlock)
 k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ list,
            const unsigned *__restrict__ n_active, float4 *__restrict__ rec0,
            float4 *__restrict__ rec1, float4 *__restrict__ rec2, uint2 *__restrict__ rect,
-           uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval) {
+           uint2 *__restrict__ pbox, uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
   const int nact = list ? (int)*n_active : s.n;
   if (j >= nact) return;
@@ -158,11 +158,12 @@ k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ l
   project(s, cam, i, p);
   float col[3], dir[3], raw[3];
   colour(s, cam, i, p.mu, col, dir, raw);
-  const float o = 1.0f / (1.0f + __expf(-s.opacity_logit[i]));
+  // log2 of the opacity: alpha = min(0.99, 2^(q' + log2 o)) in the compositing kernels
+  const float lo = -__log2f(1.0f + __expf(-s.opacity_logit[i]));
   const uint16_t pl = s.packet_layer[i];
   // a packet id outside the state tables never enters a list
   const bool ok = (p.Z > cam.near_z) && (p.det > 0.0f) && ((int)(pl >> 2) < s.num_packets);
-  uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+  uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0, px0 = 0, py0 = 0, px1 = 0, py1 = 0;
   if (ok) {
     const float itw = 1.0f / (float)tl.tile_w, ith = 1.0f / (float)tl.tile_h;
     const float ex = sqrtf(kQCut * p.a), ey = sqrtf(kQCut * p.c);
@@ -170,11 +171,18 @@ k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ l
     x1 = (uint32_t)clampf(floorf((p.u + ex) * itw) + 1.0f, 0.0f, (float)tl.tiles_x);
     y0 = (uint32_t)clampf(floorf((p.v - ey) * ith), 0.0f, (float)tl.tiles_y);
     y1 = (uint32_t)clampf(floorf((p.v + ey) * ith) + 1.0f, 0.0f, (float)tl.tiles_y);
+    // the same rectangle in pixels (half-open): a pixel centre outside it has alpha < 1/255
+    px0 = (uint32_t)clampf(floorf(p.u - ex), 0.0f, (float)cam.width);
+    px1 = (uint32_t)clampf(floorf(p.u + ex) + 1.0f, 0.0f, (float)cam.width);
+    py0 = (uint32_t)clampf(floorf(p.v - ey), 0.0f, (float)cam.height);
+    py1 = (uint32_t)clampf(floorf(p.v + ey) + 1.0f, 0.0f, (float)cam.height);
   }
-  rec0[i] = make_float4(p.u, p.v, o, __uint_as_float((uint32_t)pl));
-  rec1[i] = make_float4(p.A, p.B, p.C, p.Z);
+  // conic pre-scaled so that q' = A' dx^2 + B' dx dy + C' dy^2 = -(q/2) log2 e
+  rec0[i] = make_float4(p.u, p.v, lo, __uint_as_float((uint32_t)pl));
+  rec1[i] = make_float4(kConicA * p.A, kConicB * p.B, kConicA * p.C, p.Z);
   rec2[i] = make_float4(col[0], col[1], col[2], 0.0f);
   rect[i] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+  pbox[i] = make_uint2(px0 | (py0 << 16), px1 | (py1 << 16));
   const bool nonempty = ok && x1 > x0 && y1 > y0;
   dkey[j] = nonempty ? __float_as_uint(p.Z) : 0xFFFFFFFFu;
   dval[j] = (uint32_t)i;
@@ -191,17 +199,19 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int n = s.n;
   if (i >= n) return;
-  const float gu = g2d[i], gv = g2d[n + i], gA = g2d[2 * n + i], gB = g2d[3 * n + i];
-  const float gC = g2d[4 * n + i], go = g2d[5 * n + i];
+  // the compositing backward differentiates w.r.t. (u, v, A', B', C', log2 o): undo the scalings
+  const float gu = g2d[i], gv = g2d[n + i];
+  const float gA = kConicA * g2d[2 * n + i], gB = kConicB * g2d[3 * n + i];
+  const float gC = kConicA * g2d[4 * n + i], glo = g2d[5 * n + i];
   const float gcol[3] = {g2d[6 * n + i], g2d[7 * n + i], g2d[8 * n + i]};
   Proj p;
   project(s, cam, i, p);
   float col[3], dir[3], raw[3];
   colour(s, cam, i, p.mu, col, dir, raw);
 
-  // opacity
+  // opacity: log2 o = -log2(1 + e^{-logit}), d/dlogit = (1 - o) / ln 2
   const float o = 1.0f / (1.0f + __expf(-s.opacity_logit[i]));
-  g_logit[i] = go * o * (1.0f - o);
+  g_logit[i] = glo * (1.0f - o) * 1.4426950408889634f;
 
   float gmu[3] = {0.0f, 0.0f, 0.0f};
   // colour
@@ -320,10 +330,10 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
 
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
-                     uint2 *rect, uint32_t *dkey, uint32_t *dval, hipStream_t st) {
+                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st) {
   if (grid_n <= 0) return;
   k_geometry<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
-                                                                    rec2, rect, dkey, dval);
+                                                                    rec2, rect, pbox, dkey, dval);
 }
 
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,

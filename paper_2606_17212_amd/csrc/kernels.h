@@ -8,7 +8,7 @@ namespace dgs {
 // geometry.hip
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
-                     uint2 *rect, uint32_t *dkey, uint32_t *dval, hipStream_t st);
+                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st);
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,
                          float *g_ls, float *g_quat, float *g_logit, float *g_color, float *g_temporal,
                          hipStream_t st);
@@ -33,8 +33,13 @@ void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, c
                  uint32_t *tval, hipStream_t st);
 void launch_ranges(const uint32_t *tkey, const Header *h, int64_t cap, int tiles, uint2 *ranges,
                    hipStream_t st);
-void launch_visbits(const uint8_t *codes, int num_states, int P, int S, uint32_t *visbits,
-                    hipStream_t st);
+void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S,
+                    uint32_t *visbits, hipStream_t st);
+void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st);
+constexpr int kMaxOrderedStates = 16384;  // states ranked by present count per composite call
+void launch_state_order(const uint8_t *codes, const uint32_t *hist, int num_states, int P, uint32_t *cnt,
+                        uint32_t *order, hipStream_t st);
+void launch_tile_order(const uint2 *ranges, int tiles, uint32_t *order, hipStream_t st);
 void launch_present_flags(const uint8_t *codes_row, const uint16_t *packet_layer, int n, int P,
                           uint32_t *flags, hipStream_t st);
 void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, uint32_t *list,
@@ -45,9 +50,12 @@ void launch_fill_u64(unsigned long long *p, int n, hipStream_t st);  // zero n <
 // composite.hip
 struct CompositeArgs {
   const float4 *rec0, *rec1, *rec2;
+  const uint2 *pbox;           // per-Gaussian pixel rectangle
   const uint32_t *vals;        // sorted Gaussian ids
   const uint2 *ranges;         // per tile [start, end)
   const uint32_t *visbits;     // [groups][P*4] state bits, or null (every entry visible, S = 1)
+  const uint32_t *tile_order;  // tiles by decreasing list length
+  const uint32_t *state_order; // group slot -> state index, or null (identity)
   int P4;                      // P * 4
   int num_states, width, height, tiles_x, tiles_y, groups;
   float bg[3];
@@ -56,6 +64,7 @@ struct CompositeArgs {
   const float *reference;      // [H][Wd][3] (PSNR mode)
   float *psnr_part;            // [W][tiles] (PSNR mode)
   int state_offset;            // first state index of this launch's images
+  int launch_states;           // states composited by this launch
   unsigned long long *counters;  // [2] (count mode): alpha evaluations, blends
 };
 // mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only
@@ -65,13 +74,16 @@ void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int
 
 struct CompositeBwdArgs {
   const float4 *rec0, *rec1, *rec2;
+  const uint2 *pbox;
   const uint32_t *vals;
   const uint2 *ranges;
   const uint32_t *visbits;
+  const uint32_t *tile_order;
+  const uint32_t *state_order;
   int P4;
   int num_states, width, height, tiles_x, tiles_y, groups;
   const float *image, *grad_image;
-  float *g2d;                  // [9][n]
+  float *g2d;                  // [9][n]: d/d(u, v, A', B', C', log2 o, r, g, b)
   int n;
 };
 int launch_composite_bwd(const CompositeBwdArgs &a, int S, int tile_w, int tile_h, hipStream_t st);

@@ -70,13 +70,16 @@ def test_geometry_keys_rects_and_lists_bit_exact(tiny, tile):
     assert np.array_equal(sec["sorted_ids"].numpy()[:M].astype(np.int64), ids)
     # FP32 projection against the FP64 definition
     g = oracle.geometry_f64(w.scene, w.camera, w.basis)
-    rec0, rec1, rec2 = sec["rec0"].numpy(), sec["rec1"].numpy(), sec["rec2"].numpy()
+    rec0, rec1, rec2 = (sec[k].numpy().astype(np.float64) for k in ("rec0", "rec1", "rec2"))
     assert np.max(np.abs(rec0[valid, 0] - g["u"][valid])) < 2e-4
     assert np.max(np.abs(rec0[valid, 1] - g["v"][valid])) < 2e-4
-    assert np.max(np.abs(rec0[valid, 2] / g["o"][valid] - 1)) < 1e-5
+    # records hold log2(opacity) and the conic scaled by (-log2(e)/2, -log2(e), -log2(e)/2)
+    assert np.max(np.abs(np.exp2(rec0[valid, 2]) / g["o"][valid] - 1)) < 1e-5
+    l2e = 1.0 / np.log(2.0)
+    conic = np.stack([rec1[:, 0] / (-0.5 * l2e), rec1[:, 1] / (-l2e), rec1[:, 2] / (-0.5 * l2e)], 1)
     for j, k in enumerate(("conA", "conB", "conC")):
         scale = np.maximum(np.abs(g["conA"]), np.abs(g["conC"]))[valid]
-        assert np.max(np.abs(rec1[valid, j] - g[k][valid]) / scale) < 2e-5
+        assert np.max(np.abs(conic[valid, j] - g[k][valid]) / scale) < 2e-5
     col = np.stack([g["r"], g["g"], g["b_"]], 1)[valid]
     assert np.max(np.abs(rec2[valid, :3] - col)) < 2e-6
 
