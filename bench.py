@@ -37,11 +37,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="g250k_800px_64states")
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--states-per-group", type=int, default=16)
+    ap.add_argument("--states-per-group", type=int, default=8)
     ap.add_argument("--no-per-state", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--graph", action="store_true", help="time replays of one captured HIP graph")
+    ap.add_argument("--tune", action="store_true", help="pick tile shape and states per group by timing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -74,12 +76,25 @@ def main():
     codes = torch.from_numpy(w.codes).to(dev)
     W = int(codes.shape[0])
     bg = tuple(float(x) for x in w.background)
+    if w.total_states:
+        return psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th)
+    if args.tune:
+        res = dgs.Autotuner().tune(scene, cam, codes, w.basis, bg, reps=3)
+        (tw, th), args.states_per_group = res.tile, res.states_per_group
+        log(f"[bench] autotuner: {tw}x{th}, S={args.states_per_group} ({res.ms:.3f} ms); table {res.table}")
     r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group)
     M = r.plan(scene, cam, w.basis, W)
     log(f"[bench] {args.workload}: N={scene.n} {cam.width}x{cam.height} W={W} instances={M}")
     img = torch.empty((W, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
 
+    graph = dgs.CapturedRender(r, scene, cam, codes, w.basis, bg) if args.graph else None
+    if graph is not None:
+        img = graph.out
+
     def step():
+        if graph is not None:
+            graph.replay()
+            return
         r.bin(scene, cam, w.basis)
         r.composite(scene, cam, codes, w.basis, bg, out=img)
 
@@ -92,15 +107,25 @@ def main():
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t_start.record(st)
+    if graph is not None:
+        t_start.record(st)
+        for k in range(args.steps):
+            graph.replay()
+        t_end.record(st)
+        torch.cuda.synchronize()
+    # eager pass with events around each half (also the timed region without a graph)
+    t0, t1 = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    t0.record(st)
     for k in range(args.steps):
         ev[k][0].record(st)
         r.bin(scene, cam, w.basis)
         ev[k][1].record(st)
         r.composite(scene, cam, codes, w.basis, bg, out=img)
         ev[k][2].record(st)
-    t_end.record(st)
+    t1.record(st)
     torch.cuda.synchronize()
+    if graph is None:
+        t_start, t_end = t0, t1
     total_ms = t_start.elapsed_time(t_end)
     bin_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     comp_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
@@ -115,8 +140,7 @@ def main():
     achieved = flops / (comp_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "k_composite<16,16,16,0>" if (tw, th, args.states_per_group) == (16, 16, 16) else
-                f"k_composite<{args.states_per_group},{tw},{th},0>",
+                "kernel": f"k_composite<{args.states_per_group},{tw},{th},0>",
                 "kernel_ms": round(comp_ms, 4), "alpha_evals": alpha_evals, "blends": blends,
                 "flops_per_launch": flops}
     log(f"[bench] composite work: {alpha_evals} alpha evals, {blends} blends -> {achieved:.2f} TFLOP/s")
@@ -129,7 +153,8 @@ def main():
                       "height": cam.height, "states": W, "clusters": w.scene.num_clusters,
                       "contexts": w.scene.num_contexts, "tile": f"{tw}x{th}",
                       "states_per_group": args.states_per_group, "instances": M},
-           "batched": {"bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4)}}
+           "batched": {"bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4),
+                       "timed_as": "hip graph replay" if graph is not None else "eager launches"}}
 
     if not args.no_per_state:
         # plain per-state render, synchronized after every state
@@ -218,6 +243,64 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
     return {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
             "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
             "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+
+
+def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
+    """Utility-style sweep: every delivery state's PSNR against the
+    full-delivery render, in batches, binning shared by the whole sweep
+    (one scene, one camera, one time)."""
+    import synth
+    total, batch = w.total_states, w.batch
+    rec = synth.WORKLOADS[args.workload]
+    kind, lo, hi = rec["masks"]
+    codes_all = torch.from_numpy(synth.make_codes(kind, lo, hi, total, w.scene.num_packets, rec["layers"],
+                                                  index=w.index)).to(dev)
+    bg = tuple(float(x) for x in w.background)
+    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group)
+    ren.plan(scene, cam, w.basis, batch)
+    ref = ren.render(scene, cam, torch.ones_like(codes_all[:1]), w.basis, bg)[0].contiguous()
+    psnr = torch.empty(total, dtype=torch.float32, device=dev)
+
+    def sweep(ev=None):
+        ren.bin(scene, cam, w.basis)
+        for b in range(total // batch):
+            if ev is not None:
+                ev[b][0].record()
+            ren.composite_psnr(scene, cam, codes_all[b * batch:(b + 1) * batch], w.basis, ref, bg,
+                               out=psnr[b * batch:(b + 1) * batch])
+            if ev is not None:
+                ev[b][1].record()
+
+    for _ in range(max(1, args.warmup // 2)):
+        sweep()
+    ren.check()
+    torch.cuda.synchronize()
+    nb = total // batch
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nb)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sweep(ev)
+    e1.record()
+    torch.cuda.synchronize()
+    ren.check()
+    ms = e0.elapsed_time(e1)
+    lat = [e[0].elapsed_time(e[1]) for e in ev]
+    value = total / (ms / 1e3)
+    p = psnr.cpu().numpy()
+    log(f"[bench] psnr sweep: {total} states in {ms:.1f} ms -> {value:.1f} states/s; batch latency median "
+        f"{np.median(lat):.3f} ms; PSNR median {np.median(p):.2f} dB")
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "states/s", "n_gpus": 1, "steps": 1,
+           "warmup": max(1, args.warmup // 2), "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "gaussians": scene.n, "width": cam.width, "height": cam.height,
+                      "states": total, "batch": batch, "tile": f"{tw}x{th}",
+                      "states_per_group": args.states_per_group},
+           "batch_latency_ms": {"median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
+                                "max": round(float(np.max(lat)), 4)},
+           "psnr_db": {"median": round(float(np.median(p)), 3), "min": round(float(np.min(p)), 3),
+                       "max": round(float(np.max(p)), 3)}}
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def cpu_baseline(w, np, seconds):

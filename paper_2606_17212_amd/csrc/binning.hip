@@ -41,31 +41,54 @@ void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect,
   k_count<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, cnt);
 }
 
+// Emission: workgroup b writes the instances of the 256 depth-sorted
+// Gaussians [256 b, 256 b + 256) -- one contiguous output range -- with
+// consecutive lanes writing consecutive instances; each lane finds the
+// Gaussian owning its output position by binary search over the workgroup's
+// offsets in LDS, then its tile inside that Gaussian's rectangle (row-major).
 __global__ void __launch_bounds__(kBlock)
 k_emit(const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect, const uint32_t *__restrict__ off,
        const uint32_t *__restrict__ cnt, const unsigned *__restrict__ n_active, int grid_n, int tiles_x,
        Header *h, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= grid_n) return;
+  __shared__ uint32_t s_off[kBlock + 1];
+  __shared__ uint32_t s_id[kBlock];
+  __shared__ uint32_t s_x0y0[kBlock];
+  __shared__ uint32_t s_nx[kBlock];
   const int nact = n_active ? (int)*n_active : grid_n;
-  if (j >= nact) return;
-  const uint32_t c = cnt[j];
-  if (c == 0) return;
-  const unsigned long long o0 = off[j];
-  if (o0 + c > h->capacity) {
-    h->overflow = 1u;
+  const int j0 = blockIdx.x * kBlock;
+  if (j0 >= nact) return;  // uniform
+  const int tid = threadIdx.x;
+  const int nloc = (nact - j0) < kBlock ? (nact - j0) : kBlock;
+  if (tid < nloc) {
+    const int j = j0 + tid;
+    const uint32_t id = dval[j];
+    const uint2 r = rect[id];
+    s_off[tid] = off[j];
+    s_id[tid] = id;
+    s_x0y0[tid] = r.x;
+    s_nx[tid] = (r.y & 0xFFFFu) - (r.x & 0xFFFFu);
+    if (tid == nloc - 1) s_off[nloc] = off[j] + cnt[j];
+  }
+  __syncthreads();
+  const unsigned long long begin = s_off[0], end = s_off[nloc];
+  if (end > h->capacity) {  // the scan's total is checked against the same capacity
+    if (tid == 0) h->overflow = 1u;
     return;
   }
-  const uint32_t id = dval[j];
-  const uint2 r = rect[id];
-  const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
-  uint32_t o = (uint32_t)o0;
-  for (uint32_t ty = y0; ty < y1; ++ty)
-    for (uint32_t tx = x0; tx < x1; ++tx) {
-      tkey[o] = ty * (uint32_t)tiles_x + tx;
-      tval[o] = id;
-      ++o;
+  for (unsigned long long p = begin + tid; p < end; p += kBlock) {
+    // last local index whose offset <= p (entries with zero count share offsets)
+    int lo = 0, hi = nloc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((unsigned long long)s_off[mid] <= p) lo = mid; else hi = mid - 1;
     }
+    const uint32_t k = (uint32_t)(p - s_off[lo]);
+    const uint32_t nx = s_nx[lo];
+    const uint32_t xy = s_x0y0[lo];
+    const uint32_t dy = k / nx, dx = k - dy * nx;
+    tkey[p] = ((xy >> 16) + dy) * (uint32_t)tiles_x + (xy & 0xFFFFu) + dx;
+    tval[p] = s_id[lo];
+  }
 }
 
 void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, const uint32_t *cnt,

@@ -367,3 +367,46 @@ def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torc
     params = [getattr(scene, k) for k in PARAMS]
     return RenderFunction.apply(renderer, scene, camera, codes, tuple(float(b) for b in basis),
                                 tuple(float(x) for x in background), *params)
+
+
+class CapturedRender:
+    """``bin`` + ``composite`` (or ``composite_psnr``) of fixed tensors captured
+    in one HIP graph; ``replay()`` relaunches the whole path with one call.
+
+    The scene, codes and reference tensors are read at every replay, so their
+    contents may change between replays (not their shapes or addresses).  The
+    renderer must not be re-planned while the graph is alive."""
+
+    def __init__(self, renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
+                 background=(0, 0, 0), reference: Optional[torch.Tensor] = None):
+        r = renderer
+        W = int(codes.shape[0])
+        r._need_plan(scene, camera, basis, W)
+        dev = r.device
+        if reference is None:
+            self.out = torch.empty((W, camera.height, camera.width, 3), dtype=torch.float32, device=dev)
+        else:
+            self.out = torch.empty((W,), dtype=torch.float32, device=dev)
+
+        def body():
+            r.bin(scene, camera, basis)
+            if reference is None:
+                r.composite(scene, camera, codes, basis, background, out=self.out)
+            else:
+                r.composite_psnr(scene, camera, codes, basis, reference, background, out=self.out)
+
+        side = torch.cuda.Stream(dev)  # default priority
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            body()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            body()
+        self.renderer = r
+        self._keep = (scene, codes, reference)
+
+    def replay(self) -> torch.Tensor:
+        self.graph.replay()
+        return self.out
