@@ -135,15 +135,17 @@ def main():
     log(f"[bench] batched: {ms_step:.3f} ms/step (bin {bin_ms:.3f}, composite {comp_ms:.3f}) -> {value:.1f} states/s")
 
     # algorithmic work of one composite launch
-    alpha_evals, blends = r.composite_stats(scene, cam, codes, w.basis)
+    alpha_evals, blends, wave_evals, wave_miss = r.composite_stats(scene, cam, codes, w.basis)
     flops = FLOPS_PER_ALPHA * alpha_evals + FLOPS_PER_BLEND * blends
     achieved = flops / (comp_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                 "kernel": f"k_composite<{args.states_per_group},{tw},{th},0>",
                 "kernel_ms": round(comp_ms, 4), "alpha_evals": alpha_evals, "blends": blends,
+                "wave_alpha_evals": wave_evals, "wave_alpha_misses": wave_miss,
                 "flops_per_launch": flops}
-    log(f"[bench] composite work: {alpha_evals} alpha evals, {blends} blends -> {achieved:.2f} TFLOP/s")
+    log(f"[bench] composite work: {alpha_evals} alpha evals, {blends} blends, {wave_evals} wave evals "
+        f"({wave_miss} with no pixel >= 1/255) -> {achieved:.2f} TFLOP/s")
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "states/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),

@@ -62,7 +62,7 @@ typedef enum {
  *                          layer 0..3 (base + three refinements, Sec. 3)
  *   cluster_affine [C][12] per-cluster 3x4 affine A_{c,t} of Eq. (1) at the
  *                          render time, row-major, or NULL for the identity
- * Limits: n >= 0; rank 0..4; sh_degree 0 or 1; 1 <= C*K <= 16384.
+ * Limits: 0 <= n < 2^28; rank 0..4; sh_degree 0 or 1; 1 <= C*K <= 16384.
  */
 typedef struct {
   int32_t n;
@@ -193,10 +193,12 @@ int dgs_composite_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_
 
 /*
  * Work counters of dgs_composite for the same arguments, nothing rendered:
- * counters (device, 2 x u64, overwritten) = { alpha evaluations: (pixel,
+ * counters (device, 4 x u64, overwritten) = { alpha evaluations: (pixel,
  * list entry, state group) triples where some delivered state of the group is
- * still compositing that pixel, blends: (pixel, state, Gaussian) triples
- * composited, i.e. present Gaussians with alpha >= 1/255 before the stop }.
+ * still compositing that pixel; blends: (pixel, state, Gaussian) triples
+ * composited, i.e. present Gaussians with alpha >= 1/255 before the stop;
+ * wave evaluations: (64-pixel block, entry, group) triples evaluated; wave
+ * misses: those of them where no pixel of the block reached alpha >= 1/255 }.
  */
 int dgs_composite_stats(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
                         const dgs_tuning *tun, void *ws, size_t ws_bytes,
@@ -256,7 +258,10 @@ int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream);
  *                   only Gaussians that entered the last binning are written
  *   rect            uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16), half-open tiles
  *   ranges          uint2 [tiles]: [start, end) of each tile's list
- *   sorted_ids      u32 [capacity]: Gaussian ids in (tile, depth, id) order
+ *   sorted_ids      u32 [capacity]: Gaussian ids in (tile, depth, id) order in
+ *                   bits 0..27; bit 28 + b is set when the Gaussian can reach
+ *                   alpha >= 1/255 in the tile's 8x8 pixel block b (blocks in
+ *                   row-major order: 2x2 for 16x16 tiles, 4x1 for 32x8)
  * Returns DGS_OK or DGS_ERR_INVALID_ARG.  Host-only; launches nothing.
  */
 typedef struct {

@@ -10,6 +10,11 @@
 
 namespace dgs {
 
+__global__ void __launch_bounds__(kBlock) k_zero_u32(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 __global__ void k_clear_header(Header *h, unsigned long long capacity) {
   h->instances = 0ull;
   h->capacity = capacity;
@@ -41,6 +46,36 @@ void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect,
   k_count<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, cnt);
 }
 
+// Which of the tile's four 8x8 wave blocks a Gaussian can reach with
+// alpha >= 1/255: its pixel rectangle must overlap the block, and the largest
+// exponent q' over the block's pixel centres must not fall below log2(1/255)
+// by more than a rounding margin.  Pixels outside reached blocks would all be
+// skipped by the per-pixel test, so the mask never changes a result.
+__device__ inline uint32_t wave_block_mask(uint32_t id, uint32_t tx, uint32_t ty, int tile_w, int tile_h,
+                                           const float4 *rec0, const float4 *rec1, const uint2 *pbox) {
+  const float4 r0 = rec0[id];
+  const float4 r1 = rec1[id];
+  const uint2 pb = pbox[id];
+  const int tpx = (int)tx * tile_w, tpy = (int)ty * tile_h;
+  const int x0 = (int)(pb.x & 0xFFFFu) - tpx, y0 = (int)(pb.x >> 16) - tpy;
+  const int x1 = (int)(pb.y & 0xFFFFu) - tpx, y1 = (int)(pb.y >> 16) - tpy;
+  const float need = kQSkip - 0.01f - r0.z;
+  const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
+  uint32_t mask = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int bx = wave_block_x0(w, tile_w), by = wave_block_y0(w, tile_w);
+    if (x0 < bx + 8 && x1 > bx && y0 < by + 8 && y1 > by) {
+      const float cx0 = (float)(tpx + bx) + 0.5f, cy0 = (float)(tpy + by) + 0.5f;
+      const float m = box_max_exponent(r1.x, r1.y, r1.z, ia, ic, r0.x - (cx0 + 7.0f), r0.x - cx0,
+                                       r0.y - (cy0 + 7.0f), r0.y - cy0);
+      if (m >= need) mask |= 1u << w;
+    }
+  }
+  (void)tile_h;
+  return mask;
+}
+
 // Emission: workgroup b writes the instances of the 256 depth-sorted
 // Gaussians [256 b, 256 b + 256) -- one contiguous output range -- with
 // consecutive lanes writing consecutive instances; each lane finds the
@@ -49,7 +84,8 @@ void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect,
 __global__ void __launch_bounds__(kBlock)
 k_emit(const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect, const uint32_t *__restrict__ off,
        const uint32_t *__restrict__ cnt, const unsigned *__restrict__ n_active, int grid_n, int tiles_x,
-       Header *h, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
+       int tile_w, int tile_h, const float4 *__restrict__ rec0, const float4 *__restrict__ rec1,
+       const uint2 *__restrict__ pbox, Header *h, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
   __shared__ uint32_t s_off[kBlock + 1];
   __shared__ uint32_t s_id[kBlock];
   __shared__ uint32_t s_x0y0[kBlock];
@@ -86,17 +122,20 @@ k_emit(const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect, const 
     const uint32_t nx = s_nx[lo];
     const uint32_t xy = s_x0y0[lo];
     const uint32_t dy = k / nx, dx = k - dy * nx;
-    tkey[p] = ((xy >> 16) + dy) * (uint32_t)tiles_x + (xy & 0xFFFFu) + dx;
-    tval[p] = s_id[lo];
+    const uint32_t tx = (xy & 0xFFFFu) + dx, ty = (xy >> 16) + dy;
+    const uint32_t id = s_id[lo];
+    tkey[p] = ty * (uint32_t)tiles_x + tx;
+    tval[p] = id | (wave_block_mask(id, tx, ty, tile_w, tile_h, rec0, rec1, pbox) << kMaskShift);
   }
 }
 
 void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, const uint32_t *cnt,
-                 const unsigned *n_active, int grid_n, int tiles_x, Header *h, uint32_t *tkey,
-                 uint32_t *tval, hipStream_t st) {
+                 const unsigned *n_active, int grid_n, int tiles_x, int tile_w, int tile_h, const float4 *rec0,
+                 const float4 *rec1, const uint2 *pbox, Header *h, uint32_t *tkey, uint32_t *tval,
+                 hipStream_t st) {
   if (grid_n <= 0) return;
-  k_emit<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(dval, rect, off, cnt, n_active, grid_n,
-                                                                tiles_x, h, tkey, tval);
+  k_emit<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(dval, rect, off, cnt, n_active, grid_n, tiles_x,
+                                                                tile_w, tile_h, rec0, rec1, pbox, h, tkey, tval);
 }
 
 __global__ void __launch_bounds__(kBlock) k_zero_u2(uint2 *p, int n) {
@@ -104,26 +143,84 @@ __global__ void __launch_bounds__(kBlock) k_zero_u2(uint2 *p, int n) {
   if (i < n) p[i] = make_uint2(0u, 0u);
 }
 
+// Tile coverage as a 2D difference array: +1 at (x0, y0) and (x1, y1), -1 at
+// (x1, y0) and (x0, y1) of every binned Gaussian's rectangle; its 2D prefix
+// sum is the instance count of each tile.  Workgroups accumulate in LDS when
+// the array fits and flush non-zero entries with one global atomic each.
+constexpr int kDiffLds = 12288;  // entries (48 KB)
+
 __global__ void __launch_bounds__(kBlock)
-k_ranges(const uint32_t *__restrict__ tkey, const Header *__restrict__ h, int64_t cap, int tiles,
-         uint2 *__restrict__ ranges) {
-  // After an overflow the instance arrays are incomplete: every range stays
-  // empty, so no consumer reads an unwritten entry.
-  if (h->overflow) return;
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int64_t m = (int64_t)h->instances;
-  if (m > cap) m = cap;
-  if (p >= m) return;
-  const uint32_t t = tkey[p];
-  if (t >= (uint32_t)tiles) return;
-  if (p == 0 || tkey[p - 1] != t) ranges[t].x = (uint32_t)p;
-  if (p == m - 1 || tkey[p + 1] != t) ranges[t].y = (uint32_t)(p + 1);
+k_tile_diff(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
+            const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles_y, uint32_t *__restrict__ diff) {
+  __shared__ uint32_t sd[kDiffLds];
+  const int nx = tiles_x + 1, ne = (tiles_x + 1) * (tiles_y + 1);
+  const bool in_lds = ne <= kDiffLds;
+  if (in_lds)
+    for (int k = threadIdx.x; k < ne; k += kBlock) sd[k] = 0u;
+  __syncthreads();
+  const int nact = n_active ? (int)*n_active : grid_n;
+  uint32_t *d = in_lds ? sd : diff;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < nact; j += gridDim.x * kBlock) {
+    if (dkey[j] == 0xFFFFFFFFu) continue;
+    const uint2 r = rect[dval[j]];
+    const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
+    if (x1 <= x0 || y1 <= y0) continue;
+    atomicAdd(d + y0 * nx + x0, 1u);
+    atomicAdd(d + y0 * nx + x1, 0xFFFFFFFFu);
+    atomicAdd(d + y1 * nx + x0, 0xFFFFFFFFu);
+    atomicAdd(d + y1 * nx + x1, 1u);
+  }
+  if (!in_lds) return;
+  __syncthreads();
+  for (int k = threadIdx.x; k < ne; k += kBlock)
+    if (sd[k]) atomicAdd(diff + k, sd[k]);
 }
 
-void launch_ranges(const uint32_t *tkey, const Header *h, int64_t cap, int tiles, uint2 *ranges,
-                   hipStream_t st) {
-  k_zero_u2<<<(unsigned)ceil_div(tiles, kBlock), kBlock, 0, st>>>(ranges, tiles);
-  if (cap > 0) k_ranges<<<(unsigned)ceil_div(cap, kBlock), kBlock, 0, st>>>(tkey, h, cap, tiles, ranges);
+// One workgroup: 2D inclusive prefix sum of the difference array (rows, then
+// columns) -> instance count per tile.
+__global__ void __launch_bounds__(1024)
+k_tile_prefix(uint32_t *__restrict__ diff, int tiles_x, int tiles_y, uint32_t *__restrict__ tcnt) {
+  const int nx = tiles_x + 1;
+  for (int y = threadIdx.x; y < tiles_y; y += blockDim.x) {
+    uint32_t acc = 0;
+    for (int x = 0; x < tiles_x; ++x) {
+      acc += diff[y * nx + x];
+      diff[y * nx + x] = acc;
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < tiles_x; x += blockDim.x) {
+    uint32_t acc = 0;
+    for (int y = 0; y < tiles_y; ++y) {
+      acc += diff[y * nx + x];
+      tcnt[y * tiles_x + x] = acc;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_ranges_from_counts(const uint32_t *__restrict__ tcnt, const uint32_t *__restrict__ tstart, int tiles,
+                     const Header *__restrict__ h, uint2 *__restrict__ ranges) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= tiles) return;
+  // after an overflow the instance arrays are incomplete: every range is empty
+  ranges[t] = h->overflow ? make_uint2(0u, 0u) : make_uint2(tstart[t], tstart[t] + tcnt[t]);
+}
+
+void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+                        int grid_n, int tiles_x, int tiles_y, const Header *h, uint32_t *tdiff, uint32_t *tcnt,
+                        uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st) {
+  const int tiles = tiles_x * tiles_y;
+  const int64_t ne = (int64_t)(tiles_x + 1) * (tiles_y + 1);
+  k_zero_u32<<<(unsigned)ceil_div(ne, kBlock), kBlock, 0, st>>>(tdiff, ne);
+  if (grid_n > 0) {
+    const int per = ne <= kDiffLds ? 16384 : 1024;  // Gaussians per workgroup
+    const int blocks = (int)ceil_div(grid_n, per);
+    k_tile_diff<<<blocks, kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, tiles_x, tiles_y, tdiff);
+  }
+  k_tile_prefix<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, tcnt);
+  launch_scan_u32(tcnt, tstart, tiles, parts, nullptr, st);
+  k_ranges_from_counts<<<(unsigned)ceil_div(tiles, kBlock), kBlock, 0, st>>>(tcnt, tstart, tiles, h, ranges);
 }
 
 // visbits[g][p*4 + l], bit s set iff layer l of packet p is delivered in
@@ -163,11 +260,6 @@ k_plhist(const uint16_t *__restrict__ packet_layer, int n, int P4, uint32_t *__r
   if (i >= n) return;
   const int pl = packet_layer[i];
   if (pl < P4) atomicAdd(hist + pl, 1u);
-}
-
-__global__ void __launch_bounds__(kBlock) k_zero_u32(uint32_t *p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = 0u;
 }
 
 void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st) {

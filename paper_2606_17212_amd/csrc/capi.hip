@@ -74,7 +74,7 @@ int check_camera(const dgs_camera *cam) {
 
 int check_scene(const dgs_scene *s) {
   if (!s) return fail(DGS_ERR_INVALID_ARG, "scene is NULL");
-  if (s->n < 0) return fail(DGS_ERR_INVALID_ARG, "n = %d < 0", s->n);
+  if (s->n < 0 || s->n > kMaxGaussians) return fail(DGS_ERR_INVALID_ARG, "n = %d outside 0..2^28-1", s->n);
   if (s->rank < 0 || s->rank > 4) return fail(DGS_ERR_INVALID_ARG, "rank %d outside 0..4", s->rank);
   if (s->sh_degree != 0 && s->sh_degree != 1)
     return fail(DGS_ERR_INVALID_ARG, "sh_degree %d not 0 or 1", s->sh_degree);
@@ -153,7 +153,7 @@ int prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *sta
   if (!ws) return fail(DGS_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255u) return fail(DGS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   call->P = P;
-  call->L = make_layout(scene->n, P, call->tiling.tiles, states->num_states, cap);
+  call->L = make_layout(scene->n, P, call->tiling.tiles_x, call->tiling.tiles_y, states->num_states, cap);
   if (ws_bytes < call->L.total)
     return fail(DGS_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, call->L.total);
   call->s = scene_args(scene, states);
@@ -194,13 +194,17 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
   const int n = cl.s.n;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
   launch_emit(at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey1),
-              at<uint32_t>(ws, L.cnt), nact, n, cl.t.tiles_x, h, at<uint32_t>(ws, L.tkey0),
-              at<uint32_t>(ws, L.tval0), st);
+              at<uint32_t>(ws, L.cnt), nact, n, cl.t.tiles_x, cl.t.tile_w, cl.t.tile_h, at<float4>(ws, L.rec0),
+              at<float4>(ws, L.rec1), at<uint2>(ws, L.pbox), h, at<uint32_t>(ws, L.tkey0), at<uint32_t>(ws, L.tval0),
+              st);
+  // the last pass writes values only: tile ranges come from the rectangles
   const int r = launch_radix_sort(at<uint32_t>(ws, L.tkey0), at<uint32_t>(ws, L.tval0), at<uint32_t>(ws, L.tkey1),
                                   at<uint32_t>(ws, L.tval1), &h->instances, 1, cap, 0, cl.tiling.tile_bits,
-                                  at<uint32_t>(ws, L.hist), at<unsigned long long>(ws, L.part), st);
-  const uint32_t *tkey = r ? at<uint32_t>(ws, L.tkey1) : at<uint32_t>(ws, L.tkey0);
-  launch_ranges(tkey, h, cap, cl.tiling.tiles, at<uint2>(ws, L.ranges), st);
+                                  at<uint32_t>(ws, L.hist), at<unsigned long long>(ws, L.part), st,
+                                  /*last_pass_keys=*/false);
+  launch_tile_ranges(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
+                     cl.tiling.tiles_x, cl.tiling.tiles_y, h, at<uint32_t>(ws, L.tdiff), at<uint32_t>(ws, L.tcnt),
+                     at<uint32_t>(ws, L.tstart), at<unsigned long long>(ws, L.part), at<uint2>(ws, L.ranges), st);
   return r ? at<uint32_t>(ws, L.tval1) : at<uint32_t>(ws, L.tval0);
 }
 
@@ -268,11 +272,11 @@ const char *dgs_last_error(void) { return g_err.c_str(); }
 size_t dgs_workspace_bytes(int32_t n, int32_t num_packets, const dgs_camera *cam, const dgs_tuning *tun,
                            int32_t max_states, int64_t instance_capacity) {
   Tiling t;
-  if (n < 0 || num_packets < 1 || num_packets > 16384 || max_states < 0 || instance_capacity < 0 ||
-      instance_capacity > (int64_t)0xFFFFFFFFll)
+  if (n < 0 || n > kMaxGaussians || num_packets < 1 || num_packets > 16384 || max_states < 0 ||
+      instance_capacity < 0 || instance_capacity > (int64_t)0xFFFFFFFFll)
     return 0;
   if (check_camera(cam) || check_tuning(cam, tun, &t)) return 0;
-  return make_layout(n, num_packets, t.tiles, max_states, instance_capacity).total;
+  return make_layout(n, num_packets, t.tiles_x, t.tiles_y, max_states, instance_capacity).total;
 }
 
 int dgs_count_instances(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
@@ -329,7 +333,7 @@ int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_stat
   if (mode == 1 && W > 0 && (!reference || !psnr)) return fail(DGS_ERR_INVALID_ARG, "reference / psnr is NULL");
   if (mode == 2 && !counters) return fail(DGS_ERR_INVALID_ARG, "counters is NULL");
   hipStream_t st = (hipStream_t)stream;
-  if (mode == 2) launch_fill_u64(counters, 2, st);
+  if (mode == 2) launch_fill_u64(counters, 4, st);
   if (W == 0) return hip_check("composite launch");
   const int S = group_size(tun, W, 32);
   const int groups = (W + S - 1) / S;
@@ -503,7 +507,7 @@ int dgs_workspace_sections(int32_t n, int32_t num_packets, const dgs_camera *cam
       instance_capacity > (int64_t)0xFFFFFFFFll)
     return fail(DGS_ERR_INVALID_ARG, "sizes out of range");
   if ((rc = check_camera(cam)) || (rc = check_tuning(cam, tun, &t))) return rc;
-  const Layout L = make_layout(n, num_packets, t.tiles, max_states, instance_capacity);
+  const Layout L = make_layout(n, num_packets, t.tiles_x, t.tiles_y, max_states, instance_capacity);
   const int passes = (t.tile_bits + 7) / 8;
   out->rec0 = L.rec0;
   out->rec1 = L.rec1;

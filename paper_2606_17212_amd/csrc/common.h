@@ -23,6 +23,37 @@ constexpr float kShC1 = 0.4886025119029199f;
 constexpr float kConicA = -0.72134752044448170f;  // -log2(e) / 2
 constexpr float kConicB = -1.4426950408889634f;   // -log2(e)
 constexpr float kQSkip = -7.9943534368588578f;    // log2(1/255): alpha < 1/255 <=> q' < kQSkip
+// Tile-sorted values: Gaussian id in bits 0..27, bit 28 + w set when the
+// Gaussian can reach alpha >= 1/255 somewhere in wave block w of that tile.
+constexpr uint32_t kIdMask = 0x0FFFFFFFu;
+constexpr int kMaskShift = 28;
+constexpr int kMaxGaussians = 0x0FFFFFFF;
+
+// Origin of wave w's 8x8 pixel block inside a TW-wide tile (16x16: 2x2
+// blocks; 32x8: 4x1 blocks).
+__host__ __device__ inline int wave_block_x0(int w, int tw) { return (w * 8) % tw; }
+__host__ __device__ inline int wave_block_y0(int w, int tw) { return ((w * 8) / tw) * 8; }
+
+// Largest value of the exponent A' X^2 + B' X Y + C' Y^2 (negative definite)
+// over the box X in [xl, xh], Y in [yl, yh]: 0 when the box holds the origin,
+// otherwise on an edge, at the clamped 1D maximiser X* = B Y ia, Y* = B X ic
+// with ia = -1/(2 A), ic = -1/(2 C).  An inexact maximiser only lowers the
+// value found by a second-order amount, which the caller's margin absorbs.
+__device__ inline float box_max_exponent(float A, float B, float C, float ia, float ic, float xl, float xh,
+                                         float yl, float yh) {
+  if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return 0.0f;
+  float best = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float X = e ? xh : xl;
+    const float Y = fminf(fmaxf(B * X * ic, yl), yh);
+    best = fmaxf(best, fmaf(A * X, X, fmaf(B * X, Y, C * Y * Y)));
+    const float Yb = e ? yh : yl;
+    const float Xb = fminf(fmaxf(B * Yb * ia, xl), xh);
+    best = fmaxf(best, fmaf(A * Xb, Xb, fmaf(B * Xb, Yb, C * Yb * Yb)));
+  }
+  return best;
+}
 
 // Scene parameters passed by value to kernels.
 struct SceneArgs {
@@ -67,6 +98,8 @@ struct Layout {
   size_t tkey0, tkey1, tval0, tval1;  // tile sort ping-pong [cap]
   size_t hist;               // u32 radix histograms
   size_t ranges;             // uint2 [tiles]
+  size_t tdiff;              // u32 [(tiles_y+1)(tiles_x+1)]: 2D difference array of tile coverage
+  size_t tcnt, tstart;       // u32 [tiles]: instances per tile and their exclusive scan
   size_t grad2d;             // f32 [9][n]
   size_t plhist;             // u32 [P*4]: Gaussians per (packet, layer)
   size_t tile_order;         // u32 [tiles]: tiles by decreasing list length
@@ -88,7 +121,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-inline Layout make_layout(int64_t n, int64_t P, int64_t tiles, int64_t max_states, int64_t cap) {
+inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y, int64_t max_states,
+                          int64_t cap) {
+  const int64_t tiles = tiles_x * tiles_y;
   Layout L{};
   L.n = n; L.cap = cap; L.tiles = tiles; L.max_states = max_states; L.P = P;
   int64_t nn = n > 0 ? n : 1;
@@ -119,6 +154,9 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles, int64_t max_state
   L.tval1 = take(4 * cc);
   L.hist = take(4 * hist_entries);
   L.ranges = take(8 * (tiles > 0 ? tiles : 1));
+  L.tdiff = take(4 * (tiles_x + 1) * (tiles_y + 1));
+  L.tcnt = take(4 * (tiles > 0 ? tiles : 1));
+  L.tstart = take(4 * (tiles > 0 ? tiles : 1));
   L.grad2d = take(4 * 9 * nn);
   L.plhist = take(4 * P * 4);
   L.tile_order = take(4 * (tiles > 0 ? tiles : 1));

@@ -78,30 +78,33 @@ struct Stage {
   uint32_t id[kBlock];      // Gaussian id (backward)
 };
 
+// Stages one list entry.  The sorted value carries the Gaussian id in its low
+// 28 bits and, in bits 28..31, whether the entry can reach alpha >= 1/255 in
+// each of the tile's four 8x8 wave blocks (decided once at emission).  Per wave
+// the stage holds the entry's delivery bits, or 0 for a block it cannot reach.
 template <int TW, int TH>
-__device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t id, const float4 *rec0,
-                                            const float4 *rec1, const float4 *rec2, const uint2 *pbox,
-                                            const uint32_t *vis, int tpx, int tpy) {
+__device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, const float4 *rec0,
+                                            const float4 *rec1, const float4 *rec2, const uint32_t *vis) {
+  const uint32_t id = val & kIdMask;
   const float4 r0 = rec0[id];
   const float4 r1 = rec1[id];
-  const uint2 pb = pbox[id];
   const uint32_t vb = vis ? vis[__float_as_uint(r0.w)] : 1u;
-  const int x0 = (int)(pb.x & 0xFFFFu) - tpx, y0 = (int)(pb.x >> 16) - tpy;
-  const int x1 = (int)(pb.y & 0xFFFFu) - tpx, y1 = (int)(pb.y >> 16) - tpy;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    const int bx = wave_x0<TW>(w), by = wave_y0<TW>(w);
-    const bool hit = x0 < bx + 8 && x1 > bx && y0 < by + 8 && y1 > by;
-    st.vis[w][slot] = hit ? vb : 0u;
-  }
+  for (int w = 0; w < 4; ++w) st.vis[w][slot] = ((val >> (kMaskShift + w)) & 1u) ? vb : 0u;
   st.p0[slot] = make_float4(r0.x, r0.y, r0.z, r1.x);
   st.p1[slot] = make_float2(r1.y, r1.z);
   st.col[slot] = rec2[id];
   st.id[slot] = id;
 }
 
+// Occupancy requested from the register allocator: the state registers
+// (4 per state) dominate, so small groups can keep 8 waves per SIMD.
+template <int S>
+constexpr int waves_per_eu() { return S <= 8 ? 8 : (S <= 16 ? 5 : 2); }
+
 template <int S, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), 8)))
+k_composite(CompositeArgs a) {
   static_assert(TW * TH == kBlock, "one pixel per thread");
   int kpos, grp;
   if (!work_item(blockIdx.x, a.groups, a.tiles_x * a.tiles_y, kpos, grp)) return;
@@ -123,14 +126,14 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
   __shared__ Stage st;
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
-  uint32_t n_alpha = 0, n_blend = 0;  // MODE 2 only
+  uint32_t n_alpha = 0, n_blend = 0, n_wave_alpha = 0, n_wave_miss = 0;  // MODE 2 only
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
     int alive = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) alive |= T[s] > 0.0f;
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
-    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, a.pbox, vis, tpx, tpy);
+    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
     __syncthreads();
     const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
     uint32_t wave_alive = 0;
@@ -150,6 +153,10 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
         n_alpha += (uv & lane_alive) ? 1u : 0u;
       }
       const float q = splat_q(st.p0[k], st.p1[k], fpx, fpy);
+      if (MODE == 2 && lane == 0) {
+        ++n_wave_alpha;
+        n_wave_miss += __ballot(q >= kQSkip) == 0ull ? 1u : 0u;
+      }
       if (q < kQSkip) continue;
       const float alpha = alpha_of(q);
       const float4 C = st.col[k];
@@ -174,6 +181,8 @@ __global__ void __launch_bounds__(kBlock) k_composite(CompositeArgs a) {
     if (__lane_id() == 0) {
       atomicAdd(a.counters, c0);
       atomicAdd(a.counters + 1, c1);
+      atomicAdd(a.counters + 2, (unsigned long long)n_wave_alpha);
+      atomicAdd(a.counters + 3, (unsigned long long)n_wave_miss);
     }
     return;
   }
@@ -308,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
     for (int s = 0; s < S; ++s) alive |= T[s] > 0.0f;
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
-    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, a.pbox, vis, tpx, tpy);
+    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
     __syncthreads();
     const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
     uint32_t wave_alive = 0;

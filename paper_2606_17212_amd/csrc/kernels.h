@@ -20,19 +20,24 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, unsigned long
 // Sorts bits [begin_bit, end_bit) of the keys.  Count = *count_dev clamped to
 // max_count when count_dev is non-null, else max_count.  Ping-pongs between
 // (k0,v0) and (k1,v1); returns 0 if the result is in (k0,v0), 1 otherwise.
+// last_pass_keys = false: the final pass writes values only (keys not needed).
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const void *count_dev,
                       int count_is_u64, int64_t max_count, int begin_bit, int end_bit, uint32_t *hist,
-                      unsigned long long *parts, hipStream_t st);
+                      unsigned long long *parts, hipStream_t st, bool last_pass_keys = true);
 
 // binning.hip
 void launch_clear_header(Header *h, unsigned long long capacity, hipStream_t st);
 void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                   int grid_n, uint32_t *cnt, hipStream_t st);
 void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, const uint32_t *cnt,
-                 const unsigned *n_active, int grid_n, int tiles_x, Header *h, uint32_t *tkey,
-                 uint32_t *tval, hipStream_t st);
-void launch_ranges(const uint32_t *tkey, const Header *h, int64_t cap, int tiles, uint2 *ranges,
-                   hipStream_t st);
+                 const unsigned *n_active, int grid_n, int tiles_x, int tile_w, int tile_h, const float4 *rec0,
+                 const float4 *rec1, const uint2 *pbox, Header *h, uint32_t *tkey, uint32_t *tval,
+                 hipStream_t st);
+// Per-tile [start, end) of the tile-sorted instances, from the Gaussians'
+// tile rectangles (the same instances emission writes); empty after an overflow.
+void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+                        int grid_n, int tiles_x, int tiles_y, const Header *h, uint32_t *tdiff, uint32_t *tcnt,
+                        uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st);
 void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S,
                     uint32_t *visbits, hipStream_t st);
 void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st);

@@ -209,27 +209,33 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint32_t kk = skey[k];
     const uint32_t d = (kk >> shift) & mask;
     const uint32_t o = gbase[d] + (uint32_t)(k - (int)dstart[d]);
-    kout[o] = kk;
+    if (kout) kout[o] = kk;
     vout[o] = sval[k];
   }
 }
 
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const void *count_dev,
                       int count_is_u64, int64_t max_count, int begin_bit, int end_bit, uint32_t *hist,
-                      unsigned long long *parts, hipStream_t st) {
+                      unsigned long long *parts, hipStream_t st, bool last_pass_keys) {
   if (max_count <= 0) return 0;
   const int nblocks = (int)ceil_div(max_count, kSortTile);
+  // fewest passes of <= 8 bits, digits as equal as possible (13 bits -> 7 + 6):
+  // fewer buckets per pass give longer contiguous runs in the scatter
+  const int total_bits = end_bit - begin_bit;
+  const int passes = (total_bits + 7) / 8;
   int cur = 0;
-  for (int shift = begin_bit; shift < end_bit; shift += 8) {
-    const int nbits = (end_bit - shift) < 8 ? (end_bit - shift) : 8;
+  for (int pass = 0, shift = begin_bit; pass < passes; ++pass) {
+    const int nbits = (total_bits - (shift - begin_bit) + (passes - pass) - 1) / (passes - pass);
     uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
     k_radix_up<<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist,
                                            nblocks);
     launch_scan_u32(hist, hist, (int64_t)(1 << nbits) * nblocks, parts, nullptr, st);
-    k_radix_down<<<nblocks, kBlock, 0, st>>>(ki, vi, ko, vo, count_dev, count_is_u64, max_count, shift,
+    uint32_t *kwrite = (pass == passes - 1 && !last_pass_keys) ? nullptr : ko;
+    k_radix_down<<<nblocks, kBlock, 0, st>>>(ki, vi, kwrite, vo, count_dev, count_is_u64, max_count, shift,
                                              nbits, hist, nblocks);
     cur ^= 1;
+    shift += nbits;
   }
   return cur;
 }

@@ -216,7 +216,9 @@ class Renderer:
         return dict(rec0=sl(v.rec0, n, torch.float32, 4), rec1=sl(v.rec1, n, torch.float32, 4),
                     rec2=sl(v.rec2, n, torch.float32, 4), rect=sl(v.rect, n, torch.int32, 2),
                     ranges=sl(v.ranges, tiles, torch.int32, 2),
-                    sorted_ids=sl(v.sorted_ids, self.capacity, torch.int32, 1).reshape(-1),
+                    # sorted values: Gaussian id in bits 0..27, wave-block reach mask in bits 28..31
+                    sorted_ids=sl(v.sorted_ids, self.capacity, torch.int32, 1).reshape(-1) & 0x0FFFFFFF,
+                    wave_masks=(sl(v.sorted_ids, self.capacity, torch.int32, 1).reshape(-1) >> 28) & 0xF,
                     tiles_x=v.tiles_x, tiles_y=v.tiles_y)
 
     def check(self) -> int:
@@ -291,16 +293,15 @@ class Renderer:
         return ps
 
     def composite_stats(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis):
-        """(alpha evaluations, blends) one ``composite`` of ``codes`` performs
-        after the last ``bin`` (synchronises)."""
+        """(alpha evaluations, blends, wave evaluations, wave misses) one
+        ``composite`` of ``codes`` performs after the last ``bin`` (synchronises)."""
         self._codes(codes, scene)
-        cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
+        cnt = torch.zeros(4, dtype=torch.int64, device=self.device)
         _abi.check(_abi.lib().dgs_composite_stats(
             ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
             ctypes.byref(_c_states(codes, basis, (0, 0, 0))), ctypes.byref(self.tuning), _ptr(self.ws),
             self.ws_bytes, self.capacity, _ptr(cnt), self._stream()))
-        c = cnt.cpu().tolist()
-        return int(c[0]), int(c[1])
+        return tuple(int(x) for x in cnt.cpu().tolist())
 
     def render_psnr(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
                     reference: torch.Tensor, background=(0, 0, 0), out=None):

@@ -1,0 +1,80 @@
+"""Full-size parity for the large workloads, in the launch shape the bench
+uses: per-tile lists bit-exact on sampled tiles, sampled pixels of every state
+against the oracle (1e-4 plus its ambiguity budget), and the on-device PSNR
+against a host PSNR of the GPU's own images."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def _dev(w):
+    import paper_2606_17212_amd as dgs
+    dev = torch.device("cuda:0")
+    return (dgs.GaussianScene.from_arrays(w.scene, dev), dgs.Camera.from_arrays(w.camera),
+            torch.from_numpy(np.ascontiguousarray(w.codes)).to(dev))
+
+
+def _tile_list(m, t, tiles_x):
+    tx, ty = t % tiles_x, t // tiles_x
+    r = m["rect"]
+    sel = m["valid"] & (r[0] <= tx) & (tx < r[2]) & (r[1] <= ty) & (ty < r[3])
+    ids = np.nonzero(sel)[0]
+    return ids[np.lexsort((ids, m["zbits"][ids].astype(np.int64)))]
+
+
+def test_full_size_2700k_1080p_256states():
+    import paper_2606_17212_amd as dgs
+    w = synth.make_workload("g2700k_1080p_256states", background=(0.25, 0.5, 0.75))
+    scene, cam, codes = _dev(w)
+    r = dgs.Renderer(tile=(16, 16), states_per_group=8)
+    img = r.render(scene, cam, codes, w.basis, tuple(w.background))
+    M = r.check()
+    sec = r.sections(scene, cam, codes.shape[0])
+    m = oracle.mirror_f32(w.scene, w.camera, w.basis)
+    rect = m["rect"].astype(np.int64)
+    assert M == int(np.where(m["valid"], (rect[2] - rect[0]).clip(0) * (rect[3] - rect[1]).clip(0), 0).sum())
+    ranges = sec["ranges"].numpy().astype(np.int64)
+    ids = sec["sorted_ids"].numpy()
+    rng = np.random.default_rng(5)
+    tiles = np.concatenate([rng.integers(0, ranges.shape[0], 12), np.argsort(ranges[:, 1] - ranges[:, 0])[-4:]])
+    for t in tiles:
+        want = _tile_list(m, int(t), sec["tiles_x"])
+        assert np.array_equal(ids[ranges[t, 0]:ranges[t, 1]].astype(np.int64), want), t
+    pix = np.concatenate([np.stack([rng.integers(0, 1920, 24), rng.integers(0, 1080, 24)], 1),
+                          np.stack([rng.integers(760, 1160, 24), rng.integers(340, 740, 24)], 1)])
+    host = img[:, pix[:, 1], pix[:, 0], :].cpu().numpy()
+    ref = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
+    ex = np.abs(host.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
+    assert ex.max() <= TOL, f"excess {ex.max():.3g}"
+    ps = r.render(scene, cam, codes[[0, 128, 255]].contiguous(), w.basis, tuple(w.background), per_state=True)
+    assert torch.equal(ps, img[[0, 128, 255]])
+
+
+def test_full_size_1m_540p_psnr_batch():
+    import paper_2606_17212_amd as dgs
+    w = synth.make_workload("g1m_540p_32768states_psnr", background=(0.25, 0.5, 0.75))
+    scene, cam, codes = _dev(w)
+    bg = tuple(w.background)
+    r = dgs.Renderer(tile=(16, 16), states_per_group=8)
+    full = r.render(scene, cam, torch.ones_like(codes[:1]), w.basis, bg)[0].contiguous()
+    img = r.render(scene, cam, codes, w.basis, bg)
+    r.check()
+    ps = r.render_psnr(scene, cam, codes, w.basis, full, bg).cpu().numpy().astype(np.float64)
+    d = img.double() - full.double()[None]
+    mse = (d * d).reshape(d.shape[0], -1).mean(1).cpu().numpy()
+    host = 10 * np.log10(1 / np.maximum(mse, 1e-10))
+    assert np.max(np.abs(ps - host)) <= 1e-3
+    rng = np.random.default_rng(9)
+    pix = np.concatenate([np.stack([rng.integers(0, 960, 24), rng.integers(0, 540, 24)], 1),
+                          np.stack([rng.integers(330, 630, 24), rng.integers(120, 420, 24)], 1)])
+    host_img = img[:, pix[:, 1], pix[:, 0], :].cpu().numpy()
+    ref = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
+    ex = np.abs(host_img.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
+    assert ex.max() <= TOL, f"excess {ex.max():.3g}"

@@ -269,7 +269,8 @@ def test_bin_once_composite_many_and_work_counters(tiny):
     a = r.composite(scene, cam, codes[:5].contiguous(), w.basis, BG)
     b = r.composite(scene, cam, codes[5:].contiguous(), w.basis, BG)
     assert torch.equal(torch.cat([a, b]), full)
-    alpha_evals, blends = r.composite_stats(scene, cam, codes, w.basis)
+    alpha_evals, blends, wave_evals, wave_miss = r.composite_stats(scene, cam, codes, w.basis)
+    assert 0 <= wave_miss <= wave_evals and wave_evals * 64 >= alpha_evals
     want = int(ref["ncomp"].sum())
     amb = int((ref["budget"] > 0).sum())
     assert abs(blends - want) <= 4 * amb, (blends, want, amb)
