@@ -76,56 +76,38 @@ __device__ inline uint32_t wave_block_mask(uint32_t id, uint32_t tx, uint32_t ty
   return mask;
 }
 
-// Emission: workgroup b writes the instances of the 256 depth-sorted
-// Gaussians [256 b, 256 b + 256) -- one contiguous output range -- with
-// consecutive lanes writing consecutive instances; each lane finds the
-// Gaussian owning its output position by binary search over the workgroup's
-// offsets in LDS, then its tile inside that Gaussian's rectangle (row-major).
+// Emission: one wave per depth-sorted Gaussian (grid-stride); its lanes write
+// the Gaussian's instances [off, off + count) -- tiles of its rectangle in
+// row-major order -- to consecutive addresses, each with the tile id as key
+// and the Gaussian id plus its wave-block reach mask as value.
 __global__ void __launch_bounds__(kBlock)
 k_emit(const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect, const uint32_t *__restrict__ off,
        const uint32_t *__restrict__ cnt, const unsigned *__restrict__ n_active, int grid_n, int tiles_x,
        int tile_w, int tile_h, const float4 *__restrict__ rec0, const float4 *__restrict__ rec1,
        const uint2 *__restrict__ pbox, Header *h, uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
-  __shared__ uint32_t s_off[kBlock + 1];
-  __shared__ uint32_t s_id[kBlock];
-  __shared__ uint32_t s_x0y0[kBlock];
-  __shared__ uint32_t s_nx[kBlock];
   const int nact = n_active ? (int)*n_active : grid_n;
-  const int j0 = blockIdx.x * kBlock;
-  if (j0 >= nact) return;  // uniform
-  const int tid = threadIdx.x;
-  const int nloc = (nact - j0) < kBlock ? (nact - j0) : kBlock;
-  if (tid < nloc) {
-    const int j = j0 + tid;
+  const int lane = __lane_id();
+  const int wave = (int)(blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6));
+  const int nwaves = (int)(gridDim.x * (kBlock / kWave));
+  const unsigned long long capacity = h->capacity;
+  for (int j = wave; j < nact; j += nwaves) {
+    const uint32_t c = cnt[j];
+    if (c == 0) continue;
+    const unsigned long long o0 = off[j];
+    if (o0 + c > capacity) {
+      if (lane == 0) h->overflow = 1u;
+      continue;
+    }
     const uint32_t id = dval[j];
     const uint2 r = rect[id];
-    s_off[tid] = off[j];
-    s_id[tid] = id;
-    s_x0y0[tid] = r.x;
-    s_nx[tid] = (r.y & 0xFFFFu) - (r.x & 0xFFFFu);
-    if (tid == nloc - 1) s_off[nloc] = off[j] + cnt[j];
-  }
-  __syncthreads();
-  const unsigned long long begin = s_off[0], end = s_off[nloc];
-  if (end > h->capacity) {  // the scan's total is checked against the same capacity
-    if (tid == 0) h->overflow = 1u;
-    return;
-  }
-  for (unsigned long long p = begin + tid; p < end; p += kBlock) {
-    // last local index whose offset <= p (entries with zero count share offsets)
-    int lo = 0, hi = nloc - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((unsigned long long)s_off[mid] <= p) lo = mid; else hi = mid - 1;
+    const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16;
+    const uint32_t nx = (r.y & 0xFFFFu) - x0;
+    for (uint32_t k = lane; k < c; k += kWave) {
+      const uint32_t dy = k / nx, dx = k - dy * nx;
+      const uint32_t tx = x0 + dx, ty = y0 + dy;
+      tkey[o0 + k] = ty * (uint32_t)tiles_x + tx;
+      tval[o0 + k] = id | (wave_block_mask(id, tx, ty, tile_w, tile_h, rec0, rec1, pbox) << kMaskShift);
     }
-    const uint32_t k = (uint32_t)(p - s_off[lo]);
-    const uint32_t nx = s_nx[lo];
-    const uint32_t xy = s_x0y0[lo];
-    const uint32_t dy = k / nx, dx = k - dy * nx;
-    const uint32_t tx = (xy & 0xFFFFu) + dx, ty = (xy >> 16) + dy;
-    const uint32_t id = s_id[lo];
-    tkey[p] = ty * (uint32_t)tiles_x + tx;
-    tval[p] = id | (wave_block_mask(id, tx, ty, tile_w, tile_h, rec0, rec1, pbox) << kMaskShift);
   }
 }
 
@@ -134,13 +116,10 @@ void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, c
                  const float4 *rec1, const uint2 *pbox, Header *h, uint32_t *tkey, uint32_t *tval,
                  hipStream_t st) {
   if (grid_n <= 0) return;
-  k_emit<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(dval, rect, off, cnt, n_active, grid_n, tiles_x,
-                                                                tile_w, tile_h, rec0, rec1, pbox, h, tkey, tval);
-}
-
-__global__ void __launch_bounds__(kBlock) k_zero_u2(uint2 *p, int n) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = make_uint2(0u, 0u);
+  // one wave per Gaussian, up to 8192 workgroups striding over the rest
+  const int64_t blocks = ceil_div(grid_n, kBlock / kWave) < 8192 ? ceil_div(grid_n, kBlock / kWave) : 8192;
+  k_emit<<<(unsigned)blocks, kBlock, 0, st>>>(dval, rect, off, cnt, n_active, grid_n, tiles_x, tile_w, tile_h,
+                                              rec0, rec1, pbox, h, tkey, tval);
 }
 
 // Tile coverage as a 2D difference array: +1 at (x0, y0) and (x1, y1), -1 at
@@ -214,7 +193,8 @@ void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 
   const int64_t ne = (int64_t)(tiles_x + 1) * (tiles_y + 1);
   k_zero_u32<<<(unsigned)ceil_div(ne, kBlock), kBlock, 0, st>>>(tdiff, ne);
   if (grid_n > 0) {
-    const int per = ne <= kDiffLds ? 16384 : 1024;  // Gaussians per workgroup
+    // enough workgroups to cover the machine, few enough to keep the LDS flushes cheap
+    const int64_t per = ne <= kDiffLds ? (grid_n / 512 > 1024 ? grid_n / 512 : 1024) : 1024;
     const int blocks = (int)ceil_div(grid_n, per);
     k_tile_diff<<<blocks, kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, tiles_x, tiles_y, tdiff);
   }

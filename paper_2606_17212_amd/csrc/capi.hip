@@ -233,7 +233,6 @@ CompositeArgs composite_args(const Call &cl, void *ws, const uint32_t *vals, con
   a.rec0 = at<float4>(ws, cl.L.rec0);
   a.rec1 = at<float4>(ws, cl.L.rec1);
   a.rec2 = at<float4>(ws, cl.L.rec2);
-  a.pbox = at<uint2>(ws, cl.L.pbox);
   a.vals = vals;
   a.ranges = at<uint2>(ws, cl.L.ranges);
   a.tile_order = at<uint32_t>(ws, cl.L.tile_order);
@@ -474,7 +473,6 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
     b.rec0 = at<float4>(ws, cl.L.rec0);
     b.rec1 = at<float4>(ws, cl.L.rec1);
     b.rec2 = at<float4>(ws, cl.L.rec2);
-    b.pbox = at<uint2>(ws, cl.L.pbox);
     b.vals = sorted_vals(cl, ws);
     b.ranges = at<uint2>(ws, cl.L.ranges);
     b.visbits = visbits;

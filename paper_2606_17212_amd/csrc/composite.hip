@@ -64,11 +64,6 @@ __device__ __forceinline__ bool work_item(int L, int groups, int tiles, int &k, 
 
 __host__ __device__ inline int work_items(int tiles, int groups) { return ((tiles + 7) / 8) * 8 * groups; }
 
-// Origin of wave w's 8x8 block inside a TW x TH tile.
-template <int TW>
-__device__ __forceinline__ int wave_x0(int w) { return (w * 8) % TW; }
-template <int TW>
-__device__ __forceinline__ int wave_y0(int w) { return ((w * 8) / TW) * 8; }
 
 struct Stage {
   uint32_t vis[4][kBlock];  // per wave: delivery bits of the entry, 0 if it misses the wave's block
@@ -112,7 +107,7 @@ k_composite(CompositeArgs a) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int tpx = tx * TW, tpy = ty * TH;
-  const int px = tpx + wave_x0<TW>(wv) + (lane & 7), py = tpy + wave_y0<TW>(wv) + (lane >> 3);
+  const int px = tpx + wave_block_x0(wv, TW) + (lane & 7), py = tpy + wave_block_y0(wv, TW) + (lane >> 3);
   const bool inside = px < a.width && py < a.height;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
 
@@ -262,9 +257,21 @@ void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int
 
 // ------------------------------------------------------------------ backward
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+// Sum over the wave, valid in lane 63: inclusive row scans with DPP row
+// shifts (16-lane rows), then row broadcasts of lanes 15 and 31 into the rows
+// above.  Six VALU instructions, no LDS traffic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_step(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true);
+  return x + __int_as_float(y);
+}
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x = dpp_step<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_step<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_step<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_step<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
@@ -286,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int tpx = tx * TW, tpy = ty * TH;
-  const int px = tpx + wave_x0<TW>(wv) + (lane & 7), py = tpy + wave_y0<TW>(wv) + (lane >> 3);
+  const int px = tpx + wave_block_x0(wv, TW) + (lane & 7), py = tpy + wave_block_y0(wv, TW) + (lane >> 3);
   const bool inside = px < a.width && py < a.height;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const int64_t plane = (int64_t)a.width * a.height;
@@ -309,6 +316,8 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
   }
 
   __shared__ Stage st;
+  // per-entry gradient sums of the workgroup's waves: [value][entry]
+  __shared__ float red[9][kBlock];
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
@@ -318,6 +327,8 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
     if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) red[v][tid] = 0.0f;
     __syncthreads();
     const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
     uint32_t wave_alive = 0;
@@ -373,24 +384,27 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
           glo = dq;
         }
       }
-      gu = wave_sum(gu); gv = wave_sum(gv); gA = wave_sum(gA); gB = wave_sum(gB); gC = wave_sum(gC);
-      glo = wave_sum(glo); dcr = wave_sum(dcr); dcg = wave_sum(dcg); dcb = wave_sum(dcb);
-      if (lane == 0) {
-        const uint32_t id = st.id[k];
-        float *g = a.g2d;
-        const int64_t n = a.n;
-        unsafeAtomicAdd(g + id, gu);
-        unsafeAtomicAdd(g + n + id, gv);
-        unsafeAtomicAdd(g + 2 * n + id, gA);
-        unsafeAtomicAdd(g + 3 * n + id, gB);
-        unsafeAtomicAdd(g + 4 * n + id, gC);
-        unsafeAtomicAdd(g + 5 * n + id, glo);
-        unsafeAtomicAdd(g + 6 * n + id, dcr);
-        unsafeAtomicAdd(g + 7 * n + id, dcg);
-        unsafeAtomicAdd(g + 8 * n + id, dcb);
+      gu = wave_sum_to_lane63(gu); gv = wave_sum_to_lane63(gv); gA = wave_sum_to_lane63(gA);
+      gB = wave_sum_to_lane63(gB); gC = wave_sum_to_lane63(gC); glo = wave_sum_to_lane63(glo);
+      dcr = wave_sum_to_lane63(dcr); dcg = wave_sum_to_lane63(dcg); dcb = wave_sum_to_lane63(dcb);
+      if (lane == 63) {  // LDS float atomics fold the four waves together
+        atomicAdd(&red[0][k], gu); atomicAdd(&red[1][k], gv); atomicAdd(&red[2][k], gA);
+        atomicAdd(&red[3][k], gB); atomicAdd(&red[4][k], gC); atomicAdd(&red[5][k], glo);
+        atomicAdd(&red[6][k], dcr); atomicAdd(&red[7][k], dcg); atomicAdd(&red[8][k], dcb);
       }
     }
     __syncthreads();
+    // one atomic per value and entry for the whole workgroup
+    if (e < rg.y) {
+      const uint32_t id = st.id[tid];
+      float *g = a.g2d;
+      const int64_t n = a.n;
+#pragma unroll
+      for (int v = 0; v < 9; ++v) {
+        const float sum = red[v][tid];
+        if (sum != 0.0f) unsafeAtomicAdd(g + v * n + id, sum);
+      }
+    }
   }
 }
 

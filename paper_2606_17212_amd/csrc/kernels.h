@@ -55,8 +55,7 @@ void launch_fill_u64(unsigned long long *p, int n, hipStream_t st);  // zero n <
 // composite.hip
 struct CompositeArgs {
   const float4 *rec0, *rec1, *rec2;
-  const uint2 *pbox;           // per-Gaussian pixel rectangle
-  const uint32_t *vals;        // sorted Gaussian ids
+  const uint32_t *vals;        // tile-sorted values: Gaussian id | wave-block reach mask << 28
   const uint2 *ranges;         // per tile [start, end)
   const uint32_t *visbits;     // [groups][P*4] state bits, or null (every entry visible, S = 1)
   const uint32_t *tile_order;  // tiles by decreasing list length
@@ -79,7 +78,6 @@ void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int
 
 struct CompositeBwdArgs {
   const float4 *rec0, *rec1, *rec2;
-  const uint2 *pbox;
   const uint32_t *vals;
   const uint2 *ranges;
   const uint32_t *visbits;
