@@ -28,6 +28,7 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 # Algorithmic FLOPs (an FMA counts 2) per unit of compositing work:
 FLOPS_PER_ALPHA = 14       # dx, dy, quadratic form (8), scale, exp, x opacity, cap
 FLOPS_PER_BLEND = 8        # T*alpha, 3 FMA colour, T - T*alpha
+LAUNCH = {"auto": None, "grid": False, "persistent": True}
 
 
 def parse():
@@ -38,6 +39,9 @@ def parse():
     ap.add_argument("--workload", default="g250k_800px_64states")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--states-per-group", type=int, default=8)
+    ap.add_argument("--launch", choices=("auto", "grid", "persistent"), default="auto",
+                    help="compositing launch: one workgroup per work item, or resident workgroups "
+                         "draining per-XCD work queues (auto: the library decides)")
     ap.add_argument("--no-per-state", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -81,8 +85,10 @@ def main():
     if args.tune:
         res = dgs.Autotuner().tune(scene, cam, codes, w.basis, bg, reps=3)
         (tw, th), args.states_per_group = res.tile, res.states_per_group
-        log(f"[bench] autotuner: {tw}x{th}, S={args.states_per_group} ({res.ms:.3f} ms); table {res.table}")
-    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group)
+        args.launch = "persistent" if res.persistent else "grid"
+        log(f"[bench] autotuner: {tw}x{th}, S={args.states_per_group}, {args.launch} ({res.ms:.3f} ms); "
+            f"table {res.table}")
+    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch])
     M = r.plan(scene, cam, w.basis, W)
     log(f"[bench] {args.workload}: N={scene.n} {cam.width}x{cam.height} W={W} instances={M}")
     img = torch.empty((W, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
@@ -241,7 +247,7 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
         times.append(e0.elapsed_time(e1))
     r.check()
     finite = all(bool(torch.isfinite(p.grad).all()) for p in params.values())
-    log(f"[bench] fwd+bwd {name}: median {np.median(times):.3f} ms/iter, loss {float(loss):.5f}")
+    log(f"[bench] fwd+bwd {name}: median {np.median(times):.3f} ms/iter, loss {float(loss.detach()):.5f}")
     return {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
             "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
             "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
@@ -258,7 +264,7 @@ def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
     codes_all = torch.from_numpy(synth.make_codes(kind, lo, hi, total, w.scene.num_packets, rec["layers"],
                                                   index=w.index)).to(dev)
     bg = tuple(float(x) for x in w.background)
-    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group)
+    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch])
     ren.plan(scene, cam, w.basis, batch)
     ref = ren.render(scene, cam, torch.ones_like(codes_all[:1]), w.basis, bg)[0].contiguous()
     psnr = torch.empty(total, dtype=torch.float32, device=dev)
@@ -312,11 +318,16 @@ def cpu_baseline(w, np, seconds):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     H, Wd = w.camera.height, w.camera.width
     rng = np.random.default_rng(2606)
-    probe = np.stack([rng.integers(0, Wd, 64), rng.integers(0, H, 64)], 1)
-    t0 = time.perf_counter()
-    oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=probe)
-    per_px = (time.perf_counter() - t0) / 64
-    k = int(min(H * Wd, max(256, seconds / max(per_px, 1e-9))))
+    # two probes separate the per-call cost (geometry of every Gaussian) from the per-pixel cost
+    probe_t = []
+    for m in (64, 576):
+        probe = np.stack([rng.integers(0, Wd, m), rng.integers(0, H, m)], 1)
+        t0 = time.perf_counter()
+        oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=probe)
+        probe_t.append(time.perf_counter() - t0)
+    per_px = max((probe_t[1] - probe_t[0]) / 512, probe_t[1] / 576 * 0.1, 1e-9)
+    fixed = max(probe_t[0] - 64 * per_px, 0.0)
+    k = int(min(H * Wd, max(256, (seconds - fixed) / per_px)))
     pix = np.stack([rng.integers(0, Wd, k), rng.integers(0, H, k)], 1)
     t0 = time.perf_counter()
     oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)

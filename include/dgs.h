@@ -105,12 +105,20 @@ typedef struct {
 
 /* Launch shape.  tile_w x tile_h in {16x16, 32x8} (0,0 = 16x16);
  * states_per_group in {1,2,4,8,16,32} (0 = 16): states composited together
- * by one workgroup, sharing each splat's alpha evaluation. */
+ * by one workgroup, sharing each splat's alpha evaluation.
+ * flags: how the batched compositing is launched; results are identical.
+ *   DGS_TUNE_GRID: one workgroup per (tile, state group) work item.
+ *   DGS_TUNE_PERSISTENT: one workgroup per resident slot, draining per-XCD
+ *     work queues (heavy tiles first, then stealing from other XCDs).
+ *   0: automatic - persistent when there are at least 32 work items per
+ *     resident slot, else grid.  Setting both bits is DGS_ERR_INVALID_ARG. */
+#define DGS_TUNE_PERSISTENT 1
+#define DGS_TUNE_GRID 2
 typedef struct {
   int32_t tile_w;
   int32_t tile_h;
   int32_t states_per_group;
-  int32_t flags; /* reserved, must be 0 */
+  int32_t flags;
 } dgs_tuning;
 
 /* Parameter gradients, device pointers with the scene's shapes; overwritten. */

@@ -44,6 +44,10 @@ class States(ctypes.Structure):
                 ("basis", ctypes.c_float * 4), ("background", ctypes.c_float * 3)]
 
 
+TUNE_PERSISTENT = 1  # dgs_tuning.flags: persistent compositing launch
+TUNE_GRID = 2        # dgs_tuning.flags: one workgroup per work item (0 = automatic)
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("states_per_group", ctypes.c_int32), ("flags", ctypes.c_int32)]

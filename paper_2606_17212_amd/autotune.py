@@ -1,8 +1,9 @@
 """Launch-shape autotuner and memory-probed state-batch sizing.
 
-* ``tune``: times ``bin + composite`` for every tile shape (16x16, 32x8) and
-  states-per-group S in {2, 4, 8, 16, 32} on the caller's own scene, camera and
-  states, and keeps the fastest.  Results are cached in a JSON file keyed by
+* ``tune``: times ``bin + composite`` for every tile shape (16x16, 32x8),
+  states-per-group S in {2, 4, 8, 16, 32} and compositing launch (grid or
+  persistent) on the caller's own scene, camera and states, and keeps the
+  fastest.  Results are cached in a JSON file keyed by
   the device name and the workload's shape.
 * ``probe_state_batch``: the largest number of states whose images and
   workspace fit a memory budget.  Like the paper's probe-based world-batch
@@ -22,46 +23,52 @@ from typing import Callable, Dict, Iterable, Optional, Tuple
 
 TILES = ((16, 16), (32, 8))
 GROUP_SIZES = (2, 4, 8, 16, 32)
+LAUNCHES = (False, True)  # persistent compositing launch off / on
 
 
 @dataclass
 class TuneResult:
     tile: Tuple[int, int]
     states_per_group: int
+    persistent: bool
     ms: float
     table: Dict[str, float]
 
     def as_dict(self):
-        return {"tile": list(self.tile), "states_per_group": self.states_per_group, "ms": self.ms,
-                "table": self.table}
+        return {"tile": list(self.tile), "states_per_group": self.states_per_group,
+                "persistent": self.persistent, "ms": self.ms, "table": self.table}
 
 
 def _key(device_name: str, n: int, width: int, height: int, num_states: int, packets: int) -> str:
     return f"{device_name}|n={n}|{width}x{height}|W={num_states}|P={packets}"
 
 
-def search(timer: Callable[[Tuple[int, int], int], float], num_states: int,
-           tiles: Iterable[Tuple[int, int]] = TILES, group_sizes: Iterable[int] = GROUP_SIZES) -> TuneResult:
-    """Exhaustive search: ``timer(tile, S)`` returns milliseconds (may raise
-    to reject a candidate).  Group sizes above the state count add nothing
-    and are skipped."""
+def search(timer: Callable[[Tuple[int, int], int, bool], float], num_states: int,
+           tiles: Iterable[Tuple[int, int]] = TILES, group_sizes: Iterable[int] = GROUP_SIZES,
+           launches: Iterable[bool] = LAUNCHES) -> TuneResult:
+    """Exhaustive search: ``timer(tile, S, persistent)`` returns milliseconds
+    (may raise to reject a candidate).  Group sizes above the state count add
+    nothing and are skipped."""
     table = {}
     best = None
     cap = 1
     while cap < max(num_states, 1):
         cap *= 2
+    group_sizes = tuple(group_sizes)
     for tile in tiles:
         for S in group_sizes:
             if S > cap and S != min(group_sizes):
                 continue
-            try:
-                ms = float(timer(tile, S))
-            except Exception as e:  # a candidate that fails (e.g. out of memory) is skipped
-                table[f"{tile[0]}x{tile[1]}/S{S}"] = f"failed: {type(e).__name__}"
-                continue
-            table[f"{tile[0]}x{tile[1]}/S{S}"] = ms
-            if best is None or ms < best.ms:
-                best = TuneResult(tile, S, ms, table)
+            for pers in launches:
+                name = f"{tile[0]}x{tile[1]}/S{S}/{'persistent' if pers else 'grid'}"
+                try:
+                    ms = float(timer(tile, S, pers))
+                except Exception as e:  # a candidate that fails (e.g. out of memory) is skipped
+                    table[name] = f"failed: {type(e).__name__}"
+                    continue
+                table[name] = ms
+                if best is None or ms < best.ms:
+                    best = TuneResult(tile, S, bool(pers), ms, table)
     if best is None:
         raise RuntimeError("no launch shape could be timed")
     best.table = table
@@ -116,7 +123,7 @@ class Autotuner:
                 self.cache = json.load(f)
 
     def tune(self, scene, camera, codes, basis, background=(0, 0, 0), reps: int = 5,
-             tiles=TILES, group_sizes=GROUP_SIZES) -> TuneResult:
+             tiles=TILES, group_sizes=GROUP_SIZES, launches=LAUNCHES) -> TuneResult:
         import torch
 
         from .render import Renderer
@@ -126,12 +133,13 @@ class Autotuner:
                    int(codes.shape[0]), scene.num_packets)
         if key in self.cache:
             c = self.cache[key]
-            return TuneResult(tuple(c["tile"]), int(c["states_per_group"]), float(c["ms"]), c["table"])
+            return TuneResult(tuple(c["tile"]), int(c["states_per_group"]), bool(c.get("persistent", False)),
+                              float(c["ms"]), c["table"])
         W = int(codes.shape[0])
         img = torch.empty((W, camera.height, camera.width, 3), dtype=torch.float32, device=dev)
 
-        def timer(tile, S):
-            r = Renderer(dev, tile=tile, states_per_group=S)
+        def timer(tile, S, persistent):
+            r = Renderer(dev, tile=tile, states_per_group=S, persistent=persistent)
             r.plan(scene, camera, basis, W)
             for _ in range(2):
                 r.bin(scene, camera, basis)
@@ -147,7 +155,7 @@ class Autotuner:
             del r
             return e0.elapsed_time(e1) / reps
 
-        res = search(timer, W, tiles, group_sizes)
+        res = search(timer, W, tiles, group_sizes, launches)
         self.cache[key] = res.as_dict()
         if self.cache_path:
             with open(self.cache_path, "w") as f:

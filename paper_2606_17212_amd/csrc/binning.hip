@@ -384,4 +384,10 @@ __global__ void k_fill_u64(unsigned long long *p, int n) {
 
 void launch_fill_u64(unsigned long long *p, int n, hipStream_t st) { k_fill_u64<<<1, 64, 0, st>>>(p, n); }
 
+__global__ void k_zero_queues(unsigned int *q) {
+  if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+}
+
+void launch_zero_queues(unsigned int *queues, hipStream_t st) { k_zero_queues<<<1, 64, 0, st>>>(queues); }
+
 }  // namespace dgs

@@ -45,7 +45,10 @@ int check_tuning(const dgs_camera *cam, const dgs_tuning *tun, Tiling *t) {
   }
   if (!((tw == 16 && th == 16) || (tw == 32 && th == 8)))
     return fail(DGS_ERR_UNSUPPORTED, "tile shape %dx%d not supported (16x16 or 32x8)", tw, th);
-  if (tun && tun->flags != 0) return fail(DGS_ERR_INVALID_ARG, "tuning flags must be 0");
+  if (tun && (tun->flags & ~(DGS_TUNE_PERSISTENT | DGS_TUNE_GRID)) != 0)
+    return fail(DGS_ERR_INVALID_ARG, "unknown tuning flags");
+  if (tun && (tun->flags & DGS_TUNE_PERSISTENT) && (tun->flags & DGS_TUNE_GRID))
+    return fail(DGS_ERR_INVALID_ARG, "tuning flags: persistent and grid are exclusive");
   t->tw = tw;
   t->th = th;
   t->tiles_x = (cam->width + tw - 1) / tw;
@@ -349,7 +352,9 @@ int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_stat
   a.reference = reference;
   a.psnr_part = at<float>(ws, cl.L.psnr_part);
   a.counters = counters;
-  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, st))
+  a.queues = at<unsigned int>(ws, cl.L.queues);
+  const int launch = !tun ? 0 : (tun->flags & DGS_TUNE_PERSISTENT) ? 1 : (tun->flags & DGS_TUNE_GRID) ? 2 : 0;
+  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, launch, st))
     return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
   if (mode == 1)
     launch_psnr_finalize(a.psnr_part, W, cl.tiling.tiles, (int64_t)cl.c.width * cl.c.height, psnr, st);
@@ -423,7 +428,7 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
     a.tfinal = tfinal;
     a.state_offset = w;
     a.launch_states = 1;
-    if (launch_composite(a, 1, cl.tiling.tw, cl.tiling.th, 0, st))
+    if (launch_composite(a, 1, cl.tiling.tw, cl.tiling.th, 0, 2, st))
       return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=1");
   }
   return hip_check("render_per_state launch");

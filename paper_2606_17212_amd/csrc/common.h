@@ -107,6 +107,7 @@ struct Layout {
   size_t state_order;        // u32 [max_states]: states by increasing present count
   size_t visbits;            // u32 [max_states][P*4]
   size_t psnr_part;          // f32 [max_states][tiles]
+  size_t queues;             // u32 [8]: per-XCD work queues of the persistent compositing launch
   size_t total;
   int64_t n, cap, tiles, max_states, P;
   int64_t sort_blocks;       // blocks of the largest radix pass
@@ -164,6 +165,7 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   L.state_order = take(4 * (max_states > 0 ? max_states : 1));
   L.visbits = take(4 * (max_states > 0 ? max_states : 1) * P * 4);
   L.psnr_part = take(4 * (max_states > 0 ? max_states : 1) * (tiles > 0 ? tiles : 1));
+  L.queues = take(4 * 8);
   L.total = o;
   return L;
 }

@@ -65,11 +65,16 @@ __device__ __forceinline__ bool work_item(int L, int groups, int tiles, int &k, 
 __host__ __device__ inline int work_items(int tiles, int groups) { return ((tiles + 7) / 8) * 8 * groups; }
 
 
+struct StageRec {
+  float4 p0;   // u, v, log2 o, A'
+  float2 p1;   // B', C'
+  float2 pad;
+  float4 col;  // r, g, b, -
+};
+
 struct Stage {
   uint32_t vis[4][kBlock];  // per wave: delivery bits of the entry, 0 if it misses the wave's block
-  float4 p0[kBlock];        // u, v, log2 o, A'
-  float2 p1[kBlock];        // B', C'
-  float4 col[kBlock];       // r, g, b, -
+  StageRec rec[kBlock];     // one 48-byte record per entry: one LDS base address per entry
   uint32_t id[kBlock];      // Gaussian id (backward)
 };
 
@@ -86,9 +91,9 @@ __device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, c
   const uint32_t vb = vis ? vis[__float_as_uint(r0.w)] : 1u;
 #pragma unroll
   for (int w = 0; w < 4; ++w) st.vis[w][slot] = ((val >> (kMaskShift + w)) & 1u) ? vb : 0u;
-  st.p0[slot] = make_float4(r0.x, r0.y, r0.z, r1.x);
-  st.p1[slot] = make_float2(r1.y, r1.z);
-  st.col[slot] = rec2[id];
+  st.rec[slot].p0 = make_float4(r0.x, r0.y, r0.z, r1.x);
+  st.rec[slot].p1 = make_float2(r1.y, r1.z);
+  st.rec[slot].col = rec2[id];
   st.id[slot] = id;
 }
 
@@ -98,11 +103,8 @@ template <int S>
 constexpr int waves_per_eu() { return S <= 8 ? 8 : (S <= 16 ? 5 : 2); }
 
 template <int S, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), 8)))
-k_composite(CompositeArgs a) {
+__device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st, int kpos, int grp) {
   static_assert(TW * TH == kBlock, "one pixel per thread");
-  int kpos, grp;
-  if (!work_item(blockIdx.x, a.groups, a.tiles_x * a.tiles_y, kpos, grp)) return;
   const int tile = (int)a.tile_order[kpos];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -118,7 +120,6 @@ k_composite(CompositeArgs a) {
     cr[s] = cg[s] = cb[s] = 0.0f;
   }
 
-  __shared__ Stage st;
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
   uint32_t n_alpha = 0, n_blend = 0, n_wave_alpha = 0, n_wave_miss = 0;  // MODE 2 only
@@ -147,14 +148,14 @@ k_composite(CompositeArgs a) {
         for (int s = 0; s < S; ++s) lane_alive |= (T[s] > 0.0f ? 1u : 0u) << s;
         n_alpha += (uv & lane_alive) ? 1u : 0u;
       }
-      const float q = splat_q(st.p0[k], st.p1[k], fpx, fpy);
+      const float q = splat_q(st.rec[k].p0, st.rec[k].p1, fpx, fpy);
       if (MODE == 2 && lane == 0) {
         ++n_wave_alpha;
         n_wave_miss += __ballot(q >= kQSkip) == 0ull ? 1u : 0u;
       }
       if (q < kQSkip) continue;
       const float alpha = alpha_of(q);
-      const float4 C = st.col[k];
+      const float4 C = st.rec[k].col;
 #pragma unroll
       for (int s = 0; s < S; ++s)
         if (uv & (1u << s)) {
@@ -229,6 +230,48 @@ k_composite(CompositeArgs a) {
         a.psnr_part[(int64_t)w * ntiles + tile] = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
       }
     }
+  }
+}
+
+// Grid launch: one workgroup per work item (see work_item).  Persistent
+// launch: one workgroup per resident slot; each drains its XCD's queue of
+// work items in the same heavy-first order, then steals from the other XCDs'
+// queues.  Every workgroup leaves once all eight queues are exhausted.
+template <int S, int TW, int TH, int MODE, bool PERSISTENT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), 8)))
+k_composite(CompositeArgs a) {
+  __shared__ Stage st;
+  const int tiles = a.tiles_x * a.tiles_y;
+  int kpos, grp;
+  if (!PERSISTENT) {
+    if (work_item(blockIdx.x, a.groups, tiles, kpos, grp)) composite_item<S, TW, TH, MODE>(a, st, kpos, grp);
+    return;
+  }
+  __shared__ int s_item;
+  const int home = blockIdx.x & 7;
+  int q = 0;  // queues tried so far (thread 0)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int item = -1;
+      while (q < 8) {
+        const int x = (home + q) & 7;
+        const int L = (int)atomicAdd(&a.queues[x], 1u) * 8 + x;
+        int kk, gg;
+        if (work_item(L, a.groups, tiles, kk, gg)) {
+          item = L;
+          break;
+        }
+        ++q;  // queue x is exhausted: its later items are further out still
+      }
+      s_item = item;
+    }
+    __syncthreads();
+    const int L = s_item;
+    __syncthreads();
+    if (L < 0) break;
+    work_item(L, a.groups, tiles, kpos, grp);
+    composite_item<S, TW, TH, MODE>(a, st, kpos, grp);
+    __syncthreads();  // the stage is reused by the next item
   }
 }
 
@@ -341,8 +384,8 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
       }
       const uint32_t uv = __builtin_amdgcn_readfirstlane(st.vis[wv][k]) & wave_alive;
       if (uv == 0u) continue;
-      const float4 P0 = st.p0[k];
-      const float2 P1 = st.p1[k];
+      const float4 P0 = st.rec[k].p0;
+      const float2 P1 = st.rec[k].p1;
       const float q = splat_q(P0, P1, fpx, fpy);
       const bool hit = q >= kQSkip;
       if (!__ballot(hit)) continue;
@@ -350,7 +393,7 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
       float gu = 0.0f, gv = 0.0f, gA = 0.0f, gB = 0.0f, gC = 0.0f, glo = 0.0f;
       if (hit) {
         const float alpha = alpha_of(q);
-        const float4 C = st.col[k];
+        const float4 C = st.rec[k].col;
         const float inv1ma = 1.0f / (1.0f - alpha);
         float d_alpha = 0.0f;
 #pragma unroll
@@ -410,35 +453,63 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
 
 // ------------------------------------------------------------------ launchers
 
+// Automatic choice: the persistent launch pays off once the grid would hold
+// many waves of workgroups (per-workgroup launch cost dominates the saving).
+constexpr int kPersistentItemsPerSlot = 32;
+
+template <int S, int TW, int TH, int MODE>
+static void launch_fwd_m(const CompositeArgs &a, int launch, unsigned blocks, hipStream_t st) {
+  // resident workgroups of the persistent kernel, cached per instantiation
+  // (host-side queries only, so the launch can be captured in a graph)
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_composite<S, TW, TH, MODE, true>, kBlock, 0);
+    resident = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
+  }
+  const bool persistent = launch == 1 || (launch == 0 && (int64_t)blocks >= (int64_t)kPersistentItemsPerSlot * resident);
+  if (!persistent) {
+    k_composite<S, TW, TH, MODE, false><<<blocks, kBlock, 0, st>>>(a);
+    return;
+  }
+  const unsigned grid = (unsigned)(resident < (int)blocks ? resident : (int)blocks);
+  launch_zero_queues(a.queues, st);
+  k_composite<S, TW, TH, MODE, true><<<grid, kBlock, 0, st>>>(a);
+}
+
 template <int S, int TW, int TH>
-static void launch_fwd_t(const CompositeArgs &a, int mode, unsigned blocks, hipStream_t st) {
+static void launch_fwd_t(const CompositeArgs &a, int mode, int persistent, unsigned blocks, hipStream_t st) {
   if (mode == 0)
-    k_composite<S, TW, TH, 0><<<blocks, kBlock, 0, st>>>(a);
+    launch_fwd_m<S, TW, TH, 0>(a, persistent, blocks, st);
   else if (mode == 1)
-    k_composite<S, TW, TH, 1><<<blocks, kBlock, 0, st>>>(a);
+    launch_fwd_m<S, TW, TH, 1>(a, persistent, blocks, st);
   else
-    k_composite<S, TW, TH, 2><<<blocks, kBlock, 0, st>>>(a);
+    launch_fwd_m<S, TW, TH, 2>(a, persistent, blocks, st);
 }
 
 template <int TW, int TH>
-static int launch_fwd_s(const CompositeArgs &a, int S, int mode, unsigned blocks, hipStream_t st) {
+static int launch_fwd_s(const CompositeArgs &a, int S, int mode, int pers, unsigned blocks, hipStream_t st) {
   switch (S) {
-    case 1: launch_fwd_t<1, TW, TH>(a, mode, blocks, st); return 0;
-    case 2: launch_fwd_t<2, TW, TH>(a, mode, blocks, st); return 0;
-    case 4: launch_fwd_t<4, TW, TH>(a, mode, blocks, st); return 0;
-    case 8: launch_fwd_t<8, TW, TH>(a, mode, blocks, st); return 0;
-    case 16: launch_fwd_t<16, TW, TH>(a, mode, blocks, st); return 0;
-    case 32: launch_fwd_t<32, TW, TH>(a, mode, blocks, st); return 0;
+    case 1: launch_fwd_t<1, TW, TH>(a, mode, pers, blocks, st); return 0;
+    case 2: launch_fwd_t<2, TW, TH>(a, mode, pers, blocks, st); return 0;
+    case 4: launch_fwd_t<4, TW, TH>(a, mode, pers, blocks, st); return 0;
+    case 8: launch_fwd_t<8, TW, TH>(a, mode, pers, blocks, st); return 0;
+    case 16: launch_fwd_t<16, TW, TH>(a, mode, pers, blocks, st); return 0;
+    case 32: launch_fwd_t<32, TW, TH>(a, mode, pers, blocks, st); return 0;
     default: return 1;
   }
 }
 
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, hipStream_t st) {
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int persistent,
+                     hipStream_t st) {
   const int64_t total = work_items(a.tiles_x * a.tiles_y, a.groups);
   if (total <= 0) return 0;
   const unsigned blocks = (unsigned)total;
-  if (tile_w == 16 && tile_h == 16) return launch_fwd_s<16, 16>(a, S, mode, blocks, st);
-  if (tile_w == 32 && tile_h == 8) return launch_fwd_s<32, 8>(a, S, mode, blocks, st);
+  if (persistent != 2 && !a.queues) return 1;
+  if (tile_w == 16 && tile_h == 16) return launch_fwd_s<16, 16>(a, S, mode, persistent, blocks, st);
+  if (tile_w == 32 && tile_h == 8) return launch_fwd_s<32, 8>(a, S, mode, persistent, blocks, st);
   return 1;
 }
 

@@ -69,10 +69,14 @@ struct CompositeArgs {
   float *psnr_part;            // [W][tiles] (PSNR mode)
   int state_offset;            // first state index of this launch's images
   int launch_states;           // states composited by this launch
-  unsigned long long *counters;  // [2] (count mode): alpha evaluations, blends
+  unsigned long long *counters;  // [4] (count mode)
+  unsigned int *queues;        // [8] per-XCD work counters (persistent launch)
 };
-// mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, hipStream_t st);
+// mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only.
+// launch 0: automatic, 1: persistent, 2: grid.
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch,
+                     hipStream_t st);
+void launch_zero_queues(unsigned int *queues, hipStream_t st);
 void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int64_t pixels,
                           float *psnr, hipStream_t st);
 

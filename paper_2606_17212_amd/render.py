@@ -142,12 +142,14 @@ class Renderer:
     ``check()`` reports an overflow.
     """
 
-    def __init__(self, device="cuda", tile=(16, 16), states_per_group=16, slack=1.25):
+    def __init__(self, device="cuda", tile=(16, 16), states_per_group=16, slack=1.25, persistent=None):
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
-        self.tuning = _abi.Tuning(int(tile[0]), int(tile[1]), int(states_per_group), 0)
+        # compositing launch: True persistent, False grid, None chosen by the library
+        flags = 0 if persistent is None else (_abi.TUNE_PERSISTENT if persistent else _abi.TUNE_GRID)
+        self.tuning = _abi.Tuning(int(tile[0]), int(tile[1]), int(states_per_group), flags)
         self.slack = float(slack)
         self.ws = None
         self.ws_bytes = 0

@@ -56,6 +56,10 @@ def test_workspace_bytes_and_sections():
     bad = abi.Tuning(8, 8, 16, 0)
     assert L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(bad), 16, 0) == 0
     assert L.dgs_workspace_bytes(-1, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 0) == 0
+    for flags, ok in ((abi.TUNE_PERSISTENT, True), (abi.TUNE_GRID, True),
+                      (abi.TUNE_PERSISTENT | abi.TUNE_GRID, False), (4, False)):
+        t = abi.Tuning(16, 16, 16, flags)
+        assert (L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(t), 16, 0) == b0) == ok, flags
     v = abi.WorkspaceView()
     assert L.dgs_workspace_sections(1000, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 100000,
                                     ctypes.byref(v)) == 0

@@ -10,20 +10,23 @@ def test_search_picks_fastest_and_skips_failures():
     cost = {((16, 16), 2): 5.0, ((16, 16), 4): 3.0, ((16, 16), 8): 2.5, ((16, 16), 16): 2.7,
             ((32, 8), 2): 6.0, ((32, 8), 4): 3.5, ((32, 8), 8): 2.4, ((32, 8), 16): 9.0}
 
-    def timer(tile, S):
+    def timer(tile, S, persistent):
         if S == 32:
             raise MemoryError("too big")
-        return cost[(tile, S)]
+        return cost[(tile, S)] - (0.25 if persistent and S == 16 else 0.0)
 
     r = search(timer, num_states=64)
-    assert (r.tile, r.states_per_group, r.ms) == ((32, 8), 8, 2.4)
-    assert r.table["16x16/S32"].startswith("failed")
+    assert (r.tile, r.states_per_group, r.persistent, r.ms) == ((32, 8), 8, False, 2.4)
+    assert r.table["16x16/S32/grid"].startswith("failed")
+    assert r.table["16x16/S16/persistent"] == pytest.approx(2.45)
+    r = search(timer, num_states=64, tiles=((16, 16),))
+    assert (r.states_per_group, r.persistent) == (16, True)
 
 
 def test_search_skips_groups_larger_than_the_batch():
     seen = []
 
-    def timer(tile, S):
+    def timer(tile, S, persistent):
         seen.append(S)
         return float(S)
 

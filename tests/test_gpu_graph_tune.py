@@ -67,8 +67,8 @@ def test_autotuner_and_memory_probe(dev_workload, tmp_path):
     res = at.tune(scene, cam, codes, w.basis, BG, reps=2)
     assert res.tile in TILES and res.states_per_group in (2, 4, 8, 16, 32) and res.ms > 0
     again = dgs.Autotuner(str(tmp_path / "tune.json")).tune(scene, cam, codes, w.basis, BG)
-    assert (again.tile, again.states_per_group) == (res.tile, res.states_per_group)  # from the cache
-    r = dgs.Renderer(tile=res.tile, states_per_group=res.states_per_group)
+    assert (again.tile, again.states_per_group, again.persistent) == (res.tile, res.states_per_group, res.persistent)
+    r = dgs.Renderer(tile=res.tile, states_per_group=res.states_per_group, persistent=res.persistent)
     r.plan(scene, cam, w.basis, 16)
     per_state = cam.width * cam.height * 12
     budget = r.workspace_bytes(scene, cam, 100, r.capacity) + 100 * per_state + 1000

@@ -117,6 +117,29 @@ def test_batched_equals_per_state_and_any_launch_shape(tiny):
     assert torch.equal(base.render(scene, cam, codes, w.basis, BG), ref_img)
 
 
+def test_persistent_launch_equals_grid_launch(tiny):
+    """The persistent launch (workgroups draining per-XCD queues) computes
+    every (tile, state group) item exactly as the grid launch does: images,
+    final transmittances and PSNR bit-identical, also on a second call that
+    reuses the queues with fewer states."""
+    dgs = _dgs()
+    w, _ = tiny
+    scene, cam, codes = on_device(w)
+    for tile in ((16, 16), (32, 8)):
+        for S in (1, 8, 32):
+            g = dgs.Renderer(tile=tile, states_per_group=S)
+            p = dgs.Renderer(tile=tile, states_per_group=S, persistent=True)
+            for c in (codes, codes[: max(1, codes.shape[0] // 3)].contiguous()):
+                gi, gt = g.render(scene, cam, c, w.basis, BG, tfinal=True)
+                pi, pt = p.render(scene, cam, c, w.basis, BG, tfinal=True)
+                assert torch.equal(pi, gi) and torch.equal(pt, gt), (tile, S, c.shape[0])
+                ref = gi[0].contiguous()
+                assert torch.equal(p.render_psnr(scene, cam, c, w.basis, ref, BG),
+                                   g.render_psnr(scene, cam, c, w.basis, ref, BG))
+            p.check()
+            assert p.composite_stats(scene, cam, codes, w.basis) == g.composite_stats(scene, cam, codes, w.basis)
+
+
 def test_state_permutation_and_masks(tiny):
     dgs = _dgs()
     w, _ = tiny
