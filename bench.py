@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-per-state", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-utility", action="store_true")
+    ap.add_argument("--utility", default="g1m_540p_utility_64groups_16contexts",
+                    help="counterfactual-utility workload timed beside the main metric")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true", help="time replays of one captured HIP graph")
     ap.add_argument("--tune", action="store_true", help="pick tile shape and states per group by timing")
@@ -70,6 +73,7 @@ def main():
 
     import synth
     import paper_2606_17212_amd as dgs
+    from paper_2606_17212_amd import profile_summary
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -144,9 +148,12 @@ def main():
     alpha_evals, blends, wave_evals, wave_miss = r.composite_stats(scene, cam, codes, w.basis)
     flops = FLOPS_PER_ALPHA * alpha_evals + FLOPS_PER_BLEND * blends
     achieved = flops / (comp_ms / 1e3) / 1e12
+    plan = r.launch_plan(cam, W)
+    kernel = f"k_composite<{plan['states_per_group']},{tw},{th},0,{'true' if plan['persistent'] else 'false'}>"
+    traffic = profile_summary.measured_traffic(kernel, args.workload, ROOT)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": f"k_composite<{args.states_per_group},{tw},{th},0>",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "kernel": kernel, "launch": plan,
                 "kernel_ms": round(comp_ms, 4), "alpha_evals": alpha_evals, "blends": blends,
                 "wave_alpha_evals": wave_evals, "wave_alpha_misses": wave_miss,
                 "flops_per_launch": flops}
@@ -186,16 +193,20 @@ def main():
     out["roofline"] = roofline
 
     if args.copy_mib > 0:
-        # a plain copy kernel of known size, for scaling FETCH_SIZE / WRITE_SIZE counters
+        # one streaming pass of known size (reads and writes the buffer once),
+        # for scaling FETCH_SIZE / WRITE_SIZE counters
         nbytes = args.copy_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)
+
+    if not args.no_utility:
+        out["utility"] = utility_bench(args, dgs, synth, torch, np, dev, tw, th)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, np, args.cpu_seconds)
@@ -309,6 +320,96 @@ def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
                        "max": round(float(np.max(p)), 3)}}
     print(json.dumps(out), flush=True)
     return 0
+
+
+def utility_bench(args, dgs, synth, torch, np, dev, tw, th):
+    """Counterfactual utility (Eq. (3)-(4)): one step = binning of the scene
+    + Delta_g(m) of every (group, context) pair by the paired incremental
+    renderer + the risk-adjusted utility of every group.  Compared with the
+    same deltas from full-frame renders of both states of every pair plus
+    the on-device distortion."""
+    uw = synth.make_utility_workload(args.utility)
+    w = uw.base
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    bg = tuple(float(x) for x in w.background)
+    ctx = torch.from_numpy(uw.codes).to(dev)
+    cg = torch.from_numpy(uw.context_group).to(dev)
+    gpl = torch.from_numpy(uw.group_pl.view(np.int16)).to(dev)
+    G, J = int(gpl.shape[0]), int(ctx.shape[0])
+    offsets = torch.from_numpy(np.searchsorted(uw.context_group, np.arange(G + 1)).astype(np.int32)).to(dev)
+    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch])
+    r.plan(scene, cam, w.basis, 512)
+    # the reference I: full delivery (code 4 = every layer of every packet)
+    ref = r.render(scene, cam, torch.full_like(ctx[:1], 4), w.basis, bg)[0].contiguous()
+    r.bin(scene, cam, w.basis)
+    items = r.utility_items(scene, cam, ctx, cg, gpl, w.basis)
+    delta = torch.empty(J, dtype=torch.float32, device=dev)
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        r.bin(scene, cam, w.basis)
+        if ev: ev[1].record()
+        r.utility(scene, cam, ctx, cg, gpl, w.basis, ref, bg, item_capacity=items, out=delta)
+        if ev: ev[2].record()
+        stats = dgs.risk_adjusted(delta, offsets)
+        if ev: ev[3].record()
+        return stats
+
+    for _ in range(2):
+        step()
+    r.utility_check()
+    torch.cuda.synchronize()
+    K = max(3, args.steps // 2)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    for k in range(K):
+        stats = step(evs[k])
+    torch.cuda.synchronize()
+    r.utility_check()
+    tot = float(np.median([e[0].elapsed_time(e[3]) for e in evs]))
+    t_bin = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    t_util = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    t_risk = float(np.median([e[2].elapsed_time(e[3]) for e in evs]))
+
+    # the same deltas from full-frame renders of both states of every pair
+    mg = uw.codes.copy()
+    p = (uw.group_pl >> 2).astype(np.int64)[uw.context_group]
+    mg[np.arange(J), p] = (uw.group_pl & 3).astype(np.uint8)[uw.context_group] + 1
+    mg = torch.from_numpy(mg).to(dev)
+    chunk = 256
+    imgs = torch.empty((2 * chunk, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+    full = torch.empty(J, dtype=torch.float64, device=dev)
+
+    def full_frame():
+        r.bin(scene, cam, w.basis)
+        for b in range(0, J, chunk):
+            e = min(J, b + chunk)
+            pair = torch.cat([ctx[b:e], mg[b:e]])
+            r.composite(scene, cam, pair, w.basis, bg, out=imgs[:2 * (e - b)])
+            d = dgs.distortion(imgs[:2 * (e - b)], ref).double()
+            full[b:e] = d[:e - b] - d[e - b:]
+
+    full_frame()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    full_frame()
+    e1.record()
+    torch.cuda.synchronize()
+    t_full = e0.elapsed_time(e1)
+    diff = float((delta.double() - full).abs().max())
+    st = stats.cpu().numpy()
+    log(f"[bench] utility {args.utility}: {G} groups x {J // G} contexts, {items} tile items; "
+        f"{tot:.3f} ms/step (bin {t_bin:.3f}, deltas {t_util:.3f}, Eq.4 {t_risk:.3f}) -> {J / (tot / 1e3):.0f} "
+        f"deltas/s; full-frame pairs {t_full:.2f} ms -> speedup {t_full / tot:.2f}x; max |diff| {diff:.2e}")
+    return {"workload": args.utility, "groups": G, "contexts": J, "tile_items": items,
+            "ms_per_step": round(tot, 4), "bin_ms": round(t_bin, 4), "delta_ms": round(t_util, 4),
+            "risk_ms": round(t_risk, 4), "deltas_per_s": round(J / (tot / 1e3), 1),
+            "paired_states_per_s": round(2 * J / (tot / 1e3), 1),
+            "full_frame_ms": round(t_full, 4), "speedup_vs_full_frame": round(t_full / tot, 3),
+            "max_abs_diff_vs_full_frame": diff,
+            "risk_adjusted": {"median": round(float(np.median(st[:, 3])), 8),
+                              "negative_groups": int((st[:, 3] < 0).sum())}}
 
 
 def cpu_baseline(w, np, seconds):

@@ -15,7 +15,8 @@
  *    pointers.  The caller owns all memory: scene, codes, images, gradients
  *    and the workspace.  The library allocates nothing on the render path.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Every call except
- *    dgs_count_instances and dgs_check is asynchronous on that stream:
+ *    dgs_count_instances, dgs_check, dgs_utility_count and
+ *    dgs_utility_check is asynchronous on that stream:
  *    device buffers must stay valid until the stream's work completes.
  *  - Return value: a dgs_status.  Arguments are validated before any HIP call;
  *    on failure nothing is launched and dgs_last_error() (thread-local)
@@ -200,6 +201,18 @@ int dgs_composite_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_
                        void *stream);
 
 /*
+ * How dgs_composite launches the batched compositing of `num_states` states
+ * with this camera and tuning (host query; the device that will run it must be
+ * current, for the occupancy query).  Outputs (host): *states_per_group = S
+ * used; *persistent = 1 for the persistent launch, 0 for the grid launch;
+ * *workgroups = workgroups launched; *work_items = (tile, state group) work
+ * items.  Returns DGS_OK, DGS_ERR_INVALID_ARG, DGS_ERR_UNSUPPORTED or
+ * DGS_ERR_HIP.
+ */
+int dgs_composite_launch(const dgs_camera *cam, const dgs_tuning *tun, int32_t num_states, int32_t *states_per_group,
+                         int32_t *persistent, int64_t *workgroups, int64_t *work_items);
+
+/*
  * Work counters of dgs_composite for the same arguments, nothing rendered:
  * counters (device, 4 x u64, overwritten) = { alpha evaluations: (pixel,
  * list entry, state group) triples where some delivered state of the group is
@@ -280,6 +293,100 @@ typedef struct {
 int dgs_workspace_sections(int32_t n, int32_t num_packets, const dgs_camera *cam,
                            const dgs_tuning *tun, int32_t max_states, int64_t instance_capacity,
                            dgs_workspace_view *out);
+
+/* ---------------------------------------------------------------------------
+ * Counterfactual render utility (Sec. 5).
+ *
+ * A completion group g = (packet p, layer l) is a packet's refinement layer;
+ * its marginal utility in a context m (Eq. (3)) is
+ *     Delta_g(m) = D(I, R(m)) - D(I, R(m u g)),
+ * where m holds packet p at prefix depth exactly l (layers 0..l-1 delivered,
+ * code l) and m u g holds it at depth l + 1 (code l + 1).  D is the
+ * distortion the paper fixes for its objective (Sec. 4):
+ *     D(I, X) = MSE(I, X) + lambda (1 - SSIM(I, X))     (lambda = 0.20 there)
+ * with MSE and SSIM averaged over every pixel and channel; SSIM uses the
+ * 11 x 11 Gaussian window (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, and zero
+ * padding outside the image.  The two renders differ only near g's Gaussians,
+ * so each context composites only the tiles of g's Gaussians plus a ring of
+ * tiles 10 pixels deep, both states at once.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Bytes of the utility workspace (caller-owned, 256-byte aligned, separate
+ * from the render workspace) for num_groups groups, num_contexts contexts
+ * and item_capacity work items (one item = one context x one tile of its
+ * group's region; dgs_utility_count gives the number needed).  0 for invalid
+ * arguments.  Host-only.
+ */
+size_t dgs_utility_workspace_bytes(int32_t num_packets, const dgs_camera *cam, const dgs_tuning *tun,
+                                   int32_t num_groups, int32_t num_contexts, int64_t item_capacity);
+
+/*
+ * Work items dgs_utility needs for these groups and contexts (synchronises).
+ * Arguments as for dgs_utility; the scene, camera, tuning and render
+ * workspace must be those of the last dgs_bin.  *items (host) = work items.
+ * Returns DGS_ERR_INVALID_ARG when a group names a packet outside the scene,
+ * two groups name the same (packet, layer), or a context does not hold its
+ * group's packet at exactly the group's layer.
+ */
+int dgs_utility_count(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *contexts,
+                      const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t instance_capacity,
+                      const int32_t *context_group, const uint16_t *group_pl, int32_t num_groups,
+                      void *uws, size_t uws_bytes, int64_t *items, void *stream);
+
+/*
+ * Eq. (3) for every context, from the per-tile lists of the last dgs_bin of
+ * this scene, camera and tuning in `ws`.
+ *   contexts       codes u8 [J][P] (device) = the contexts m; basis and
+ *                  background as for dgs_render
+ *   context_group  i32 [J] (device): the group of each context
+ *   group_pl       u16 [G] (device): (packet << 2) | layer of each group
+ *   reference      f32 [H][W][3] (device): the image I
+ *   lambda         weight of (1 - SSIM) in D
+ *   uws            utility workspace of dgs_utility_workspace_bytes(...,
+ *                  item_capacity)
+ *   delta          f32 [J] (device, written): Delta_g(m); NaN for an invalid
+ *                  context and for every context after an item overflow
+ * Asynchronous; dgs_utility_check reports invalid groups or contexts and
+ * overflow.
+ */
+int dgs_utility(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *contexts,
+                const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t instance_capacity,
+                const int32_t *context_group, const uint16_t *group_pl, int32_t num_groups,
+                const float *reference, float lambda, void *uws, size_t uws_bytes,
+                int64_t item_capacity, float *delta, void *stream);
+
+/*
+ * Status of the last dgs_utility on `uws` (synchronises): DGS_OK,
+ * DGS_ERR_INVALID_ARG (as for dgs_utility_count) or DGS_ERR_OVERFLOW (more
+ * work items than item_capacity).  *items (host, may be NULL) = items needed.
+ */
+int dgs_utility_check(void *uws, size_t uws_bytes, int64_t item_capacity, int64_t *items, void *stream);
+
+/*
+ * D(I, X) = MSE + lambda (1 - SSIM) of each of num_images images X
+ * [num_images][H][W][3] (device) against reference I [H][W][3] (device), as
+ * defined above; d f32 [num_images] (device, written).  scratch (device,
+ * 8-byte aligned) of dgs_distortion_scratch_bytes() bytes.  Asynchronous.
+ */
+size_t dgs_distortion_scratch_bytes(int32_t num_images, int32_t width, int32_t height);
+int dgs_distortion(const float *images, int32_t num_images, int32_t width, int32_t height,
+                   const float *reference, float lambda, void *scratch, size_t scratch_bytes, float *d,
+                   void *stream);
+
+/*
+ * Risk-adjusted utility, Eq. (4), per group:
+ *     ((1 - alpha) E[Delta] + alpha Q_q(Delta)) / (1 + beta Std(Delta))
+ * over the values of group k = values[offsets[k] .. offsets[k+1]) (device
+ * f32 / i32 [G+1]; 1..4096 values per group).  The quantile interpolates
+ * linearly between order statistics at position (n - 1) q; Std is the
+ * population standard deviation.  out f32 [G][4] (device, written) = (mean,
+ * quantile, std, risk-adjusted); all NaN for a group with a NaN value or a
+ * count outside 1..4096.  The paper uses alpha = 0.25, beta = 0.05,
+ * q = 0.10.  Asynchronous.
+ */
+int dgs_risk_adjusted(const float *values, const int32_t *offsets, int32_t num_groups, float alpha,
+                      float beta, float quantile, float *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -6,6 +6,7 @@ under many incomplete delivery states in one batched launch, forward and
 backward, through the hand-written HIP kernels of ``libdgs.so``.
 """
 
-from .render import CapturedRender, Camera, GaussianScene, Renderer, RenderFunction, render  # noqa: F401
+from .render import (CapturedRender, Camera, GaussianScene, Renderer, RenderFunction, distortion,  # noqa: F401
+                     render, risk_adjusted)
 from .autotune import Autotuner  # noqa: F401
 from ._abi import DgsError, lib  # noqa: F401

@@ -20,7 +20,9 @@ EXPORTS = (
     "dgs_abi_version", "dgs_status_string", "dgs_last_error", "dgs_workspace_bytes",
     "dgs_count_instances", "dgs_render", "dgs_render_per_state", "dgs_render_psnr",
     "dgs_backward", "dgs_check", "dgs_workspace_sections", "dgs_bin", "dgs_composite",
-    "dgs_composite_psnr", "dgs_composite_stats",
+    "dgs_composite_psnr", "dgs_composite_stats", "dgs_composite_launch", "dgs_utility_workspace_bytes",
+    "dgs_utility_count", "dgs_utility", "dgs_utility_check", "dgs_distortion_scratch_bytes", "dgs_distortion",
+    "dgs_risk_adjusted",
 )
 
 
@@ -98,6 +100,8 @@ def lib():
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = common + [i64, vp, vp, vp]
+    L.dgs_composite_launch.restype = ctypes.c_int
+    L.dgs_composite_launch.argtypes = [P(Camera), P(Tuning), i32, P(i32), P(i32), P(i64), P(i64)]
     L.dgs_bin.restype = ctypes.c_int
     L.dgs_bin.argtypes = common + [i64, vp]
     L.dgs_composite.restype = ctypes.c_int
@@ -114,6 +118,21 @@ def lib():
     L.dgs_check.argtypes = [vp, sz, P(i64), vp]
     L.dgs_workspace_sections.restype = ctypes.c_int
     L.dgs_workspace_sections.argtypes = [i32, i32, P(Camera), P(Tuning), i32, i64, P(WorkspaceView)]
+    fp = ctypes.c_float
+    L.dgs_utility_workspace_bytes.restype = sz
+    L.dgs_utility_workspace_bytes.argtypes = [i32, P(Camera), P(Tuning), i32, i32, i64]
+    L.dgs_utility_count.restype = ctypes.c_int
+    L.dgs_utility_count.argtypes = common + [i64, vp, vp, i32, vp, sz, P(i64), vp]
+    L.dgs_utility.restype = ctypes.c_int
+    L.dgs_utility.argtypes = common + [i64, vp, vp, i32, vp, fp, vp, sz, i64, vp, vp]
+    L.dgs_utility_check.restype = ctypes.c_int
+    L.dgs_utility_check.argtypes = [vp, sz, i64, P(i64), vp]
+    L.dgs_distortion_scratch_bytes.restype = sz
+    L.dgs_distortion_scratch_bytes.argtypes = [i32, i32, i32]
+    L.dgs_distortion.restype = ctypes.c_int
+    L.dgs_distortion.argtypes = [vp, i32, i32, i32, vp, fp, vp, sz, vp, vp]
+    L.dgs_risk_adjusted.restype = ctypes.c_int
+    L.dgs_risk_adjusted.argtypes = [vp, vp, i32, fp, fp, fp, vp, vp]
     _lib = L
     return L
 

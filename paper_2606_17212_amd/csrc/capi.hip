@@ -216,6 +216,12 @@ const uint32_t *sorted_vals(const Call &cl, void *ws) {
   return (passes & 1) ? at<uint32_t>(ws, cl.L.tval1) : at<uint32_t>(ws, cl.L.tval0);
 }
 
+// 0 automatic, 1 persistent, 2 grid (validated by check_tuning)
+int launch_kind(const dgs_tuning *tun) {
+  if (!tun) return 0;
+  return (tun->flags & DGS_TUNE_PERSISTENT) ? 1 : (tun->flags & DGS_TUNE_GRID) ? 2 : 0;
+}
+
 int group_size(const dgs_tuning *tun, int W, int max_s) {
   int S = (tun && tun->states_per_group) ? tun->states_per_group : 16;
   if (S < 1) S = 1;
@@ -249,6 +255,84 @@ CompositeArgs composite_args(const Call &cl, void *ws, const uint32_t *vals, con
   a.groups = groups;
   for (int k = 0; k < 3; ++k) a.bg[k] = states->background[k];
   return a;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus > 0 ? cus : 256;
+}
+
+// Validation and argument set-up shared by dgs_utility_count and dgs_utility.
+int utility_prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *contexts,
+                    const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, const int32_t *context_group,
+                    const uint16_t *group_pl, int32_t num_groups, void *uws, size_t uws_bytes,
+                    int64_t item_capacity, Call *cl, UtilArgs *u) {
+  // the render workspace is read only in its state-independent sections
+  if (!contexts) return fail(DGS_ERR_INVALID_ARG, "contexts is NULL");
+  dgs_states none = *contexts;
+  none.num_states = 0;
+  int rc = prepare(scene, cam, &none, tun, ws, ws_bytes, cap, 0, cl);
+  if (rc) return rc;
+  if ((rc = check_states(contexts, cl->P, 1))) return rc;
+  if (num_groups < 1 || num_groups > 1 << 20) return fail(DGS_ERR_INVALID_ARG, "num_groups %d outside 1..2^20", num_groups);
+  if (!group_pl) return fail(DGS_ERR_INVALID_ARG, "group_pl is NULL");
+  if (contexts->num_states > 0 && !context_group) return fail(DGS_ERR_INVALID_ARG, "context_group is NULL");
+  if (contexts->num_states > (1 << 24)) return fail(DGS_ERR_INVALID_ARG, "more than 2^24 contexts");
+  if (item_capacity < 0 || item_capacity > (int64_t)0x7FFFFFFFll)
+    return fail(DGS_ERR_INVALID_ARG, "item capacity %lld outside 0..2^31-1", (long long)item_capacity);
+  if (!uws) return fail(DGS_ERR_INVALID_ARG, "utility workspace is NULL");
+  if (((uintptr_t)uws) & 255u) return fail(DGS_ERR_INVALID_ARG, "utility workspace not 256-byte aligned");
+  const UtilLayout U = make_util_layout(cl->P, cl->tiling.tiles, num_groups, contexts->num_states, item_capacity);
+  if (uws_bytes < U.total)
+    return fail(DGS_ERR_WORKSPACE, "utility workspace %zu bytes < %zu needed", uws_bytes, U.total);
+  *u = UtilArgs{};
+  u->hdr = at<UtilHeader>(uws, U.hdr);
+  u->pl2g = at<int>(uws, U.pl2g);
+  u->core = at<uint32_t>(uws, U.core);
+  u->region = at<uint32_t>(uws, U.region);
+  u->wcount = at<uint32_t>(uws, U.wcount);
+  u->wprefix = at<uint32_t>(uws, U.wprefix);
+  u->region_tiles = at<uint32_t>(uws, U.region_tiles);
+  u->group_base = at<uint32_t>(uws, U.group_base);
+  u->icount = at<uint32_t>(uws, U.icount);
+  u->item_base = at<uint32_t>(uws, U.item_base);
+  u->bad = at<uint32_t>(uws, U.bad);
+  u->pvis = at<uint32_t>(uws, U.pvis);
+  u->parts = at<unsigned long long>(uws, U.parts);
+  u->partial = at<float>(uws, U.partial);
+  u->patches = at<float>(uws, U.patches);
+  u->item_total = &u->hdr->items;
+  u->queue = u->hdr->queue;
+  u->item_capacity = (uint64_t)item_capacity;
+  u->num_contexts = contexts->num_states;
+  u->words = (int)U.words;
+  u->tiles_x = cl->tiling.tiles_x;
+  u->tiles_y = cl->tiling.tiles_y;
+  u->width = cl->c.width;
+  u->height = cl->c.height;
+  u->context_group = context_group;
+  return DGS_OK;
+}
+
+// Group tables, regions and per-context work items (from the last dgs_bin).
+void utility_setup(const Call &cl, void *ws, const UtilArgs &u, const dgs_states *contexts, const uint16_t *group_pl,
+                   int G, hipStream_t st) {
+  launch_clear_util_header(u.hdr, st);
+  const int rx = (10 + cl.tiling.tw - 1) / cl.tiling.tw, ry = (10 + cl.tiling.th - 1) / cl.tiling.th;
+  launch_group_setup(u, group_pl, G, cl.P, at<float4>(ws, cl.L.rec0), at<uint2>(ws, cl.L.rect), cl.s.n, rx, ry, st);
+  if (u.num_contexts > 0) launch_pair_setup(u, contexts->codes, group_pl, G, cl.P, st);
+}
+
+int utility_status(const UtilHeader &h, int64_t item_capacity) {
+  if (h.bad_group & 1u) return fail(DGS_ERR_INVALID_ARG, "a group names a packet outside the scene");
+  if (h.bad_group & 2u) return fail(DGS_ERR_INVALID_ARG, "two groups name the same (packet, layer)");
+  if (h.bad_context)
+    return fail(DGS_ERR_INVALID_ARG, "a context does not hold its group's packet at exactly the group's layer");
+  if ((int64_t)h.items > item_capacity)
+    return fail(DGS_ERR_OVERFLOW, "%llu work items exceed capacity %lld", h.items, (long long)item_capacity);
+  return DGS_OK;
 }
 
 }  // namespace
@@ -353,8 +437,7 @@ int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_stat
   a.psnr_part = at<float>(ws, cl.L.psnr_part);
   a.counters = counters;
   a.queues = at<unsigned int>(ws, cl.L.queues);
-  const int launch = !tun ? 0 : (tun->flags & DGS_TUNE_PERSISTENT) ? 1 : (tun->flags & DGS_TUNE_GRID) ? 2 : 0;
-  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, launch, st))
+  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, launch_kind(tun), st))
     return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
   if (mode == 1)
     launch_psnr_finalize(a.psnr_part, W, cl.tiling.tiles, (int64_t)cl.c.width * cl.c.height, psnr, st);
@@ -523,6 +606,26 @@ int dgs_workspace_sections(int32_t n, int32_t num_packets, const dgs_camera *cam
   return DGS_OK;
 }
 
+int dgs_composite_launch(const dgs_camera *cam, const dgs_tuning *tun, int32_t num_states, int32_t *states_per_group,
+                         int32_t *persistent, int64_t *workgroups, int64_t *work_items) {
+  g_err.clear();
+  Tiling t;
+  int rc;
+  if (!states_per_group || !persistent || !workgroups || !work_items)
+    return fail(DGS_ERR_INVALID_ARG, "output pointer is NULL");
+  if (num_states < 0) return fail(DGS_ERR_INVALID_ARG, "num_states < 0");
+  if ((rc = check_camera(cam)) || (rc = check_tuning(cam, tun, &t))) return rc;
+  const int S = group_size(tun, num_states, 32);
+  CompositePlan p;
+  if (plan_composite(S, t.tw, t.th, t.tiles, (num_states + S - 1) / S, launch_kind(tun), &p))
+    return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
+  *states_per_group = S;
+  *persistent = p.persistent ? 1 : 0;
+  *workgroups = p.workgroups;
+  *work_items = p.items;
+  return hip_check("occupancy query");
+}
+
 int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream) {
   g_err.clear();
   if (!ws || ws_bytes < sizeof(Header)) return fail(DGS_ERR_INVALID_ARG, "workspace missing");
@@ -535,6 +638,124 @@ int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream) {
   if (hh.overflow)
     return fail(DGS_ERR_OVERFLOW, "%llu instances exceed capacity %llu", hh.instances, hh.capacity);
   return hip_check("check");
+}
+
+size_t dgs_utility_workspace_bytes(int32_t num_packets, const dgs_camera *cam, const dgs_tuning *tun,
+                                   int32_t num_groups, int32_t num_contexts, int64_t item_capacity) {
+  g_err.clear();
+  Tiling t;
+  if (num_packets < 1 || num_packets > 16384 || num_groups < 1 || num_groups > 1 << 20 || num_contexts < 0 ||
+      num_contexts > (1 << 24) || item_capacity < 0 || item_capacity > (int64_t)0x7FFFFFFFll)
+    return 0;
+  if (check_camera(cam) || check_tuning(cam, tun, &t)) return 0;
+  return make_util_layout(num_packets, t.tiles, num_groups, num_contexts, item_capacity).total;
+}
+
+int dgs_utility_count(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *contexts,
+                      const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, const int32_t *context_group,
+                      const uint16_t *group_pl, int32_t num_groups, void *uws, size_t uws_bytes, int64_t *items,
+                      void *stream) {
+  g_err.clear();
+  if (!items) return fail(DGS_ERR_INVALID_ARG, "items is NULL");
+  Call cl;
+  UtilArgs u;
+  int rc = utility_prepare(scene, cam, contexts, tun, ws, ws_bytes, cap, context_group, group_pl, num_groups, uws,
+                           uws_bytes, 0, &cl, &u);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  utility_setup(cl, ws, u, contexts, group_pl, num_groups, st);
+  UtilHeader h;
+  if (hipMemcpyAsync(&h, u.hdr, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return hip_check("utility count");
+  *items = (int64_t)h.items;
+  if ((rc = utility_status(h, INT64_MAX))) return rc;
+  return hip_check("utility count");
+}
+
+int dgs_utility(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *contexts, const dgs_tuning *tun,
+                void *ws, size_t ws_bytes, int64_t cap, const int32_t *context_group, const uint16_t *group_pl,
+                int32_t num_groups, const float *reference, float lambda, void *uws, size_t uws_bytes,
+                int64_t item_capacity, float *delta, void *stream) {
+  g_err.clear();
+  Call cl;
+  UtilArgs u;
+  int rc = utility_prepare(scene, cam, contexts, tun, ws, ws_bytes, cap, context_group, group_pl, num_groups, uws,
+                           uws_bytes, item_capacity, &cl, &u);
+  if (rc) return rc;
+  if (contexts->num_states > 0 && (!reference || !delta))
+    return fail(DGS_ERR_INVALID_ARG, "reference / delta is NULL");
+  if (!isfinite(lambda)) return fail(DGS_ERR_INVALID_ARG, "lambda not finite");
+  if (contexts->num_states == 0) return DGS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  u.reference = reference;
+  u.lambda = lambda;
+  u.delta = delta;
+  utility_setup(cl, ws, u, contexts, group_pl, num_groups, st);
+  CompositeArgs a = composite_args(cl, ws, sorted_vals(cl, ws), contexts, u.pvis, 1);
+  a.image = u.patches;
+  a.queues = u.queue;
+  a.pair.item_total = u.item_total;
+  a.pair.item_capacity = u.item_capacity;
+  a.pair.num_contexts = u.num_contexts;
+  a.pair.item_base = u.item_base;
+  a.pair.context_group = context_group;
+  a.pair.group_base = u.group_base;
+  a.pair.region_tiles = u.region_tiles;
+  const int cus = device_cus();
+  if (launch_composite_pairs(a, cl.tiling.tw, cl.tiling.th, cus * 8, st))
+    return fail(DGS_ERR_UNSUPPORTED, "no pair compositing variant for this tile shape");
+  if (launch_pair_ssim(u, cl.tiling.tw, cl.tiling.th, cus * 4, st))
+    return fail(DGS_ERR_UNSUPPORTED, "no pair SSIM variant for this tile shape");
+  return hip_check("utility launch");
+}
+
+int dgs_utility_check(void *uws, size_t uws_bytes, int64_t item_capacity, int64_t *items, void *stream) {
+  g_err.clear();
+  if (!uws || uws_bytes < sizeof(UtilHeader)) return fail(DGS_ERR_INVALID_ARG, "utility workspace missing");
+  hipStream_t st = (hipStream_t)stream;
+  UtilHeader h;
+  if (hipMemcpyAsync(&h, uws, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return hip_check("utility check copy");
+  if (items) *items = (int64_t)h.items;
+  int rc = utility_status(h, item_capacity);
+  if (rc) return rc;
+  return hip_check("utility check");
+}
+
+size_t dgs_distortion_scratch_bytes(int32_t num_images, int32_t width, int32_t height) {
+  if (num_images < 0 || width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
+  return (size_t)num_images * (size_t)ceil_div(width, 16) * (size_t)ceil_div(height, 16) * 2 * sizeof(double) + 8;
+}
+
+int dgs_distortion(const float *images, int32_t num_images, int32_t width, int32_t height, const float *reference,
+                   float lambda, void *scratch, size_t scratch_bytes, float *d, void *stream) {
+  g_err.clear();
+  if (num_images < 0 || width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(DGS_ERR_INVALID_ARG, "sizes out of range");
+  if (num_images == 0) return DGS_OK;
+  if (!images || !reference || !d || !scratch) return fail(DGS_ERR_INVALID_ARG, "pointer is NULL");
+  if (((uintptr_t)scratch) & 7u) return fail(DGS_ERR_INVALID_ARG, "scratch not 8-byte aligned");
+  if (!isfinite(lambda)) return fail(DGS_ERR_INVALID_ARG, "lambda not finite");
+  if (scratch_bytes < dgs_distortion_scratch_bytes(num_images, width, height))
+    return fail(DGS_ERR_WORKSPACE, "scratch %zu bytes < %zu needed", scratch_bytes,
+                dgs_distortion_scratch_bytes(num_images, width, height));
+  if (num_images > 65535) return fail(DGS_ERR_INVALID_ARG, "more than 65535 images per call");
+  launch_distortion(images, num_images, width, height, reference, lambda, (double *)scratch, d, (hipStream_t)stream);
+  return hip_check("distortion launch");
+}
+
+int dgs_risk_adjusted(const float *values, const int32_t *offsets, int32_t num_groups, float alpha, float beta,
+                      float quantile, float *out, void *stream) {
+  g_err.clear();
+  if (num_groups < 0) return fail(DGS_ERR_INVALID_ARG, "num_groups < 0");
+  if (num_groups == 0) return DGS_OK;
+  if (!values || !offsets || !out) return fail(DGS_ERR_INVALID_ARG, "pointer is NULL");
+  if (!isfinite(alpha) || !isfinite(beta) || !(quantile >= 0.0f && quantile <= 1.0f))
+    return fail(DGS_ERR_INVALID_ARG, "alpha / beta not finite or quantile outside [0, 1]");
+  launch_risk_adjusted(values, offsets, num_groups, alpha, beta, quantile, out, (hipStream_t)stream);
+  return hip_check("risk launch");
 }
 
 }  // extern "C"

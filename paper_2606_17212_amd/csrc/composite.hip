@@ -102,10 +102,13 @@ __device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, c
 template <int S>
 constexpr int waves_per_eu() { return S <= 8 ? 8 : (S <= 16 ? 5 : 2); }
 
+// Composites one tile for the S states of one group.  `vis` holds the
+// group's delivery bits per (packet, layer); `grp` indexes the outputs (the
+// state group, or in pair mode the work item).
 template <int S, int TW, int TH, int MODE>
-__device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st, int kpos, int grp) {
+__device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st, int tile, int grp,
+                                               const uint32_t *vis) {
   static_assert(TW * TH == kBlock, "one pixel per thread");
-  const int tile = (int)a.tile_order[kpos];
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int tpx = tx * TW, tpy = ty * TH;
@@ -121,7 +124,6 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
   }
 
   const uint2 rg = a.ranges[tile];
-  const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
   uint32_t n_alpha = 0, n_blend = 0, n_wave_alpha = 0, n_wave_miss = 0;  // MODE 2 only
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
     int alive = 0;
@@ -131,37 +133,48 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
     const uint32_t e = b0 + tid;
     if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
     __syncthreads();
-    const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
+    // entries of this batch; wave-uniform, kept in scalar registers
+    const int cnt = __builtin_amdgcn_readfirstlane(
+        (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock));
     uint32_t wave_alive = 0;
-    for (int k = 0; k < cnt; ++k) {
-      if ((k & 63) == 0) {  // states still compositing some pixel of this wave
+    // four entries per step: one 16-byte read of their delivery bits and
+    // constant offsets from one record address
+    for (int k0 = 0; k0 < cnt; k0 += 4) {
+      if ((k0 & 63) == 0) {  // states still compositing some pixel of this wave
         wave_alive = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s)
           if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
       }
-      const uint32_t uv = __builtin_amdgcn_readfirstlane(st.vis[wv][k]) & wave_alive;
-      if (uv == 0u) continue;
-      if (MODE == 2) {
-        uint32_t lane_alive = 0;
+      const uint4 v4 = *reinterpret_cast<const uint4 *>(&st.vis[wv][k0]);
+      const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
+      const StageRec *rp = &st.rec[k0];
 #pragma unroll
-        for (int s = 0; s < S; ++s) lane_alive |= (T[s] > 0.0f ? 1u : 0u) << s;
-        n_alpha += (uv & lane_alive) ? 1u : 0u;
-      }
-      const float q = splat_q(st.rec[k].p0, st.rec[k].p1, fpx, fpy);
-      if (MODE == 2 && lane == 0) {
-        ++n_wave_alpha;
-        n_wave_miss += __ballot(q >= kQSkip) == 0ull ? 1u : 0u;
-      }
-      if (q < kQSkip) continue;
-      const float alpha = alpha_of(q);
-      const float4 C = st.rec[k].col;
+      for (int j = 0; j < 4; ++j) {
+        if (k0 + j >= cnt) break;
+        const uint32_t uv = __builtin_amdgcn_readfirstlane(vv[j]) & wave_alive;
+        if (uv == 0u) continue;
+        if (MODE == 2) {
+          uint32_t lane_alive = 0;
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        if (uv & (1u << s)) {
-          if (MODE == 2) n_blend += T[s] > 0.0f ? 1u : 0u;
-          blend(T[s], cr[s], cg[s], cb[s], alpha, C.x, C.y, C.z);
+          for (int s = 0; s < S; ++s) lane_alive |= (T[s] > 0.0f ? 1u : 0u) << s;
+          n_alpha += (uv & lane_alive) ? 1u : 0u;
         }
+        const float q = splat_q(rp[j].p0, rp[j].p1, fpx, fpy);
+        if (MODE == 2 && lane == 0) {
+          ++n_wave_alpha;
+          n_wave_miss += __ballot(q >= kQSkip) == 0ull ? 1u : 0u;
+        }
+        if (q < kQSkip) continue;
+        const float alpha = alpha_of(q);
+        const float4 C = rp[j].col;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (uv & (1u << s)) {
+            if (MODE == 2) n_blend += T[s] > 0.0f ? 1u : 0u;
+            blend(T[s], cr[s], cg[s], cb[s], alpha, C.x, C.y, C.z);
+          }
+      }
     }
     __syncthreads();
   }
@@ -179,6 +192,20 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
       atomicAdd(a.counters + 1, c1);
       atomicAdd(a.counters + 2, (unsigned long long)n_wave_alpha);
       atomicAdd(a.counters + 3, (unsigned long long)n_wave_miss);
+    }
+    return;
+  }
+
+  if (MODE == 3) {
+    // pair mode: the tile's pixels of both states into the work item's patch
+    if (!inside) return;
+    float *o = a.image + ((int64_t)grp * S * kBlock + (int64_t)(py - tpy) * TW + (px - tpx)) * 3;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float Tf = fabsf(T[s]);
+      o[(int64_t)s * kBlock * 3 + 0] = fmaf(Tf, a.bg[0], cr[s]);
+      o[(int64_t)s * kBlock * 3 + 1] = fmaf(Tf, a.bg[1], cg[s]);
+      o[(int64_t)s * kBlock * 3 + 2] = fmaf(Tf, a.bg[2], cb[s]);
     }
     return;
   }
@@ -244,7 +271,9 @@ k_composite(CompositeArgs a) {
   const int tiles = a.tiles_x * a.tiles_y;
   int kpos, grp;
   if (!PERSISTENT) {
-    if (work_item(blockIdx.x, a.groups, tiles, kpos, grp)) composite_item<S, TW, TH, MODE>(a, st, kpos, grp);
+    if (work_item(blockIdx.x, a.groups, tiles, kpos, grp))
+      composite_item<S, TW, TH, MODE>(a, st, (int)a.tile_order[kpos], grp,
+                                      a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr);
     return;
   }
   __shared__ int s_item;
@@ -270,9 +299,54 @@ k_composite(CompositeArgs a) {
     __syncthreads();
     if (L < 0) break;
     work_item(L, a.groups, tiles, kpos, grp);
-    composite_item<S, TW, TH, MODE>(a, st, kpos, grp);
+    composite_item<S, TW, TH, MODE>(a, st, (int)a.tile_order[kpos], grp,
+                                    a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr);
     __syncthreads();  // the stage is reused by the next item
   }
+}
+
+// Paired states of the counterfactual utility: each work item is (context j,
+// slot of a tile in the region of j's completion group); both states (the
+// context m and m u g) are composited together as one S = 2 group and written
+// to the item's patch.  Resident workgroups take items from one queue.
+template <int TW, int TH>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_composite_pairs(CompositeArgs a) {
+  __shared__ Stage st;
+  __shared__ int s_item;
+  // after an overflow nothing is composited (every delta becomes NaN)
+  const unsigned long long total = *a.pair.item_total;
+  const uint32_t n_items = total <= a.pair.item_capacity ? (uint32_t)total : 0u;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(a.queues, 1u);
+    __syncthreads();
+    const uint32_t item = (uint32_t)s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    // context of the item: the last j with item_base[j] <= item
+    int lo = 0, hi = a.pair.num_contexts - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.pair.item_base[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const int j = lo;
+    const int g = a.pair.context_group[j];
+    const int tile = (int)a.pair.region_tiles[a.pair.group_base[g] + (item - a.pair.item_base[j])];
+    composite_item<2, TW, TH, 3>(a, st, tile, (int)item, a.visbits + (int64_t)j * a.P4);
+    __syncthreads();
+  }
+}
+
+int launch_composite_pairs(const CompositeArgs &a, int tile_w, int tile_h, int workgroups, hipStream_t st) {
+  if (workgroups <= 0) return 0;
+  launch_zero_queues(a.queues, st);
+  if (tile_w == 16 && tile_h == 16)
+    k_composite_pairs<16, 16><<<workgroups, kBlock, 0, st>>>(a);
+  else if (tile_w == 32 && tile_h == 8)
+    k_composite_pairs<32, 8><<<workgroups, kBlock, 0, st>>>(a);
+  else
+    return 1;
+  return 0;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -457,10 +531,10 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
 // many waves of workgroups (per-workgroup launch cost dominates the saving).
 constexpr int kPersistentItemsPerSlot = 32;
 
+// Resident workgroups of the persistent kernel, cached per instantiation
+// (host-side queries only, so a launch can be captured in a graph).
 template <int S, int TW, int TH, int MODE>
-static void launch_fwd_m(const CompositeArgs &a, int launch, unsigned blocks, hipStream_t st) {
-  // resident workgroups of the persistent kernel, cached per instantiation
-  // (host-side queries only, so the launch can be captured in a graph)
+static int resident_slots() {
   static int resident = 0;
   if (!resident) {
     int dev = 0, cus = 0, per_cu = 0;
@@ -469,48 +543,85 @@ static void launch_fwd_m(const CompositeArgs &a, int launch, unsigned blocks, hi
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_composite<S, TW, TH, MODE, true>, kBlock, 0);
     resident = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
   }
-  const bool persistent = launch == 1 || (launch == 0 && (int64_t)blocks >= (int64_t)kPersistentItemsPerSlot * resident);
-  if (!persistent) {
-    k_composite<S, TW, TH, MODE, false><<<blocks, kBlock, 0, st>>>(a);
+  return resident;
+}
+
+template <int S, int TW, int TH, int MODE>
+static CompositePlan plan_fwd_m(int launch, int64_t items) {
+  const int64_t resident = resident_slots<S, TW, TH, MODE>();
+  CompositePlan p;
+  p.items = items;
+  p.persistent = launch == 1 || (launch == 0 && items >= kPersistentItemsPerSlot * resident);
+  p.workgroups = p.persistent ? (resident < items ? resident : items) : items;
+  return p;
+}
+
+template <int S, int TW, int TH, int MODE>
+static void launch_fwd_m(const CompositeArgs &a, int launch, int64_t items, hipStream_t st) {
+  const CompositePlan p = plan_fwd_m<S, TW, TH, MODE>(launch, items);
+  if (!p.persistent) {
+    k_composite<S, TW, TH, MODE, false><<<(unsigned)p.workgroups, kBlock, 0, st>>>(a);
     return;
   }
-  const unsigned grid = (unsigned)(resident < (int)blocks ? resident : (int)blocks);
   launch_zero_queues(a.queues, st);
-  k_composite<S, TW, TH, MODE, true><<<grid, kBlock, 0, st>>>(a);
+  k_composite<S, TW, TH, MODE, true><<<(unsigned)p.workgroups, kBlock, 0, st>>>(a);
 }
 
-template <int S, int TW, int TH>
-static void launch_fwd_t(const CompositeArgs &a, int mode, int persistent, unsigned blocks, hipStream_t st) {
-  if (mode == 0)
-    launch_fwd_m<S, TW, TH, 0>(a, persistent, blocks, st);
-  else if (mode == 1)
-    launch_fwd_m<S, TW, TH, 1>(a, persistent, blocks, st);
-  else
-    launch_fwd_m<S, TW, TH, 2>(a, persistent, blocks, st);
-}
-
-template <int TW, int TH>
-static int launch_fwd_s(const CompositeArgs &a, int S, int mode, int pers, unsigned blocks, hipStream_t st) {
+// Calls F::run<S, TW, TH, MODE>(args...) for the runtime shape; false if unsupported.
+template <typename F, int TW, int TH, int MODE, typename... A>
+static bool dispatch_s(int S, A &&...args) {
   switch (S) {
-    case 1: launch_fwd_t<1, TW, TH>(a, mode, pers, blocks, st); return 0;
-    case 2: launch_fwd_t<2, TW, TH>(a, mode, pers, blocks, st); return 0;
-    case 4: launch_fwd_t<4, TW, TH>(a, mode, pers, blocks, st); return 0;
-    case 8: launch_fwd_t<8, TW, TH>(a, mode, pers, blocks, st); return 0;
-    case 16: launch_fwd_t<16, TW, TH>(a, mode, pers, blocks, st); return 0;
-    case 32: launch_fwd_t<32, TW, TH>(a, mode, pers, blocks, st); return 0;
-    default: return 1;
+    case 1: F::template run<1, TW, TH, MODE>(args...); return true;
+    case 2: F::template run<2, TW, TH, MODE>(args...); return true;
+    case 4: F::template run<4, TW, TH, MODE>(args...); return true;
+    case 8: F::template run<8, TW, TH, MODE>(args...); return true;
+    case 16: F::template run<16, TW, TH, MODE>(args...); return true;
+    case 32: F::template run<32, TW, TH, MODE>(args...); return true;
+    default: return false;
   }
 }
 
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int persistent,
+template <typename F, int TW, int TH, typename... A>
+static bool dispatch_m(int S, int mode, A &&...args) {
+  if (mode == 0) return dispatch_s<F, TW, TH, 0>(S, args...);
+  if (mode == 1) return dispatch_s<F, TW, TH, 1>(S, args...);
+  return dispatch_s<F, TW, TH, 2>(S, args...);
+}
+
+template <typename F, typename... A>
+static bool dispatch_shape(int S, int tile_w, int tile_h, int mode, A &&...args) {
+  if (tile_w == 16 && tile_h == 16) return dispatch_m<F, 16, 16>(S, mode, args...);
+  if (tile_w == 32 && tile_h == 8) return dispatch_m<F, 32, 8>(S, mode, args...);
+  return false;
+}
+
+struct LaunchFwd {
+  template <int S, int TW, int TH, int MODE>
+  static void run(const CompositeArgs &a, int launch, int64_t items, hipStream_t st) {
+    launch_fwd_m<S, TW, TH, MODE>(a, launch, items, st);
+  }
+};
+
+struct PlanFwd {
+  template <int S, int TW, int TH, int MODE>
+  static void run(int launch, int64_t items, CompositePlan *out) {
+    *out = plan_fwd_m<S, TW, TH, MODE>(launch, items);
+  }
+};
+
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch,
                      hipStream_t st) {
-  const int64_t total = work_items(a.tiles_x * a.tiles_y, a.groups);
-  if (total <= 0) return 0;
-  const unsigned blocks = (unsigned)total;
-  if (persistent != 2 && !a.queues) return 1;
-  if (tile_w == 16 && tile_h == 16) return launch_fwd_s<16, 16>(a, S, mode, persistent, blocks, st);
-  if (tile_w == 32 && tile_h == 8) return launch_fwd_s<32, 8>(a, S, mode, persistent, blocks, st);
-  return 1;
+  const int64_t items = work_items(a.tiles_x * a.tiles_y, a.groups);
+  if (items <= 0) return 0;
+  if (launch != 2 && !a.queues) return 1;
+  return dispatch_shape<LaunchFwd>(S, tile_w, tile_h, mode, a, launch, items, st) ? 0 : 1;
+}
+
+int plan_composite(int S, int tile_w, int tile_h, int tiles, int groups, int launch, CompositePlan *out) {
+  const int64_t items = work_items(tiles, groups);
+  *out = CompositePlan{false, 0, 0};
+  if (items <= 0) return 0;
+  return dispatch_shape<PlanFwd>(S, tile_w, tile_h, 0, launch, items, out) ? 0 : 1;
 }
 
 template <int TW, int TH>

@@ -71,12 +71,32 @@ struct CompositeArgs {
   int launch_states;           // states composited by this launch
   unsigned long long *counters;  // [4] (count mode)
   unsigned int *queues;        // [8] per-XCD work counters (persistent launch)
+  struct {                     // pair mode (counterfactual utility)
+    const unsigned long long *item_total;  // work items wanted (device)
+    uint64_t item_capacity;                // patches available
+    int num_contexts;
+    const uint32_t *item_base;     // [J + 1] first work item of each context
+    const int32_t *context_group;  // [J]
+    const uint32_t *group_base;    // [G + 1] first region tile of each group
+    const uint32_t *region_tiles;  // tiles of each group's region, by group
+  } pair;
 };
 // mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only.
 // launch 0: automatic, 1: persistent, 2: grid.
 int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch,
                      hipStream_t st);
 void launch_zero_queues(unsigned int *queues, hipStream_t st);
+// Pair mode: composites every (context, region tile) work item for the
+// context and the context plus its group into a.image patches
+// [item][2][tile_w * tile_h][3]; a.visbits holds [J][P*4] two-bit words.
+int launch_composite_pairs(const CompositeArgs &a, int tile_w, int tile_h, int workgroups, hipStream_t st);
+// How launch_composite runs image mode for `groups` state groups (host only).
+struct CompositePlan {
+  bool persistent;
+  int64_t workgroups;  // workgroups launched
+  int64_t items;       // (tile, state group) work items
+};
+int plan_composite(int S, int tile_w, int tile_h, int tiles, int groups, int launch, CompositePlan *out);
 void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int64_t pixels,
                           float *psnr, hipStream_t st);
 
@@ -94,5 +114,79 @@ struct CompositeBwdArgs {
   int n;
 };
 int launch_composite_bwd(const CompositeBwdArgs &a, int S, int tile_w, int tile_h, hipStream_t st);
+
+// utility.hip: counterfactual render utility, distortion, risk adjustment
+struct UtilHeader {
+  unsigned long long regions;  // region tiles over all groups
+  unsigned long long items;    // work items over all contexts
+  unsigned int bad_group;      // 1: a group's packet is out of range; 2: two groups name one (packet, layer)
+  unsigned int bad_context;    // 1: a context lacks its group's packet at exactly the group's layer
+  unsigned int queue[8];
+  unsigned int pad[2];
+};
+
+constexpr int kMaxRiskValues = 4096;  // contexts per group in dgs_risk_adjusted
+
+struct UtilLayout {
+  size_t hdr, pl2g, core, region, wcount, wprefix, region_tiles, group_base, icount, item_base, bad, pvis, parts,
+      partial, patches, total;
+  int64_t words;
+};
+
+inline UtilLayout make_util_layout(int64_t P, int64_t tiles, int64_t G, int64_t J, int64_t cap) {
+  UtilLayout L{};
+  L.words = ceil_div(tiles, 32);
+  const int64_t gw = G * L.words;
+  const int64_t scan_n = gw > J ? gw : J;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + (bytes > 0 ? bytes : 1)); return at; };
+  L.hdr = take(sizeof(UtilHeader));
+  L.pl2g = take(4 * P * 4);
+  L.core = take(4 * gw);
+  L.region = take(4 * gw);
+  L.wcount = take(4 * gw);
+  L.wprefix = take(4 * gw);
+  L.region_tiles = take(4 * G * tiles);
+  L.group_base = take(4 * (G + 1));
+  L.icount = take(4 * J);
+  L.item_base = take(4 * J);
+  L.bad = take(4 * J);
+  L.pvis = take(4 * J * P * 4);
+  L.parts = take(8 * (ceil_div(scan_n, kScanTile) + 1));
+  L.partial = take(4 * cap);
+  L.patches = take((size_t)4 * cap * 2 * kBlock * 3);
+  L.total = o;
+  return L;
+}
+
+struct UtilArgs {
+  UtilHeader *hdr;
+  int *pl2g;
+  uint32_t *core, *region, *wcount, *wprefix, *region_tiles, *group_base, *icount, *item_base, *bad, *pvis;
+  unsigned long long *parts;
+  float *partial, *patches, *delta;
+  const unsigned long long *item_total;  // &hdr->items
+  unsigned int *queue;                   // hdr->queue
+  uint64_t item_capacity;
+  int num_contexts, words, tiles_x, tiles_y, width, height;
+  const int32_t *context_group;
+  const float *reference;
+  float lambda;
+};
+
+void launch_clear_util_header(UtilHeader *h, hipStream_t st);
+// Group tables, core tiles, regions (core dilated by rx, ry tiles) and the
+// region tile lists, from the rectangles of the last binning.
+void launch_group_setup(const UtilArgs &u, const uint16_t *group_pl, int G, int P, const float4 *rec0,
+                        const uint2 *rect, int n, int rx, int ry, hipStream_t st);
+// Pair delivery bits and work items per context (total in hdr->items).
+void launch_pair_setup(const UtilArgs &u, const uint8_t *codes, const uint16_t *group_pl, int G, int P,
+                       hipStream_t st);
+// Per-item SSIM / squared-error differences, then Delta per context.
+int launch_pair_ssim(const UtilArgs &u, int tile_w, int tile_h, int workgroups, hipStream_t st);
+void launch_distortion(const float *images, int num_images, int width, int height, const float *reference,
+                       float lambda, double *part, float *d, hipStream_t st);
+void launch_risk_adjusted(const float *values, const int32_t *offsets, int G, float alpha, float beta, float q,
+                          float *out, hipStream_t st);
 
 }  // namespace dgs

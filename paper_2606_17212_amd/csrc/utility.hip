@@ -1,0 +1,553 @@
+// Counterfactual render utility (paper Sec. 5): Eq. (3)
+//   Delta_g(m) = D(I, R(m)) - D(I, R(m u g)),  D = MSE + lambda (1 - SSIM)
+// (the distortion fixed for the objective in Sec. 4), and the risk-adjusted
+// utility of Eq. (4) over the contexts of each group.
+//
+// R(m) and R(m u g) differ only in pixels that a Gaussian of the completion
+// group g = (packet, layer) reaches, i.e. inside the tiles of g's Gaussians'
+// rectangles (the "core").  SSIM at a pixel depends on the 11x11 window around
+// it, so the SSIM term can change only within 5 px of the core, and those
+// pixels' windows lie within 10 px of the core.  The paired renderer
+// therefore composites, for each context, only the "region" = core dilated by
+// enough tiles to cover 10 px, both states at once (one S = 2 group), and
+// sums the per-pixel differences there.  Pixels of the region whose window
+// reaches outside it see the same (zero) values in both states and so add
+// exactly zero.  Delta is that sum over all pixels and channels divided by
+// 3 H W.
+//
+// The SSIM windows are the 11x11 Gaussian (sigma 1.5) applied as two 11-tap
+// passes; image values are shifted by -0.5 before the moments are formed
+// (variances and covariances do not change under a common shift, and the
+// shifted moments lose less to cancellation in FP32).
+
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace dgs {
+
+constexpr float kSsimC1 = 1.0e-4f;  // (0.01)^2
+constexpr float kSsimC2 = 9.0e-4f;  // (0.03)^2
+constexpr float kShift = 0.5f;
+constexpr int kSsimR = 5;           // window radius
+
+// ------------------------------------------------------------------ groups
+__global__ void k_group_table(const uint16_t *__restrict__ group_pl, int G, int P, int *__restrict__ pl2g,
+                              UtilHeader *h) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= G) return;
+  const uint32_t pl = group_pl[k];
+  if ((int)(pl >> 2) >= P) {
+    atomicOr(&h->bad_group, 1u);
+    return;
+  }
+  if (atomicCAS(&pl2g[pl], -1, k) != -1) atomicOr(&h->bad_group, 2u);  // two groups name one (packet, layer)
+}
+
+// Core tiles of every group: the tile rectangles of its Gaussians.
+__global__ void __launch_bounds__(kBlock)
+k_group_core(const float4 *__restrict__ rec0, const uint2 *__restrict__ rect, int n, const int *__restrict__ pl2g,
+             int tiles_x, int words, uint32_t *__restrict__ core) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const uint2 r = rect[i];
+    const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
+    if (x1 <= x0 || y1 <= y0) continue;
+    const int g = pl2g[__float_as_uint(rec0[i].w) & 0xFFFFu];
+    if (g < 0) continue;
+    uint32_t *row = core + (int64_t)g * words;
+    for (int y = y0; y < y1; ++y)
+      for (int x = x0; x < x1; ++x) {
+        const int t = y * tiles_x + x;
+        atomicOr(row + (t >> 5), 1u << (t & 31));
+      }
+  }
+}
+
+__device__ __forceinline__ bool bit_at(const uint32_t *row, int t) { return (row[t >> 5] >> (t & 31)) & 1u; }
+
+// Region = core dilated by (rx, ry) tiles; one thread per (group, 32-tile word).
+__global__ void __launch_bounds__(kBlock)
+k_group_region(const uint32_t *__restrict__ core, int G, int tiles_x, int tiles_y, int words, int rx, int ry,
+               uint32_t *__restrict__ region, uint32_t *__restrict__ wcount) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= (int64_t)G * words) return;
+  const int g = (int)(id / words), w = (int)(id % words);
+  const uint32_t *row = core + (int64_t)g * words;
+  const int tiles = tiles_x * tiles_y;
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int t = w * 32 + b;
+    if (t >= tiles) break;
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    bool any = false;
+    for (int dy = -ry; dy <= ry && !any; ++dy) {
+      const int yy = ty + dy;
+      if (yy < 0 || yy >= tiles_y) continue;
+      for (int dx = -rx; dx <= rx; ++dx) {
+        const int xx = tx + dx;
+        if (xx >= 0 && xx < tiles_x && bit_at(row, yy * tiles_x + xx)) {
+          any = true;
+          break;
+        }
+      }
+    }
+    bits |= (any ? 1u : 0u) << b;
+  }
+  region[id] = bits;
+  wcount[id] = (uint32_t)__popc(bits);
+}
+
+// Tiles of every region in tile order: slot = exclusive word prefix + bits below.
+__global__ void __launch_bounds__(kBlock)
+k_region_tiles(const uint32_t *__restrict__ region, const uint32_t *__restrict__ wprefix, int64_t gw,
+               int words, uint32_t *__restrict__ rtiles) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= gw) return;
+  uint32_t bits = region[id];
+  uint32_t o = wprefix[id];
+  const int w = (int)(id % words);
+  while (bits) {
+    const int b = __ffs(bits) - 1;
+    bits &= bits - 1;
+    rtiles[o++] = (uint32_t)(w * 32 + b);
+  }
+}
+
+// First region tile of each group (group_base[G] = total) from the word prefix.
+__global__ void k_group_base(const uint32_t *__restrict__ wprefix, const unsigned long long *total, int G, int words,
+                             uint32_t *__restrict__ gbase) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < G) gbase[g] = wprefix[(int64_t)g * words];
+  if (g == G) gbase[G] = (uint32_t)*total;
+}
+
+// Work items per context (its group's region size) and the pair delivery
+// bits: bit 0 for m, bit 1 for m u g.  A context must hold the group's packet
+// at prefix depth exactly the group's layer.
+__global__ void __launch_bounds__(kBlock)
+k_pair_setup(const uint8_t *__restrict__ codes, const int32_t *__restrict__ context_group,
+             const uint16_t *__restrict__ group_pl, const uint32_t *__restrict__ gbase, int J, int G, int P,
+             uint32_t *__restrict__ icount, uint32_t *__restrict__ pvis, uint32_t *__restrict__ bad,
+             UtilHeader *h) {
+  const int j = blockIdx.x;
+  if (j >= J) return;
+  const int g = context_group[j];
+  const bool gok = g >= 0 && g < G;
+  const uint32_t gpl = gok ? group_pl[g] : 0u;
+  const int gp = (int)(gpl >> 2), gl = (int)(gpl & 3u);
+  const uint8_t *row = codes + (int64_t)j * P;
+  const bool ok = gok && gp < P && row[gp] == gl;
+  if (threadIdx.x == 0) {
+    icount[j] = ok ? gbase[g + 1] - gbase[g] : 0u;
+    bad[j] = ok ? 0u : 1u;
+    if (!ok) atomicOr(&h->bad_context, 1u);
+  }
+  uint32_t *out = pvis + (int64_t)j * P * 4;
+  for (int e = threadIdx.x; e < P * 4; e += kBlock) {
+    const int p = e >> 2, l = e & 3;
+    const int c = row[p];
+    const int cg = (ok && p == gp) ? gl + 1 : c;
+    out[e] = (l < c ? 1u : 0u) | (l < cg ? 2u : 0u);
+  }
+}
+
+// ------------------------------------------------------------------- SSIM
+// LDS of the window statistics of NX images against one reference, one
+// channel at a time, for a TW x TH output block with a 5-pixel apron: the
+// caller fills x and y (shifted values, apron row-major), ssim_moments then
+// returns this thread's pixel's shifted window means and second moments.
+template <int NX, int TW, int TH>
+struct SsimLds {
+  static constexpr int AW = TW + 2 * kSsimR, AH = TH + 2 * kSsimR, A = AW * AH;
+  float x[NX][A];
+  float y[A];
+  // horizontal pass, rows [0, NX) mu_k, NX mu_y, [NX+1, 2NX+1) e_kk, 2NX+1 e_yy, [2NX+2, 3NX+2) e_ky
+  float h[3 * NX + 2][AH * TW];
+};
+
+struct SsimWeights {
+  float w[2 * kSsimR + 1];
+};
+
+template <int NX, int TW, int TH>
+__device__ __forceinline__ void ssim_moments(SsimLds<NX, TW, TH> &L, const SsimWeights &W, float (&mu)[NX],
+                                             float &muy, float (&ekk)[NX], float &eyy, float (&eky)[NX]) {
+  using SL = SsimLds<NX, TW, TH>;
+  // horizontal 11-tap pass over every apron row, for the TW output columns
+  for (int q = threadIdx.x; q < SL::AH * TW; q += kBlock) {
+    const int r = q / TW, cx = q % TW;
+    float sm[NX], sk[NX], sky[NX], smy = 0.0f, syy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NX; ++k) sm[k] = sk[k] = sky[k] = 0.0f;
+#pragma unroll
+    for (int d = 0; d <= 2 * kSsimR; ++d) {
+      const int a = r * SL::AW + cx + d;
+      const float wd = W.w[d];
+      const float yv = L.y[a];
+      smy = fmaf(wd, yv, smy);
+      syy = fmaf(wd, yv * yv, syy);
+#pragma unroll
+      for (int k = 0; k < NX; ++k) {
+        const float xv = L.x[k][a];
+        sm[k] = fmaf(wd, xv, sm[k]);
+        sk[k] = fmaf(wd, xv * xv, sk[k]);
+        sky[k] = fmaf(wd, xv * yv, sky[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      L.h[k][q] = sm[k];
+      L.h[NX + 1 + k][q] = sk[k];
+      L.h[2 * NX + 2 + k][q] = sky[k];
+    }
+    L.h[NX][q] = smy;
+    L.h[2 * NX + 1][q] = syy;
+  }
+  __syncthreads();
+  // vertical 11-tap pass for this thread's output pixel
+  const int ox = threadIdx.x % TW, oy = threadIdx.x / TW;
+  muy = eyy = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NX; ++k) mu[k] = ekk[k] = eky[k] = 0.0f;
+#pragma unroll
+  for (int d = 0; d <= 2 * kSsimR; ++d) {
+    const int q = (oy + d) * TW + ox;
+    const float wd = W.w[d];
+    muy = fmaf(wd, L.h[NX][q], muy);
+    eyy = fmaf(wd, L.h[2 * NX + 1][q], eyy);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      mu[k] = fmaf(wd, L.h[k][q], mu[k]);
+      ekk[k] = fmaf(wd, L.h[NX + 1 + k][q], ekk[k]);
+      eky[k] = fmaf(wd, L.h[2 * NX + 2 + k][q], eky[k]);
+    }
+  }
+}
+
+// SSIM from shifted window moments.
+__device__ __forceinline__ float ssim_value(float mx, float my, float exx, float eyy, float exy) {
+  const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
+  const float ux = mx + kShift, uy = my + kShift;
+  const float num = (2.0f * ux * uy + kSsimC1) * (2.0f * sxy + kSsimC2);
+  const float den = (ux * ux + uy * uy + kSsimC1) * (sxx + syy + kSsimC2);
+  return num / den;
+}
+
+// Sum over the workgroup (every thread gets it).
+__device__ __forceinline__ float block_sum(float v, float *red) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// Pair items: per-pixel  sum_c (x1 - y)^2 - (x2 - y)^2 - lambda (ssim1 - ssim2)
+// over the item's tile, for items whose 3x3 tile neighbourhood meets the core.
+template <int TW, int TH>
+__global__ void __launch_bounds__(kBlock)
+k_pair_ssim(UtilArgs u, SsimWeights W) {
+  __shared__ SsimLds<2, TW, TH> L;
+  __shared__ float red[4];
+  __shared__ int s_item;
+  using SL = SsimLds<2, TW, TH>;
+  const unsigned long long total = *u.item_total;
+  const uint32_t n_items = total <= u.item_capacity ? (uint32_t)total : 0u;  // nothing after an overflow
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(u.queue, 1u);
+    __syncthreads();
+    const uint32_t item = (uint32_t)s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    int lo = 0, hi = u.num_contexts - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (u.item_base[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const int j = lo;
+    const int g = u.context_group[j];
+    const int tile = (int)u.region_tiles[u.group_base[g] + (item - u.item_base[j])];
+    const int tx = tile % u.tiles_x, ty = tile / u.tiles_x;
+    const uint32_t *crow = u.core + (int64_t)g * u.words;
+    const uint32_t *rrow = u.region + (int64_t)g * u.words;
+    const uint32_t *rpre = u.wprefix + (int64_t)g * u.words;
+    int near = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = tx + dx, yy = ty + dy;
+        if (xx >= 0 && xx < u.tiles_x && yy >= 0 && yy < u.tiles_y && bit_at(crow, yy * u.tiles_x + xx)) near = 1;
+      }
+    // Without a core tile in the 3x3 neighbourhood every window of this tile
+    // sees identical values in both states: the item adds zero.  The branch
+    // is made wave-uniform explicitly and every path reaches the same
+    // barriers (no early continue: a thread-0-only store before a jump back
+    // to the barrier that publishes the next item can let the other lanes
+    // re-read the old item).
+    near = __builtin_amdgcn_readfirstlane(near);
+    const int x0 = tx * TW - kSsimR, y0 = ty * TH - kSsimR;
+    float acc = 0.0f;
+    for (int c = 0; c < (near ? 3 : 0); ++c) {
+      for (int a = threadIdx.x; a < SL::A; a += kBlock) {
+        const int gx = x0 + a % SL::AW, gy = y0 + a / SL::AW;
+        float v1 = -kShift, v2 = -kShift, vy = -kShift;  // zero outside the image
+        if (gx >= 0 && gx < u.width && gy >= 0 && gy < u.height) {
+          vy = u.reference[((int64_t)gy * u.width + gx) * 3 + c] - kShift;
+          const int nt = (gy / TH) * u.tiles_x + gx / TW;
+          if (bit_at(rrow, nt)) {  // outside the region: the same value in both states
+            // slot of tile nt within group g's region (the word prefix counts every group)
+            const uint32_t w = (uint32_t)nt >> 5, b = (uint32_t)nt & 31u;
+            const uint32_t slot = rpre[w] - u.group_base[g] + (uint32_t)__popc(rrow[w] & ((1u << b) - 1u));
+            const int64_t it = (int64_t)u.item_base[j] + slot;
+            const int lp = (gy - (gy / TH) * TH) * TW + (gx - (gx / TW) * TW);
+            const float *pp = u.patches + (it * 2 * kBlock + lp) * 3 + c;
+            v1 = pp[0] - kShift;
+            v2 = pp[kBlock * 3] - kShift;
+          }
+        }
+        L.x[0][a] = v1;
+        L.x[1][a] = v2;
+        L.y[a] = vy;
+      }
+      __syncthreads();
+      float mu[2], muy, ekk[2], eyy, eky[2];
+      ssim_moments<2, TW, TH>(L, W, mu, muy, ekk, eyy, eky);
+      const int ox = threadIdx.x % TW, oy = threadIdx.x / TW;
+      const int px = tx * TW + ox, py = ty * TH + oy;
+      if (px < u.width && py < u.height) {
+        const int a = (oy + kSsimR) * SL::AW + ox + kSsimR;
+        const float d1 = L.x[0][a] - L.y[a], d2 = L.x[1][a] - L.y[a];
+        const float s1 = ssim_value(mu[0], muy, ekk[0], eyy, eky[0]);
+        const float s2 = ssim_value(mu[1], muy, ekk[1], eyy, eky[1]);
+        acc += (d1 * d1 - d2 * d2) - u.lambda * (s1 - s2);
+      }
+      __syncthreads();
+    }
+    const float tot = block_sum(acc, red);
+    if (threadIdx.x == 0) u.partial[item] = tot;
+    __syncthreads();
+  }
+}
+
+// Delta per context: its items' partial sums (in FP64, in item order) / 3HW;
+// NaN for an invalid context or after an item overflow.
+__global__ void k_context_delta(UtilArgs u, const uint32_t *__restrict__ bad, float *__restrict__ delta) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= u.num_contexts) return;
+  const unsigned long long total = *u.item_total;
+  if (bad[j] || total > u.item_capacity) {
+    delta[j] = __int_as_float(0x7FC00000);
+    return;
+  }
+  const uint32_t b = u.item_base[j], e = j + 1 < u.num_contexts ? u.item_base[j + 1] : (uint32_t)total;
+  double s = 0.0;
+  for (uint32_t i = b; i < e; ++i) s += (double)u.partial[i];
+  delta[j] = (float)(s / (3.0 * (double)u.width * (double)u.height));
+}
+
+// Full images: per (image, 16x16 block) sums of squared error and SSIM.
+__global__ void __launch_bounds__(kBlock)
+k_distortion_tiles(const float *__restrict__ images, const float *__restrict__ reference, int width, int height,
+                   int bx, int by, SsimWeights W, double *__restrict__ part) {
+  __shared__ SsimLds<1, 16, 16> L;
+  __shared__ float red[4];
+  using SL = SsimLds<1, 16, 16>;
+  const int blk = blockIdx.x, img = blockIdx.y;
+  const int tx = blk % bx, ty = blk / bx;
+  const float *im = images + (int64_t)img * width * height * 3;
+  const int x0 = tx * 16 - kSsimR, y0 = ty * 16 - kSsimR;
+  float se = 0.0f, ss = 0.0f;
+  for (int c = 0; c < 3; ++c) {
+    for (int a = threadIdx.x; a < SL::A; a += kBlock) {
+      const int gx = x0 + a % SL::AW, gy = y0 + a / SL::AW;
+      float v = -kShift, vy = -kShift;
+      if (gx >= 0 && gx < width && gy >= 0 && gy < height) {
+        const int64_t o = ((int64_t)gy * width + gx) * 3 + c;
+        v = im[o] - kShift;
+        vy = reference[o] - kShift;
+      }
+      L.x[0][a] = v;
+      L.y[a] = vy;
+    }
+    __syncthreads();
+    float mu[1], muy, ekk[1], eyy, eky[1];
+    ssim_moments<1, 16, 16>(L, W, mu, muy, ekk, eyy, eky);
+    const int ox = threadIdx.x % 16, oy = threadIdx.x / 16;
+    if (tx * 16 + ox < width && ty * 16 + oy < height) {
+      const int a = (oy + kSsimR) * SL::AW + ox + kSsimR;
+      const float d = L.x[0][a] - L.y[a];
+      se += d * d;
+      ss += ssim_value(mu[0], muy, ekk[0], eyy, eky[0]);
+    }
+    __syncthreads();
+  }
+  const float tse = block_sum(se, red);
+  const float tss = block_sum(ss, red);
+  if (threadIdx.x == 0) {
+    part[((int64_t)img * bx * by + blk) * 2 + 0] = (double)tse;
+    part[((int64_t)img * bx * by + blk) * 2 + 1] = (double)tss;
+  }
+}
+
+__global__ void k_distortion_finalize(const double *__restrict__ part, int num_images, int blocks, int64_t values,
+                                      float lambda, float *__restrict__ d) {
+  const int img = blockIdx.x * blockDim.x + threadIdx.x;
+  if (img >= num_images) return;
+  double se = 0.0, ss = 0.0;
+  for (int b = 0; b < blocks; ++b) {
+    se += part[((int64_t)img * blocks + b) * 2 + 0];
+    ss += part[((int64_t)img * blocks + b) * 2 + 1];
+  }
+  d[img] = (float)(se / (double)values + (double)lambda * (1.0 - ss / (double)values));
+}
+
+// ------------------------------------------------------------ Eq. (4)
+// One workgroup per group: bitonic sort of its values in LDS, then mean,
+// population standard deviation, linear-interpolation quantile (FP64).
+__global__ void __launch_bounds__(kBlock)
+k_risk_adjusted(const float *__restrict__ values, const int32_t *__restrict__ offsets, float alpha, float beta,
+                float q, float *__restrict__ out) {
+  __shared__ float v[kMaxRiskValues];
+  __shared__ double red[4];
+  const int g = blockIdx.x;
+  const int b = offsets[g], n = offsets[g + 1] - b;
+  float *o = out + (int64_t)g * 4;
+  if (n <= 0 || n > kMaxRiskValues) {
+    if (threadIdx.x < 4) o[threadIdx.x] = __int_as_float(0x7FC00000);
+    return;
+  }
+  int np = 1;
+  while (np < n) np <<= 1;
+  bool nan = false;
+  for (int i = threadIdx.x; i < np; i += kBlock) {
+    const float x = i < n ? values[b + i] : INFINITY;
+    v[i] = x;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) nan |= v[i] != v[i];
+  if (__syncthreads_or(nan)) {
+    if (threadIdx.x < 4) o[threadIdx.x] = __int_as_float(0x7FC00000);
+    return;
+  }
+  for (int k = 2; k <= np; k <<= 1)
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int i = threadIdx.x; i < np; i += kBlock) {
+        const int p = i ^ jj;
+        if (p > i) {
+          const bool up = (i & k) == 0;
+          const float a = v[i], c = v[p];
+          if ((a > c) == up) {
+            v[i] = c;
+            v[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // mean and population standard deviation, two passes in FP64
+  auto sum = [&](double x) {
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, kWave);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+  };
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += (double)v[i];
+  const double mean = sum(s) / n;
+  double s2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const double d = (double)v[i] - mean;
+    s2 += d * d;
+  }
+  const double sd = sqrt(sum(s2) / n);
+  if (threadIdx.x == 0) {
+    const double h = (double)(n - 1) * (double)q;
+    int lo = (int)floor(h);
+    if (lo < 0) lo = 0;
+    if (lo > n - 1) lo = n - 1;
+    const int hi = lo + 1 < n ? lo + 1 : n - 1;
+    const double qv = (double)v[lo] + (h - lo) * ((double)v[hi] - (double)v[lo]);
+    o[0] = (float)mean;
+    o[1] = (float)qv;
+    o[2] = (float)sd;
+    o[3] = (float)(((1.0 - alpha) * mean + alpha * qv) / (1.0 + beta * sd));
+  }
+}
+
+__global__ void k_fill_i32(int *p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_clear_util_header(UtilHeader *h) {
+  if (threadIdx.x == 0) *h = UtilHeader{};
+}
+
+// ----------------------------------------------------------------- launchers
+void launch_clear_util_header(UtilHeader *h, hipStream_t st) { k_clear_util_header<<<1, 64, 0, st>>>(h); }
+
+static SsimWeights ssim_weights() {
+  SsimWeights W;
+  double g[2 * kSsimR + 1], s = 0.0;
+  for (int d = -kSsimR; d <= kSsimR; ++d) s += (g[d + kSsimR] = exp(-(double)(d * d) / (2.0 * 1.5 * 1.5)));
+  for (int d = 0; d <= 2 * kSsimR; ++d) W.w[d] = (float)(g[d] / s);
+  return W;
+}
+
+void launch_group_setup(const UtilArgs &u, const uint16_t *group_pl, int G, int P, const float4 *rec0,
+                        const uint2 *rect, int n, int rx, int ry, hipStream_t st) {
+  const int64_t gw = (int64_t)G * u.words;
+  k_fill_i32<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)P * 4, kBlock), 1024), kBlock, 0, st>>>(u.pl2g, (int64_t)P * 4, -1);
+  k_fill_i32<<<(unsigned)std::min<int64_t>(ceil_div(gw, kBlock), 4096), kBlock, 0, st>>>(reinterpret_cast<int *>(u.core), gw, 0);
+  k_group_table<<<(unsigned)ceil_div(G, kBlock), kBlock, 0, st>>>(group_pl, G, P, u.pl2g, u.hdr);
+  if (n > 0) {
+    const int blocks = (int)std::min<int64_t>(ceil_div(n, kBlock), 4096);
+    k_group_core<<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, u.core);
+  }
+  k_group_region<<<(unsigned)ceil_div(gw, kBlock), kBlock, 0, st>>>(u.core, G, u.tiles_x, u.tiles_y, u.words,
+                                                                    rx, ry, u.region, u.wcount);
+  launch_scan_u32(u.wcount, u.wprefix, gw, u.parts, &u.hdr->regions, st);
+  k_region_tiles<<<(unsigned)ceil_div(gw, kBlock), kBlock, 0, st>>>(u.region, u.wprefix, gw, u.words,
+                                                                    u.region_tiles);
+  k_group_base<<<(unsigned)ceil_div(G + 1, kBlock), kBlock, 0, st>>>(u.wprefix, &u.hdr->regions, G, u.words,
+                                                                     u.group_base);
+}
+
+void launch_pair_setup(const UtilArgs &u, const uint8_t *codes, const uint16_t *group_pl, int G, int P,
+                       hipStream_t st) {
+  k_pair_setup<<<u.num_contexts, kBlock, 0, st>>>(codes, u.context_group, group_pl, u.group_base, u.num_contexts,
+                                                  G, P, u.icount, u.pvis, u.bad, u.hdr);
+  launch_scan_u32(u.icount, u.item_base, u.num_contexts, u.parts, &u.hdr->items, st);
+}
+
+int launch_pair_ssim(const UtilArgs &u, int tile_w, int tile_h, int workgroups, hipStream_t st) {
+  const SsimWeights W = ssim_weights();
+  launch_zero_queues(u.queue, st);
+  if (tile_w == 16 && tile_h == 16)
+    k_pair_ssim<16, 16><<<workgroups, kBlock, 0, st>>>(u, W);
+  else if (tile_w == 32 && tile_h == 8)
+    k_pair_ssim<32, 8><<<workgroups, kBlock, 0, st>>>(u, W);
+  else
+    return 1;
+  k_context_delta<<<(unsigned)ceil_div(u.num_contexts, kBlock), kBlock, 0, st>>>(u, u.bad, u.delta);
+  return 0;
+}
+
+void launch_distortion(const float *images, int num_images, int width, int height, const float *reference,
+                       float lambda, double *part, float *d, hipStream_t st) {
+  const int bx = (int)ceil_div(width, 16), by = (int)ceil_div(height, 16);
+  k_distortion_tiles<<<dim3(bx * by, num_images), kBlock, 0, st>>>(images, reference, width, height, bx, by,
+                                                                  ssim_weights(), part);
+  k_distortion_finalize<<<(unsigned)ceil_div(num_images, kBlock), kBlock, 0, st>>>(
+      part, num_images, bx * by, (int64_t)width * height * 3, lambda, d);
+}
+
+void launch_risk_adjusted(const float *values, const int32_t *offsets, int G, float alpha, float beta, float q,
+                          float *out, hipStream_t st) {
+  k_risk_adjusted<<<G, kBlock, 0, st>>>(values, offsets, alpha, beta, q, out);
+}
+
+}  // namespace dgs

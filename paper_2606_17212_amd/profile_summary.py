@@ -1,14 +1,38 @@
-"""Summarise a rocprofv3 kernel-trace database (``*_results.db``) per kernel:
-share of GPU time, dispatch count, average / min / max duration.
+"""Summaries of rocprofv3 output, and the measured HBM traffic of a kernel.
 
-    python -m paper_2606_17212_amd.profile_summary <results.db> [--top N]
+    python -m paper_2606_17212_amd.profile_summary trace <results.db> [--top N]
+    python -m paper_2606_17212_amd.profile_summary pmc <counter_collection.csv>... [--match NAME]
+    python -m paper_2606_17212_amd.profile_summary traffic --fetch <csv> --write <csv>
+        --kernel NAME --workload NAME --copy-bytes B --command "..." --out <json>
+
+``traffic`` turns two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+runs (KiB per dispatch) into bytes per launch of one kernel.  Each counter is
+scaled by what it reads for a plain device copy of known size in the same run
+(``bench.py --copy-mib``: one ``torch.neg`` over a buffer of that size, which
+reads and writes it once; its dispatches summed), so the result is in true
+bytes.  The JSON records a hash of the
+kernel's sources; ``measured_traffic`` returns the figure only while the
+sources are unchanged.
 """
 
+from __future__ import annotations
+
 import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
 import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# sources that define the compositing kernels
+KERNEL_SOURCES = ("csrc/composite.hip", "csrc/common.h", "csrc/kernels.h")
+COPY_KERNEL = "neg_kernel"  # the calibration pass of bench.py --copy-mib
 
 
 def summarize(db: str, top: int = 25) -> str:
+    """Per kernel: share of GPU time, dispatches, average / min / max duration."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, count(*), avg(end - start), min(end - start), max(end - start), "
                        "sum(end - start) from kernels group by name order by sum(end - start) desc").fetchall()
@@ -20,29 +44,106 @@ def summarize(db: str, top: int = 25) -> str:
     return "\n".join(out)
 
 
-if __name__ == "__main__":
-    ap = argparse.ArgumentParser()
-    ap.add_argument("db")
-    ap.add_argument("--top", type=int, default=25)
-    a = ap.parse_args()
-    print(summarize(a.db, a.top))
+def _pmc_rows(paths, match=None):
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for p in paths:
+        with open(p) as f:
+            for row in csv.DictReader(f):
+                name = row["Kernel_Name"]
+                if match and not any(m in name for m in match):
+                    continue
+                acc[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    return acc
 
 
 def summarize_pmc(csv_paths, match=None) -> str:
-    """Per-kernel averages of rocprofv3 ``--pmc ... --output-format csv``
-    counter files (``*_counter_collection.csv``)."""
-    import collections
-    import csv
-    acc = collections.defaultdict(lambda: collections.defaultdict(list))
-    for p in csv_paths:
-        for row in csv.DictReader(open(p)):
-            name = row["Kernel_Name"]
-            if match and not any(m in name for m in match):
-                continue
-            acc[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    """Per-kernel means of rocprofv3 ``--pmc ... --output-format csv`` files."""
     lines = []
-    for name, ctrs in acc.items():
+    for name, ctrs in _pmc_rows(csv_paths, match).items():
         lines.append(name)
         for c, v in sorted(ctrs.items()):
             lines.append(f"    {c:24s} mean {sum(v) / len(v):16.1f}   dispatches {len(v)}")
     return "\n".join(lines)
+
+
+def kernel_sources_hash(pkg_dir: str = HERE) -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(pkg_dir, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def traffic_path(root: str, workload: str) -> str:
+    return os.path.join(root, "profiles", f"traffic_k_composite_{workload}.json")
+
+
+def traffic_record(fetch_csv: str, write_csv: str, kernel: str, workload: str, copy_bytes: int,
+                   command: str) -> dict:
+    """Calibrated HBM bytes per launch of ``kernel`` from FETCH_SIZE and
+    WRITE_SIZE counter files of two runs of the same command."""
+    rec = {"kernel": kernel, "workload": workload, "command": command, "copy_bytes": copy_bytes,
+           "sources_sha256": kernel_sources_hash()}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _pmc_rows([path])
+        ks = [v for name, c in rows.items() if kernel in name.replace(" ", "") for v in c.get(counter, [])]
+        cp = [v for name, c in rows.items() if COPY_KERNEL in name for v in c.get(counter, [])]
+        if not ks or not cp:
+            raise ValueError(f"{counter}: no dispatches of {kernel!r} or of the copy kernel in {path}")
+        copy_kib = sum(cp)  # one call, possibly split over dispatches
+        factor = copy_bytes / (copy_kib * 1024.0)
+        key = counter.split("_")[0].lower()
+        rec[f"{key}_kib_per_dispatch"] = sum(ks) / len(ks)
+        rec[f"{key}_dispatches"] = len(ks)
+        rec[f"{key}_copy_kib"] = copy_kib
+        rec[f"{key}_factor"] = factor
+        rec[f"{key}_bytes"] = sum(ks) / len(ks) * 1024.0 * factor
+    rec["traffic_bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+    return rec
+
+
+def measured_traffic(kernel: str, workload: str, root: str):
+    """Calibrated HBM bytes per launch of ``kernel`` on ``workload`` from the
+    committed counter record, or None if there is none or the kernel's sources
+    changed since it was taken."""
+    path = traffic_path(root, workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != kernel_sources_hash():
+        return None
+    return round(float(rec["traffic_bytes"]))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--top", type=int, default=25)
+    p = sub.add_parser("pmc")
+    p.add_argument("csv", nargs="+")
+    p.add_argument("--match", action="append")
+    r = sub.add_parser("traffic")
+    r.add_argument("--fetch", required=True)
+    r.add_argument("--write", required=True)
+    r.add_argument("--kernel", required=True)
+    r.add_argument("--workload", required=True)
+    r.add_argument("--copy-bytes", type=int, required=True)
+    r.add_argument("--command", required=True)
+    r.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        print(summarize(a.db, a.top))
+    elif a.cmd == "pmc":
+        print(summarize_pmc(a.csv, a.match))
+    else:
+        rec = traffic_record(a.fetch, a.write, a.kernel, a.workload, a.copy_bytes, a.command)
+        with open(a.out, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,8 @@ class Renderer:
         self.capacity = 0
         self.max_states = 0
         self.generation = 0  # bumps whenever the workspace's sorted lists change
+        self.uws = None       # utility workspace
+        self.utility_capacity = 0
         self._key = None
 
     # ---------------------------------------------------------------- planning
@@ -305,6 +307,79 @@ class Renderer:
             self.ws_bytes, self.capacity, _ptr(cnt), self._stream()))
         return tuple(int(x) for x in cnt.cpu().tolist())
 
+    def launch_plan(self, camera: Camera, num_states: int):
+        """How ``composite`` launches for ``num_states`` states: dict with
+        ``states_per_group``, ``persistent``, ``workgroups``, ``work_items``."""
+        with torch.cuda.device(self.device):
+            S, pers = ctypes.c_int32(), ctypes.c_int32()
+            wg, items = ctypes.c_int64(), ctypes.c_int64()
+            _abi.check(_abi.lib().dgs_composite_launch(ctypes.byref(_c_camera(camera)), ctypes.byref(self.tuning),
+                                                       int(num_states), ctypes.byref(S), ctypes.byref(pers),
+                                                       ctypes.byref(wg), ctypes.byref(items)))
+        return {"states_per_group": S.value, "persistent": bool(pers.value), "workgroups": wg.value,
+                "work_items": items.value}
+
+    # ------------------------------------------------- counterfactual utility
+    def _utility_args(self, scene, camera, contexts, context_group, group_pl):
+        self._codes(contexts, scene)
+        _check_tensor(context_group, "context_group", torch.int32, self.device)
+        _check_tensor(group_pl, "group_pl", torch.int16, self.device)
+        if context_group.shape != (contexts.shape[0],) or group_pl.dim() != 1 or group_pl.shape[0] < 1:
+            raise ValueError("context_group must be [J] and group_pl [G] with G >= 1")
+
+    def _ensure_uws(self, scene, camera, G, J, capacity):
+        nbytes = _abi.lib().dgs_utility_workspace_bytes(scene.num_packets, ctypes.byref(_c_camera(camera)),
+                                                        ctypes.byref(self.tuning), int(G), int(J), int(capacity))
+        if nbytes == 0:
+            raise ValueError("invalid arguments for dgs_utility_workspace_bytes")
+        if getattr(self, "uws", None) is None or self.uws.numel() < nbytes:
+            self.uws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return int(nbytes)
+
+    def utility_items(self, scene: GaussianScene, camera: Camera, contexts: torch.Tensor,
+                      context_group: torch.Tensor, group_pl: torch.Tensor, basis) -> int:
+        """Work items ``utility`` needs (synchronises; uses the last ``bin``)."""
+        self._utility_args(scene, camera, contexts, context_group, group_pl)
+        G, J = int(group_pl.shape[0]), int(contexts.shape[0])
+        nbytes = self._ensure_uws(scene, camera, G, J, 0)
+        items = ctypes.c_int64(0)
+        _abi.check(_abi.lib().dgs_utility_count(
+            ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(contexts, basis, (0, 0, 0))), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(context_group), _ptr(group_pl), G, _ptr(self.uws), nbytes,
+            ctypes.byref(items), self._stream()))
+        return int(items.value)
+
+    def utility(self, scene: GaussianScene, camera: Camera, contexts: torch.Tensor, context_group: torch.Tensor,
+                group_pl: torch.Tensor, basis, reference: torch.Tensor, background=(0, 0, 0), lam: float = 0.20,
+                item_capacity: Optional[int] = None, out=None) -> torch.Tensor:
+        """Eq. (3): Delta_g(m) [J] for contexts [J, P] (u8), each paired with
+        group ``group_pl[context_group[j]]`` = (packet << 2) | layer, against
+        ``reference`` [H, Wd, 3], from the lists of the last ``bin``.  Without
+        ``item_capacity`` the work items are counted first (synchronises)."""
+        self._utility_args(scene, camera, contexts, context_group, group_pl)
+        _check_tensor(reference, "reference", torch.float32, self.device)
+        G, J = int(group_pl.shape[0]), int(contexts.shape[0])
+        if item_capacity is None:
+            item_capacity = self.utility_items(scene, camera, contexts, context_group, group_pl, basis)
+        nbytes = self._ensure_uws(scene, camera, G, J, item_capacity)
+        delta = out if out is not None else torch.empty(J, dtype=torch.float32, device=self.device)
+        _abi.check(_abi.lib().dgs_utility(
+            ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+            ctypes.byref(_c_states(contexts, basis, background)), ctypes.byref(self.tuning), _ptr(self.ws),
+            self.ws_bytes, self.capacity, _ptr(context_group), _ptr(group_pl), G, _ptr(reference), float(lam),
+            _ptr(self.uws), nbytes, int(item_capacity), _ptr(delta), self._stream()))
+        self.utility_capacity = int(item_capacity)
+        return delta
+
+    def utility_check(self) -> int:
+        """Synchronise; work items of the last ``utility``; raises DgsError on
+        an invalid group or context or an item overflow."""
+        items = ctypes.c_int64(0)
+        _abi.check(_abi.lib().dgs_utility_check(_ptr(self.uws), self.uws.numel(), self.utility_capacity,
+                                                ctypes.byref(items), self._stream()))
+        return int(items.value)
+
     def render_psnr(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
                     reference: torch.Tensor, background=(0, 0, 0), out=None):
         """PSNR [W] of each state against ``reference`` [H, Wd, 3]."""
@@ -362,6 +437,40 @@ class RenderFunction(torch.autograd.Function):
             r.render(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, params=p)
         g = r.backward(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, img, grad_image, params=p)
         return (None, None, None, None, None, None) + tuple(g[k] for k in PARAMS)
+
+
+def distortion(images: torch.Tensor, reference: torch.Tensor, lam: float = 0.20) -> torch.Tensor:
+    """D = MSE + lam (1 - SSIM) of each image [W, H, Wd, 3] against
+    ``reference`` [H, Wd, 3] (Sec. 4's distortion), computed on the device."""
+    _check_tensor(images, "images", torch.float32, images.device)
+    _check_tensor(reference, "reference", torch.float32, images.device)
+    if images.dim() != 4 or images.shape[-1] != 3 or tuple(reference.shape) != tuple(images.shape[1:]):
+        raise ValueError("images must be [W, H, Wd, 3] and reference [H, Wd, 3]")
+    W, H, Wd = (int(x) for x in images.shape[:3])
+    L = _abi.lib()
+    nbytes = L.dgs_distortion_scratch_bytes(W, Wd, H)
+    scratch = torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device=images.device)
+    d = torch.empty(W, dtype=torch.float32, device=images.device)
+    with torch.cuda.device(images.device):
+        st = ctypes.c_void_p(torch.cuda.current_stream(images.device).cuda_stream)
+        _abi.check(L.dgs_distortion(_ptr(images), W, Wd, H, _ptr(reference), float(lam), _ptr(scratch),
+                                    int(nbytes), _ptr(d), st))
+    return d
+
+
+def risk_adjusted(values: torch.Tensor, offsets: torch.Tensor, alpha: float = 0.25, beta: float = 0.05,
+                  quantile: float = 0.10) -> torch.Tensor:
+    """Eq. (4) per group: [G, 4] = (mean, quantile, std, risk-adjusted) of
+    values[offsets[k]:offsets[k+1]] (float32 / int32 device tensors)."""
+    _check_tensor(values, "values", torch.float32, values.device)
+    _check_tensor(offsets, "offsets", torch.int32, values.device)
+    G = int(offsets.shape[0]) - 1
+    out = torch.empty((max(G, 0), 4), dtype=torch.float32, device=values.device)
+    with torch.cuda.device(values.device):
+        st = ctypes.c_void_p(torch.cuda.current_stream(values.device).cuda_stream)
+        _abi.check(_abi.lib().dgs_risk_adjusted(_ptr(values), _ptr(offsets), G, float(alpha), float(beta),
+                                                float(quantile), _ptr(out), st))
+    return out
 
 
 def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,

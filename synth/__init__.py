@@ -21,4 +21,8 @@ from .workloads import (  # noqa: F401
     subscene,
     make_workload,
     permute_gaussians,
+    UTILITY_WORKLOADS,
+    UtilityWorkload,
+    make_utility_contexts,
+    make_utility_workload,
 )

@@ -300,3 +300,62 @@ def make_workload(name: str, background=(0.0, 0.0, 0.0), t: float = 0.5,
                     basis=temporal_basis(t, scene.rank), t=t,
                     background=np.asarray(background, dtype=np.float32),
                     batch=r.get("batch", 0), total_states=r.get("total_states", 0))
+
+
+# Counterfactual-utility sweeps (Eq. (3)-(4)): completion groups and the
+# contexts each group is evaluated in.  ``scene`` names the workload whose
+# scene and camera are used.
+UTILITY_WORKLOADS = {
+    # one group per cluster of the 1M-Gaussian 64x16 scene, 16 contexts each
+    "g1m_540p_utility_64groups_16contexts": dict(scene="g1m_540p_32768states_psnr", groups_per_cluster=1,
+                                                 contexts_per_group=16, p_lo=0.2, p_hi=1.0, stream=6),
+    # the 250k 4-layer scene: one (packet, layer) group per cluster, 8 contexts each
+    "g250k_800px_utility_32groups_8contexts": dict(scene="g250k_800px_64states", groups_per_cluster=1,
+                                                   contexts_per_group=8, p_lo=0.3, p_hi=1.0, stream=6),
+}
+
+
+@dataclass
+class UtilityWorkload:
+    base: Workload
+    group_pl: np.ndarray       # uint16 [G]: (packet << 2) | layer
+    codes: np.ndarray          # uint8 [J][P]: the contexts m
+    context_group: np.ndarray  # int32 [J]
+
+
+def make_utility_contexts(num_clusters: int, num_contexts: int, layers: int, groups_per_cluster: int,
+                          contexts_per_group: int, p_lo: float, p_hi: float, index: int, stream: int):
+    """Groups: per cluster, ``groups_per_cluster`` distinct random packets of
+    that cluster, each with a random layer.  Contexts: per group, states drawn
+    as in ``make_codes`` (p_w ~ U[p_lo, p_hi], packets ~ Bernoulli(p_w), prefix
+    depth ~ UniformInt{0..layers-1}), then the group's packet set to prefix
+    depth exactly the group's layer (its prerequisites delivered, the group
+    itself not)."""
+    rng = _rng(index, stream)
+    P = num_clusters * num_contexts
+    gp, gl = [], []
+    for c in range(num_clusters):
+        ks = rng.choice(num_contexts, size=groups_per_cluster, replace=False)
+        for k in ks:
+            gp.append(c * num_contexts + int(k))
+            gl.append(int(rng.integers(0, layers)))
+    G = len(gp)
+    J = G * contexts_per_group
+    pw = rng.uniform(p_lo, p_hi, size=J)
+    present = rng.random((J, P)) < pw[:, None]
+    depth = rng.integers(0, layers, size=(J, P))
+    codes = np.where(present, depth + 1, 0).astype(np.uint8)
+    group = np.repeat(np.arange(G, dtype=np.int32), contexts_per_group)
+    codes[np.arange(J), np.asarray(gp)[group]] = np.asarray(gl, dtype=np.uint8)[group]
+    group_pl = ((np.asarray(gp, dtype=np.uint32) << 2) | np.asarray(gl, dtype=np.uint32)).astype(np.uint16)
+    return group_pl, np.ascontiguousarray(codes), group
+
+
+def make_utility_workload(name: str, background=(0.0, 0.0, 0.0)) -> UtilityWorkload:
+    r = UTILITY_WORKLOADS[name]
+    base = make_workload(r["scene"], background=background)
+    rb = WORKLOADS[r["scene"]]
+    gpl, codes, cg = make_utility_contexts(rb["clusters"], rb["contexts"], rb["layers"], r["groups_per_cluster"],
+                                           r["contexts_per_group"], r["p_lo"], r["p_hi"], rb["index"], r["stream"])
+    return UtilityWorkload(base=base, group_pl=gpl, codes=codes, context_group=cg)
+
