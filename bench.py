@@ -24,7 +24,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "delivery-states rendered/s batched vs per-state; fwd+bwd ms/iter @250k G"
-PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak (counts packed FP32 FMA)
+# Without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic FLOPs (an FMA counts 2) per unit of compositing work:
 FLOPS_PER_ALPHA = 14       # dx, dy, quadratic form (8), scale, exp, x opacity, cap
 FLOPS_PER_BLEND = 8        # T*alpha, 3 FMA colour, T - T*alpha
@@ -154,6 +156,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": kernel, "launch": plan,
+                "peak_nonpacked": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
+                "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "kernel_ms": round(comp_ms, 4), "alpha_evals": alpha_evals, "blends": blends,
                 "wave_alpha_evals": wave_evals, "wave_alpha_misses": wave_miss,
                 "flops_per_launch": flops}
