@@ -186,6 +186,59 @@ k_ranges_from_counts(const uint32_t *__restrict__ tcnt, const uint32_t *__restri
   ranges[t] = h->overflow ? make_uint2(0u, 0u) : make_uint2(tstart[t], tstart[t] + tcnt[t]);
 }
 
+// One workgroup, the whole difference array in LDS: 2D prefix (rows, then
+// columns) -> instances per tile, exclusive scan over tiles -> [start, end)
+// per tile, all without leaving the workgroup (used when the array fits LDS).
+__global__ void __launch_bounds__(1024)
+k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, const Header *__restrict__ h,
+                  uint2 *__restrict__ ranges) {
+  __shared__ uint32_t sd[kDiffLds];
+  __shared__ uint32_t wsum[16];
+  const int nx = tiles_x + 1, ne = (tiles_x + 1) * (tiles_y + 1), tiles = tiles_x * tiles_y;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int k = tid; k < ne; k += 1024) sd[k] = diff[k];
+  __syncthreads();
+  for (int y = tid; y < tiles_y; y += 1024) {
+    uint32_t acc = 0;
+    for (int x = 0; x < tiles_x; ++x) {
+      acc += sd[y * nx + x];
+      sd[y * nx + x] = acc;
+    }
+  }
+  __syncthreads();
+  for (int x = tid; x < tiles_x; x += 1024) {
+    uint32_t acc = 0;
+    for (int y = 0; y < tiles_y; ++y) {
+      acc += sd[y * nx + x];
+      sd[y * nx + x] = acc;
+    }
+  }
+  __syncthreads();
+  // counts of tile t = sd[(t / tiles_x) * nx + t % tiles_x]; each thread scans
+  // a contiguous run of tiles, runs are combined by wave and workgroup scans
+  const int per = (tiles + 1023) / 1024;
+  const int t0 = tid * per;
+  uint32_t run = 0;
+  for (int k = 0; k < per; ++k) {
+    const int t = t0 + k;
+    if (t < tiles) run += sd[(t / tiles_x) * nx + t % tiles_x];
+  }
+  const uint32_t incl = wave_incl_scan(run);
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int k = 0; k < w; ++k) off += wsum[k];
+  uint32_t start = off + incl - run;
+  const bool over = h->overflow != 0u;  // after an overflow every range is empty
+  for (int k = 0; k < per; ++k) {
+    const int t = t0 + k;
+    if (t >= tiles) break;
+    const uint32_t c = sd[(t / tiles_x) * nx + t % tiles_x];
+    ranges[t] = over ? make_uint2(0u, 0u) : make_uint2(start, start + c);
+    start += c;
+  }
+}
+
 void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                         int grid_n, int tiles_x, int tiles_y, const Header *h, uint32_t *tdiff, uint32_t *tcnt,
                         uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st) {
@@ -197,6 +250,10 @@ void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 
     const int64_t per = ne <= kDiffLds ? (grid_n / 512 > 1024 ? grid_n / 512 : 1024) : 1024;
     const int blocks = (int)ceil_div(grid_n, per);
     k_tile_diff<<<blocks, kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, tiles_x, tiles_y, tdiff);
+  }
+  if (ne <= kDiffLds) {
+    k_tile_ranges_lds<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, h, ranges);
+    return;
   }
   k_tile_prefix<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, tcnt);
   launch_scan_u32(tcnt, tstart, tiles, parts, nullptr, st);

@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kBlock)
 k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const void *count_dev,
              int is_u64, int64_t max_count, int shift, int nbits, const uint32_t *__restrict__ hist,
-             int nblocks) {
+             int nblocks, int fused) {
   __shared__ uint32_t wc[4][256];
   __shared__ uint32_t dstart[256];
   __shared__ uint32_t gbase[256];
@@ -190,7 +190,29 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     wc[1][d] = ex + c0;
     wc[2][d] = ex + c0 + c1;
     wc[3][d] = ex + c0 + c1 + c2;
-    gbase[d] = (d <= (int)mask) ? hist[(int64_t)d * nblocks + blockIdx.x] : 0u;
+    if (!fused) gbase[d] = (d <= (int)mask) ? hist[(int64_t)d * nblocks + blockIdx.x] : 0u;
+  }
+  if (fused) {
+    // global offset of (digit d, this block) from the raw histograms:
+    // sum over all blocks of the lower digits + this digit in earlier blocks
+    const int d = tid;
+    uint32_t tot = 0, before = 0;
+    if (d <= (int)mask) {
+      const uint32_t *row = hist + (int64_t)d * nblocks;
+#pragma unroll 8
+      for (int b = 0; b < nblocks; ++b) {
+        const uint32_t c = row[b];
+        tot += c;
+        before += b < (int)blockIdx.x ? c : 0u;
+      }
+    }
+    const uint32_t incl = wave_incl_scan(tot);
+    __syncthreads();
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    gbase[d] = off + incl - tot + before;
   }
   __syncthreads();
 #pragma unroll
@@ -214,6 +236,8 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
   }
 }
 
+constexpr int kFusedScanBlocks = 256;
+
 int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, const void *count_dev,
                       int count_is_u64, int64_t max_count, int begin_bit, int end_bit, uint32_t *hist,
                       unsigned long long *parts, hipStream_t st, bool last_pass_keys) {
@@ -230,10 +254,13 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
     k_radix_up<<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist,
                                            nblocks);
-    launch_scan_u32(hist, hist, (int64_t)(1 << nbits) * nblocks, parts, nullptr, st);
+    // few blocks: each scatter workgroup forms its digit offsets from the raw
+    // histograms itself (no separate scan launches)
+    const int fused = nblocks <= kFusedScanBlocks ? 1 : 0;
+    if (!fused) launch_scan_u32(hist, hist, (int64_t)(1 << nbits) * nblocks, parts, nullptr, st);
     uint32_t *kwrite = (pass == passes - 1 && !last_pass_keys) ? nullptr : ko;
     k_radix_down<<<nblocks, kBlock, 0, st>>>(ki, vi, kwrite, vo, count_dev, count_is_u64, max_count, shift,
-                                             nbits, hist, nblocks);
+                                             nbits, hist, nblocks, fused);
     cur ^= 1;
     shift += nbits;
   }
