@@ -5,6 +5,8 @@
 // Gaussians are first sorted by (depth bits, index); instances are emitted in
 // that order and then sorted stably by tile id alone, which yields the
 // (tile, depth, index) order with a sort over 12-13 key bits instead of 44-45.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -51,29 +53,35 @@ void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect,
 // exponent q' over the block's pixel centres must not fall below log2(1/255)
 // by more than a rounding margin.  Pixels outside reached blocks would all be
 // skipped by the per-pixel test, so the mask never changes a result.
-__device__ inline uint32_t wave_block_mask(uint32_t id, uint32_t tx, uint32_t ty, int tile_w, int tile_h,
-                                           const float4 *rec0, const float4 *rec1, const uint2 *pbox) {
-  const float4 r0 = rec0[id];
-  const float4 r1 = rec1[id];
-  const uint2 pb = pbox[id];
+__device__ inline uint32_t block_reach_mask(const float4 &r0, const float4 &r1, const uint2 &pb, uint32_t tx,
+                                            uint32_t ty, int tile_w, int tile_h) {
   const int tpx = (int)tx * tile_w, tpy = (int)ty * tile_h;
   const int x0 = (int)(pb.x & 0xFFFFu) - tpx, y0 = (int)(pb.x >> 16) - tpy;
   const int x1 = (int)(pb.y & 0xFFFFu) - tpx, y1 = (int)(pb.y >> 16) - tpy;
   const float need = kQSkip - 0.01f - r0.z;
   const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
+  const float ftx = (float)tpx + 0.5f, fty = (float)tpy + 0.5f;
+  if (box_all_reach(r1.x, r1.y, r1.z, r0.x - (ftx + (float)(tile_w - 1)), r0.x - ftx, r0.y - (fty + (float)(tile_h - 1)),
+                    r0.y - fty, need))
+    return 0xFu;  // every pixel of the tile reached
   uint32_t mask = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const int bx = wave_block_x0(w, tile_w), by = wave_block_y0(w, tile_w);
     if (x0 < bx + 8 && x1 > bx && y0 < by + 8 && y1 > by) {
       const float cx0 = (float)(tpx + bx) + 0.5f, cy0 = (float)(tpy + by) + 0.5f;
-      const float m = box_max_exponent(r1.x, r1.y, r1.z, ia, ic, r0.x - (cx0 + 7.0f), r0.x - cx0,
-                                       r0.y - (cy0 + 7.0f), r0.y - cy0);
-      if (m >= need) mask |= 1u << w;
+      if (box_reaches(r1.x, r1.y, r1.z, ia, ic, r0.x - (cx0 + 7.0f), r0.x - cx0, r0.y - (cy0 + 7.0f), r0.y - cy0,
+                      need))
+        mask |= 1u << w;
     }
   }
   (void)tile_h;
   return mask;
+}
+
+__device__ inline uint32_t wave_block_mask(uint32_t id, uint32_t tx, uint32_t ty, int tile_w, int tile_h,
+                                           const float4 *rec0, const float4 *rec1, const uint2 *pbox) {
+  return block_reach_mask(rec0[id], rec1[id], pbox[id], tx, ty, tile_w, tile_h);
 }
 
 // Emission: one wave per depth-sorted Gaussian (grid-stride); its lanes write
@@ -126,7 +134,6 @@ void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, c
 // (x1, y0) and (x0, y1) of every binned Gaussian's rectangle; its 2D prefix
 // sum is the instance count of each tile.  Workgroups accumulate in LDS when
 // the array fits and flush non-zero entries with one global atomic each.
-constexpr int kDiffLds = 12288;  // entries (48 KB)
 
 __global__ void __launch_bounds__(kBlock)
 k_tile_diff(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
@@ -190,10 +197,15 @@ k_ranges_from_counts(const uint32_t *__restrict__ tcnt, const uint32_t *__restri
 // columns) -> instances per tile, exclusive scan over tiles -> [start, end)
 // per tile, all without leaving the workgroup (used when the array fits LDS).
 __global__ void __launch_bounds__(1024)
-k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, const Header *__restrict__ h,
+k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, Header *__restrict__ h,
                   uint2 *__restrict__ ranges) {
   __shared__ uint32_t sd[kDiffLds];
   __shared__ uint32_t wsum[16];
+  __shared__ unsigned long long wtot[16];
+  if (threadIdx.x < 16) {
+    wsum[threadIdx.x] = 0u;
+    wtot[threadIdx.x] = 0ull;
+  }
   const int nx = tiles_x + 1, ne = (tiles_x + 1) * (tiles_y + 1), tiles = tiles_x * tiles_y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int k = tid; k < ne; k += 1024) sd[k] = diff[k];
@@ -219,17 +231,32 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, c
   const int per = (tiles + 1023) / 1024;
   const int t0 = tid * per;
   uint32_t run = 0;
+  unsigned long long run64 = 0;  // the total may exceed 32 bits; the ranges only matter when it does not
   for (int k = 0; k < per; ++k) {
     const int t = t0 + k;
-    if (t < tiles) run += sd[(t / tiles_x) * nx + t % tiles_x];
+    if (t < tiles) {
+      const uint32_t c = sd[(t / tiles_x) * nx + t % tiles_x];
+      run += c;
+      run64 += c;
+    }
   }
   const uint32_t incl = wave_incl_scan(run);
+  for (int d = 32; d >= 1; d >>= 1) run64 += __shfl_xor(run64, d, kWave);
   if (lane == 63) wsum[w] = incl;
+  if (lane == 0) wtot[w] = run64;
   __syncthreads();
   uint32_t off = 0;
+  unsigned long long total = 0;
   for (int k = 0; k < w; ++k) off += wsum[k];
+  for (int k = 0; k < 16; ++k) total += wtot[k];
   uint32_t start = off + incl - run;
-  const bool over = h->overflow != 0u;  // after an overflow every range is empty
+  // the instance count of this binning; more than the capacity is an
+  // overflow, after which every range is empty
+  const bool over = total > h->capacity;
+  if (tid == 0) {
+    h->instances = total;
+    if (over) h->overflow = 1u;
+  }
   for (int k = 0; k < per; ++k) {
     const int t = t0 + k;
     if (t >= tiles) break;
@@ -239,8 +266,228 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, c
   }
 }
 
+bool tile_ranges_in_lds(int tiles_x, int tiles_y) {
+  return (int64_t)(tiles_x + 1) * (tiles_y + 1) <= kDiffLds && (int64_t)tiles_x * tiles_y <= kChunkTiles;
+}
+
+// ---------------------------------------------------------------------------
+// One-pass stable scatter of the tile instances (used when the tile grid fits
+// LDS).  The depth-sorted Gaussians are cut into chunks of kChunk; one wave
+// per chunk counts the chunk's instances per tile, the counts are turned into
+// each chunk's first slot in every tile's range (ranges[t].x plus the counts
+// of the earlier chunks), and one wave per chunk then walks its Gaussians in
+// depth order writing every instance to its tile's next slot.  Within a tile
+// the instances end up in depth order (chunk by chunk, then in order inside
+// the chunk): the order a stable sort by tile of the depth-ordered emission
+// gives.  The tiles of one Gaussian are distinct, so the per-tile slot
+// counters in LDS need no atomics; successive Gaussians are ordered by the
+// wave's program order.
+
+// The 64 Gaussians [jb, jb + 64) of a wave, one per lane: id and tile
+// rectangle (zero for culled or missing ones), and the records the reach
+// masks need.
+struct WaveGaussians {
+  uint32_t id, rx, ry;
+  float4 r0, r1;
+  uint2 pb;
+};
+
+template <bool RECORDS>
+__device__ __forceinline__ WaveGaussians load_wave_gaussians(const uint32_t *__restrict__ dkey,
+                                                             const uint32_t *__restrict__ dval,
+                                                             const uint2 *__restrict__ rect, int j, int j1,
+                                                             const float4 *__restrict__ rec0,
+                                                             const float4 *__restrict__ rec1,
+                                                             const uint2 *__restrict__ pbox) {
+  WaveGaussians q{};
+  if (j < j1 && dkey[j] != 0xFFFFFFFFu) {
+    q.id = dval[j];
+    const uint2 r = rect[q.id];
+    q.rx = r.x;
+    q.ry = r.y;
+    if (RECORDS) {
+      q.r0 = rec0[q.id];
+      q.r1 = rec1[q.id];
+      q.pb = pbox[q.id];
+    }
+  }
+  return q;
+}
+
+// Visits the tiles of the wave's Gaussians g = 0..ng-1 in order, lanes over
+// each rectangle (row-major); f(g, tile, tx, ty) runs once per instance.
+template <typename F>
+__device__ __forceinline__ void for_wave_instances(const WaveGaussians &q, int ng, int tiles_x, F &&f) {
+  for (int g = 0; g < ng; ++g) {
+    const uint32_t gx = __builtin_amdgcn_readlane(q.rx, g), gy = __builtin_amdgcn_readlane(q.ry, g);
+    const uint32_t x0 = gx & 0xFFFFu, y0 = gx >> 16, x1 = gy & 0xFFFFu, y1 = gy >> 16;
+    if (x1 <= x0 || y1 <= y0) continue;  // culled (all zero) or empty
+    const uint32_t nx = x1 - x0, area = nx * (y1 - y0);
+    for (uint32_t k = __lane_id(); k < area; k += kWave) {
+      const uint32_t dy = k / nx, tx = x0 + (k - dy * nx), ty = y0 + dy;
+      f(g, ty * (uint32_t)tiles_x + tx, tx, ty);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t readlane_u(uint32_t v, int g) { return __builtin_amdgcn_readlane(v, g); }
+__device__ __forceinline__ float readlane_f(float v, int g) {
+  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), g));
+}
+
+// Instances per tile of chunk c (kChunk depth-ordered Gaussians, four waves
+// of 64), counted with LDS atomics.
+__global__ void __launch_bounds__(kBlock)
+k_chunk_hist(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
+             const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles, uint32_t *__restrict__ chist) {
+  extern __shared__ uint32_t cnt[];
+  const int nact = n_active ? (int)*n_active : grid_n;
+  for (int t = threadIdx.x; t < tiles; t += kBlock) cnt[t] = 0u;
+  __syncthreads();
+  const int jb = blockIdx.x * kChunk + (threadIdx.x >> 6) * kWave;
+  const int j1 = (blockIdx.x * kChunk + kChunk) < nact ? (blockIdx.x * kChunk + kChunk) : nact;
+  if (jb < j1) {
+    const WaveGaussians q = load_wave_gaussians<false>(dkey, dval, rect, jb + __lane_id(), j1, nullptr, nullptr,
+                                                       nullptr);
+    const int ng = (j1 - jb) < kWave ? (j1 - jb) : kWave;
+    for_wave_instances(q, ng, tiles_x, [&](int, uint32_t t, uint32_t, uint32_t) { atomicAdd(&cnt[t], 1u); });
+  }
+  __syncthreads();
+  uint32_t *row = chist + (int64_t)blockIdx.x * tiles;
+  for (int t = threadIdx.x; t < tiles; t += kBlock) row[t] = cnt[t];
+}
+
+// Totals of segments of kSegChunks chunks per tile (thread = tile, y = segment).
+__global__ void __launch_bounds__(kBlock)
+k_chunk_segsum(const uint32_t *__restrict__ chist, int chunks, int tiles, uint32_t *__restrict__ segsum) {
+  const int t = blockIdx.x * kBlock + threadIdx.x, sg = blockIdx.y;
+  if (t >= tiles) return;
+  const int c0 = sg * kSegChunks, c1 = (c0 + kSegChunks) < chunks ? (c0 + kSegChunks) : chunks;
+  uint32_t s = 0;
+  for (int c = c0; c < c1; ++c) s += chist[(int64_t)c * tiles + t];
+  segsum[(int64_t)sg * tiles + t] = s;
+}
+
+// chist[c][t] <- ranges[t].x + instances of tile t in chunks before c.
+__global__ void __launch_bounds__(kBlock)
+k_chunk_offsets(uint32_t *__restrict__ chist, const uint32_t *__restrict__ segsum, const uint2 *__restrict__ ranges,
+                int chunks, int tiles) {
+  const int t = blockIdx.x * kBlock + threadIdx.x, sg = blockIdx.y;
+  if (t >= tiles) return;
+  uint32_t base = ranges[t].x;
+  for (int k = 0; k < sg; ++k) base += segsum[(int64_t)k * tiles + t];
+  const int c0 = sg * kSegChunks, c1 = (c0 + kSegChunks) < chunks ? (c0 + kSegChunks) : chunks;
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t v = chist[(int64_t)c * tiles + t];
+    chist[(int64_t)c * tiles + t] = base;
+    base += v;
+  }
+}
+
+// Scatter of chunk c: wave w owns Gaussians [c kChunk + 64 w, +64).  Its
+// instances of tile t go after the chunk's first slot choff[c][t] and the
+// instances of tile t owned by waves < w.  ABS: the four waves' absolute next
+// slots per tile live in LDS (u32, grids up to kChunkTilesAbs tiles);
+// otherwise 16-bit relative counts (at most 64 per wave and tile) are added
+// to choff[c][t] read per instance.
+template <bool ABS>
+__global__ void __launch_bounds__(kBlock)
+k_chunk_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
+                const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles, int tile_w, int tile_h,
+                const float4 *__restrict__ rec0, const float4 *__restrict__ rec1, const uint2 *__restrict__ pbox,
+                const uint32_t *__restrict__ choff, const Header *__restrict__ h, uint32_t *__restrict__ tval) {
+  using Slot = typename std::conditional<ABS, uint32_t, uint16_t>::type;
+  extern __shared__ uint32_t lds_raw[];
+  Slot *rel = reinterpret_cast<Slot *>(lds_raw);  // [4][tiles]
+  if (h->overflow) return;  // the ranges are empty; nothing may be written past the capacity
+  const int nact = n_active ? (int)*n_active : grid_n;
+  const int w = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < 4 * tiles; t += kBlock) rel[t] = 0;
+  __syncthreads();
+  const int jb = blockIdx.x * kChunk + w * kWave;
+  const int j1 = (blockIdx.x * kChunk + kChunk) < nact ? (blockIdx.x * kChunk + kChunk) : nact;
+  const int ng = jb < j1 ? ((j1 - jb) < kWave ? (j1 - jb) : kWave) : 0;
+  const WaveGaussians q = load_wave_gaussians<true>(dkey, dval, rect, jb + __lane_id(), j1, rec0, rec1, pbox);
+  Slot *mine = rel + w * tiles;
+  // per-wave counts (each Gaussian's tiles are distinct; Gaussians in program order)
+  for_wave_instances(q, ng, tiles_x, [&](int, uint32_t t, uint32_t, uint32_t) { mine[t] = (Slot)(mine[t] + 1); });
+  __syncthreads();
+  const uint32_t *row = choff + (int64_t)blockIdx.x * tiles;
+  for (int t = threadIdx.x; t < tiles; t += kBlock) {  // counts -> first slot of each wave
+    const uint32_t a = rel[t], b = rel[tiles + t], c = rel[2 * tiles + t];
+    const uint32_t base = ABS ? row[t] : 0u;
+    rel[t] = (Slot)base;
+    rel[tiles + t] = (Slot)(base + a);
+    rel[2 * tiles + t] = (Slot)(base + a + b);
+    rel[3 * tiles + t] = (Slot)(base + a + b + c);
+  }
+  __syncthreads();
+  // per Gaussian of the wave: the reciprocals of the reach test, once
+  const float ia = -0.5f * __builtin_amdgcn_rcpf(q.r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(q.r1.z);
+  for (int g = 0; g < ng; ++g) {
+    const uint32_t gx = readlane_u(q.rx, g), gy = readlane_u(q.ry, g);
+    const uint32_t x0 = gx & 0xFFFFu, y0 = gx >> 16, x1 = gy & 0xFFFFu, y1 = gy >> 16;
+    if (x1 <= x0 || y1 <= y0) continue;
+    const uint32_t nx = x1 - x0, area = nx * (y1 - y0);
+    const uint32_t id = readlane_u(q.id, g);
+    const float u = readlane_f(q.r0.x, g), v = readlane_f(q.r0.y, g), lo = readlane_f(q.r0.z, g);
+    const float A = readlane_f(q.r1.x, g), B = readlane_f(q.r1.y, g), C = readlane_f(q.r1.z, g);
+    const float gia = readlane_f(ia, g), gic = readlane_f(ic, g);
+    const uint32_t pbx = readlane_u(q.pb.x, g), pby = readlane_u(q.pb.y, g);
+    const float need = kQSkip - 0.01f - lo;
+    for (uint32_t k = __lane_id(); k < area; k += kWave) {
+      const uint32_t dy = k / nx, tx = x0 + (k - dy * nx), ty = y0 + dy;
+      const uint32_t t = ty * (uint32_t)tiles_x + tx;
+      const uint32_t slot = ABS ? (uint32_t)mine[t] : row[t] + (uint32_t)mine[t];
+      mine[t] = (Slot)(mine[t] + 1);
+      // which of the tile's four 8x8 wave blocks the Gaussian reaches (as block_reach_mask)
+      const int tpx = (int)tx * tile_w, tpy = (int)ty * tile_h;
+      const int px0 = (int)(pbx & 0xFFFFu) - tpx, py0 = (int)(pbx >> 16) - tpy;
+      const int px1 = (int)(pby & 0xFFFFu) - tpx, py1 = (int)(pby >> 16) - tpy;
+      // every pixel of the tile reached: all four blocks, no per-block search
+      const float ftx = (float)tpx + 0.5f, fty = (float)tpy + 0.5f;
+      const bool whole = box_all_reach(A, B, C, u - (ftx + (float)(tile_w - 1)), u - ftx,
+                                       v - (fty + (float)(tile_h - 1)), v - fty, need);
+      uint32_t mask = whole ? 0xFu : 0u;
+#pragma unroll
+      for (int wb = 0; wb < 4; ++wb) {
+        if (whole) break;
+        const int bx = wave_block_x0(wb, tile_w), by = wave_block_y0(wb, tile_w);
+        if (px0 < bx + 8 && px1 > bx && py0 < by + 8 && py1 > by) {
+          const float cx0 = (float)(tpx + bx) + 0.5f, cy0 = (float)(tpy + by) + 0.5f;
+          if (box_reaches(A, B, C, gia, gic, u - (cx0 + 7.0f), u - cx0, v - (cy0 + 7.0f), v - cy0, need))
+            mask |= 1u << wb;
+        }
+      }
+      tval[slot] = id | (mask << kMaskShift);
+    }
+  }
+}
+
+void launch_chunk_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+                          int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
+                          const float4 *rec1, const uint2 *pbox, const uint2 *ranges, const Header *h,
+                          uint32_t *chist, uint32_t *segsum, uint32_t *tval, hipStream_t st) {
+  const int chunks = (int)ceil_div(grid_n, kChunk);
+  if (chunks <= 0) return;
+  const int tiles = tiles_x * tiles_y;
+  const int nseg = (int)ceil_div(chunks, kSegChunks);
+  const dim3 tg((unsigned)ceil_div(tiles, kBlock), (unsigned)nseg);
+  k_chunk_hist<<<chunks, kBlock, sizeof(uint32_t) * (size_t)tiles, st>>>(dkey, dval, rect, n_active, grid_n,
+                                                                       tiles_x, tiles, chist);
+  k_chunk_segsum<<<tg, kBlock, 0, st>>>(chist, chunks, tiles, segsum);
+  k_chunk_offsets<<<tg, kBlock, 0, st>>>(chist, segsum, ranges, chunks, tiles);
+  if (tiles <= kChunkTilesAbs)
+    k_chunk_scatter<true><<<chunks, kBlock, sizeof(uint32_t) * 4 * (size_t)tiles, st>>>(
+        dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
+  else
+    k_chunk_scatter<false><<<chunks, kBlock, sizeof(uint16_t) * 4 * (size_t)tiles, st>>>(
+        dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
+
+}
+
 void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
-                        int grid_n, int tiles_x, int tiles_y, const Header *h, uint32_t *tdiff, uint32_t *tcnt,
+                        int grid_n, int tiles_x, int tiles_y, Header *h, uint32_t *tdiff, uint32_t *tcnt,
                         uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st) {
   const int tiles = tiles_x * tiles_y;
   const int64_t ne = (int64_t)(tiles_x + 1) * (tiles_y + 1);

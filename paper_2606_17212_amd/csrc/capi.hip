@@ -183,11 +183,24 @@ void project_and_count(const Call &cl, void *ws, bool list_mode, hipStream_t st)
   launch_radix_sort(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.dkey1),
                     at<uint32_t>(ws, L.dval1), nact, 0, n, 0, 32, at<uint32_t>(ws, L.hist),
                     at<unsigned long long>(ws, L.part), st);
+  if (tile_ranges_in_lds(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
+    // per-tile counts, ranges and the instance count straight from the rectangles
+    launch_tile_ranges(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
+                       cl.tiling.tiles_x, cl.tiling.tiles_y, h, at<uint32_t>(ws, L.tdiff), at<uint32_t>(ws, L.tcnt),
+                       at<uint32_t>(ws, L.tstart), at<unsigned long long>(ws, L.part), at<uint2>(ws, L.ranges), st);
+    return;
+  }
   launch_count(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
                at<uint32_t>(ws, L.cnt), st);
   // offsets go to dkey1 (free after the depth sort)
   launch_scan_u32(at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.dkey1), n, at<unsigned long long>(ws, L.part),
                   &h->instances, st);
+}
+
+// Buffer holding the tile-sorted values after a binning.
+const uint32_t *sorted_vals(const Call &cl, void *ws) {
+  const int passes = (cl.tiling.tile_bits + 7) / 8;
+  return (passes & 1) ? at<uint32_t>(ws, cl.L.tval1) : at<uint32_t>(ws, cl.L.tval0);
 }
 
 // Emission, tile sort and ranges; returns the sorted Gaussian ids.
@@ -196,6 +209,15 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
   Header *h = at<Header>(ws, L.header);
   const int n = cl.s.n;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
+  if (tile_ranges_in_lds(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
+    // the ranges exist already (project_and_count); one pass puts every instance in place
+    uint32_t *out = const_cast<uint32_t *>(sorted_vals(cl, ws));
+    launch_chunk_scatter(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
+                         cl.tiling.tiles_x, cl.tiling.tiles_y, cl.t.tile_w, cl.t.tile_h, at<float4>(ws, L.rec0),
+                         at<float4>(ws, L.rec1), at<uint2>(ws, L.pbox), at<uint2>(ws, L.ranges), h,
+                         at<uint32_t>(ws, L.chist), at<uint32_t>(ws, L.segsum), out, st);
+    return out;
+  }
   launch_emit(at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey1),
               at<uint32_t>(ws, L.cnt), nact, n, cl.t.tiles_x, cl.t.tile_w, cl.t.tile_h, at<float4>(ws, L.rec0),
               at<float4>(ws, L.rec1), at<uint2>(ws, L.pbox), h, at<uint32_t>(ws, L.tkey0), at<uint32_t>(ws, L.tval0),
@@ -211,10 +233,6 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
   return r ? at<uint32_t>(ws, L.tval1) : at<uint32_t>(ws, L.tval0);
 }
 
-const uint32_t *sorted_vals(const Call &cl, void *ws) {
-  const int passes = (cl.tiling.tile_bits + 7) / 8;
-  return (passes & 1) ? at<uint32_t>(ws, cl.L.tval1) : at<uint32_t>(ws, cl.L.tval0);
-}
 
 // 0 automatic, 1 persistent, 2 grid (validated by check_tuning)
 int launch_kind(const dgs_tuning *tun) {

@@ -35,24 +35,44 @@ __host__ __device__ inline int wave_block_x0(int w, int tw) { return (w * 8) % t
 __host__ __device__ inline int wave_block_y0(int w, int tw) { return ((w * 8) / tw) * 8; }
 
 // Largest value of the exponent A' X^2 + B' X Y + C' Y^2 (negative definite)
-// over the box X in [xl, xh], Y in [yl, yh]: 0 when the box holds the origin,
-// otherwise on an edge, at the clamped 1D maximiser X* = B Y ia, Y* = B X ic
-// with ia = -1/(2 A), ic = -1/(2 C).  An inexact maximiser only lowers the
-// value found by a second-order amount, which the caller's margin absorbs.
+// over the box X in [xl, xh], Y in [yl, yh]: 0 when the box holds the origin.
+// Otherwise the maximum lies on an edge facing the origin (from any other
+// boundary point the segment towards the origin enters the box and the
+// concave exponent increases along it), at most one X edge and one Y edge,
+// at the clamped 1D maximiser X* = B Y ia, Y* = B X ic with ia = -1/(2 A),
+// ic = -1/(2 C).  An inexact maximiser only lowers the value found by a
+// second-order amount, which the caller's margin absorbs.
 __device__ inline float box_max_exponent(float A, float B, float C, float ia, float ic, float xl, float xh,
                                          float yl, float yh) {
-  if (xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f) return 0.0f;
+  const bool inx = xl <= 0.0f && xh >= 0.0f, iny = yl <= 0.0f && yh >= 0.0f;
+  if (inx && iny) return 0.0f;
   float best = -INFINITY;
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const float X = e ? xh : xl;
+  if (!inx) {
+    const float X = xl > 0.0f ? xl : xh;
     const float Y = fminf(fmaxf(B * X * ic, yl), yh);
+    best = fmaf(A * X, X, fmaf(B * X, Y, C * Y * Y));
+  }
+  if (!iny) {
+    const float Y = yl > 0.0f ? yl : yh;
+    const float X = fminf(fmaxf(B * Y * ia, xl), xh);
     best = fmaxf(best, fmaf(A * X, X, fmaf(B * X, Y, C * Y * Y)));
-    const float Yb = e ? yh : yl;
-    const float Xb = fminf(fmaxf(B * Yb * ia, xl), xh);
-    best = fmaxf(best, fmaf(A * Xb, Xb, fmaf(B * Xb, Yb, C * Yb * Yb)));
   }
   return best;
+}
+
+__device__ inline bool box_reaches(float A, float B, float C, float ia, float ic, float xl, float xh, float yl,
+                                   float yh, float need) {
+  return box_max_exponent(A, B, C, ia, ic, xl, xh, yl, yh) >= need;
+}
+
+// Whether every pixel centre of a box reaches `need`: the exponent is concave,
+// so its minimum over the box is at a corner.
+__device__ inline bool box_all_reach(float A, float B, float C, float xl, float xh, float yl, float yh, float need) {
+  const float q00 = fmaf(A * xl, xl, fmaf(B * xl, yl, C * yl * yl));
+  const float q01 = fmaf(A * xl, xl, fmaf(B * xl, yh, C * yh * yh));
+  const float q10 = fmaf(A * xh, xh, fmaf(B * xh, yl, C * yl * yl));
+  const float q11 = fmaf(A * xh, xh, fmaf(B * xh, yh, C * yh * yh));
+  return fminf(fminf(q00, q01), fminf(q10, q11)) >= need;
 }
 
 // Scene parameters passed by value to kernels.
@@ -99,6 +119,8 @@ struct Layout {
   size_t hist;               // u32 radix histograms
   size_t ranges;             // uint2 [tiles]
   size_t tdiff;              // u32 [(tiles_y+1)(tiles_x+1)]: 2D difference array of tile coverage
+  size_t chist;              // u32 [chunks][tiles]: per-chunk instance counts, then first slots
+  size_t segsum;             // u32 [segments][tiles]
   size_t tcnt, tstart;       // u32 [tiles]: instances per tile and their exclusive scan
   size_t grad2d;             // f32 [9][n]
   size_t plhist;             // u32 [P*4]: Gaussians per (packet, layer)
@@ -114,6 +136,11 @@ struct Layout {
   int64_t scan_parts;        // entries of the partials buffer
 };
 
+constexpr int kDiffLds = 12288;   // tile-coverage entries held in LDS (48 KB): (tiles_x + 1) (tiles_y + 1)
+constexpr int kChunk = 256;       // depth-ordered Gaussians per workgroup of the one-pass instance scatter
+constexpr int kChunkTiles = 8192; // tiles whose per-wave 16-bit counts fit one workgroup's LDS (64 KB)
+constexpr int kChunkTilesAbs = 4096;  // tiles whose per-wave 32-bit slots fit it
+constexpr int kSegChunks = 32;    // chunks per segment of its offset scan
 constexpr int kSortIpt = 16;
 constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per radix workgroup
 constexpr int kScanTile = kBlock * 16;        // 4096 values per scan workgroup
@@ -156,6 +183,13 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   L.hist = take(4 * hist_entries);
   L.ranges = take(8 * (tiles > 0 ? tiles : 1));
   L.tdiff = take(4 * (tiles_x + 1) * (tiles_y + 1));
+  {
+    const int64_t chunks = ceil_div(nn, kChunk), segs = ceil_div(chunks, kSegChunks);
+    // the one-pass scatter's condition
+    const bool lds_grid = (tiles_x + 1) * (tiles_y + 1) <= kDiffLds && tiles <= kChunkTiles;
+    L.chist = take(lds_grid ? 4 * chunks * (tiles > 0 ? tiles : 1) : 4);
+    L.segsum = take(lds_grid ? 4 * segs * (tiles > 0 ? tiles : 1) : 4);
+  }
   L.tcnt = take(4 * (tiles > 0 ? tiles : 1));
   L.tstart = take(4 * (tiles > 0 ? tiles : 1));
   L.grad2d = take(4 * 9 * nn);

@@ -70,6 +70,26 @@ def test_geometry_keys_rects_and_lists_bit_exact(tiny, tile):
     assert np.array_equal(sec["sorted_ids"].numpy()[:M].astype(np.int64), ids)
     # FP32 projection against the FP64 definition
     g = oracle.geometry_f64(w.scene, w.camera, w.basis)
+    # wave-block reach masks are conservative: a tile's 8x8 block holding a
+    # pixel centre where the Gaussian's FP64 alpha >= (1/255)(1 + 1e-3) has its bit set
+    masks = sec["wave_masks"].numpy()[:M].astype(np.int64)
+    tile_of = np.repeat(np.arange(ranges.shape[0]), ranges[:, 1] - ranges[:, 0])
+    tiles_x = sec["tiles_x"]
+    need_any = np.zeros((M, 4), bool)
+    for b in range(4):
+        bx, by = (8 * b) % tile[0], ((8 * b) // tile[0]) * 8
+        px = (tile_of % tiles_x) * tile[0] + bx
+        py = (tile_of // tiles_x) * tile[1] + by
+        for dy in range(8):
+            for dx in range(8):
+                x = px + dx + 0.5 - g["u"][ids]
+                y = py + dy + 0.5 - g["v"][ids]
+                q = g["conA"][ids] * x * x + 2 * g["conB"][ids] * x * y + g["conC"][ids] * y * y
+                inside = (px + dx < w.camera.width) & (py + dy < w.camera.height)
+                need_any[:, b] |= inside & (g["o"][ids] * np.exp(-0.5 * q) >= (1 / 255) * (1 + 1e-3))
+    bits = (masks[:, None] >> np.arange(4)[None, :]) & 1
+    assert not np.any(need_any & (bits == 0)), "a reached wave block has no mask bit"
+    assert bits.sum() < 4 * M  # and the masks do cull blocks
     rec0, rec1, rec2 = (sec[k].numpy().astype(np.float64) for k in ("rec0", "rec1", "rec2"))
     assert np.max(np.abs(rec0[valid, 0] - g["u"][valid])) < 2e-4
     assert np.max(np.abs(rec0[valid, 1] - g["v"][valid])) < 2e-4
