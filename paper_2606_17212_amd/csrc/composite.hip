@@ -72,6 +72,23 @@ struct StageRec {
   float4 col;  // r, g, b, -
 };
 
+// A copy of an LDS pointer that the compiler must keep in a vector register
+// (reads through it stay LDS reads).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using lds_cptr = const __attribute__((address_space(3))) T *;
+
+template <typename T>
+__device__ __forceinline__ lds_cptr<T> vgpr_lds_ptr(const T *p) {
+  uint32_t a = (uint32_t)(uintptr_t)(lds_cptr<T>)p;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(a) : "s"(a));
+  return (lds_cptr<T>)(uintptr_t)a;
+}
+#else  // the host pass only parses device code
+template <typename T>
+__device__ __forceinline__ const T *vgpr_lds_ptr(const T *p) { return p; }
+#endif
+
 struct Stage {
   uint32_t vis[4][kBlock];  // per wave: delivery bits of the entry, 0 if it misses the wave's block
   StageRec rec[kBlock];     // one 48-byte record per entry: one LDS base address per entry
@@ -148,7 +165,10 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
       }
       const uint4 v4 = *reinterpret_cast<const uint4 *>(&st.vis[wv][k0]);
       const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
-      const StageRec *rp = &st.rec[k0];
+      // The record address is wave-uniform; held in a vector register (one
+      // move per four entries) the reads below use it with immediate offsets
+      // instead of a move from a scalar register before every read.
+      const StageRec *rp = vgpr_lds_ptr(&st.rec[k0]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (k0 + j >= cnt) break;
@@ -160,7 +180,9 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
           for (int s = 0; s < S; ++s) lane_alive |= (T[s] > 0.0f ? 1u : 0u) << s;
           n_alpha += (uv & lane_alive) ? 1u : 0u;
         }
-        const float q = splat_q(rp[j].p0, rp[j].p1, fpx, fpy);
+        const float4 P0 = rp[j].p0;
+        const float2 P1 = rp[j].p1;
+        const float q = splat_q(P0, P1, fpx, fpy);
         if (MODE == 2 && lane == 0) {
           ++n_wave_alpha;
           n_wave_miss += __ballot(q >= kQSkip) == 0ull ? 1u : 0u;
