@@ -214,3 +214,37 @@ def present_mask(scene, codes_row) -> np.ndarray:
     """bool [N]: Gaussian present under one state's codes (layer < code)."""
     pl = scene.packet_layer.astype(np.int64)
     return (pl & 3) < np.asarray(codes_row, np.int64)[pl >> 2]
+
+
+# ----------------------------------------------------------- state sampler
+class _Channel(ctypes.Structure):
+    _fields_ = [("p_gb", ctypes.c_float), ("p_bg", ctypes.c_float), ("loss_good", ctypes.c_float),
+                ("loss_bad", ctypes.c_float), ("p_start_bad", ctypes.c_float), ("deadline", ctypes.c_int32)]
+
+
+CHANNEL_DTYPE = np.dtype([("p_gb", np.float32), ("p_bg", np.float32), ("loss_good", np.float32),
+                          ("loss_bad", np.float32), ("p_start_bad", np.float32), ("deadline", np.int32)])
+
+
+def philox4x32_10(counter, key) -> np.ndarray:
+    """Philox4x32-10 of a 4-word counter under a 2-word key."""
+    c = np.ascontiguousarray(counter, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(c.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
+                           out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def sample_states(channels: np.ndarray, num_packets: int, num_layers: int, seed: int) -> np.ndarray:
+    """Delivery codes [W][P] of the Gilbert-Elliott / deadline sampler
+    (``channels``: structured array of CHANNEL_DTYPE, one per world)."""
+    ch = np.ascontiguousarray(channels, dtype=CHANNEL_DTYPE)
+    W = ch.shape[0]
+    codes = np.zeros((W, num_packets), dtype=np.uint8)
+    rc = lib().or_sample_states(ch.ctypes.data_as(ctypes.c_void_p), ctypes.c_int(W), ctypes.c_int(num_packets),
+                                ctypes.c_int(num_layers), ctypes.c_uint64(seed),
+                                codes.ctypes.data_as(ctypes.c_void_p))
+    assert rc == 0
+    return codes
+

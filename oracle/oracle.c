@@ -447,3 +447,92 @@ int or_render(const or_scene *s, const or_camera *cam, const float *basis, int n
   free(geo); free(mf); free(rect); free(valid);
   return err;
 }
+
+/* ------------------------------------------------------------------------
+ * Delivery-state sampler (Sec. 4: a training world samples erasures from an
+ * IID process and a Gilbert-Elliott burst process; dependencies are enforced
+ * after delivery and turned into cluster-layer masks).
+ *
+ * Every (packet p, layer l) is one datagram, sent layer-major (all base
+ * layers, then every first refinement, ...): slot s = l P + p.  The channel
+ * of world w is a two-state Markov chain (good / bad) over the slots: the
+ * datagram of slot s is erased with the loss probability of the current
+ * state, then the chain moves (good -> bad with p_gb, bad -> good with p_bg);
+ * the first state is bad with probability p_start_bad.  Datagrams of slots
+ * >= deadline arrive too late (deadline < 0: none).  Layer l of packet p is
+ * usable when layers 0..l all arrived, so the state's code for p is the
+ * number of leading arrived layers.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
+ * the 64-bit seed, counter (s / 2, w, 0x44475331, 0) for slot s: outputs
+ * (x0, x1) serve even slots and (x2, x3) odd ones as (erasure, transition)
+ * draws; counter (0xffffffff, w, 0x44475331, 0) output x0 draws the first
+ * state.  An event of probability p happens when the draw is below
+ * floor(p 2^32) (p <= 0: never; p >= 1: always).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  float p_gb, p_bg, loss_good, loss_bad, p_start_bad;
+  int32_t deadline;
+} or_channel;
+
+static const uint32_t OR_SAMPLER_TAG = 0x44475331u;
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static uint64_t or_threshold(float p) {
+  if (!(p > 0.0f)) return 0;
+  if (p >= 1.0f) return (uint64_t)1 << 32;
+  return (uint64_t)floor((double)p * 4294967296.0);
+}
+
+int or_sample_states(const or_channel *ch, int num_states, int P, int L, uint64_t seed, uint8_t *codes) {
+  if (num_states < 0 || P < 1 || L < 1 || L > 4) return 1;
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const int n = L * P;
+  uint8_t *arrived = (uint8_t *)malloc((size_t)n);
+  if (!arrived) return 2;
+  for (int w = 0; w < num_states; ++w) {
+    const or_channel c = ch[w];
+    uint32_t out[4];
+    uint32_t ctr[4] = {0xffffffffu, (uint32_t)w, OR_SAMPLER_TAG, 0u};
+    or_philox4x32_10(ctr, key, out);
+    int bad = (uint64_t)out[0] < or_threshold(c.p_start_bad);
+    for (int s = 0; s < n; ++s) {
+      const uint32_t cs[4] = {(uint32_t)(s >> 1), (uint32_t)w, OR_SAMPLER_TAG, 0u};
+      or_philox4x32_10(cs, key, out);
+      const uint32_t u_loss = (s & 1) ? out[2] : out[0];
+      const uint32_t u_move = (s & 1) ? out[3] : out[1];
+      int lost = (uint64_t)u_loss < or_threshold(bad ? c.loss_bad : c.loss_good);
+      if (c.deadline >= 0 && s >= c.deadline) lost = 1;
+      arrived[s] = (uint8_t)!lost;
+      if (!bad) {
+        if ((uint64_t)u_move < or_threshold(c.p_gb)) bad = 1;
+      } else {
+        if ((uint64_t)u_move < or_threshold(c.p_bg)) bad = 0;
+      }
+    }
+    for (int p = 0; p < P; ++p) {
+      int code = 0;
+      while (code < L && arrived[code * P + p]) ++code;
+      codes[(int64_t)w * P + p] = (uint8_t)code;
+    }
+  }
+  free(arrived);
+  return 0;
+}
