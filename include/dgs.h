@@ -388,6 +388,47 @@ int dgs_distortion(const float *images, int32_t num_images, int32_t width, int32
 int dgs_risk_adjusted(const float *values, const int32_t *offsets, int32_t num_groups, float alpha,
                       float beta, float quantile, float *out, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Delivery states drawn on the device (Sec. 4: a training world samples
+ * erasures from an IID and a Gilbert-Elliott burst process; dependencies are
+ * enforced after delivery and become cluster-layer masks).
+ *
+ * Every (packet p, layer l) is one datagram, sent layer-major: slot
+ * s = l * num_packets + p.  A world's channel is a two-state Markov chain
+ * over the slots: the datagram of slot s is erased with the current state's
+ * loss probability, then the chain moves (good -> bad with p_gb, bad -> good
+ * with p_bg); the first state is bad with probability p_start_bad (IID
+ * erasure: p_gb = p_start_bad = 0).  Slots >= deadline arrive too late
+ * (deadline < 0: no deadline).  Layer l of packet p is usable when layers
+ * 0..l all arrived, so code[w][p] = number of leading arrived layers (the
+ * code convention of dgs_states).
+ *
+ * Draws: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed (low
+ * word first).  Counter (s / 2, w, 0x44475331, 0) gives the (erasure,
+ * transition) draws of slot s from outputs (0, 1) for even s and (2, 3) for
+ * odd s; counter (0xffffffff, w, 0x44475331, 0) output 0 draws the first
+ * state.  An event of probability p happens when its 32-bit draw is below
+ * floor(p * 2^32) (never for p <= 0, always for p >= 1).  World w's codes
+ * depend only on (seed, w, its channel), not on num_states.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  float p_gb;         /* good -> bad per datagram */
+  float p_bg;         /* bad -> good per datagram */
+  float loss_good;    /* erasure probability in the good state */
+  float loss_bad;     /* erasure probability in the bad state */
+  float p_start_bad;  /* probability that the first datagram meets the bad state */
+  int32_t deadline;   /* slots that arrive before the playout deadline; < 0: all */
+} dgs_channel;
+
+/*
+ *   channels  dgs_channel [num_states] (device)
+ *   codes     u8 [num_states][num_packets] (device, written)
+ * num_packets in 1..16384, num_layers in 1..4.  Asynchronous.  Returns
+ * DGS_OK or DGS_ERR_INVALID_ARG.
+ */
+int dgs_sample_states(const dgs_channel *channels, int32_t num_states, int32_t num_packets, int32_t num_layers,
+                      uint64_t seed, uint8_t *codes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

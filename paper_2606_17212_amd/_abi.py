@@ -22,7 +22,7 @@ EXPORTS = (
     "dgs_backward", "dgs_check", "dgs_workspace_sections", "dgs_bin", "dgs_composite",
     "dgs_composite_psnr", "dgs_composite_stats", "dgs_composite_launch", "dgs_utility_workspace_bytes",
     "dgs_utility_count", "dgs_utility", "dgs_utility_check", "dgs_distortion_scratch_bytes", "dgs_distortion",
-    "dgs_risk_adjusted",
+    "dgs_risk_adjusted", "dgs_sample_states",
 )
 
 
@@ -133,6 +133,8 @@ def lib():
     L.dgs_distortion.argtypes = [vp, i32, i32, i32, vp, fp, vp, sz, vp, vp]
     L.dgs_risk_adjusted.restype = ctypes.c_int
     L.dgs_risk_adjusted.argtypes = [vp, vp, i32, fp, fp, fp, vp, vp]
+    L.dgs_sample_states.restype = ctypes.c_int
+    L.dgs_sample_states.argtypes = [vp, i32, i32, i32, ctypes.c_uint64, vp, vp]
     _lib = L
     return L
 

@@ -776,4 +776,18 @@ int dgs_risk_adjusted(const float *values, const int32_t *offsets, int32_t num_g
   return hip_check("risk launch");
 }
 
+int dgs_sample_states(const dgs_channel *channels, int32_t num_states, int32_t num_packets, int32_t num_layers,
+                      uint64_t seed, uint8_t *codes, void *stream) {
+  g_err.clear();
+  static_assert(sizeof(dgs_channel) == sizeof(SamplerChannel), "dgs_channel layout");
+  if (num_states < 0) return fail(DGS_ERR_INVALID_ARG, "num_states < 0");
+  if (num_packets < 1 || num_packets > 16384) return fail(DGS_ERR_INVALID_ARG, "num_packets %d outside 1..16384", num_packets);
+  if (num_layers < 1 || num_layers > 4) return fail(DGS_ERR_INVALID_ARG, "num_layers %d outside 1..4", num_layers);
+  if (num_states == 0) return DGS_OK;
+  if (!channels || !codes) return fail(DGS_ERR_INVALID_ARG, "channels / codes is NULL");
+  launch_sample_states(reinterpret_cast<const SamplerChannel *>(channels), num_states, num_packets, num_layers, seed,
+                       codes, (hipStream_t)stream);
+  return hip_check("sample_states launch");
+}
+
 }  // extern "C"

@@ -198,4 +198,12 @@ void launch_distortion(const float *images, int num_images, int width, int heigh
 void launch_risk_adjusted(const float *values, const int32_t *offsets, int G, float alpha, float beta, float q,
                           float *out, hipStream_t st);
 
+// sampler.hip: delivery states drawn on the device (layout of dgs_channel)
+struct SamplerChannel {
+  float p_gb, p_bg, loss_good, loss_bad, p_start_bad;
+  int32_t deadline;
+};
+void launch_sample_states(const SamplerChannel *channels, int num_states, int P, int L, uint64_t seed,
+                          uint8_t *codes, hipStream_t st);
+
 }  // namespace dgs

@@ -11,6 +11,7 @@ import ctypes
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _abi
@@ -471,6 +472,34 @@ def risk_adjusted(values: torch.Tensor, offsets: torch.Tensor, alpha: float = 0.
         _abi.check(_abi.lib().dgs_risk_adjusted(_ptr(values), _ptr(offsets), G, float(alpha), float(beta),
                                                 float(quantile), _ptr(out), st))
     return out
+
+
+CHANNEL_DTYPE = np.dtype([("p_gb", np.float32), ("p_bg", np.float32), ("loss_good", np.float32),
+                          ("loss_bad", np.float32), ("p_start_bad", np.float32), ("deadline", np.int32)])
+
+
+def channels_to_device(channels, device) -> torch.Tensor:
+    """A structured array of CHANNEL_DTYPE (one dgs_channel per world) as
+    device bytes [W, 24] for ``sample_states``."""
+    a = np.ascontiguousarray(channels, dtype=CHANNEL_DTYPE)
+    return torch.from_numpy(a.view(np.uint8).reshape(a.shape[0], CHANNEL_DTYPE.itemsize).copy()).to(device)
+
+
+def sample_states(channels: torch.Tensor, num_packets: int, num_layers: int, seed: int, out=None) -> torch.Tensor:
+    """Delivery codes [W, num_packets] (uint8) drawn on the device from one
+    Gilbert-Elliott / deadline channel per world (``channels``: uint8 [W, 24]
+    from ``channels_to_device``)."""
+    if channels.dtype != torch.uint8 or channels.dim() != 2 or channels.shape[1] != CHANNEL_DTYPE.itemsize:
+        raise ValueError("channels must be uint8 [W, 24] (see channels_to_device)")
+    if not channels.is_contiguous():
+        raise ValueError("channels must be contiguous")
+    W = int(channels.shape[0])
+    codes = out if out is not None else torch.empty((W, int(num_packets)), dtype=torch.uint8, device=channels.device)
+    with torch.cuda.device(channels.device):
+        st = ctypes.c_void_p(torch.cuda.current_stream(channels.device).cuda_stream)
+        _abi.check(_abi.lib().dgs_sample_states(_ptr(channels), W, int(num_packets), int(num_layers),
+                                                ctypes.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), _ptr(codes), st))
+    return codes
 
 
 def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
