@@ -211,6 +211,7 @@ def main():
 
     if not args.no_utility:
         out["utility"] = utility_bench(args, dgs, synth, torch, np, dev, tw, th)
+        out["sampler"] = sampler_bench(dgs, torch, np, dev, scene.num_packets)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, np, args.cpu_seconds)
@@ -414,6 +415,35 @@ def utility_bench(args, dgs, synth, torch, np, dev, tw, th):
             "max_abs_diff_vs_full_frame": diff,
             "risk_adjusted": {"median": round(float(np.median(st[:, 3])), 8),
                               "negative_groups": int((st[:, 3] < 0).sum())}}
+
+
+def sampler_bench(dgs, torch, np, dev, num_packets):
+    """Delivery states drawn on the device: 32,768 worlds of this scene's
+    packets x 4 layers through Gilbert-Elliott channels with deadlines."""
+    W, L = 32768, 4
+    rng = np.random.default_rng(2606)
+    ch = np.zeros(W, dtype=dgs.CHANNEL_DTYPE)
+    ch["p_gb"], ch["p_bg"] = rng.uniform(0.0, 0.1, W), rng.uniform(0.1, 0.5, W)
+    ch["loss_good"], ch["loss_bad"] = rng.uniform(0.0, 0.05, W), rng.uniform(0.3, 0.9, W)
+    ch["p_start_bad"] = ch["p_gb"] / (ch["p_gb"] + ch["p_bg"])
+    ch["deadline"] = rng.integers(num_packets, L * num_packets + 1, W)
+    dch = dgs.channels_to_device(ch, dev)
+    codes = torch.empty((W, num_packets), dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        dgs.sample_states(dch, num_packets, L, 7, out=codes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for k in range(reps):
+        dgs.sample_states(dch, num_packets, L, 7 + k, out=codes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    log(f"[bench] sampler: {W} worlds x {num_packets} packets x {L} layers in {ms:.3f} ms -> "
+        f"{W / (ms / 1e3):.3g} states/s; mean code {codes.float().mean().item():.3f}")
+    return {"worlds": W, "packets": num_packets, "layers": L, "ms": round(ms, 4),
+            "states_per_s": round(W / (ms / 1e3), 1)}
 
 
 def cpu_baseline(w, np, seconds):
