@@ -422,8 +422,13 @@ __device__ __forceinline__ float wave_sum_to_lane63(float x) {
 //   dL/dc_k     = g T_k a_k
 //   dL/da_k     = T_k (g . c_k) - (g . rem_k) / (1 - a_k)
 // summed over the group's states; then, below the 0.99 cap, through
-// a = 2^q' to (u, v, A', B', C', log2 o), reduced over the wave and added to
-// the Gaussian's 2D gradient with one atomic per value.
+// a = 2^q' to (u, v, A', B', C', log2 o), reduced over the wave with DPP,
+// stored per wave in LDS for a window of 64 entries, folded over the four
+// waves and added to the Gaussian's 2D gradient with one atomic per value
+// and entry.
+constexpr int kBwdWindow = 64;  // entries per fold of the backward's per-wave gradient sums
+constexpr int kBwdVals = 12;    // nine values, padded for 16-byte stores
+
 template <int S, int TW, int TH>
 __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
   int kpos, grp;
@@ -455,10 +460,12 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
   }
 
   __shared__ Stage st;
-  // per-entry gradient sums of the workgroup's waves: [value][entry]
-  __shared__ float red[9][kBlock];
+  // per-entry gradient sums of each wave over a window of kBwdWindow entries:
+  // [wave][entry][value] (plain stores, folded once per window)
+  __shared__ float red[4][kBwdWindow][kBwdVals];
   const uint2 rg = a.ranges[tile];
   const uint32_t *vis = a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr;
+  float *red_flat = &red[0][0][0];
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
     int alive = 0;
 #pragma unroll
@@ -466,83 +473,79 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
     if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
-#pragma unroll
-    for (int v = 0; v < 9; ++v) red[v][tid] = 0.0f;
-    __syncthreads();
     const int cnt = (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock);
-    uint32_t wave_alive = 0;
-    for (int k = 0; k < cnt; ++k) {
-      if ((k & 63) == 0) {
-        wave_alive = 0;
+    for (int w0 = 0; w0 < cnt; w0 += kBwdWindow) {
+      for (int i = tid; i < 4 * kBwdWindow * kBwdVals; i += kBlock) red_flat[i] = 0.0f;
+      __syncthreads();  // stage (first window) and cleared sums visible
+      const int w1 = (w0 + kBwdWindow) < cnt ? (w0 + kBwdWindow) : cnt;
+      uint32_t wave_alive = 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-          if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
-      }
-      const uint32_t uv = __builtin_amdgcn_readfirstlane(st.vis[wv][k]) & wave_alive;
-      if (uv == 0u) continue;
-      const float4 P0 = st.rec[k].p0;
-      const float2 P1 = st.rec[k].p1;
-      const float q = splat_q(P0, P1, fpx, fpy);
-      const bool hit = q >= kQSkip;
-      if (!__ballot(hit)) continue;
-      float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f;
-      float gu = 0.0f, gv = 0.0f, gA = 0.0f, gB = 0.0f, gC = 0.0f, glo = 0.0f;
-      if (hit) {
-        const float alpha = alpha_of(q);
-        const float4 C = st.rec[k].col;
-        const float inv1ma = 1.0f / (1.0f - alpha);
-        float d_alpha = 0.0f;
+      for (int s = 0; s < S; ++s)
+        if (__ballot(T[s] > 0.0f)) wave_alive |= 1u << s;
+      for (int k = w0; k < w1; ++k) {
+        const uint32_t uv = __builtin_amdgcn_readfirstlane(st.vis[wv][k]) & wave_alive;
+        if (uv == 0u) continue;
+        const float4 P0 = st.rec[k].p0;
+        const float2 P1 = st.rec[k].p1;
+        const float q = splat_q(P0, P1, fpx, fpy);
+        const bool hit = q >= kQSkip;
+        if (!__ballot(hit)) continue;
+        float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f;
+        float gu = 0.0f, gv = 0.0f, gA = 0.0f, gB = 0.0f, gC = 0.0f, glo = 0.0f;
+        if (hit) {
+          const float alpha = alpha_of(q);
+          const float4 C = st.rec[k].col;
+          const float inv1ma = 1.0f / (1.0f - alpha);
+          float d_alpha = 0.0f;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          if (uv & (1u << s)) {
-            const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
-            rr[s] = fmaf(-ta, C.x, rr[s]);
-            rgn[s] = fmaf(-ta, C.y, rgn[s]);
-            rb[s] = fmaf(-ta, C.z, rb[s]);
-            const float gcol = gr[s] * C.x + gg[s] * C.y + gb[s] * C.z;
-            const float grem = gr[s] * rr[s] + gg[s] * rgn[s] + gb[s] * rb[s];
-            const float Tp = fmaxf(T[s], 0.0f);
-            const float da = Tp * gcol - grem * inv1ma;
-            d_alpha += (T[s] > 0.0f) ? da : 0.0f;
-            dcr = fmaf(gr[s], ta, dcr);
-            dcg = fmaf(gg[s], ta, dcg);
-            dcb = fmaf(gb[s], ta, dcb);
-            const float Tn = T[s] - ta;
-            T[s] = (Tn < kTStop) ? -fabsf(Tn) : Tn;
+          for (int s = 0; s < S; ++s) {
+            if (uv & (1u << s)) {
+              const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
+              rr[s] = fmaf(-ta, C.x, rr[s]);
+              rgn[s] = fmaf(-ta, C.y, rgn[s]);
+              rb[s] = fmaf(-ta, C.z, rb[s]);
+              const float gcol = gr[s] * C.x + gg[s] * C.y + gb[s] * C.z;
+              const float grem = gr[s] * rr[s] + gg[s] * rgn[s] + gb[s] * rb[s];
+              const float Tp = fmaxf(T[s], 0.0f);
+              const float da = Tp * gcol - grem * inv1ma;
+              d_alpha += (T[s] > 0.0f) ? da : 0.0f;
+              dcr = fmaf(gr[s], ta, dcr);
+              dcg = fmaf(gg[s], ta, dcg);
+              dcb = fmaf(gb[s], ta, dcb);
+              const float Tn = T[s] - ta;
+              T[s] = (Tn < kTStop) ? -fabsf(Tn) : Tn;
+            }
+          }
+          // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap passes nothing
+          if (alpha < kAlphaMax) {
+            const float dq = d_alpha * alpha * 0.69314718055994531f;
+            const float dx = P0.x - fpx, dy = P0.y - fpy;
+            gu = dq * (2.0f * P0.w * dx + P1.x * dy);
+            gv = dq * (P1.x * dx + 2.0f * P1.y * dy);
+            gA = dq * dx * dx;
+            gB = dq * dx * dy;
+            gC = dq * dy * dy;
+            glo = dq;
           }
         }
-        // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap passes nothing
-        if (alpha < kAlphaMax) {
-          const float dq = d_alpha * alpha * 0.69314718055994531f;
-          const float dx = P0.x - fpx, dy = P0.y - fpy;
-          gu = dq * (2.0f * P0.w * dx + P1.x * dy);
-          gv = dq * (P1.x * dx + 2.0f * P1.y * dy);
-          gA = dq * dx * dx;
-          gB = dq * dx * dy;
-          gC = dq * dy * dy;
-          glo = dq;
+        gu = wave_sum_to_lane63(gu); gv = wave_sum_to_lane63(gv); gA = wave_sum_to_lane63(gA);
+        gB = wave_sum_to_lane63(gB); gC = wave_sum_to_lane63(gC); glo = wave_sum_to_lane63(glo);
+        dcr = wave_sum_to_lane63(dcr); dcg = wave_sum_to_lane63(dcg); dcb = wave_sum_to_lane63(dcb);
+        if (lane == 63) {  // this wave's sums for entry k: three plain LDS stores
+          float *o = red[wv][k - w0];
+          *reinterpret_cast<float4 *>(o) = make_float4(gu, gv, gA, gB);
+          *reinterpret_cast<float4 *>(o + 4) = make_float4(gC, glo, dcr, dcg);
+          o[8] = dcb;
         }
       }
-      gu = wave_sum_to_lane63(gu); gv = wave_sum_to_lane63(gv); gA = wave_sum_to_lane63(gA);
-      gB = wave_sum_to_lane63(gB); gC = wave_sum_to_lane63(gC); glo = wave_sum_to_lane63(glo);
-      dcr = wave_sum_to_lane63(dcr); dcg = wave_sum_to_lane63(dcg); dcb = wave_sum_to_lane63(dcb);
-      if (lane == 63) {  // LDS float atomics fold the four waves together
-        atomicAdd(&red[0][k], gu); atomicAdd(&red[1][k], gv); atomicAdd(&red[2][k], gA);
-        atomicAdd(&red[3][k], gB); atomicAdd(&red[4][k], gC); atomicAdd(&red[5][k], glo);
-        atomicAdd(&red[6][k], dcr); atomicAdd(&red[7][k], dcg); atomicAdd(&red[8][k], dcb);
+      __syncthreads();
+      // fold the four waves; one atomic per value and entry for the workgroup
+      for (int i = tid; i < (w1 - w0) * 9; i += kBlock) {
+        const int k = i / 9, v = i - k * 9;
+        const float sum = red[0][k][v] + red[1][k][v] + red[2][k][v] + red[3][k][v];
+        if (sum != 0.0f) unsafeAtomicAdd(a.g2d + (int64_t)v * a.n + st.id[w0 + k], sum);
       }
-    }
-    __syncthreads();
-    // one atomic per value and entry for the whole workgroup
-    if (e < rg.y) {
-      const uint32_t id = st.id[tid];
-      float *g = a.g2d;
-      const int64_t n = a.n;
-#pragma unroll
-      for (int v = 0; v < 9; ++v) {
-        const float sum = red[v][tid];
-        if (sum != 0.0f) unsafeAtomicAdd(g + v * n + id, sum);
-      }
+      __syncthreads();  // sums read before the next window clears them
     }
   }
 }
