@@ -396,21 +396,33 @@ void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int
 
 // ------------------------------------------------------------------ backward
 
-// Sum over the wave, valid in lane 63: inclusive row scans with DPP row
-// shifts (16-lane rows), then row broadcasts of lanes 15 and 31 into the rows
-// above.  Six VALU instructions, no LDS traffic.
+// One DPP step of a row scan: x plus the value CTRL moves into this lane
+// (zero where the source lies outside the row).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_step(float x) {
   const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true);
   return x + __int_as_float(y);
 }
-__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+
+// Two values folded over the wave halves into one register: lanes 0-31 hold
+// x[i] + x[i+32], lanes 32-63 hold y[i-32] + y[i] (one half swap, one add).
+__device__ __forceinline__ float half_pair_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// Two half-folded registers folded over row pairs into one: row 0 holds the
+// sum of x's rows 0-1, row 1 of y's rows 0-1, row 2 of x's rows 2-3, row 3
+// of y's rows 2-3.
+__device__ __forceinline__ float row_pair_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// Inclusive scan within each 16-lane row: lane 15 of a row holds its sum.
+__device__ __forceinline__ float row_sum_to_lane15(float x) {
   x = dpp_step<0x111, 0xf>(x);  // row_shr:1
   x = dpp_step<0x112, 0xf>(x);  // row_shr:2
   x = dpp_step<0x114, 0xf>(x);  // row_shr:4
   x = dpp_step<0x118, 0xf>(x);  // row_shr:8
-  x = dpp_step<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x = dpp_step<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
@@ -422,12 +434,12 @@ __device__ __forceinline__ float wave_sum_to_lane63(float x) {
 //   dL/dc_k     = g T_k a_k
 //   dL/da_k     = T_k (g . c_k) - (g . rem_k) / (1 - a_k)
 // summed over the group's states; then, below the 0.99 cap, through
-// a = 2^q' to (u, v, A', B', C', log2 o), reduced over the wave with DPP,
-// stored per wave in LDS for a window of 64 entries, folded over the four
+// a = 2^q' to (u, v, A', B', C', log2 o), reduced over the wave with lane
+// swaps and DPP, stored per wave in LDS for a window of 64 entries, folded over the four
 // waves and added to the Gaussian's 2D gradient with one atomic per value
 // and entry.
 constexpr int kBwdWindow = 64;  // entries per fold of the backward's per-wave gradient sums
-constexpr int kBwdVals = 12;    // nine values, padded for 16-byte stores
+constexpr int kBwdVals = 12;    // nine values, padded to a 16-byte multiple
 
 template <int S, int TW, int TH>
 __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
@@ -528,14 +540,20 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
             glo = dq;
           }
         }
-        gu = wave_sum_to_lane63(gu); gv = wave_sum_to_lane63(gv); gA = wave_sum_to_lane63(gA);
-        gB = wave_sum_to_lane63(gB); gC = wave_sum_to_lane63(gC); glo = wave_sum_to_lane63(glo);
-        dcr = wave_sum_to_lane63(dcr); dcg = wave_sum_to_lane63(dcg); dcb = wave_sum_to_lane63(dcb);
-        if (lane == 63) {  // this wave's sums for entry k: three plain LDS stores
+        // the nine wave sums share their steps: halves, then row pairs fold
+        // values into registers that hold four (one per row), then row scans;
+        // register q0 ends with rows (gu, gA, gv, gB), q1 with (gC, dcr, glo,
+        // dcg), q2 with dcb in every row
+        const float q0 = row_sum_to_lane15(row_pair_sum(half_pair_sum(gu, gv), half_pair_sum(gA, gB)));
+        const float q1 = row_sum_to_lane15(row_pair_sum(half_pair_sum(gC, glo), half_pair_sum(dcr, dcg)));
+        const float d8 = half_pair_sum(dcb, dcb);
+        const float q2 = row_sum_to_lane15(row_pair_sum(d8, d8));
+        if ((lane & 15) == 15) {  // this wave's sums for entry k: plain LDS stores
+          const int row = lane >> 4, v = ((row & 1) << 1) | (row >> 1);
           float *o = red[wv][k - w0];
-          *reinterpret_cast<float4 *>(o) = make_float4(gu, gv, gA, gB);
-          *reinterpret_cast<float4 *>(o + 4) = make_float4(gC, glo, dcr, dcg);
-          o[8] = dcb;
+          o[v] = q0;
+          o[4 + v] = q1;
+          if (row == 0) o[8] = q2;
         }
       }
       __syncthreads();
