@@ -9,12 +9,15 @@ Contents:
 * ``liboracle.so`` (``oracle.c``): FP64 per-pixel renderer, FP64 geometry,
   FP32 mirror of the integer decisions (culling, tile rectangles, depth keys).
 * ``tile_lists``: per-tile (depth, index) order via ``numpy.lexsort``.
+* ``refined_scene`` / ``render_refined``: attribute-level prefix refinement
+  (Sec. 3): every delivery state decodes to a plain scene, rendered as above.
 * ``grad``: FP64 dense formulation in plain PyTorch CPU ops whose autograd
   gives the exact derivative with every discrete decision frozen.
 """
 
 from __future__ import annotations
 
+import copy
 import ctypes
 import os
 
@@ -35,7 +38,8 @@ class _Scene(ctypes.Structure):
                 ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
                 ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
                 ("color", ctypes.c_void_p), ("temporal", ctypes.c_void_p),
-                ("packet_layer", ctypes.c_void_p), ("cluster_affine", ctypes.c_void_p)]
+                ("packet_layer", ctypes.c_void_p), ("cluster_affine", ctypes.c_void_p),
+                ("offset", ctypes.c_void_p)]
 
 
 class _Camera(ctypes.Structure):
@@ -77,12 +81,15 @@ class _Pinned:
         if scene.cluster_affine is not None:
             aff = _f32(scene.cluster_affine)
             self.arrs["cluster_affine"] = aff
+        off = getattr(scene, "offset", None)
+        if off is not None:
+            self.arrs["offset"] = _f32(off)
         ptr = lambda k: self.arrs[k].ctypes.data if k in self.arrs else None  # noqa: E731
         n = scene.mean.shape[1]
         self.scene = _Scene(n, scene.rank, scene.sh_degree, scene.num_clusters * scene.num_contexts,
                             scene.num_contexts, ptr("mean"), ptr("log_scale"), ptr("quat"),
                             ptr("opacity_logit"), ptr("color"), ptr("temporal"),
-                            ptr("packet_layer"), ptr("cluster_affine"))
+                            ptr("packet_layer"), ptr("cluster_affine"), ptr("offset"))
         c = _Camera()
         R = _f32(cam.R_cw).reshape(9)
         t = _f32(cam.t_cw).reshape(3)
@@ -214,6 +221,56 @@ def present_mask(scene, codes_row) -> np.ndarray:
     """bool [N]: Gaussian present under one state's codes (layer < code)."""
     pl = scene.packet_layer.astype(np.int64)
     return (pl & 3) < np.asarray(codes_row, np.int64)[pl >> 2]
+
+
+# ------------------------------------------------- attribute refinement levels
+def refine_rows(sh_degree: int) -> int:
+    """Rows of one refinement level: position residual 3, log-scale 3,
+    quaternion 4, opacity logit 1, colour 3 (RGB) or 12 (SH-1)."""
+    return 11 + (3 if sh_degree == 0 else 12)
+
+
+def refined_scene(scene, refine, codes_row):
+    """The plain scene that one delivery state decodes to (Sec. 3: scale,
+    rotation, opacity and colour are a base plus three refinements; the
+    position carries residual levels on top of Eq. (1)'s deformation).
+
+    ``refine``: float32 [3][rows][N], level j = 1..3 at index j - 1, rows as
+    in ``refine_rows``.  A Gaussian whose packet is delivered to depth d
+    (code d + 1, codes above 4 act as 4) takes base + level 1 + ... + level
+    d, summed in FP32 in that order (the storage precision of every
+    attribute); its position residual o = level 1 + ... + level d (0 at d = 0)
+    is added after the deformation.  Presence is unchanged: layer < code."""
+    refine = np.asarray(refine, np.float32)
+    n = scene.mean.shape[1]
+    rows = refine_rows(scene.sh_degree)
+    assert refine.shape == (3, rows, n), (refine.shape, (3, rows, n))
+    pl = scene.packet_layer.astype(np.int64)
+    depth = np.minimum(np.asarray(codes_row, np.int64)[pl >> 2], 4) - 1  # -1: packet absent
+    base = np.concatenate([np.zeros((3, n), np.float32), _f32(scene.log_scale), _f32(scene.quat),
+                           _f32(scene.opacity_logit).reshape(1, n), _f32(scene.color)])
+    acc = base.copy()
+    for j in range(1, 4):
+        take = depth >= j
+        acc[:, take] = acc[:, take] + refine[j - 1][:, take]
+    out = copy.copy(scene)
+    out.offset = np.ascontiguousarray(acc[:3])
+    out.log_scale = np.ascontiguousarray(acc[3:6])
+    out.quat = np.ascontiguousarray(acc[6:10])
+    out.opacity_logit = np.ascontiguousarray(acc[10])
+    out.color = np.ascontiguousarray(acc[11:])
+    return out
+
+
+def render_refined(scene, refine, cam, basis, codes, background, pixels=None) -> dict:
+    """FP64 render of a scene with refinement levels: each state's plain
+    scene (``refined_scene``) through ``render``.  Same outputs as ``render``."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    parts = [render(refined_scene(scene, refine, codes[w]), cam, basis, codes[w:w + 1], background, pixels)
+             for w in range(codes.shape[0])]
+    if not parts:
+        return render(scene, cam, basis, codes, background, pixels)
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
 
 
 # ----------------------------------------------------------- state sampler

@@ -9,8 +9,10 @@
  *  - Delivery decode: Gaussian i (packet p_i, layer l_i) is present in state w
  *    iff l_i < codes[w][p_i]; codes are post-closure cluster/context masks with
  *    a delivered prefix depth (Sec. 4, Sec. 3 "one base + three refinements").
- *  - Deformation, Eq. (1) of Sec. 3 without the residual levels:
- *        mu_i = A_c [mubar_i; 1] + sum_r b_r q_{i,r}.
+ *  - Deformation, Eq. (1) of Sec. 3:
+ *        mu_i = A_c [mubar_i; 1] + sum_r b_r q_{i,r} + o_i,
+ *    o_i = the delivered residual levels (delta terms) at the render time, or
+ *    0 when the scene carries none.
  *  - Projection: camera-frame mean, covariance R diag(e^{2s}) R^T seen through
  *    the world->camera rotation, local affine (EWA) Jacobian with its x/z and
  *    y/z arguments clamped to 1.3x the half field of view, +0.3 px^2 on the
@@ -51,6 +53,7 @@ typedef struct {
   const float *temporal;      /* [3*rank][n], row = r*3 + axis */
   const uint16_t *packet_layer; /* [n] (packet << 2) | layer */
   const float *cluster_affine;  /* [C][12] row-major 3x4, or NULL (identity) */
+  const float *offset;          /* [3][n] position residual added after the deformation, or NULL */
 } or_scene;
 
 typedef struct {
@@ -96,7 +99,7 @@ static inline float clampf(float x, float lo, float hi) {
  *   valid [n]   : 1 unless culled (z32 <= near, or det <= 0)
  * Arithmetic order (each product, quotient, sum rounded separately):
  *   mu_k  = ((A_k0 m0 + A_k1 m1) + A_k2 m2) + A_k3   (or m_k with no affine),
- *           then mu_k += b_r q_{r,k} for r = 0..R-1
+ *           then mu_k += b_r q_{r,k} for r = 0..R-1, then mu_k += o_k (offset)
  *   P_k   = ((R_k0 mu0 + R_k1 mu1) + R_k2 mu2) + t_k;  (X,Y,Z) = P
  *   xz = X/Z, yz = Y/Z, u = fx xz + cx, v = fy yz + cy
  *   limx = (0.65 W)/fx, limy = (0.65 H)/fy, txz = clamp(xz), tyz = clamp(yz)
@@ -131,6 +134,7 @@ static void mirror_one(const or_scene *s, const or_camera *cam, const float *bas
       mu[k] = (k == 0) ? m0 : (k == 1) ? m1 : m2;
     }
     for (int r = 0; r < s->rank; ++r) mu[k] = mu[k] + basis[r] * s->temporal[(3 * r + k) * n + i];
+    if (s->offset) mu[k] = mu[k] + s->offset[k * n + i];
   }
   float P[3];
   for (int k = 0; k < 3; ++k)
@@ -241,6 +245,7 @@ static void geometry_one(const or_scene *s, const or_camera *cam, const float *b
       mu[k] = m[k];
     }
     for (int r = 0; r < s->rank; ++r) mu[k] += (double)basis[r] * (double)s->temporal[(3 * r + k) * n + i];
+    if (s->offset) mu[k] += (double)s->offset[k * n + i];
   }
   double Rc[9];
   for (int k = 0; k < 9; ++k) Rc[k] = cam->R[k];

@@ -12,6 +12,7 @@ from .workloads import (  # noqa: F401
     Workload,
     WORKLOADS,
     make_scene,
+    make_refinement,
     make_camera,
     ring_camera,
     make_codes,

@@ -2,7 +2,8 @@
 
 Every array is drawn from ``numpy.random.default_rng(SeedSequence([2606,
 workload_index, stream]))`` with stream 0 = scene, 1 = delivery states,
-2 = parameter perturbation, 3 = finite-difference subscene.  Values are drawn in
+2 = parameter perturbation, 3 = finite-difference subscene, 4 = refinement
+levels.  Values are drawn in
 float64 and stored as float32; both the oracle and the GPU path read the
 float32 values.
 
@@ -18,6 +19,11 @@ Layouts (component-major structure of arrays, ``[k][N]``):
   row index = r*3 + axis
 * ``packet_layer [N]``   uint16 ``(packet << 2) | layer`` with
   ``packet = cluster * K + context``
+
+Refinement levels (optional) are ``refine [3][rows][N]``, level j = 1..3 at
+index j - 1, rows: position residual 3, log-scale 3, quaternion 4, opacity
+logit 1, colour 3 or 12.  A Gaussian delivered to depth d carries base +
+levels 1..d; the position residuals are added after the deformation.
 
 Delivery states are ``codes [W][P]`` uint8: 0 = packet absent, d+1 = prefix
 depth d (layers 0..d delivered).  A Gaussian of layer l in packet p is present
@@ -182,6 +188,25 @@ def make_scene(n: int, clusters: int, contexts: int, layers: int, color: str,
         rank=rank,
         sh_degree=sh_degree,
     )
+
+
+def make_refinement(scene: SceneArrays, index: int = 0, stream: int = 4, scale: float = 1.0) -> np.ndarray:
+    """Three refinement levels of a scene: float32 [3][11 + C][N].
+
+    Level j draws N(0, sigma 2^-(j-1)) per row with sigma = 0.01 (position
+    residual), 0.1 (log-scale), 0.1 (quaternion), 0.5 (opacity logit) and
+    0.05 (colour), times ``scale``.  The two residual position levels of
+    Eq. (1) (delta^(2), delta^(3)) ride on levels 1 and 2; level 3 carries no
+    position residual."""
+    rng = _rng(index, stream)
+    n = scene.n
+    C = 3 if scene.sh_degree == 0 else 12
+    sig = np.concatenate([np.full(3, 0.01), np.full(3, 0.1), np.full(4, 0.1), [0.5], np.full(C, 0.05)])
+    out = np.zeros((3, 11 + C, n), np.float64)
+    for j in range(3):
+        out[j] = rng.normal(0.0, 1.0, size=(11 + C, n)) * (sig * scale * 2.0 ** -j)[:, None]
+    out[2, :3] = 0.0
+    return np.ascontiguousarray(out, dtype=np.float32)
 
 
 def ring_camera(width: int, height: int, theta: float = 0.0, radius: float = 3.0,
