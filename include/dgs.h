@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define DGS_ABI_VERSION 1
+#define DGS_ABI_VERSION 2
 
 typedef enum {
   DGS_OK = 0,
@@ -45,7 +45,8 @@ typedef enum {
   DGS_ERR_WORKSPACE = 2,   /* workspace smaller than dgs_workspace_bytes() */
   DGS_ERR_OVERFLOW = 3,    /* tile instances exceeded the capacity (dgs_check) */
   DGS_ERR_HIP = 4,         /* a HIP runtime call failed (message in dgs_last_error) */
-  DGS_ERR_UNSUPPORTED = 5  /* tuning outside the compiled variants */
+  DGS_ERR_UNSUPPORTED = 5  /* tuning outside the compiled variants, or a call
+                              that does not take refinement levels */
 } dgs_status;
 
 /*
@@ -63,7 +64,25 @@ typedef enum {
  *                          layer 0..3 (base + three refinements, Sec. 3)
  *   cluster_affine [C][12] per-cluster 3x4 affine A_{c,t} of Eq. (1) at the
  *                          render time, row-major, or NULL for the identity
- * Limits: 0 <= n < 2^28; rank 0..4; sh_degree 0 or 1; 1 <= C*K <= 16384.
+ *   refine        [3][rows][n]  attribute refinement levels 1..3 (Sec. 3:
+ *                          scale, rotation, opacity and colour are a base
+ *                          plus three refinements; the position carries
+ *                          residual levels on top of the deformation), or
+ *                          NULL.  rows = 14 (sh_degree 0) or 23 (sh_degree 1):
+ *                          position residual at the render time 3, log-scale
+ *                          3, quaternion 4, opacity logit 1, colour 3 or 12
+ *                          (same row order as `color`).
+ * Limits: 0 <= n < 2^28 (4n < 2^28 with refine); rank 0..4; sh_degree 0 or 1;
+ * 1 <= C*K <= 16384.
+ *
+ * With refine, a Gaussian of packet p delivered to depth d (code d+1, present
+ * when its layer <= d) is drawn with base + level 1 + ... + level d of every
+ * attribute (each sum rounded once, in that order) and its position residual
+ * (level 1 + ... + level d, summed from zero) added after the deformation.
+ * The renderer projects one record per (Gaussian, depth) - 4n records, size
+ * the workspace for n_records = 4n - and each state draws the record of the
+ * depth it delivers.  dgs_render_per_state, dgs_backward and the utility calls
+ * return DGS_ERR_UNSUPPORTED for such scenes.
  */
 typedef struct {
   int32_t n;
@@ -79,6 +98,7 @@ typedef struct {
   const float *temporal;
   const uint16_t *packet_layer;
   const float *cluster_affine;
+  const float *refine;
 } dgs_scene;
 
 /* Pinhole camera (host struct): world -> camera rotation R_cw (row-major) and
@@ -139,7 +159,7 @@ const char *dgs_last_error(void);
 
 /*
  * Bytes of device workspace needed by the calls below for a scene of n
- * Gaussians and num_packets = C*K packets seen by `cam` with tuning `tun`,
+ * projected records (n Gaussians, or 4n with refinement levels) and num_packets = C*K packets seen by `cam` with tuning `tun`,
  * at most max_states states per call, and room for instance_capacity
  * (tile, Gaussian) instances.  Returns 0 on invalid arguments.
  * The workspace is caller-owned device memory, at least 256-byte aligned.
@@ -273,13 +293,15 @@ int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream);
 /*
  * Byte offsets, inside a workspace laid out for the given sizes, of the
  * intermediate results a render leaves behind (for inspection and tests):
- *   rec0/rec1/rec2  float4 [n] per Gaussian: (u, v, log2 opacity,
- *                   packet_layer bits), (conic A, B, C scaled by -log2(e)/2,
+ *   rec0/rec1/rec2  float4 [n] per record (Gaussian i, or 4i + d for depth d
+ *                   with refinement levels): (u, v, log2 opacity,
+ *                   packet_layer bits - the layer field holds d with
+ *                   refinement levels), (conic A, B, C scaled by -log2(e)/2,
  *                   -log2(e), -log2(e)/2, FP32 camera depth), (r, g, b, 0);
- *                   only Gaussians that entered the last binning are written
+ *                   only records that entered the last binning are written
  *   rect            uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16), half-open tiles
  *   ranges          uint2 [tiles]: [start, end) of each tile's list
- *   sorted_ids      u32 [capacity]: Gaussian ids in (tile, depth, id) order in
+ *   sorted_ids      u32 [capacity]: record ids in (tile, depth, id) order in
  *                   bits 0..27; bit 28 + b is set when the Gaussian can reach
  *                   alpha >= 1/255 in the tile's 8x8 pixel block b (blocks in
  *                   row-major order: 2x2 for 16x16 tiles, 4x1 for 32x8)

@@ -32,7 +32,7 @@ class Scene(ctypes.Structure):
                 ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p), ("quat", ctypes.c_void_p),
                 ("opacity_logit", ctypes.c_void_p), ("color", ctypes.c_void_p),
                 ("temporal", ctypes.c_void_p), ("packet_layer", ctypes.c_void_p),
-                ("cluster_affine", ctypes.c_void_p)]
+                ("cluster_affine", ctypes.c_void_p), ("refine", ctypes.c_void_p)]
 
 
 class Camera(ctypes.Structure):
@@ -67,6 +67,9 @@ class WorkspaceView(ctypes.Structure):
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32)]
 
 
+ABI_VERSION = 2  # the structs below match include/dgs.h of this version
+
+
 class DgsError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"dgs status {status}: {message}")
@@ -88,6 +91,9 @@ def lib():
     P = ctypes.POINTER
     vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
     L.dgs_abi_version.restype = ctypes.c_int
+    if L.dgs_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {L.dgs_abi_version()}, the binding expects "
+                          f"{ABI_VERSION}; rebuild it")
     L.dgs_status_string.restype = ctypes.c_char_p
     L.dgs_status_string.argtypes = [ctypes.c_int]
     L.dgs_last_error.restype = ctypes.c_char_p

@@ -508,10 +508,13 @@ void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 
 }
 
 // visbits[g][p*4 + l], bit s set iff layer l of packet p is delivered in
-// state order[g*S + s] (l < code).
+// state order[g*S + s] (l < code).  exact: records of a scene with
+// refinement levels, where l is the delivered depth a record was projected
+// at; the bit is set iff the state delivers exactly that depth (codes above
+// 4 act as 4).
 __global__ void __launch_bounds__(kBlock)
 k_visbits(const uint8_t *__restrict__ codes, const uint32_t *__restrict__ order, int num_states, int P, int S,
-          int groups, uint32_t *__restrict__ visbits) {
+          int groups, int exact, uint32_t *__restrict__ visbits) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t P4 = (int64_t)P * 4;
   if (idx >= (int64_t)groups * P4) return;
@@ -523,18 +526,19 @@ k_visbits(const uint8_t *__restrict__ codes, const uint32_t *__restrict__ order,
     const int k = g * S + s;
     if (k >= num_states) break;
     const int w = order ? (int)order[k] : k;
-    if (l < (int)codes[(int64_t)w * P + p]) bits |= 1u << s;
+    const int code = codes[(int64_t)w * P + p];
+    if (exact ? (code < 4 ? code : 4) == l + 1 : l < code) bits |= 1u << s;
   }
   visbits[idx] = bits;
 }
 
-void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S,
+void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S, bool exact,
                     uint32_t *visbits, hipStream_t st) {
   const int groups = (int)ceil_div(num_states, S);
   const int64_t total = (int64_t)groups * P * 4;
   if (total <= 0) return;
   k_visbits<<<(unsigned)ceil_div(total, kBlock), kBlock, 0, st>>>(codes, order, num_states, P, S, groups,
-                                                                  visbits);
+                                                                  exact ? 1 : 0, visbits);
 }
 
 // Gaussians per (packet, layer) of the binned scene.

@@ -90,6 +90,8 @@ int check_scene(const dgs_scene *s) {
       return fail(DGS_ERR_INVALID_ARG, "scene array pointer is NULL");
     if (s->rank > 0 && !s->temporal) return fail(DGS_ERR_INVALID_ARG, "temporal is NULL with rank > 0");
   }
+  if (s->refine && (int64_t)s->n * 4 > kMaxGaussians)
+    return fail(DGS_ERR_INVALID_ARG, "n = %d with refinement levels: 4n outside 0..2^28-1", s->n);
   return DGS_OK;
 }
 
@@ -118,6 +120,8 @@ SceneArgs scene_args(const dgs_scene *s, const dgs_states *st) {
   a.temporal = s->temporal;
   a.packet_layer = s->packet_layer;
   a.affine = s->cluster_affine;
+  a.refine = s->refine;
+  a.refine_rows = s->refine ? 11 + (s->sh_degree == 0 ? 3 : 12) : 0;
   for (int k = 0; k < 4; ++k) a.basis[k] = (k < s->rank) ? st->basis[k] : 0.0f;
   return a;
 }
@@ -142,7 +146,14 @@ struct Call {
   Tiling tiling;
   Layout L;
   int P;
+  int records;  // projected records: n, or 4n (one per delivered depth) with refinement levels
 };
+
+// Entry points that need one record per Gaussian.
+int reject_refined(const dgs_scene *scene, const char *what) {
+  if (scene && scene->refine) return fail(DGS_ERR_UNSUPPORTED, "%s: scenes with refinement levels are not supported", what);
+  return DGS_OK;
+}
 
 int prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
             const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, int need_codes, Call *call) {
@@ -156,7 +167,8 @@ int prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *sta
   if (!ws) return fail(DGS_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)ws) & 255u) return fail(DGS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   call->P = P;
-  call->L = make_layout(scene->n, P, call->tiling.tiles_x, call->tiling.tiles_y, states->num_states, cap);
+  call->records = scene->refine ? 4 * scene->n : scene->n;
+  call->L = make_layout(call->records, P, call->tiling.tiles_x, call->tiling.tiles_y, states->num_states, cap);
   if (ws_bytes < call->L.total)
     return fail(DGS_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, call->L.total);
   call->s = scene_args(scene, states);
@@ -173,7 +185,7 @@ int prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *sta
 void project_and_count(const Call &cl, void *ws, bool list_mode, hipStream_t st) {
   const Layout &L = cl.L;
   Header *h = at<Header>(ws, L.header);
-  const int n = cl.s.n;
+  const int n = cl.records;
   const uint32_t *list = list_mode ? at<uint32_t>(ws, L.present) : nullptr;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
   launch_geometry(cl.s, cl.c, cl.t, list, nact, n, at<float4>(ws, L.rec0), at<float4>(ws, L.rec1),
@@ -207,7 +219,7 @@ const uint32_t *sorted_vals(const Call &cl, void *ws) {
 const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t cap, hipStream_t st) {
   const Layout &L = cl.L;
   Header *h = at<Header>(ws, L.header);
-  const int n = cl.s.n;
+  const int n = cl.records;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
   if (tile_ranges_in_lds(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
     // the ranges exist already (project_and_count); one pass puts every instance in place
@@ -289,6 +301,7 @@ int utility_prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_sta
                     int64_t item_capacity, Call *cl, UtilArgs *u) {
   // the render workspace is read only in its state-independent sections
   if (!contexts) return fail(DGS_ERR_INVALID_ARG, "contexts is NULL");
+  if (int rc0 = reject_refined(scene, "counterfactual utility")) return rc0;
   dgs_states none = *contexts;
   none.num_states = 0;
   int rc = prepare(scene, cam, &none, tun, ws, ws_bytes, cap, 0, cl);
@@ -445,7 +458,7 @@ int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_stat
   uint32_t *order = at<uint32_t>(ws, cl.L.state_order);
   launch_state_order(states->codes, at<uint32_t>(ws, cl.L.plhist), W, cl.P, at<uint32_t>(ws, cl.L.state_cnt),
                      order, st);
-  launch_visbits(states->codes, order, W, cl.P, S, visbits, st);
+  launch_visbits(states->codes, order, W, cl.P, S, scene->refine != nullptr, visbits, st);
   CompositeArgs a = composite_args(cl, ws, sorted_vals(cl, ws), states, visbits, groups);
   a.state_order = order;
   a.launch_states = W;
@@ -505,8 +518,8 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
                          float *tfinal, void *stream) {
   g_err.clear();
   Call cl;
-  int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl);
-  if (rc) return rc;
+  int rc = reject_refined(scene, "dgs_render_per_state");
+  if (rc || (rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl))) return rc;
   if (states->num_states > 0 && !image) return fail(DGS_ERR_INVALID_ARG, "image is NULL");
   hipStream_t st = (hipStream_t)stream;
   const int W = states->num_states;
@@ -554,8 +567,8 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
                  const dgs_scene_grad *grad, void *stream) {
   g_err.clear();
   Call cl;
-  int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl);
-  if (rc) return rc;
+  int rc = reject_refined(scene, "dgs_backward");
+  if (rc || (rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl))) return rc;
   if (!grad || (scene->n > 0 && (!grad->mean || !grad->log_scale || !grad->quat || !grad->opacity_logit ||
                                  !grad->color || (scene->rank > 0 && !grad->temporal))))
     return fail(DGS_ERR_INVALID_ARG, "gradient pointer is NULL");
@@ -572,7 +585,7 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
     uint32_t *order = at<uint32_t>(ws, cl.L.state_order);
     launch_state_order(states->codes, at<uint32_t>(ws, cl.L.plhist), W, cl.P, at<uint32_t>(ws, cl.L.state_cnt),
                        order, st);
-    launch_visbits(states->codes, order, W, cl.P, S, visbits, st);
+    launch_visbits(states->codes, order, W, cl.P, S, false, visbits, st);
     CompositeBwdArgs b{};
     b.tile_order = at<uint32_t>(ws, cl.L.tile_order);
     b.state_order = order;

@@ -81,6 +81,8 @@ struct SceneArgs {
   const float *mean, *log_scale, *quat, *opacity_logit, *color, *temporal;
   const uint16_t *packet_layer;
   const float *affine;
+  const float *refine;  // [3][refine_rows][n] refinement levels, or null
+  int refine_rows;
   float basis[4];
 };
 

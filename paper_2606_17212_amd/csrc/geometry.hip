@@ -1,7 +1,14 @@
-// Per-Gaussian deformation (Eq. (1) of Sec. 3, without the residual levels)
-// and EWA projection, forward and backward.  One thread per Gaussian,
-// component-major (SoA) loads: lanes of a wave read consecutive floats of
-// every component row, so each row is one coalesced stream.
+// Per-Gaussian deformation (Eq. (1) of Sec. 3) and EWA projection, forward
+// and backward.  One thread per Gaussian (or per Gaussian and delivered
+// depth when the scene carries refinement levels), component-major (SoA)
+// loads: lanes of a wave read consecutive floats of every component row, so
+// each row is one coalesced stream.
+//
+// Refinement levels (Sec. 3: scale, rotation, opacity and colour are a base
+// plus three refinements; the position has residual levels on top of the
+// deformation): at delivered depth d an attribute is base + level 1 + ... +
+// level d, each sum rounded once in that order; the position residual is
+// summed the same way from zero and added to the deformed mean.
 //
 // The forward follows a fixed FP32 operation order (every product, quotient,
 // square root and sum rounded once, no contraction; e^x by Cody-Waite
@@ -34,6 +41,12 @@ __device__ inline float exp_cw(float x) {
 
 __device__ inline float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
 
+// Row `row` of Gaussian i's refinement levels 1..d added to x.
+__device__ inline float refined(const SceneArgs &s, float x, int row, int64_t i, int d) {
+  for (int j = 0; j < d; ++j) x = x + s.refine[((int64_t)j * s.refine_rows + row) * s.n + i];
+  return x;
+}
+
 // Intermediate quantities of one Gaussian's projection.
 struct Proj {
   float mu[3];
@@ -47,8 +60,9 @@ struct Proj {
   float u, v;
 };
 
-__device__ inline void project(const SceneArgs &s, const CamArgs &cam, int i, Proj &p) {
-  const int n = s.n;
+// d: delivered depth of a refined scene (0 and unused otherwise).
+__device__ inline void project(const SceneArgs &s, const CamArgs &cam, int i, int d, Proj &p) {
+  const int64_t n = s.n;
   const float m0 = s.mean[i], m1 = s.mean[n + i], m2 = s.mean[2 * n + i];
   int cl = 0;
   if (s.affine) {
@@ -65,6 +79,7 @@ __device__ inline void project(const SceneArgs &s, const CamArgs &cam, int i, Pr
       mk = (k == 0) ? m0 : (k == 1) ? m1 : m2;
     }
     for (int r = 0; r < s.rank; ++r) mk = mk + s.basis[r] * s.temporal[(3 * r + k) * n + i];
+    if (s.refine) mk = mk + refined(s, 0.0f, k, i, d);
     p.mu[k] = mk;
   }
   float P[3];
@@ -85,7 +100,8 @@ __device__ inline void project(const SceneArgs &s, const CamArgs &cam, int i, Pr
   p.j11 = cam.fy / p.Z;
   p.j12 = -(cam.fy * p.tyz) / p.Z;
 
-  const float qw = s.quat[i], qx = s.quat[n + i], qy = s.quat[2 * n + i], qz = s.quat[3 * n + i];
+  const float qw = refined(s, s.quat[i], 6, i, d), qx = refined(s, s.quat[n + i], 7, i, d);
+  const float qy = refined(s, s.quat[2 * n + i], 8, i, d), qz = refined(s, s.quat[3 * n + i], 9, i, d);
   const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   p.qnorm = sqrtf(n2);
   const float w = qw / p.qnorm, x = qx / p.qnorm, y = qy / p.qnorm, z = qz / p.qnorm;
@@ -100,7 +116,7 @@ __device__ inline void project(const SceneArgs &s, const CamArgs &cam, int i, Pr
   p.Rq[7] = 2.0f * (y * z + w * x);
   p.Rq[8] = 1.0f - 2.0f * (x * x + y * y);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) p.vs[k] = exp_cw(2.0f * s.log_scale[k * n + i]);
+  for (int k = 0; k < 3; ++k) p.vs[k] = exp_cw(2.0f * refined(s, s.log_scale[k * n + i], 3 + k, i, d));
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     p.M[j] = p.j00 * cam.R[j] + p.j02 * cam.R[6 + j];
@@ -123,12 +139,12 @@ __device__ inline void project(const SceneArgs &s, const CamArgs &cam, int i, Pr
 
 // Colour: RGB, or degree-1 real SH (Condon-Shortley phase) + 0.5 clamped at 0
 // along the direction from the camera centre to the deformed mean.
-__device__ inline void colour(const SceneArgs &s, const CamArgs &cam, int i, const float mu[3],
+__device__ inline void colour(const SceneArgs &s, const CamArgs &cam, int i, int d, const float mu[3],
                               float col[3], float dir[3], float raw[3]) {
-  const int n = s.n;
+  const int64_t n = s.n;
   if (s.sh_degree == 0) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) { col[ch] = s.color[ch * n + i]; raw[ch] = col[ch]; }
+    for (int ch = 0; ch < 3; ++ch) { col[ch] = refined(s, s.color[ch * n + i], 11 + ch, i, d); raw[ch] = col[ch]; }
     dir[0] = dir[1] = dir[2] = 0.0f;
     return;
   }
@@ -137,32 +153,46 @@ __device__ inline void colour(const SceneArgs &s, const CamArgs &cam, int i, con
   dir[0] = d0 * inv; dir[1] = d1 * inv; dir[2] = d2 * inv;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    float k0 = s.color[ch * n + i], k1 = s.color[(3 + ch) * n + i];
-    float k2 = s.color[(6 + ch) * n + i], k3 = s.color[(9 + ch) * n + i];
+    const float k0 = refined(s, s.color[ch * n + i], 11 + ch, i, d);
+    const float k1 = refined(s, s.color[(3 + ch) * n + i], 14 + ch, i, d);
+    const float k2 = refined(s, s.color[(6 + ch) * n + i], 17 + ch, i, d);
+    const float k3 = refined(s, s.color[(9 + ch) * n + i], 20 + ch, i, d);
     float val = 0.5f + kShC0 * k0 + kShC1 * (-dir[1] * k1 + dir[2] * k2 - dir[0] * k3);
     raw[ch] = val;
     col[ch] = fmaxf(val, 0.0f);
   }
 }
 
+// REFINED: one thread per record slot v = 4 i + d (Gaussian i at delivered
+// depth d); the slot exists when d >= the Gaussian's layer, and its record
+// carries (packet << 2) | d so that the compositing tables select it in the
+// states that deliver exactly depth d.
+template <bool REFINED>
 __global__ void __launch_bounds__(kBlock)
 k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ list,
            const unsigned *__restrict__ n_active, float4 *__restrict__ rec0,
            float4 *__restrict__ rec1, float4 *__restrict__ rec2, uint2 *__restrict__ rect,
            uint2 *__restrict__ pbox, uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
-  const int nact = list ? (int)*n_active : s.n;
+  const int nact = list ? (int)*n_active : (REFINED ? 4 * s.n : s.n);
   if (j >= nact) return;
-  const int i = list ? (int)list[j] : j;
+  const int v = list ? (int)list[j] : j;
+  const int i = REFINED ? (v >> 2) : v;
+  const int d = REFINED ? (v & 3) : 0;
   Proj p;
-  project(s, cam, i, p);
+  project(s, cam, i, d, p);
   float col[3], dir[3], raw[3];
-  colour(s, cam, i, p.mu, col, dir, raw);
+  colour(s, cam, i, d, p.mu, col, dir, raw);
   // log2 of the opacity: alpha = min(0.99, 2^(q' + log2 o)) in the compositing kernels
-  const float lo = -__log2f(1.0f + __expf(-s.opacity_logit[i]));
-  const uint16_t pl = s.packet_layer[i];
+  const float lo = -__log2f(1.0f + __expf(-refined(s, s.opacity_logit[i], 10, i, d)));
+  uint16_t pl = s.packet_layer[i];
+  bool exists = true;
+  if (REFINED) {
+    exists = (int)(pl & 3u) <= d;
+    pl = (uint16_t)((pl & ~3u) | (uint32_t)d);
+  }
   // a packet id outside the state tables never enters a list
-  const bool ok = (p.Z > cam.near_z) && (p.det > 0.0f) && ((int)(pl >> 2) < s.num_packets);
+  const bool ok = exists && (p.Z > cam.near_z) && (p.det > 0.0f) && ((int)(pl >> 2) < s.num_packets);
   uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0, px0 = 0, py0 = 0, px1 = 0, py1 = 0;
   if (ok) {
     const float itw = 1.0f / (float)tl.tile_w, ith = 1.0f / (float)tl.tile_h;
@@ -178,14 +208,14 @@ k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ l
     py1 = (uint32_t)clampf(floorf(p.v + ey) + 1.0f, 0.0f, (float)cam.height);
   }
   // conic pre-scaled so that q' = A' dx^2 + B' dx dy + C' dy^2 = -(q/2) log2 e
-  rec0[i] = make_float4(p.u, p.v, lo, __uint_as_float((uint32_t)pl));
-  rec1[i] = make_float4(kConicA * p.A, kConicB * p.B, kConicA * p.C, p.Z);
-  rec2[i] = make_float4(col[0], col[1], col[2], 0.0f);
-  rect[i] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
-  pbox[i] = make_uint2(px0 | (py0 << 16), px1 | (py1 << 16));
+  rec0[v] = make_float4(p.u, p.v, lo, __uint_as_float((uint32_t)pl));
+  rec1[v] = make_float4(kConicA * p.A, kConicB * p.B, kConicA * p.C, p.Z);
+  rec2[v] = make_float4(col[0], col[1], col[2], 0.0f);
+  rect[v] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+  pbox[v] = make_uint2(px0 | (py0 << 16), px1 | (py1 << 16));
   const bool nonempty = ok && x1 > x0 && y1 > y0;
   dkey[j] = nonempty ? __float_as_uint(p.Z) : 0xFFFFFFFFu;
-  dval[j] = (uint32_t)i;
+  dval[j] = (uint32_t)v;
 }
 
 // Chain rule from the per-Gaussian 2D gradients (u, v, conic A, B, C,
@@ -197,7 +227,7 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
                float *__restrict__ g_ls, float *__restrict__ g_quat, float *__restrict__ g_logit,
                float *__restrict__ g_color, float *__restrict__ g_temporal) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int n = s.n;
+  const int64_t n = s.n;
   if (i >= n) return;
   // the compositing backward differentiates w.r.t. (u, v, A', B', C', log2 o): undo the scalings
   const float gu = g2d[i], gv = g2d[n + i];
@@ -205,9 +235,9 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
   const float gC = kConicA * g2d[4 * n + i], glo = g2d[5 * n + i];
   const float gcol[3] = {g2d[6 * n + i], g2d[7 * n + i], g2d[8 * n + i]};
   Proj p;
-  project(s, cam, i, p);
+  project(s, cam, i, 0, p);
   float col[3], dir[3], raw[3];
-  colour(s, cam, i, p.mu, col, dir, raw);
+  colour(s, cam, i, 0, p.mu, col, dir, raw);
 
   // opacity: log2 o = -log2(1 + e^{-logit}), d/dlogit = (1 - o) / ln 2
   const float o = 1.0f / (1.0f + __expf(-s.opacity_logit[i]));
@@ -332,8 +362,12 @@ void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, co
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
                      uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st) {
   if (grid_n <= 0) return;
-  k_geometry<<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
-                                                                    rec2, rect, pbox, dkey, dval);
+  if (s.refine)
+    k_geometry<true><<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
+                                                                            rec2, rect, pbox, dkey, dval);
+  else
+    k_geometry<false><<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
+                                                                             rec2, rect, pbox, dkey, dval);
 }
 
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,

@@ -47,7 +47,7 @@ void launch_chunk_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
                           int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
                           const float4 *rec1, const uint2 *pbox, const uint2 *ranges, const Header *h,
                           uint32_t *chist, uint32_t *segsum, uint32_t *tval, hipStream_t st);
-void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S,
+void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S, bool exact,
                     uint32_t *visbits, hipStream_t st);
 void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st);
 constexpr int kMaxOrderedStates = 16384;  // states ranked by present count per composite call

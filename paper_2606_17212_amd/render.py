@@ -34,25 +34,36 @@ class GaussianScene:
     rank: int
     sh_degree: int
     cluster_affine: Optional[torch.Tensor] = None
+    # [3][rows][n] refinement levels (position residual 3, log-scale 3,
+    # quaternion 4, opacity logit 1, colour 3 or 12), or None
+    refine: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
         return int(self.mean.shape[1])
 
     @property
+    def records(self) -> int:
+        """Projected records: one per Gaussian, or one per (Gaussian,
+        delivered depth) with refinement levels."""
+        return self.n * (4 if self.refine is not None else 1)
+
+    @property
     def num_packets(self) -> int:
         return self.num_clusters * self.num_contexts
 
     @staticmethod
-    def from_arrays(a, device="cuda") -> "GaussianScene":
-        """From a host container with numpy fields of the same names."""
+    def from_arrays(a, device="cuda", refine=None) -> "GaussianScene":
+        """From a host container with numpy fields of the same names;
+        ``refine``: optional host array of refinement levels [3][rows][n]."""
         import numpy as np
 
         t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(device)  # noqa: E731
         pl = torch.from_numpy(np.ascontiguousarray(a.packet_layer, dtype=np.uint16).view(np.int16)).to(device)
         aff = None if a.cluster_affine is None else t(a.cluster_affine)
         return GaussianScene(t(a.mean), t(a.log_scale), t(a.quat), t(a.opacity_logit), t(a.color),
-                             t(a.temporal), pl, a.num_clusters, a.num_contexts, a.rank, a.sh_degree, aff)
+                             t(a.temporal), pl, a.num_clusters, a.num_contexts, a.rank, a.sh_degree, aff,
+                             None if refine is None else t(refine))
 
     def with_params(self, **p) -> "GaussianScene":
         d = dict(self.__dict__)
@@ -105,9 +116,14 @@ def _c_scene(s: GaussianScene, params=None) -> _abi.Scene:
     for k, shp in shapes.items():
         if tuple(p[k].shape) != shp:
             raise ValueError(f"{k} has shape {tuple(p[k].shape)}, expected {shp}")
+    if s.refine is not None:
+        _check_tensor(s.refine, "refine", torch.float32, dev)
+        shp = (3, 11 + (3 if s.sh_degree == 0 else 12), n)
+        if tuple(s.refine.shape) != shp:
+            raise ValueError(f"refine has shape {tuple(s.refine.shape)}, expected {shp}")
     return _abi.Scene(n, s.rank, s.sh_degree, s.num_clusters, s.num_contexts, _ptr(p["mean"]),
                       _ptr(p["log_scale"]), _ptr(p["quat"]), _ptr(p["opacity_logit"]), _ptr(p["color"]),
-                      _ptr(p["temporal"]), _ptr(s.packet_layer), _ptr(s.cluster_affine))
+                      _ptr(p["temporal"]), _ptr(s.packet_layer), _ptr(s.cluster_affine), _ptr(s.refine))
 
 
 def _c_camera(c: Camera) -> _abi.Camera:
@@ -172,7 +188,7 @@ class Renderer:
             self.ws_bytes = int(nbytes)
 
     def workspace_bytes(self, scene: GaussianScene, camera: Camera, max_states: int, capacity: int) -> int:
-        b = _abi.lib().dgs_workspace_bytes(scene.n, scene.num_packets, ctypes.byref(_c_camera(camera)),
+        b = _abi.lib().dgs_workspace_bytes(scene.records, scene.num_packets, ctypes.byref(_c_camera(camera)),
                                            ctypes.byref(self.tuning), int(max_states), int(capacity))
         if b == 0:
             raise ValueError("invalid arguments for dgs_workspace_bytes")
@@ -197,22 +213,22 @@ class Renderer:
         self.capacity = cap
         self.max_states = int(max_states)
         self._ensure_ws(self.workspace_bytes(scene, camera, max_states, cap))
-        self._key = (scene.n, camera.width, camera.height)
+        self._key = (scene.records, camera.width, camera.height)
         return m
 
     def _need_plan(self, scene, camera, basis, W, params=None):
-        if self._key != (scene.n, camera.width, camera.height) or W > self.max_states or self.capacity == 0:
+        if self._key != (scene.records, camera.width, camera.height) or W > self.max_states or self.capacity == 0:
             self.plan(scene, camera, basis, max(W, self.max_states), params)
 
     def sections(self, scene: GaussianScene, camera: Camera, num_states: int) -> dict:
-        """Intermediate results of the last render (synchronises): per-Gaussian
-        records and rectangles, per-tile ranges and the sorted ids."""
+        """Intermediate results of the last render (synchronises): per-record
+        data and rectangles, per-tile ranges and the sorted ids."""
         v = _abi.WorkspaceView()
         _abi.check(_abi.lib().dgs_workspace_sections(
-            scene.n, scene.num_packets, ctypes.byref(_c_camera(camera)), ctypes.byref(self.tuning),
+            scene.records, scene.num_packets, ctypes.byref(_c_camera(camera)), ctypes.byref(self.tuning),
             int(num_states), self.capacity, ctypes.byref(v)))
         torch.cuda.synchronize(self.device)
-        n, tiles = scene.n, v.tiles_x * v.tiles_y
+        n, tiles = scene.records, v.tiles_x * v.tiles_y
 
         def sl(off, count, dtype, width):
             nbytes = count * width * torch.tensor([], dtype=dtype).element_size()

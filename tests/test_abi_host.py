@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
     assert sorted(abi.EXPORTS) == decl
     for name in decl:
         assert hasattr(L, name), name
-    assert L.dgs_abi_version() == 1
+    assert L.dgs_abi_version() == 2
     assert L.dgs_status_string(3) == b"instance capacity exceeded"
 
 

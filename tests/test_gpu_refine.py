@@ -1,0 +1,160 @@
+"""GPU parity for scenes with refinement levels (Sec. 3: scale, rotation,
+opacity and colour as a base plus three refinements, position residual
+levels on top of Eq. (1)): the renderer's per-(Gaussian, depth) records and
+exact-depth state tables against the oracle, which decodes each state into
+its plain scene.
+
+Bars: images within 1e-4 of the FP64 oracle plus its ambiguity budget; every
+record's depth key and tile rectangle bit-exact with the FP32 mirror of the
+decoded scene at that depth; group size and tile shape change no pixel;
+all-zero levels give the plain renderer's images bit for bit; calls that take
+no refinement levels raise DGS_ERR_UNSUPPORTED.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+BG = (0.25, 0.5, 0.75)
+TOL = 1e-4
+
+
+def _dgs():
+    import paper_2606_17212_amd as dgs
+    return dgs
+
+
+def _case(n=3000, W=24, width=100, height=75, seed=5):
+    scene = synth.make_scene(n, 4, 4, 4, "sh1", index=seed, stream=0)
+    scene.log_scale[:] += np.float32(0.4)
+    cam = synth.ring_camera(width, height)
+    basis = synth.temporal_basis(0.5, scene.rank)
+    levels = synth.make_refinement(scene, index=seed)
+    codes = synth.make_codes("present_depth", 0.4, 1.0, W, scene.num_packets, 4, index=seed)
+    codes[0] = 1   # base only
+    codes[1] = 4   # everything
+    codes[2] = 7   # above 4 acts as 4
+    codes[3] = 0   # nothing
+    codes[4, ::2] = 9
+    return scene, cam, basis, levels, codes
+
+
+@pytest.fixture(scope="module")
+def case():
+    scene, cam, basis, levels, codes = _case()
+    ref = oracle.render_refined(scene, levels, cam, basis, codes, np.asarray(BG, np.float32))
+    return scene, cam, basis, levels, codes, ref
+
+
+def test_refined_images_match_oracle_any_group_and_tile(case):
+    dgs = _dgs()
+    scene, cam, basis, levels, codes, ref = case
+    dev = torch.device("cuda:0")
+    s = dgs.GaussianScene.from_arrays(scene, dev, refine=levels)
+    c = dgs.Camera.from_arrays(cam)
+    cd = torch.from_numpy(codes).to(dev)
+    first = None
+    for tile in ((16, 16), (32, 8)):
+        for S in (1, 8, 32):
+            r = dgs.Renderer(dev, tile=tile, states_per_group=S)
+            img = r.render(s, c, cd, basis, BG).cpu().numpy()
+            assert r.check() > 0
+            d = np.abs(img.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
+            assert d.max() <= TOL, (tile, S, d.max(), np.unravel_index(d.argmax(), d.shape))
+            if first is None:
+                first = img
+            else:
+                assert np.array_equal(img, first), (tile, S)
+    # the levels matter for this scene
+    plain = oracle.render(scene, cam, basis, codes[1:2], np.asarray(BG, np.float32))["image"][0]
+    assert np.abs(plain - ref["image"][1]).max() > 1e-2
+    # states 1 and 2 deliver the same depths
+    assert np.array_equal(first[1], first[2])
+    assert np.allclose(first[3], np.asarray(BG, np.float32)[None, None], atol=0)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_depth_records_match_mirror(case, tile):
+    dgs = _dgs()
+    scene, cam, basis, levels, codes, _ = case
+    dev = torch.device("cuda:0")
+    s = dgs.GaussianScene.from_arrays(scene, dev, refine=levels)
+    c = dgs.Camera.from_arrays(cam)
+    cd = torch.from_numpy(codes).to(dev)
+    r = dgs.Renderer(dev, tile=tile)
+    r.render(s, c, cd, basis, BG)
+    M = r.check()
+    sec = r.sections(s, c, codes.shape[0])
+    n = scene.n
+    layer = (scene.packet_layer & 3).astype(np.int64)
+    zb = sec["rec1"][:, 3].numpy().view(np.uint32).reshape(n, 4)
+    rect = sec["rect"].numpy().view(np.uint32).reshape(n, 4, 2)
+    pl = sec["rec0"][:, 3].numpy().view(np.uint32).reshape(n, 4)
+    ids = sec["sorted_ids"].numpy()[:M].astype(np.int64)
+    for d in range(4):
+        full = np.full(scene.num_packets, d + 1, np.uint8)
+        m = oracle.mirror_f32(oracle.refined_scene(scene, levels, full), cam, basis, *tile)
+        have = m["valid"] & (layer <= d)
+        assert np.array_equal(zb[have, d], m["zbits"][have]), d
+        x0, y0 = rect[:, d, 0] & 0xFFFF, rect[:, d, 0] >> 16
+        x1, y1 = rect[:, d, 1] & 0xFFFF, rect[:, d, 1] >> 16
+        gr = np.stack([x0, y0, x1, y1]).astype(np.int64)
+        assert np.array_equal(gr[:, have], m["rect"][:, have].astype(np.int64)), d
+        # each record names its depth in the layer field
+        assert np.all((pl[have, d] & 3) == d) and np.all((pl[have, d] >> 2) == (scene.packet_layer[have] >> 2))
+    # no record below its Gaussian's layer enters a list
+    assert np.all((ids & 3) >= layer[ids >> 2])
+    # instance count: every (Gaussian, depth) record's tiles, counted from the mirrors
+    want = 0
+    for d in range(4):
+        full = np.full(scene.num_packets, d + 1, np.uint8)
+        m = oracle.mirror_f32(oracle.refined_scene(scene, levels, full), cam, basis, *tile)
+        have = m["valid"] & (layer <= d)
+        rr = m["rect"].astype(np.int64)
+        want += int((np.clip(rr[2] - rr[0], 0, None) * np.clip(rr[3] - rr[1], 0, None))[have].sum())
+    assert M == want
+
+
+def test_zero_levels_equal_plain_render_bit_for_bit():
+    dgs = _dgs()
+    scene, cam, basis, levels, codes = _case(n=2000, W=12, seed=6)
+    dev = torch.device("cuda:0")
+    c = dgs.Camera.from_arrays(cam)
+    cd = torch.from_numpy(codes).to(dev)
+    plain = dgs.GaussianScene.from_arrays(scene, dev)
+    zero = dgs.GaussianScene.from_arrays(scene, dev, refine=np.zeros_like(levels))
+    for tile in ((16, 16), (32, 8)):
+        r = dgs.Renderer(dev, tile=tile, states_per_group=8)
+        a = r.render(plain, c, cd, basis, BG).cpu().numpy()
+        b = r.render(zero, c, cd, basis, BG).cpu().numpy()
+        assert np.array_equal(a, b), tile
+
+
+def test_refined_psnr_and_unsupported_calls(case):
+    dgs = _dgs()
+    scene, cam, basis, levels, codes, ref = case
+    dev = torch.device("cuda:0")
+    s = dgs.GaussianScene.from_arrays(scene, dev, refine=levels)
+    c = dgs.Camera.from_arrays(cam)
+    cd = torch.from_numpy(codes).to(dev)
+    r = dgs.Renderer(dev)
+    target = torch.from_numpy(ref["image"][1].astype(np.float32)).to(dev)
+    ps = r.render_psnr(s, c, cd, basis, target, BG).cpu().numpy().astype(np.float64)
+    want = oracle.psnr(ref["image"], ref["image"][1])
+    fin = np.isfinite(want) & (want < 90)
+    assert np.allclose(ps[fin], want[fin], atol=2e-2), (ps, want)
+    with pytest.raises(dgs.DgsError) as e:
+        r.render(s, c, cd, basis, BG, per_state=True)
+    assert e.value.status == 5
+    img = r.render(s, c, cd, basis, BG)
+    with pytest.raises(dgs.DgsError) as e:
+        r.backward(s, c, cd, basis, BG, img, torch.ones_like(img))
+    assert e.value.status == 5
+    # a refine array of the wrong shape is refused before any launch
+    bad = s.with_params(refine=s.refine[:, :5].contiguous())
+    with pytest.raises(ValueError):
+        r.render(bad, c, cd, basis, BG)
