@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-utility", action="store_true")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the leg with attribute refinement levels on the same workload")
     ap.add_argument("--utility", default="g1m_540p_utility_64groups_16contexts",
                     help="counterfactual-utility workload timed beside the main metric")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -209,6 +211,9 @@ def main():
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)
 
+    if not args.no_refined:
+        out["refined"] = refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg)
+
     if not args.no_utility:
         out["utility"] = utility_bench(args, dgs, synth, torch, np, dev, tw, th)
         out["sampler"] = sampler_bench(dgs, torch, np, dev, scene.num_packets)
@@ -267,6 +272,46 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
     return {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
             "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
             "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+
+
+def refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg):
+    """The same states of the same scene with three attribute refinement
+    levels (Sec. 3): one record per (Gaussian, delivered depth), exact-depth
+    state tables.  Timed like the main leg (bin + composite per step)."""
+    levels = synth.make_refinement(w.scene, index=w.index)
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev, refine=levels)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(w.codes).to(dev)
+    W = int(codes.shape[0])
+    M = r.plan(scene, cam, w.basis, W)
+    for _ in range(max(args.warmup, 1)):
+        r.bin(scene, cam, w.basis)
+        r.composite(scene, cam, codes, w.basis, bg, out=img)
+    r.check()
+    st = torch.cuda.current_stream(dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        ev[k][0].record(st)
+        r.bin(scene, cam, w.basis)
+        ev[k][1].record(st)
+        r.composite(scene, cam, codes, w.basis, bg, out=img)
+        ev[k][2].record(st)
+    torch.cuda.synchronize()
+    r.check()
+    total_ms = ev[0][0].elapsed_time(ev[-1][2])
+    bin_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    comp_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    alpha_evals, blends, wave_evals, wave_miss = r.composite_stats(scene, cam, codes, w.basis)
+    flops = FLOPS_PER_ALPHA * alpha_evals + FLOPS_PER_BLEND * blends
+    value = W * args.steps / (total_ms / 1e3)
+    log(f"[bench] refined: {total_ms / args.steps:.3f} ms/step (bin {bin_ms:.3f}, composite {comp_ms:.3f}) "
+        f"-> {value:.1f} states/s; {M} instances")
+    return {"workload": args.workload + "_refined", "value": round(value, 2), "unit": "states/s",
+            "records": scene.records, "instances": M, "ms_per_step": round(total_ms / args.steps, 4),
+            "bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4),
+            "achieved_tflops": round(flops / (comp_ms / 1e3) / 1e12, 3),
+            "alpha_evals": alpha_evals, "blends": blends}
 
 
 def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
