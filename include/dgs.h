@@ -451,6 +451,64 @@ typedef struct {
 int dgs_sample_states(const dgs_channel *channels, int32_t num_states, int32_t num_packets, int32_t num_layers,
                       uint64_t seed, uint8_t *codes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Packet-conditioned rendering objective (Sec. 4, Eq. (2)) and its gradient
+ * with respect to the rendered images, for one training batch:
+ *
+ *   L = E[D] + lambda_c CVaR_alpha(D) + lambda_t F + lambda_m M + lambda_a D_anchor
+ *
+ * D_k = MSE + lambda_ssim (1 - SSIM) of image k against targets[target_of[k]]
+ * (SSIM: 11x11 Gaussian window, sigma 1.5, C1 = 0.01^2, C2 = 0.03^2, zero
+ * padding, mean over pixels and channels).  Roles (device int32 lists of image
+ * indices):
+ *   expect   [num_expect]     partial delivery states: E[D] is their mean D;
+ *                             CVaR_alpha the mean of the worst alpha fraction
+ *                             of their D (the largest floor(alpha n) count
+ *                             fully, the next the remainder, over alpha n;
+ *                             ties by list position)
+ *   anchor   [num_anchor]     complete-prefix states (mean D)
+ *   mono     [num_mono][2]    (a, b): state b grows a's prefix; M = mean of
+ *                             max(0, D_b - D_a)
+ *   temporal [num_temporal][2] (a, b): one world at two times; F = mean over
+ *                             pairs of the mean of ((I_b - I_a) - (G_b - G_a))^2
+ * The rate proxy R of Eq. (2) has weight 0 in the configuration the paper
+ * locks and does not depend on the images; it is not part of L here.
+ * Paper's weights: lambda_ssim 0.20, lambda_c 0.30, alpha 0.05, lambda_t 0.10,
+ * lambda_m 2.0, lambda_a 0.50.
+ */
+typedef struct {
+  float lambda_ssim, lambda_c, alpha, lambda_t, lambda_m, lambda_a;
+} dgs_objective_weights;
+
+/* Scratch bytes for dgs_objective (0 on invalid sizes): about 36 B per image
+ * pixel plus per-block partial sums.  num_images <= 65536, num_temporal <= 65536. */
+size_t dgs_objective_scratch_bytes(int32_t num_images, int32_t width, int32_t height, int32_t num_temporal);
+
+/*
+ * images [num_images][height][width][3] FP32 and targets [num_targets][...]
+ * (device); target_of [num_images] int32 (device).  Outputs (device):
+ *   loss       float [6]: L, E[D], CVaR, F, M, anchor D (required)
+ *   distortion float [num_images]: D per image, or NULL
+ *   grad       float [num_images][height][width][3]: dL/d images, or NULL
+ *              (the gradient of every image, zero for images in no role)
+ * scratch: caller-owned device memory of dgs_objective_scratch_bytes, 256-byte
+ * aligned, overwritten.  Limits: num_expect <= 4096, the other lists <= 65536;
+ * weights finite and >= 0, alpha in (0, 1].  Asynchronous, deterministic
+ * (every sum in a fixed order).  An index out of range in a device list
+ * makes the loss NaN and is reported by dgs_objective_check.  Returns DGS_OK,
+ * DGS_ERR_INVALID_ARG, DGS_ERR_WORKSPACE or DGS_ERR_HIP.
+ */
+int dgs_objective(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                  int32_t num_targets, const int32_t *target_of, const int32_t *expect, int32_t num_expect,
+                  const int32_t *anchor, int32_t num_anchor, const int32_t *mono, int32_t num_mono,
+                  const int32_t *temporal, int32_t num_temporal, const dgs_objective_weights *weights,
+                  float *loss, float *distortion, float *grad, void *scratch, size_t scratch_bytes,
+                  void *stream);
+
+/* SYNCHRONISES the stream; DGS_ERR_INVALID_ARG if the last dgs_objective on
+ * this scratch met an index out of range, else DGS_OK. */
+int dgs_objective_check(void *scratch, size_t scratch_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

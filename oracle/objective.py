@@ -116,7 +116,8 @@ def objective(images, targets, target_of, expect, anchor=(), mono=(), temporal=(
     else:
         F = zero
     L = E + wts["lambda_c"] * cv + wts["lambda_t"] * F + wts["lambda_m"] * M + wts["lambda_a"] * A
-    out = dict(loss=float(L), E=float(E), cvar=float(cv), F=float(F), M=float(M), anchor=float(A),
+    L_, E_, cv_, F_, M_, A_ = (float(v.detach()) for v in (L, E, cv, F, M, A))
+    out = dict(loss=L_, E=E_, cvar=cv_, F=F_, M=M_, anchor=A_,
                D=D.detach().numpy().copy())
     if grad:
         L.backward()

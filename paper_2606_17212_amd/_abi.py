@@ -22,7 +22,8 @@ EXPORTS = (
     "dgs_backward", "dgs_check", "dgs_workspace_sections", "dgs_bin", "dgs_composite",
     "dgs_composite_psnr", "dgs_composite_stats", "dgs_composite_launch", "dgs_utility_workspace_bytes",
     "dgs_utility_count", "dgs_utility", "dgs_utility_check", "dgs_distortion_scratch_bytes", "dgs_distortion",
-    "dgs_risk_adjusted", "dgs_sample_states",
+    "dgs_risk_adjusted", "dgs_sample_states", "dgs_objective_scratch_bytes", "dgs_objective",
+    "dgs_objective_check",
 )
 
 
@@ -33,6 +34,11 @@ class Scene(ctypes.Structure):
                 ("opacity_logit", ctypes.c_void_p), ("color", ctypes.c_void_p),
                 ("temporal", ctypes.c_void_p), ("packet_layer", ctypes.c_void_p),
                 ("cluster_affine", ctypes.c_void_p), ("refine", ctypes.c_void_p)]
+
+
+class ObjectiveWeights(ctypes.Structure):
+    _fields_ = [("lambda_ssim", ctypes.c_float), ("lambda_c", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("lambda_t", ctypes.c_float), ("lambda_m", ctypes.c_float), ("lambda_a", ctypes.c_float)]
 
 
 class Camera(ctypes.Structure):
@@ -141,6 +147,13 @@ def lib():
     L.dgs_risk_adjusted.argtypes = [vp, vp, i32, fp, fp, fp, vp, vp]
     L.dgs_sample_states.restype = ctypes.c_int
     L.dgs_sample_states.argtypes = [vp, i32, i32, i32, ctypes.c_uint64, vp, vp]
+    L.dgs_objective_scratch_bytes.restype = sz
+    L.dgs_objective_scratch_bytes.argtypes = [i32, i32, i32, i32]
+    L.dgs_objective.restype = ctypes.c_int
+    L.dgs_objective.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, i32, vp, i32, vp, i32, vp, i32,
+                                P(ObjectiveWeights), vp, vp, vp, vp, sz, vp]
+    L.dgs_objective_check.restype = ctypes.c_int
+    L.dgs_objective_check.argtypes = [vp, sz, vp]
     _lib = L
     return L
 

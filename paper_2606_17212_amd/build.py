@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgs.so")
-SOURCES = ["geometry.hip", "sort.hip", "binning.hip", "composite.hip", "utility.hip", "sampler.hip", "capi.hip"]
+SOURCES = ["geometry.hip", "sort.hip", "binning.hip", "composite.hip", "utility.hip", "sampler.hip", "objective.hip",
+           "capi.hip"]
 ARCH = os.environ.get("DGS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

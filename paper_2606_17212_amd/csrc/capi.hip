@@ -10,6 +10,7 @@
 #include "../../include/dgs.h"
 #include "common.h"
 #include "kernels.h"
+#include "objective.h"
 
 using namespace dgs;
 
@@ -801,6 +802,100 @@ int dgs_sample_states(const dgs_channel *channels, int32_t num_states, int32_t n
   launch_sample_states(reinterpret_cast<const SamplerChannel *>(channels), num_states, num_packets, num_layers, seed,
                        codes, (hipStream_t)stream);
   return hip_check("sample_states launch");
+}
+
+// ---------------------------------------------------------------- objective
+static bool finite_weight(float v) { return isfinite(v) && v >= 0.0f; }
+
+size_t dgs_objective_scratch_bytes(int32_t num_images, int32_t width, int32_t height, int32_t num_temporal) {
+  if (num_images < 0 || num_images > kObjMaxImages || width < 1 || height < 1 || width > 16384 ||
+      height > 16384 || num_temporal < 0 || num_temporal > kObjMaxPairs)
+    return 0;
+  return make_obj_layout(num_images, width, height, num_temporal).total;
+}
+
+int dgs_objective(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                  int32_t num_targets, const int32_t *target_of, const int32_t *expect, int32_t num_expect,
+                  const int32_t *anchor, int32_t num_anchor, const int32_t *mono, int32_t num_mono,
+                  const int32_t *temporal, int32_t num_temporal, const dgs_objective_weights *w, float *loss,
+                  float *distortion, float *grad, void *scratch, size_t scratch_bytes, void *stream) {
+  g_err.clear();
+  if (num_images < 0 || num_images > kObjMaxImages)
+    return fail(DGS_ERR_INVALID_ARG, "num_images %d outside 0..%d", num_images, kObjMaxImages);
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(DGS_ERR_INVALID_ARG, "image size %dx%d outside 1..16384", width, height);
+  if (num_expect < 0 || num_expect > kObjMaxExpect)
+    return fail(DGS_ERR_INVALID_ARG, "num_expect %d outside 0..%d", num_expect, kObjMaxExpect);
+  if (num_anchor < 0 || num_anchor > kObjMaxPairs || num_mono < 0 || num_mono > kObjMaxPairs ||
+      num_temporal < 0 || num_temporal > kObjMaxPairs)
+    return fail(DGS_ERR_INVALID_ARG, "anchor / pair counts outside 0..%d", kObjMaxPairs);
+  if (!w) return fail(DGS_ERR_INVALID_ARG, "weights is NULL");
+  if (!finite_weight(w->lambda_ssim) || !finite_weight(w->lambda_c) || !finite_weight(w->lambda_t) ||
+      !finite_weight(w->lambda_m) || !finite_weight(w->lambda_a))
+    return fail(DGS_ERR_INVALID_ARG, "weights must be finite and >= 0");
+  if (!(w->alpha > 0.0f && w->alpha <= 1.0f)) return fail(DGS_ERR_INVALID_ARG, "alpha outside (0, 1]");
+  if (!loss) return fail(DGS_ERR_INVALID_ARG, "loss is NULL");
+  if (num_images > 0 && (!images || !targets || !target_of || num_targets < 1))
+    return fail(DGS_ERR_INVALID_ARG, "images / targets / target_of missing");
+  if ((num_expect > 0 && !expect) || (num_anchor > 0 && !anchor) || (num_mono > 0 && !mono) ||
+      (num_temporal > 0 && !temporal))
+    return fail(DGS_ERR_INVALID_ARG, "an index list is NULL");
+  if (num_images == 0 && (num_expect > 0 || num_anchor > 0 || num_mono > 0 || num_temporal > 0))
+    return fail(DGS_ERR_INVALID_ARG, "roles given for an empty batch");
+  if (!scratch) return fail(DGS_ERR_INVALID_ARG, "scratch is NULL");
+  if (((uintptr_t)scratch) & 255u) return fail(DGS_ERR_INVALID_ARG, "scratch not 256-byte aligned");
+  const ObjLayout L = make_obj_layout(num_images, width, height, num_temporal);
+  if (scratch_bytes < L.total) return fail(DGS_ERR_WORKSPACE, "scratch %zu bytes < %zu needed", scratch_bytes, L.total);
+  ObjArgs a{};
+  a.images = images;
+  a.targets = targets;
+  a.target_of = target_of;
+  a.expect = expect;
+  a.anchor = anchor;
+  a.mono = mono;
+  a.temporal = temporal;
+  a.K = num_images;
+  a.T = num_targets;
+  a.width = width;
+  a.height = height;
+  a.n_expect = num_expect;
+  a.n_anchor = num_anchor;
+  a.n_mono = num_mono;
+  a.n_temporal = num_temporal;
+  a.bx = (int)ceil_div(width, 16);
+  a.by = (int)ceil_div(height, 16);
+  a.w = ObjWeights{w->lambda_ssim, w->lambda_c, w->alpha, w->lambda_t, w->lambda_m, w->lambda_a};
+  a.loss = loss;
+  a.distortion = distortion;
+  a.grad = grad;
+  a.hdr = at<ObjHeader>(scratch, L.header);
+  a.dpart = at<double>(scratch, L.dpart);
+  a.tpart = at<double>(scratch, L.tpart);
+  a.maps = at<float>(scratch, L.maps);
+  a.coef = at<float>(scratch, L.coef);
+  a.d = at<float>(scratch, L.d);
+  a.cnt = at<int>(scratch, L.cnt);
+  a.tcnt = at<int>(scratch, L.tcnt);
+  a.tkey0 = at<uint32_t>(scratch, L.tkey0);
+  a.tkey1 = at<uint32_t>(scratch, L.tkey1);
+  a.tval0 = at<uint32_t>(scratch, L.tval0);
+  a.tval1 = at<uint32_t>(scratch, L.tval1);
+  a.thist = at<uint32_t>(scratch, L.thist);
+  a.tparts = at<unsigned long long>(scratch, L.tparts);
+  launch_objective(a, (hipStream_t)stream);
+  return hip_check("objective launch");
+}
+
+int dgs_objective_check(void *scratch, size_t scratch_bytes, void *stream) {
+  g_err.clear();
+  if (!scratch || scratch_bytes < sizeof(ObjHeader)) return fail(DGS_ERR_INVALID_ARG, "objective scratch missing");
+  hipStream_t st = (hipStream_t)stream;
+  ObjHeader h;
+  if (hipMemcpyAsync(&h, scratch, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return hip_check("objective check copy");
+  if (h.bad) return fail(DGS_ERR_INVALID_ARG, "an index in the objective's lists or target_of is out of range");
+  return hip_check("objective check");
 }
 
 }  // extern "C"

@@ -26,13 +26,9 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "ssim.h"
 
 namespace dgs {
-
-constexpr float kSsimC1 = 1.0e-4f;  // (0.01)^2
-constexpr float kSsimC2 = 9.0e-4f;  // (0.03)^2
-constexpr float kShift = 0.5f;
-constexpr int kSsimR = 5;           // window radius
 
 // ------------------------------------------------------------------ groups
 __global__ void k_group_table(const uint16_t *__restrict__ group_pl, int G, int P, int *__restrict__ pl2g,
@@ -152,97 +148,6 @@ k_pair_setup(const uint8_t *__restrict__ codes, const int32_t *__restrict__ cont
     const int cg = (ok && p == gp) ? gl + 1 : c;
     out[e] = (l < c ? 1u : 0u) | (l < cg ? 2u : 0u);
   }
-}
-
-// ------------------------------------------------------------------- SSIM
-// LDS of the window statistics of NX images against one reference, one
-// channel at a time, for a TW x TH output block with a 5-pixel apron: the
-// caller fills x and y (shifted values, apron row-major), ssim_moments then
-// returns this thread's pixel's shifted window means and second moments.
-template <int NX, int TW, int TH>
-struct SsimLds {
-  static constexpr int AW = TW + 2 * kSsimR, AH = TH + 2 * kSsimR, A = AW * AH;
-  float x[NX][A];
-  float y[A];
-  // horizontal pass, rows [0, NX) mu_k, NX mu_y, [NX+1, 2NX+1) e_kk, 2NX+1 e_yy, [2NX+2, 3NX+2) e_ky
-  float h[3 * NX + 2][AH * TW];
-};
-
-struct SsimWeights {
-  float w[2 * kSsimR + 1];
-};
-
-template <int NX, int TW, int TH>
-__device__ __forceinline__ void ssim_moments(SsimLds<NX, TW, TH> &L, const SsimWeights &W, float (&mu)[NX],
-                                             float &muy, float (&ekk)[NX], float &eyy, float (&eky)[NX]) {
-  using SL = SsimLds<NX, TW, TH>;
-  // horizontal 11-tap pass over every apron row, for the TW output columns
-  for (int q = threadIdx.x; q < SL::AH * TW; q += kBlock) {
-    const int r = q / TW, cx = q % TW;
-    float sm[NX], sk[NX], sky[NX], smy = 0.0f, syy = 0.0f;
-#pragma unroll
-    for (int k = 0; k < NX; ++k) sm[k] = sk[k] = sky[k] = 0.0f;
-#pragma unroll
-    for (int d = 0; d <= 2 * kSsimR; ++d) {
-      const int a = r * SL::AW + cx + d;
-      const float wd = W.w[d];
-      const float yv = L.y[a];
-      smy = fmaf(wd, yv, smy);
-      syy = fmaf(wd, yv * yv, syy);
-#pragma unroll
-      for (int k = 0; k < NX; ++k) {
-        const float xv = L.x[k][a];
-        sm[k] = fmaf(wd, xv, sm[k]);
-        sk[k] = fmaf(wd, xv * xv, sk[k]);
-        sky[k] = fmaf(wd, xv * yv, sky[k]);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      L.h[k][q] = sm[k];
-      L.h[NX + 1 + k][q] = sk[k];
-      L.h[2 * NX + 2 + k][q] = sky[k];
-    }
-    L.h[NX][q] = smy;
-    L.h[2 * NX + 1][q] = syy;
-  }
-  __syncthreads();
-  // vertical 11-tap pass for this thread's output pixel
-  const int ox = threadIdx.x % TW, oy = threadIdx.x / TW;
-  muy = eyy = 0.0f;
-#pragma unroll
-  for (int k = 0; k < NX; ++k) mu[k] = ekk[k] = eky[k] = 0.0f;
-#pragma unroll
-  for (int d = 0; d <= 2 * kSsimR; ++d) {
-    const int q = (oy + d) * TW + ox;
-    const float wd = W.w[d];
-    muy = fmaf(wd, L.h[NX][q], muy);
-    eyy = fmaf(wd, L.h[2 * NX + 1][q], eyy);
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      mu[k] = fmaf(wd, L.h[k][q], mu[k]);
-      ekk[k] = fmaf(wd, L.h[NX + 1 + k][q], ekk[k]);
-      eky[k] = fmaf(wd, L.h[2 * NX + 2 + k][q], eky[k]);
-    }
-  }
-}
-
-// SSIM from shifted window moments.
-__device__ __forceinline__ float ssim_value(float mx, float my, float exx, float eyy, float exy) {
-  const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
-  const float ux = mx + kShift, uy = my + kShift;
-  const float num = (2.0f * ux * uy + kSsimC1) * (2.0f * sxy + kSsimC2);
-  const float den = (ux * ux + uy * uy + kSsimC1) * (sxx + syy + kSsimC2);
-  return num / den;
-}
-
-// Sum over the workgroup (every thread gets it).
-__device__ __forceinline__ float block_sum(float v, float *red) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
 }
 
 // Pair items: per-pixel  sum_c (x1 - y)^2 - (x2 - y)^2 - lambda (ssim1 - ssim2)
@@ -488,14 +393,6 @@ __global__ void k_clear_util_header(UtilHeader *h) {
 
 // ----------------------------------------------------------------- launchers
 void launch_clear_util_header(UtilHeader *h, hipStream_t st) { k_clear_util_header<<<1, 64, 0, st>>>(h); }
-
-static SsimWeights ssim_weights() {
-  SsimWeights W;
-  double g[2 * kSsimR + 1], s = 0.0;
-  for (int d = -kSsimR; d <= kSsimR; ++d) s += (g[d + kSsimR] = exp(-(double)(d * d) / (2.0 * 1.5 * 1.5)));
-  for (int d = 0; d <= 2 * kSsimR; ++d) W.w[d] = (float)(g[d] / s);
-  return W;
-}
 
 void launch_group_setup(const UtilArgs &u, const uint16_t *group_pl, int G, int P, const float4 *rec0,
                         const uint2 *rect, int n, int rx, int ry, hipStream_t st) {

@@ -518,6 +518,92 @@ def sample_states(channels: torch.Tensor, num_packets: int, num_layers: int, see
     return codes
 
 
+# Eq. (2) weights the paper locks (Sec. 4)
+OBJECTIVE_WEIGHTS = dict(lambda_ssim=0.20, lambda_c=0.30, alpha=0.05, lambda_t=0.10, lambda_m=2.0, lambda_a=0.50)
+
+
+def _index_tensor(x, name, device, pairs=False):
+    if x is None:
+        return None, 0
+    t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x, np.int32).reshape(-1))
+    t = t.to(device=device, dtype=torch.int32).contiguous().reshape(-1)
+    if pairs and t.numel() % 2:
+        raise ValueError(f"{name} must hold (a, b) pairs")
+    return t, int(t.numel() // (2 if pairs else 1))
+
+
+class Objective:
+    """Eq. (2) of a training batch on the device: ``__call__`` returns
+    (loss parts [6] = L, E, CVaR, F, M, anchor; D per image; dL/d images).
+    Keeps its scratch buffer between calls."""
+
+    def __init__(self, device, weights=None):
+        self.device = torch.device(device)
+        w = dict(OBJECTIVE_WEIGHTS)
+        w.update(weights or {})
+        self.weights = _abi.ObjectiveWeights(*(float(w[k]) for k in ("lambda_ssim", "lambda_c", "alpha",
+                                                                         "lambda_t", "lambda_m", "lambda_a")))
+        self.scratch = None
+        self.scratch_bytes = 0
+
+    def __call__(self, images, targets, target_of, expect, anchor=None, mono=None, temporal=None, grad=True,
+                 out_grad=None):
+        dev = self.device
+        _check_tensor(images, "images", torch.float32, dev)
+        _check_tensor(targets, "targets", torch.float32, dev)
+        if images.dim() != 4 or images.shape[-1] != 3 or targets.dim() != 4 or \
+                tuple(targets.shape[1:]) != tuple(images.shape[1:]):
+            raise ValueError("images [K, H, W, 3] and targets [T, H, W, 3] of one image size")
+        K, H, Wd = (int(x) for x in images.shape[:3])
+        tof, nt = _index_tensor(target_of, "target_of", dev)
+        if nt != K:
+            raise ValueError("target_of needs one entry per image")
+        ex, ne = _index_tensor(expect, "expect", dev)
+        an, na = _index_tensor(anchor, "anchor", dev)
+        mo, nm = _index_tensor(mono, "mono", dev, pairs=True)
+        te, nq = _index_tensor(temporal, "temporal", dev, pairs=True)
+        L = _abi.lib()
+        nbytes = int(L.dgs_objective_scratch_bytes(K, Wd, H, nq))
+        if nbytes == 0:
+            raise ValueError("invalid sizes for dgs_objective")
+        if nbytes > self.scratch_bytes:
+            self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            self.scratch_bytes = nbytes
+        loss = torch.empty(6, dtype=torch.float32, device=dev)
+        d = torch.empty(K, dtype=torch.float32, device=dev)
+        g = None
+        if grad:
+            g = out_grad if out_grad is not None else torch.empty_like(images)
+        with torch.cuda.device(dev):
+            st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+            _abi.check(L.dgs_objective(_ptr(images), K, Wd, H, _ptr(targets), int(targets.shape[0]), _ptr(tof),
+                                       _ptr(ex), ne, _ptr(an), na, _ptr(mo), nm, _ptr(te), nq,
+                                       ctypes.byref(self.weights), _ptr(loss), _ptr(d), _ptr(g),
+                                       _ptr(self.scratch), self.scratch_bytes, st))
+        return loss, d, g
+
+    def check(self):
+        """Synchronise; raises DgsError if the last call met an index out of range."""
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            _abi.check(_abi.lib().dgs_objective_check(_ptr(self.scratch), self.scratch_bytes, st))
+
+
+class ObjectiveFunction(torch.autograd.Function):
+    """Eq. (2) as a differentiable function of the rendered images: the
+    forward returns L, the backward the device gradient scaled by dL."""
+
+    @staticmethod
+    def forward(ctx, objective, images, targets, target_of, expect, anchor, mono, temporal):
+        loss, d, g = objective(images.detach().contiguous(), targets, target_of, expect, anchor, mono, temporal)
+        ctx.image_grad = g
+        return loss[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        return (None, ctx.image_grad * grad_loss, None, None, None, None, None, None)
+
+
 def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
            background=(0, 0, 0)):
     """Differentiable render of every state in ``codes`` -> [W, H, Wd, 3]."""
