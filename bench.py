@@ -210,6 +210,7 @@ def main():
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)
+        out["train_step"] = train_step(dgs, synth, torch, np, dev, args)
 
     if not args.no_refined:
         out["refined"] = refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg)
@@ -272,6 +273,82 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
     return {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
             "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
             "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+
+
+def train_step(dgs, synth, torch, np, dev, args):
+    """One step of the packet-conditioned objective (Eq. (2) with the weights
+    the paper locks) on the 250k-Gaussian 1280x720 workload: 8 worlds (7
+    partial delivery states and the complete prefix) rendered at two times,
+    D of each image against the full-delivery render of the perturbed scene
+    at its time, CVaR over the 14 partial images, prefix pairs to the anchor
+    of each time, temporal pairs between the times, and the backward through
+    both renders to the six parameter tensors."""
+    name = "g250k_720p_8states_fwdbwd"
+    w = synth.make_workload(name)
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(w.codes).to(dev).clone()
+    codes[7] = 4  # the complete prefix
+    bg = tuple(float(x) for x in w.background)
+    bases = [synth.temporal_basis(t, w.scene.rank) for t in (w.t, w.t + 0.1)]
+    pert = dgs.GaussianScene.from_arrays(synth.perturb_scene(w.scene, 0.01, index=w.index), dev)
+    full = torch.full((1, w.scene.num_packets), 4, dtype=torch.uint8, device=dev)
+    rs = [dgs.Renderer(dev, tile=(16, 16), states_per_group=8) for _ in bases]
+    targets = torch.stack([rs[i].render(pert, cam, full, bases[i], bg)[0].clone() for i in range(2)])
+    for i in range(2):
+        rs[i].plan(scene, cam, bases[i], int(codes.shape[0]))
+    from paper_2606_17212_amd.render import PARAMS
+    params = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    sc = scene.with_params(**params)
+    ob = dgs.Objective(dev)
+    i32 = lambda a: torch.as_tensor(np.asarray(a, np.int32).reshape(-1)).to(dev)  # noqa: E731
+    expect = [k for k in range(16) if k % 8 != 7]
+    roles = dict(target_of=i32(np.repeat([0, 1], 8)), expect=i32(expect), anchor=i32([7, 15]),
+                 mono=i32([(k, 7 if k < 8 else 15) for k in expect]), temporal=i32([(k, k + 8) for k in range(8)]))
+
+    def it():
+        for p in params.values():
+            p.grad = None
+        imgs = torch.cat([dgs.render(rs[i], sc, cam, codes, bases[i], bg) for i in range(2)])
+        loss = dgs.ObjectiveFunction.apply(ob, imgs, targets, roles["target_of"], roles["expect"], roles["anchor"],
+                                           roles["mono"], roles["temporal"])
+        loss.backward()
+        return loss, imgs
+
+    for _ in range(3):
+        it()
+    for r in rs:
+        r.check()
+    ob.check()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    iters = max(5, args.steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(iters):
+        e0.record(st)
+        loss, imgs = it()
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    # the objective alone (forward parts + gradient images of the 16 images)
+    x = imgs.detach().contiguous()
+    ot = []
+    for _ in range(iters):
+        e0.record(st)
+        parts, _, _ = ob(x, targets, roles["target_of"], roles["expect"], roles["anchor"], roles["mono"],
+                         roles["temporal"])
+        e1.record(st)
+        torch.cuda.synchronize()
+        ot.append(e0.elapsed_time(e1))
+    ob.check()
+    finite = all(bool(torch.isfinite(p.grad).all()) for p in params.values())
+    pv = [round(float(v), 6) for v in parts.cpu()]
+    log(f"[bench] train step (Eq. 2) {name}: median {np.median(times):.3f} ms/iter for 2 x 8 states "
+        f"(objective {np.median(ot):.3f} ms); L, E, CVaR, F, M, anchor = {pv}")
+    return {"workload": name + "_eq2", "images": 16, "times": 2, "states_per_time": 8,
+            "ms_per_iter": round(float(np.median(times)), 4), "objective_ms": round(float(np.median(ot)), 4),
+            "loss_parts": pv, "grads_finite": finite}
 
 
 def refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg):

@@ -871,6 +871,7 @@ int dgs_objective(const float *images, int32_t num_images, int32_t width, int32_
   a.hdr = at<ObjHeader>(scratch, L.header);
   a.dpart = at<double>(scratch, L.dpart);
   a.tpart = at<double>(scratch, L.tpart);
+  a.tsum = at<double>(scratch, L.tsum);
   a.maps = at<float>(scratch, L.maps);
   a.coef = at<float>(scratch, L.coef);
   a.d = at<float>(scratch, L.d);

@@ -30,6 +30,7 @@ struct ObjLayout {
   size_t thist;   // u32 radix histograms for 2Q keys
   size_t tparts;  // scan partials
   size_t d;       // float [K]: D per image
+  size_t tsum;    // double [Q]: temporal squared error per pair
   size_t total;
 };
 
@@ -47,7 +48,7 @@ struct ObjArgs {
   ObjWeights w;
   float *loss, *distortion, *grad;
   ObjHeader *hdr;
-  double *dpart, *tpart;
+  double *dpart, *tpart, *tsum;
   float *maps, *coef, *d;
   int *cnt, *tcnt;
   uint32_t *tkey0, *tkey1, *tval0, *tval1, *thist;

@@ -61,6 +61,7 @@ ObjLayout make_obj_layout(int64_t K, int64_t width, int64_t height, int64_t Q) {
   L.thist = take(4 * 256 * sort_blocks);
   L.tparts = take(8 * (ceil_div(256 * sort_blocks, kScanTile) + 1));
   L.d = take(4 * kk);
+  L.tsum = take(8 * qq);
   L.total = o;
   return L;
 }
@@ -180,11 +181,20 @@ __device__ double block_sum_f64(double v, double *red) {
   return r;
 }
 
-// D per image (one workgroup per image).
+// D per image (workgroups 0..K-1) and the squared temporal-change error per
+// pair (workgroups K..K+Q-1), each summed over the 16x16 blocks in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_obj_dfinal(ObjArgs a) {
   __shared__ double red[4];
-  const int k = blockIdx.x;
   const int blocks = a.bx * a.by;
+  if ((int)blockIdx.x >= a.K) {
+    const int j = blockIdx.x - a.K;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += kBlock) s += a.tpart[(int64_t)j * blocks + b];
+    s = block_sum_f64(s, red);
+    if (threadIdx.x == 0) a.tsum[j] = s;
+    return;
+  }
+  const int k = blockIdx.x;
   double se = 0.0, ss = 0.0;
   for (int b = threadIdx.x; b < blocks; b += kBlock) {
     se += a.dpart[((int64_t)k * blocks + b) * 2];
@@ -293,16 +303,13 @@ __global__ void __launch_bounds__(kBlock) k_obj_weights(ObjArgs a) {
       atomicAdd(&cM[ia], -1);
     }
   }
-  const int blocks = a.bx * a.by;
   double sF = 0.0;
   for (int j = tid; j < a.n_temporal; j += kBlock) {
     const int ia = a.temporal[2 * j], ib = a.temporal[2 * j + 1];
     if (ia < 0 || ia >= K || ib < 0 || ib >= K) continue;  // flagged by k_obj_temporal
     const int ta = a.target_of[ia], tb = a.target_of[ib];
     if (ta < 0 || ta >= a.T || tb < 0 || tb >= a.T) continue;  // likewise
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += a.tpart[(int64_t)j * blocks + b];
-    sF += s;
+    sF += a.tsum[j];
     atomicAdd(&a.tcnt[ia], 1);
     atomicAdd(&a.tcnt[ib], 1);
   }
@@ -462,7 +469,7 @@ void launch_objective(const ObjArgs &a, hipStream_t st) {
                                     0, bits, a.thist, a.tparts, st, /*last_pass_keys=*/false);
     tvals = r ? a.tval1 : a.tval0;
   }
-  if (a.K > 0) k_obj_dfinal<<<a.K, kBlock, 0, st>>>(a);
+  if (a.K + a.n_temporal > 0) k_obj_dfinal<<<a.K + a.n_temporal, kBlock, 0, st>>>(a);
   k_obj_weights<<<1, kBlock, 0, st>>>(a);
   if (a.K > 0 && a.grad) k_obj_grad<<<dim3(blocks, a.K), kBlock, 0, st>>>(a, W, tvals);
 }
