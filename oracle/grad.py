@@ -57,6 +57,8 @@ def project(p: dict, scene, cam, basis):
         mu = torch.einsum("nkj,jn->kn", Ai[:, :, :3], mean) + Ai[:, :, 3].T
     for r in range(scene.rank):
         mu = mu + float(basis[r]) * p["temporal"][3 * r:3 * r + 3]
+    if "offset" in p:  # delivered position residual levels, after the deformation
+        mu = mu + p["offset"]
     Rc = torch.as_tensor(np.asarray(cam.R_cw, np.float64))
     tc = torch.as_tensor(np.asarray(cam.t_cw, np.float64))
     P = Rc @ mu + tc[:, None]
@@ -187,6 +189,57 @@ def gradients(scene, cam, basis, codes, background, grad_image, pixels=None) -> 
         full = np.zeros(np.asarray(getattr(scene, k)).shape, dtype=np.float64)
         full[..., sel] = params[k].grad.numpy()
         out[k] = full
+    return out
+
+
+def render_dense_refined(scene, refine, cam, basis, codes, background, pixels=None, base=None, levels=None):
+    """FP64 render of a scene with refinement levels (Sec. 3) as a
+    differentiable function of the base parameters ``base`` (dict of PARAMS)
+    and the levels ``levels`` ([3][rows][N]).  Each state w renders its
+    decoded scene: Gaussian i, delivered to depth d, carries base + level 1 +
+    ... + level d, and the position residual level 1 + ... + level d after the
+    deformation.  Discrete decisions come from the FP32 decoded scene
+    (``oracle.refined_scene``) and are frozen.  Returns [W][K][3]."""
+    from . import refined_scene
+    codes = np.asarray(codes, np.uint8)
+    if base is None:
+        base = params_from_scene(scene, requires_grad=False)
+    if levels is None:
+        levels = torch.tensor(np.asarray(refine, np.float64))
+    pl = scene.packet_layer.astype(np.int64)
+    out = []
+    for w in range(codes.shape[0]):
+        depth = np.minimum(codes[w][pl >> 2].astype(np.int64), 4) - 1
+        add = sum(levels[j] * torch.as_tensor((depth >= j + 1).astype(np.float64)) for j in range(3))
+        p = {"mean": base["mean"], "temporal": base["temporal"], "log_scale": base["log_scale"] + add[3:6],
+             "quat": base["quat"] + add[6:10], "opacity_logit": base["opacity_logit"] + add[10],
+             "color": base["color"] + add[11:], "offset": add[0:3]}
+        dec = refined_scene(scene, refine, codes[w])
+        img, _ = render_dense(dec, cam, basis, codes[w:w + 1], background, pixels, params=p)
+        out.append(img[0])
+    return torch.stack(out, 0)
+
+
+def gradients_refined(scene, refine, cam, basis, codes, background, grad_image, pixels=None) -> dict:
+    """Reference gradients of a scene with refinement levels for an upstream
+    image gradient: autograd of ``render_dense_refined``.  Returns the base
+    parameter gradients (PARAMS) and ``refine`` [3][rows][N]."""
+    codes = np.asarray(codes, np.uint8)
+    W = codes.shape[0]
+    base = params_from_scene(scene)
+    lv = torch.tensor(np.asarray(refine, np.float64), requires_grad=True)
+    out = {k: np.zeros(np.asarray(getattr(scene, k)).shape, dtype=np.float64) for k in PARAMS}
+    out["refine"] = np.zeros(lv.shape, dtype=np.float64)
+    if W == 0:
+        return out
+    gi = torch.as_tensor(np.asarray(grad_image, np.float64).reshape(W, -1, 3))
+    img = render_dense_refined(scene, refine, cam, basis, codes, background, pixels, base, lv)
+    (img * gi).sum().backward()
+    for k in PARAMS:
+        if base[k].grad is not None:
+            out[k] = base[k].grad.numpy().copy()
+    if lv.grad is not None:
+        out["refine"] = lv.grad.numpy().copy()
     return out
 
 

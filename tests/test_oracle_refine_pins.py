@@ -244,3 +244,78 @@ def test_refinement_generator_shapes_and_scales():
     for j in range(3):
         assert lv[j, 10].std() == pytest.approx(0.5 * 2.0 ** -j, rel=0.1)
     assert np.array_equal(lv, synth.make_refinement(sc, index=3))
+
+
+# ------------------------------------------------------------- gradients
+def _grad_case(n=24, seed=3):
+    import oracle.grad as og  # noqa: F401
+    from tests.scenes_for_tests import overlap_scene
+    sc = overlap_scene(n=n, seed=seed, sh_degree=1, rank=2)
+    cam = synth.ring_camera(24, 20)
+    basis = np.array([0.5, 0.25], np.float32)
+    rng = np.random.default_rng(seed)
+    lv = (rng.normal(0, 1, (3, oracle.refine_rows(1), n)) *
+          np.array([0.01] * 3 + [0.1] * 3 + [0.1] * 4 + [0.5] + [0.05] * 12)[None, :, None]).astype(np.float32)
+    codes = np.array([[1, 2, 3, 4], [4, 4, 4, 4], [0, 3, 2, 1], [2, 0, 4, 3]], np.uint8)
+    return sc, cam, basis, lv, codes
+
+
+def test_dense_refined_forward_matches_the_per_state_decode():
+    """The differentiable FP64 formulation (attribute sums in FP64, alphas in
+    dense rows) against the C renderer of each decoded state (FP32 sums)."""
+    import oracle.grad as og
+    sc, cam, basis, lv, codes = _grad_case()
+    dense = og.render_dense_refined(sc, lv, cam, basis, codes, BG).detach().numpy()
+    ref = oracle.render_refined(sc, lv, cam, basis, codes, BG)
+    d = np.abs(dense.reshape(ref["image"].shape) - ref["image"]).max(-1) - ref["budget"]
+    assert d.max() <= 2e-6, d.max()
+
+
+def test_refined_gradients_match_central_differences():
+    import torch
+    import oracle.grad as og
+    sc, cam, basis, lv, codes = _grad_case()
+    rng = np.random.default_rng(1)
+    gi = rng.normal(size=(codes.shape[0], cam.height * cam.width, 3))
+    g = og.gradients_refined(sc, lv, cam, basis, codes, BG, gi)
+    base = og.params_from_scene(sc, requires_grad=False)
+    lvt = torch.tensor(lv.astype(np.float64))
+
+    def f(b, l):
+        return float((og.render_dense_refined(sc, lv, cam, basis, codes, BG, None, b, l) * torch.as_tensor(gi)).sum())
+
+    h = 1e-6
+    picks = [("refine", (j, r, i)) for j in range(3) for r in (0, 2, 4, 7, 10, 13) for i in (0, 5, 11)]
+    picks += [(k, idx) for k, idx in (("mean", (0, 3)), ("log_scale", (1, 7)), ("quat", (2, 9)),
+                                      ("opacity_logit", (4,)), ("color", (5, 2)), ("temporal", (3, 6)))]
+    checked = 0
+    for k, idx in picks:
+        if k == "refine":
+            lp, lm = lvt.clone(), lvt.clone()
+            lp[idx] += h
+            lm[idx] -= h
+            fd = (f(base, lp) - f(base, lm)) / (2 * h)
+        else:
+            bp = {kk: v.clone() for kk, v in base.items()}
+            bm = {kk: v.clone() for kk, v in base.items()}
+            bp[k][idx] += h
+            bm[k][idx] -= h
+            fd = (f(bp, lvt) - f(bm, lvt)) / (2 * h)
+        assert g[k][idx] == pytest.approx(fd, abs=1e-6, rel=1e-5), (k, idx, g[k][idx], fd)
+        checked += abs(fd) > 1e-4
+    assert checked >= 10  # the picks exercise real gradients
+
+
+def test_refined_gradients_of_base_only_states():
+    """States delivering depth 0 everywhere use no level: the level gradients
+    are exactly zero and the base gradients are the plain renderer's."""
+    import oracle.grad as og
+    sc, cam, basis, lv, _ = _grad_case()
+    codes = np.array([[1, 1, 1, 1], [1, 0, 1, 1]], np.uint8)
+    rng = np.random.default_rng(2)
+    gi = rng.normal(size=(2, cam.height * cam.width, 3))
+    g = og.gradients_refined(sc, lv, cam, basis, codes, BG, gi)
+    assert np.all(g["refine"] == 0.0)
+    plain = og.gradients(sc, cam, basis, codes, BG, gi)
+    for k in og.PARAMS:
+        np.testing.assert_allclose(g[k], plain[k], rtol=0, atol=1e-12, err_msg=k)
