@@ -81,8 +81,9 @@ typedef enum {
  * (level 1 + ... + level d, summed from zero) added after the deformation.
  * The renderer projects one record per (Gaussian, depth) - 4n records, size
  * the workspace for n_records = 4n - and each state draws the record of the
- * depth it delivers.  dgs_render_per_state, dgs_backward and the utility calls
- * return DGS_ERR_UNSUPPORTED for such scenes.
+ * depth it delivers.  dgs_backward also returns the levels' gradients
+ * (dgs_scene_grad.refine).  dgs_render_per_state and the utility calls return
+ * DGS_ERR_UNSUPPORTED for such scenes.
  */
 typedef struct {
   int32_t n;
@@ -142,7 +143,10 @@ typedef struct {
   int32_t flags;
 } dgs_tuning;
 
-/* Parameter gradients, device pointers with the scene's shapes; overwritten. */
+/* Parameter gradients, device pointers with the scene's shapes; overwritten.
+ * refine: [3][rows][n] gradients of the refinement levels (required when the
+ * scene has them, else ignored): level j's gradient sums the gradients of the
+ * Gaussian's records at depths >= j; the base parameters' sum all its records. */
 typedef struct {
   float *mean;
   float *log_scale;
@@ -150,6 +154,7 @@ typedef struct {
   float *opacity_logit;
   float *color;
   float *temporal;
+  float *refine;
 } dgs_scene_grad;
 
 int dgs_abi_version(void);

@@ -64,7 +64,7 @@ class Tuning(ctypes.Structure):
 class SceneGrad(ctypes.Structure):
     _fields_ = [("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p), ("quat", ctypes.c_void_p),
                 ("opacity_logit", ctypes.c_void_p), ("color", ctypes.c_void_p),
-                ("temporal", ctypes.c_void_p)]
+                ("temporal", ctypes.c_void_p), ("refine", ctypes.c_void_p)]
 
 
 class WorkspaceView(ctypes.Structure):

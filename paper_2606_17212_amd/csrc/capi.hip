@@ -568,15 +568,16 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
                  const dgs_scene_grad *grad, void *stream) {
   g_err.clear();
   Call cl;
-  int rc = reject_refined(scene, "dgs_backward");
-  if (rc || (rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl))) return rc;
+  int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl);
+  if (rc) return rc;
   if (!grad || (scene->n > 0 && (!grad->mean || !grad->log_scale || !grad->quat || !grad->opacity_logit ||
-                                 !grad->color || (scene->rank > 0 && !grad->temporal))))
+                                 !grad->color || (scene->rank > 0 && !grad->temporal) ||
+                                 (scene->refine && !grad->refine))))
     return fail(DGS_ERR_INVALID_ARG, "gradient pointer is NULL");
   const int W = states->num_states;
   if (W > 0 && (!image || !grad_image)) return fail(DGS_ERR_INVALID_ARG, "image / grad_image is NULL");
   hipStream_t st = (hipStream_t)stream;
-  const int n = cl.s.n;
+  const int n = cl.records;  // 2D gradients per projected record
   float *g2d = at<float>(ws, cl.L.grad2d);
   launch_fill_f32(g2d, (int64_t)9 * n, 0.0f, st);
   if (W > 0) {
@@ -586,7 +587,7 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
     uint32_t *order = at<uint32_t>(ws, cl.L.state_order);
     launch_state_order(states->codes, at<uint32_t>(ws, cl.L.plhist), W, cl.P, at<uint32_t>(ws, cl.L.state_cnt),
                        order, st);
-    launch_visbits(states->codes, order, W, cl.P, S, false, visbits, st);
+    launch_visbits(states->codes, order, W, cl.P, S, scene->refine != nullptr, visbits, st);
     CompositeBwdArgs b{};
     b.tile_order = at<uint32_t>(ws, cl.L.tile_order);
     b.state_order = order;
@@ -611,7 +612,7 @@ int dgs_backward(const dgs_scene *scene, const dgs_camera *cam, const dgs_states
       return fail(DGS_ERR_UNSUPPORTED, "no backward variant for S=%d", S);
   }
   launch_geometry_bwd(cl.s, cl.c, g2d, grad->mean, grad->log_scale, grad->quat, grad->opacity_logit,
-                      grad->color, grad->temporal, st);
+                      grad->color, grad->temporal, grad->refine, st);
   return hip_check("backward launch");
 }
 

@@ -218,47 +218,74 @@ k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ l
   dval[j] = (uint32_t)v;
 }
 
-// Chain rule from the per-Gaussian 2D gradients (u, v, conic A, B, C,
-// opacity, colour) to the parameters.  Discrete decisions are frozen: the
-// clamps of x/z, y/z and of the SH colour pass zero gradient; depth only
-// orders and carries none.
-__global__ void __launch_bounds__(kBlock)
-k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *__restrict__ g_mean,
-               float *__restrict__ g_ls, float *__restrict__ g_quat, float *__restrict__ g_logit,
-               float *__restrict__ g_color, float *__restrict__ g_temporal) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int64_t n = s.n;
-  if (i >= n) return;
+// Gradients of one projected record with respect to the attributes it was
+// projected from: the deformed mean, log-scale, raw quaternion, opacity logit
+// and colour coefficients (at the record's delivered depth d with refinement
+// levels).  Discrete decisions are frozen: the clamps of x/z, y/z and of the
+// SH colour pass zero gradient; depth only orders and carries none.
+struct AttrGrad {
+  float mu[3], ls[3], q[4], logit, col[12];
+};
+
+__device__ inline void zero_grad(AttrGrad &g) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.mu[k] = g.ls[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g.q[k] = 0.0f;
+  g.logit = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) g.col[k] = 0.0f;
+}
+
+__device__ inline void add_grad(AttrGrad &a, const AttrGrad &b) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { a.mu[k] += b.mu[k]; a.ls[k] += b.ls[k]; }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a.q[k] += b.q[k];
+  a.logit += b.logit;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a.col[k] += b.col[k];
+}
+
+// g2d: [9][nrec] gradients of record v w.r.t. (u, v, A', B', C', log2 o, r, g, b).
+// Returns false (and leaves g zero) for a record that received no gradient.
+__device__ inline bool record_grads(const SceneArgs &s, const CamArgs &cam, const float *__restrict__ g2d,
+                                    int64_t nrec, int64_t v, int i, int d, AttrGrad &g) {
+  zero_grad(g);
   // the compositing backward differentiates w.r.t. (u, v, A', B', C', log2 o): undo the scalings
-  const float gu = g2d[i], gv = g2d[n + i];
-  const float gA = kConicA * g2d[2 * n + i], gB = kConicB * g2d[3 * n + i];
-  const float gC = kConicA * g2d[4 * n + i], glo = g2d[5 * n + i];
-  const float gcol[3] = {g2d[6 * n + i], g2d[7 * n + i], g2d[8 * n + i]};
+  const float gu = g2d[v], gv = g2d[nrec + v];
+  const float gA = kConicA * g2d[2 * nrec + v], gB = kConicB * g2d[3 * nrec + v];
+  const float gC = kConicA * g2d[4 * nrec + v], glo = g2d[5 * nrec + v];
+  const float gcol[3] = {g2d[6 * nrec + v], g2d[7 * nrec + v], g2d[8 * nrec + v]};
+  if (gu == 0.0f && gv == 0.0f && gA == 0.0f && gB == 0.0f && gC == 0.0f && glo == 0.0f && gcol[0] == 0.0f &&
+      gcol[1] == 0.0f && gcol[2] == 0.0f)
+    return false;  // not composited anywhere (or culled): nothing flows back
+  const int64_t n = s.n;
   Proj p;
-  project(s, cam, i, 0, p);
+  project(s, cam, i, d, p);
   float col[3], dir[3], raw[3];
-  colour(s, cam, i, 0, p.mu, col, dir, raw);
+  colour(s, cam, i, d, p.mu, col, dir, raw);
 
   // opacity: log2 o = -log2(1 + e^{-logit}), d/dlogit = (1 - o) / ln 2
-  const float o = 1.0f / (1.0f + __expf(-s.opacity_logit[i]));
-  g_logit[i] = glo * (1.0f - o) * 1.4426950408889634f;
+  const float o = 1.0f / (1.0f + __expf(-refined(s, s.opacity_logit[i], 10, i, d)));
+  g.logit = glo * (1.0f - o) * 1.4426950408889634f;
 
-  float gmu[3] = {0.0f, 0.0f, 0.0f};
   // colour
   if (s.sh_degree == 0) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) g_color[ch * n + i] = gcol[ch];
+    for (int ch = 0; ch < 3; ++ch) g.col[ch] = gcol[ch];
   } else {
     float gd[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       const float gr = raw[ch] > 0.0f ? gcol[ch] : 0.0f;
-      const float k1 = s.color[(3 + ch) * n + i], k2 = s.color[(6 + ch) * n + i];
-      const float k3 = s.color[(9 + ch) * n + i];
-      g_color[ch * n + i] = kShC0 * gr;
-      g_color[(3 + ch) * n + i] = -kShC1 * dir[1] * gr;
-      g_color[(6 + ch) * n + i] = kShC1 * dir[2] * gr;
-      g_color[(9 + ch) * n + i] = -kShC1 * dir[0] * gr;
+      const float k1 = refined(s, s.color[(3 + ch) * n + i], 14 + ch, i, d);
+      const float k2 = refined(s, s.color[(6 + ch) * n + i], 17 + ch, i, d);
+      const float k3 = refined(s, s.color[(9 + ch) * n + i], 20 + ch, i, d);
+      g.col[ch] = kShC0 * gr;
+      g.col[3 + ch] = -kShC1 * dir[1] * gr;
+      g.col[6 + ch] = kShC1 * dir[2] * gr;
+      g.col[9 + ch] = -kShC1 * dir[0] * gr;
       gd[0] += -kShC1 * k3 * gr;
       gd[1] += -kShC1 * k1 * gr;
       gd[2] += kShC1 * k2 * gr;
@@ -267,7 +294,7 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
     const float inv = 1.0f / sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
     const float dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) * inv;
+    for (int k = 0; k < 3; ++k) g.mu[k] += (gd[k] - dir[k] * dd) * inv;
   }
 
   // conic (A, B, C) -> 2D covariance (a, b, c): d(Sigma^-1) = -Sigma^-1 dSigma Sigma^-1
@@ -278,17 +305,14 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
 
   // (a, b, c) -> V (2x3) and the scale variances
   float gV[6];
-  float gls[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const float v0 = p.V[k], v1 = p.V[3 + k], vs = p.vs[k];
     gV[k] = (2.0f * ga * v0 + gb * v1) * vs;
     gV[3 + k] = (2.0f * gc * v1 + gb * v0) * vs;
     const float gvs = ga * v0 * v0 + gb * v0 * v1 + gc * v1 * v1;
-    gls[k] = 2.0f * vs * gvs;
+    g.ls[k] = 2.0f * vs * gvs;
   }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) g_ls[k * n + i] = gls[k];
 
   // V = M Rq
   float gM[6], gR[9];
@@ -322,7 +346,7 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
              gj12 * fy * (iny ? 2.0f * p.yz : p.tyz) * iz2;
   // P = R_cw mu + t
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gmu[k] += cam.R[k] * gX + cam.R[3 + k] * gY + cam.R[6 + k] * gZ;
+  for (int k = 0; k < 3; ++k) g.mu[k] += cam.R[k] * gX + cam.R[3 + k] * gY + cam.R[6 + k] * gZ;
 
   // rotation -> normalised quaternion -> raw quaternion
   const float w = p.qw, x = p.qx, y = p.qy, z = p.qz;
@@ -335,25 +359,80 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
                            y * gR[5] + x * gR[6] + y * gR[7]);
   const float dq = w * gw + x * gx + y * gy + z * gz;
   const float iq = 1.0f / p.qnorm;
-  g_quat[i] = (gw - w * dq) * iq;
-  g_quat[n + i] = (gx - x * dq) * iq;
-  g_quat[2 * n + i] = (gy - y * dq) * iq;
-  g_quat[3 * n + i] = (gz - z * dq) * iq;
+  g.q[0] = (gw - w * dq) * iq;
+  g.q[1] = (gx - x * dq) * iq;
+  g.q[2] = (gy - y * dq) * iq;
+  g.q[3] = (gz - z * dq) * iq;
+  return true;
+}
 
-  // deformation: mu = A_c [m; 1] + sum_r b_r q_r
+// Base parameter gradients from attribute gradients: the deformation
+// mu = A_c [m; 1] + sum_r b_r q_r takes the mean's share.
+__device__ inline void write_base_grads(const SceneArgs &s, int64_t i, const AttrGrad &g, float *__restrict__ g_mean,
+                                        float *__restrict__ g_ls, float *__restrict__ g_quat,
+                                        float *__restrict__ g_logit, float *__restrict__ g_color,
+                                        float *__restrict__ g_temporal) {
+  const int64_t n = s.n;
+  g_logit[i] = g.logit;
+  const int ncol = s.sh_degree == 0 ? 3 : 12;
+  for (int k = 0; k < ncol; ++k) g_color[k * n + i] = g.col[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g_ls[k * n + i] = g.ls[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g_quat[k * n + i] = g.q[k];
   if (s.affine) {
     const int pk = (int)(s.packet_layer[i] >> 2);
     const int cl = (pk < s.num_packets ? pk : 0) / s.num_contexts;
     const float *Af = s.affine + 12 * cl;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) g_mean[j * n + i] = Af[j] * gmu[0] + Af[4 + j] * gmu[1] + Af[8 + j] * gmu[2];
+    for (int j = 0; j < 3; ++j) g_mean[j * n + i] = Af[j] * g.mu[0] + Af[4 + j] * g.mu[1] + Af[8 + j] * g.mu[2];
   } else {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) g_mean[k * n + i] = gmu[k];
+    for (int k = 0; k < 3; ++k) g_mean[k * n + i] = g.mu[k];
   }
   for (int r = 0; r < s.rank; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) g_temporal[(3 * r + k) * n + i] = s.basis[r] * gmu[k];
+    for (int k = 0; k < 3; ++k) g_temporal[(3 * r + k) * n + i] = s.basis[r] * g.mu[k];
+}
+
+// REFINED: one thread per Gaussian walks its records from depth 3 down; the
+// running sum over depths >= d is the gradient of level d (every record of
+// depth >= d carries level d), the full sum the base parameters'.  g_refine:
+// [3][rows][n] in the layout of the scene's levels.
+template <bool REFINED>
+__global__ void __launch_bounds__(kBlock)
+k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *__restrict__ g_mean,
+               float *__restrict__ g_ls, float *__restrict__ g_quat, float *__restrict__ g_logit,
+               float *__restrict__ g_color, float *__restrict__ g_temporal, float *__restrict__ g_refine) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int64_t n = s.n;
+  if (i >= n) return;
+  AttrGrad acc;
+  if (!REFINED) {
+    record_grads(s, cam, g2d, n, i, i, 0, acc);
+  } else {
+    zero_grad(acc);
+    const int layer = (int)(s.packet_layer[i] & 3u);
+    const int ncol = s.sh_degree == 0 ? 3 : 12;
+    const int64_t rows = s.refine_rows;
+#pragma unroll 1
+    for (int d = 3; d >= 0; --d) {
+      AttrGrad g;
+      if (d >= layer && record_grads(s, cam, g2d, 4 * n, 4 * (int64_t)i + d, i, d, g)) add_grad(acc, g);
+      if (d >= 1) {
+        float *L = g_refine + (int64_t)(d - 1) * rows * n + i;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L[k * n] = acc.mu[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L[(3 + k) * n] = acc.ls[k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) L[(6 + k) * n] = acc.q[k];
+        L[10 * n] = acc.logit;
+        for (int k = 0; k < ncol; ++k) L[(11 + k) * n] = acc.col[k];
+      }
+    }
+  }
+  write_base_grads(s, i, acc, g_mean, g_ls, g_quat, g_logit, g_color, g_temporal);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -372,10 +451,14 @@ void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, co
 
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,
                          float *g_ls, float *g_quat, float *g_logit, float *g_color, float *g_temporal,
-                         hipStream_t st) {
+                         float *g_refine, hipStream_t st) {
   if (s.n <= 0) return;
-  k_geometry_bwd<<<(unsigned)ceil_div(s.n, kBlock), kBlock, 0, st>>>(s, c, g2d, g_mean, g_ls, g_quat,
-                                                                     g_logit, g_color, g_temporal);
+  if (s.refine)
+    k_geometry_bwd<true><<<(unsigned)ceil_div(s.n, kBlock), kBlock, 0, st>>>(s, c, g2d, g_mean, g_ls, g_quat,
+                                                                             g_logit, g_color, g_temporal, g_refine);
+  else
+    k_geometry_bwd<false><<<(unsigned)ceil_div(s.n, kBlock), kBlock, 0, st>>>(s, c, g2d, g_mean, g_ls, g_quat,
+                                                                              g_logit, g_color, g_temporal, nullptr);
 }
 
 }  // namespace dgs

@@ -11,7 +11,7 @@ void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, co
                      uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st);
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,
                          float *g_ls, float *g_quat, float *g_logit, float *g_color, float *g_temporal,
-                         hipStream_t st);
+                         float *g_refine, hipStream_t st);
 
 // sort.hip: exclusive scan of u32 values (total written as u64 when non-null)
 // and stable LSD radix sort of (u32 key, u32 value) pairs.

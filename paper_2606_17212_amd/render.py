@@ -415,10 +415,13 @@ class Renderer:
     def backward(self, scene: GaussianScene, camera: Camera, codes, basis, background, image, grad_image,
                  params=None):
         """Parameter gradients (dict of tensors) for dL/d image; the workspace
-        must still hold this render's lists (see ``RenderFunction``)."""
+        must still hold this render's lists (see ``RenderFunction``).  With
+        refinement levels the dict also holds ``refine``."""
         p = params or {k: getattr(scene, k) for k in PARAMS}
         grads = {k: torch.empty_like(p[k]) for k in PARAMS}
-        g = _abi.SceneGrad(*[_ptr(grads[k]) for k in PARAMS])
+        if scene.refine is not None:
+            grads["refine"] = torch.empty_like(scene.refine)
+        g = _abi.SceneGrad(*[_ptr(grads[k]) for k in PARAMS], _ptr(grads.get("refine")))
         image = image.contiguous()
         grad_image = grad_image.contiguous()
         _abi.check(_abi.lib().dgs_backward(
@@ -429,7 +432,9 @@ class Renderer:
 
 
 class RenderFunction(torch.autograd.Function):
-    """Differentiable batched render: gradients for the six parameter tensors.
+    """Differentiable batched render: gradients for the six parameter tensors
+    (and the refinement levels, passed as a seventh tensor, when the scene has
+    them).
 
     The backward replays each tile's compositing from the forward's sorted
     lists.  If the renderer's workspace was reused by another call in between,
@@ -438,6 +443,8 @@ class RenderFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, renderer, scene, camera, codes, basis, background, *params):
         p = dict(zip(PARAMS, params))
+        if len(params) > len(PARAMS):
+            scene = scene.with_params(refine=params[len(PARAMS)])
         img = renderer.render(scene, camera, codes, basis, background, params=p)
         ctx.renderer, ctx.scene, ctx.camera = renderer, scene, camera
         ctx.codes, ctx.basis, ctx.background = codes, basis, background
@@ -453,7 +460,8 @@ class RenderFunction(torch.autograd.Function):
         if r.generation != ctx.generation:
             r.render(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, params=p)
         g = r.backward(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, img, grad_image, params=p)
-        return (None, None, None, None, None, None) + tuple(g[k] for k in PARAMS)
+        out = tuple(g[k] for k in PARAMS) + ((g["refine"],) if len(params) > len(PARAMS) else ())
+        return (None, None, None, None, None, None) + out
 
 
 def distortion(images: torch.Tensor, reference: torch.Tensor, lam: float = 0.20) -> torch.Tensor:
@@ -606,8 +614,11 @@ class ObjectiveFunction(torch.autograd.Function):
 
 def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
            background=(0, 0, 0)):
-    """Differentiable render of every state in ``codes`` -> [W, H, Wd, 3]."""
+    """Differentiable render of every state in ``codes`` -> [W, H, Wd, 3]
+    (gradients also reach ``scene.refine`` when the scene has levels)."""
     params = [getattr(scene, k) for k in PARAMS]
+    if scene.refine is not None:
+        params.append(scene.refine)
     return RenderFunction.apply(renderer, scene, camera, codes, tuple(float(b) for b in basis),
                                 tuple(float(x) for x in background), *params)
 

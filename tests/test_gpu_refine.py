@@ -8,7 +8,10 @@ Bars: images within 1e-4 of the FP64 oracle plus its ambiguity budget; every
 record's depth key and tile rectangle bit-exact with the FP32 mirror of the
 decoded scene at that depth; group size and tile shape change no pixel;
 all-zero levels give the plain renderer's images bit for bit; calls that take
-no refinement levels raise DGS_ERR_UNSUPPORTED.
+no refinement levels raise DGS_ERR_UNSUPPORTED.  Gradients of the base
+parameters and of the levels against the FP64 oracle with the bar of the plain
+backward (per tensor relative norm <= 1e-3, elementwise <= 1e-3 (|g*| +
+rms g*) outside Gaussians that touch an ambiguous pixel).
 """
 
 import numpy as np
@@ -16,6 +19,7 @@ import pytest
 import torch
 
 import oracle
+import oracle.grad as og
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -150,11 +154,65 @@ def test_refined_psnr_and_unsupported_calls(case):
     with pytest.raises(dgs.DgsError) as e:
         r.render(s, c, cd, basis, BG, per_state=True)
     assert e.value.status == 5
-    img = r.render(s, c, cd, basis, BG)
-    with pytest.raises(dgs.DgsError) as e:
-        r.backward(s, c, cd, basis, BG, img, torch.ones_like(img))
-    assert e.value.status == 5
     # a refine array of the wrong shape is refused before any launch
     bad = s.with_params(refine=s.refine[:, :5].contiguous())
     with pytest.raises(ValueError):
         r.render(bad, c, cd, basis, BG)
+
+
+def _ambiguous(scene, levels, cam, basis, codes, budget):
+    """Gaussians reaching alpha >= 1/(2*255), at any delivered depth, at a
+    pixel where some state has a nonzero ambiguity budget."""
+    pix = np.argwhere(budget.max(0) > 0)[:, ::-1]
+    out = np.zeros(scene.n, dtype=bool)
+    for d in range(4):
+        dec = oracle.refined_scene(scene, levels, np.full(scene.num_packets, d + 1, np.uint8))
+        g = oracle.geometry_f64(dec, cam, basis)
+        for (px, py) in pix:
+            dx, dy = g["u"] - (px + 0.5), g["v"] - (py + 0.5)
+            q = g["conA"] * dx * dx + 2 * g["conB"] * dx * dy + g["conC"] * dy * dy
+            out |= g["o"] * np.exp(-0.5 * q) >= 0.5 / 255
+    return out
+
+
+def _compare(got, ref, exclude, rel=1e-3):
+    for k in ref:
+        a, b = got[k], ref[k]
+        nb = np.linalg.norm(b)
+        if nb == 0:
+            assert np.linalg.norm(a) <= 1e-6, k
+            continue
+        assert np.linalg.norm(a - b) / nb <= rel, (k, np.linalg.norm(a - b) / nb)
+        rms = np.sqrt(np.mean(b * b))
+        bad = (np.abs(a - b) > rel * (np.abs(b) + rms)) & ~exclude
+        assert not bad.any(), (k, int(bad.sum()), np.argwhere(bad)[:5])
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_refined_gradients_match_fp64_oracle(tile):
+    from paper_2606_17212_amd.render import PARAMS
+    dgs = _dgs()
+    w = synth.subscene(256, 64, 64, states=8, log_scale_mean=-2.0, background=BG)
+    levels = synth.make_refinement(w.scene, index=31)
+    codes = w.codes.copy()
+    codes[0] = 4
+    codes[1] = 1
+    dev = torch.device("cuda:0")
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev, refine=levels)
+    cam = dgs.Camera.from_arrays(w.camera)
+    p = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    p["refine"] = scene.refine.clone().requires_grad_(True)
+    sc = scene.with_params(**p)
+    r = dgs.Renderer(dev, tile=tile, states_per_group=8)
+    img = dgs.render(r, sc, cam, torch.from_numpy(codes).to(dev), w.basis, BG)
+    rng = np.random.default_rng(8)
+    gimg = rng.normal(size=img.shape)
+    (img * torch.from_numpy(gimg.astype(np.float32)).to(dev)).sum().backward()
+    r.check()
+    got = {k: v.grad.double().cpu().numpy() for k, v in p.items()}
+    ref_img = oracle.render_refined(w.scene, levels, w.camera, w.basis, codes, np.asarray(BG, np.float32))
+    d = np.abs(img.detach().cpu().numpy() - ref_img["image"]).max(-1) - ref_img["budget"]
+    assert d.max() <= TOL
+    ref = og.gradients_refined(w.scene, levels, w.camera, w.basis, codes, BG, gimg)
+    assert np.abs(ref["refine"]).max() > 0
+    _compare(got, ref, _ambiguous(w.scene, levels, w.camera, w.basis, codes, ref_img["budget"]))
