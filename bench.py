@@ -270,9 +270,42 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
     r.check()
     finite = all(bool(torch.isfinite(p.grad).all()) for p in params.values())
     log(f"[bench] fwd+bwd {name}: median {np.median(times):.3f} ms/iter, loss {float(loss.detach()):.5f}")
-    return {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
-            "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
-            "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+    out = {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
+           "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
+           "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+
+    # the same step with three refinement levels (gradients for base and levels)
+    levels = synth.make_refinement(w.scene, index=w.index)
+    rs = dgs.GaussianScene.from_arrays(w.scene, dev, refine=levels)
+    rp = {k: getattr(rs, k).clone().requires_grad_(True) for k in PARAMS}
+    rp["refine"] = rs.refine.clone().requires_grad_(True)
+    rsc = rs.with_params(**rp)
+    r.plan(rs, cam, w.basis, codes.shape[0])
+
+    def it_refined():
+        for p in rp.values():
+            p.grad = None
+        img = dgs.render(r, rsc, cam, codes, w.basis, bg)
+        loss = (img - target).abs().mean()
+        loss.backward()
+        return loss
+
+    for _ in range(3):
+        it_refined()
+    r.check()
+    rtimes = []
+    for _ in range(iters):
+        e0.record(st)
+        it_refined()
+        e1.record(st)
+        torch.cuda.synchronize()
+        rtimes.append(e0.elapsed_time(e1))
+    r.check()
+    rfinite = all(bool(torch.isfinite(p.grad).all()) for p in rp.values())
+    log(f"[bench] fwd+bwd with refinement levels: median {np.median(rtimes):.3f} ms/iter")
+    out["refined"] = {"ms_per_iter": round(float(np.median(rtimes)), 4), "records": rs.records,
+                      "grads_finite": rfinite}
+    return out
 
 
 def train_step(dgs, synth, torch, np, dev, args):
