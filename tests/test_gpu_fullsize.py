@@ -78,3 +78,48 @@ def test_full_size_1m_540p_psnr_batch():
     ref = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
     ex = np.abs(host_img.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
     assert ex.max() <= TOL, f"excess {ex.max():.3g}"
+
+
+def test_full_size_250k_800px_64states_refined():
+    """The headline workload with three refinement levels, in the bench's
+    launch shape: instance count from the mirrors of the four depth records,
+    sampled tiles' lists (records of the Gaussian at each depth) and sampled
+    pixels of every state against the per-state decode of the oracle."""
+    import paper_2606_17212_amd as dgs
+    w = synth.make_workload("g250k_800px_64states", background=(0.25, 0.5, 0.75))
+    levels = synth.make_refinement(w.scene, index=w.index)
+    dev = torch.device("cuda:0")
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev, refine=levels)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(np.ascontiguousarray(w.codes)).to(dev)
+    r = dgs.Renderer(tile=(16, 16), states_per_group=8)
+    img = r.render(scene, cam, codes, w.basis, tuple(w.background))
+    M = r.check()
+    sec = r.sections(scene, cam, codes.shape[0])
+    n = w.scene.n
+    layer = (w.scene.packet_layer & 3).astype(np.int64)
+    # record 4 i + d: Gaussian i at depth d, present when layer_i <= d
+    zb = np.zeros(4 * n, np.uint32)
+    rect = np.zeros((4, 4 * n), np.int64)
+    valid = np.zeros(4 * n, bool)
+    for d in range(4):
+        m = oracle.mirror_f32(oracle.refined_scene(w.scene, levels, np.full(w.scene.num_packets, d + 1, np.uint8)),
+                              w.camera, w.basis)
+        zb[d::4] = m["zbits"]
+        rect[:, d::4] = m["rect"]
+        valid[d::4] = m["valid"] & (layer <= d)
+    mm = dict(zbits=zb, rect=rect, valid=valid)
+    assert M == int(np.where(valid, (rect[2] - rect[0]).clip(0) * (rect[3] - rect[1]).clip(0), 0).sum())
+    ranges = sec["ranges"].numpy().astype(np.int64)
+    ids = sec["sorted_ids"].numpy()
+    rng = np.random.default_rng(6)
+    tiles = np.concatenate([rng.integers(0, ranges.shape[0], 8), np.argsort(ranges[:, 1] - ranges[:, 0])[-3:]])
+    for t in tiles:
+        want = _tile_list(mm, int(t), sec["tiles_x"])
+        assert np.array_equal(ids[ranges[t, 0]:ranges[t, 1]].astype(np.int64), want), t
+    pix = np.concatenate([np.stack([rng.integers(0, 800, 12), rng.integers(0, 800, 12)], 1),
+                          np.stack([rng.integers(250, 550, 12), rng.integers(250, 550, 12)], 1)])
+    host = img[:, pix[:, 1], pix[:, 0], :].cpu().numpy()
+    ref = oracle.render_refined(w.scene, levels, w.camera, w.basis, w.codes, w.background, pixels=pix)
+    ex = np.abs(host.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
+    assert ex.max() <= TOL, f"excess {ex.max():.3g}"
