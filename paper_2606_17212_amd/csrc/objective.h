@@ -22,7 +22,7 @@ struct ObjLayout {
   size_t header;  // ObjHeader
   size_t dpart;   // double [K][blocks][2]: squared error and SSIM sums per 16x16 block
   size_t tpart;   // double [Q][blocks]: temporal squared error per block
-  size_t maps;    // float [K][9][H][W]: SSIM gradient coefficients (a, b, c) per channel
+  size_t maps;    // float [K][H][W][9]: SSIM gradient coefficients (a, b, c) per channel
   size_t cnt;     // int [5][K]: role counts (expect, tail, tail boundary, anchor, hinge sign)
   size_t coef;    // float [K]: dL/dD per image
   size_t tcnt;    // int [K + 1]: temporal pairs per image, then their offsets

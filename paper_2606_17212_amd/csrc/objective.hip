@@ -67,10 +67,34 @@ ObjLayout make_obj_layout(int64_t K, int64_t width, int64_t height, int64_t Q) {
 }
 
 // ------------------------------------------------------------- moments
+// One 16x16 block of one image.  The three channels of the 26x26 apron are
+// read at once (12 contiguous bytes per pixel), the horizontal 11-tap pass
+// of the five window sums runs for all channels with two adjacent output
+// columns per task (12 reads for 22 taps), then the vertical pass, SSIM and
+// the coefficient maps per channel.  Three barriers in all.
+constexpr int kObjAW = 16 + 2 * kSsimR, kObjAH = 16 + 2 * kSsimR, kObjA = kObjAW * kObjAH;
+
+// Horizontal 11-tap sums of rows r of `in` (apron layout) for output columns
+// cx and cx + 1.
+__device__ __forceinline__ void hpass2(const float *__restrict__ in, const SsimWeights &W, int r, int cx,
+                                       float &o0, float &o1) {
+  const float *row = in + r * kObjAW + cx;
+  float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+  for (int d = 0; d <= 2 * kSsimR + 1; ++d) {
+    const float v = row[d];
+    if (d <= 2 * kSsimR) s0 = fmaf(W.w[d], v, s0);
+    if (d >= 1) s1 = fmaf(W.w[d - 1], v, s1);
+  }
+  o0 = s0;
+  o1 = s1;
+}
+
 __global__ void __launch_bounds__(kBlock) k_obj_moments(ObjArgs a, SsimWeights W) {
-  __shared__ SsimLds<1, 16, 16> L;
+  __shared__ float xs[3][kObjA], ys[3][kObjA];
+  // horizontal sums per channel: x, y, xx, yy, xy over (26 rows x 16 columns)
+  __shared__ float hs[3][5][kObjAH * 16];
   __shared__ float red[4];
-  using SL = SsimLds<1, 16, 16>;
   const int blk = blockIdx.x, k = blockIdx.y;
   const int tx = blk % a.bx, ty = blk / a.bx;
   const int64_t plane = (int64_t)a.width * a.height;
@@ -80,46 +104,83 @@ __global__ void __launch_bounds__(kBlock) k_obj_moments(ObjArgs a, SsimWeights W
   if (!tok && threadIdx.x == 0) atomicOr(&a.hdr->bad, 1u);
   const float *tg = tok ? a.targets + (int64_t)t * plane * 3 : im;  // in bounds; the loss is NaN then
   const int x0 = tx * 16 - kSsimR, y0 = ty * 16 - kSsimR;
+  for (int q = threadIdx.x; q < kObjA; q += kBlock) {
+    const int gx = x0 + q % kObjAW, gy = y0 + q / kObjAW;
+    float v0 = -kShift, v1 = -kShift, v2 = -kShift, w0 = -kShift, w1 = -kShift, w2 = -kShift;
+    if (gx >= 0 && gx < a.width && gy >= 0 && gy < a.height) {
+      const int64_t o = ((int64_t)gy * a.width + gx) * 3;
+      v0 = im[o] - kShift; v1 = im[o + 1] - kShift; v2 = im[o + 2] - kShift;
+      w0 = tg[o] - kShift; w1 = tg[o + 1] - kShift; w2 = tg[o + 2] - kShift;
+    }
+    xs[0][q] = v0; xs[1][q] = v1; xs[2][q] = v2;
+    ys[0][q] = w0; ys[1][q] = w1; ys[2][q] = w2;
+  }
+  __syncthreads();
+  for (int task = threadIdx.x; task < 3 * kObjAH * 8; task += kBlock) {
+    const int c = task / (kObjAH * 8), rem = task % (kObjAH * 8), r = rem / 8, cx = (rem % 8) * 2;
+    const float *xr = &xs[c][r * kObjAW + cx], *yr = &ys[c][r * kObjAW + cx];
+    float m0 = 0, m1 = 0, n0 = 0, n1 = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0, s0 = 0, s1 = 0;
+#pragma unroll
+    for (int d = 0; d <= 2 * kSsimR + 1; ++d) {
+      const float xv = xr[d], yv = yr[d];
+      const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
+      if (d <= 2 * kSsimR) {
+        const float wd = W.w[d];
+        m0 = fmaf(wd, xv, m0); n0 = fmaf(wd, yv, n0); p0 = fmaf(wd, xx, p0); q0 = fmaf(wd, yy, q0);
+        s0 = fmaf(wd, xy, s0);
+      }
+      if (d >= 1) {
+        const float wd = W.w[d - 1];
+        m1 = fmaf(wd, xv, m1); n1 = fmaf(wd, yv, n1); p1 = fmaf(wd, xx, p1); q1 = fmaf(wd, yy, q1);
+        s1 = fmaf(wd, xy, s1);
+      }
+    }
+    const int o = r * 16 + cx;
+    hs[c][0][o] = m0; hs[c][0][o + 1] = m1;
+    hs[c][1][o] = n0; hs[c][1][o + 1] = n1;
+    hs[c][2][o] = p0; hs[c][2][o + 1] = p1;
+    hs[c][3][o] = q0; hs[c][3][o + 1] = q1;
+    hs[c][4][o] = s0; hs[c][4][o + 1] = s1;
+  }
+  __syncthreads();
   const int ox = threadIdx.x % 16, oy = threadIdx.x / 16;
   const int px = tx * 16 + ox, py = ty * 16 + oy;
-  const bool in = px < a.width && py < a.height;
   float se = 0.0f, ss = 0.0f;
-  for (int c = 0; c < 3; ++c) {
-    for (int q = threadIdx.x; q < SL::A; q += kBlock) {
-      const int gx = x0 + q % SL::AW, gy = y0 + q / SL::AW;
-      float v = -kShift, vy = -kShift;
-      if (gx >= 0 && gx < a.width && gy >= 0 && gy < a.height) {
-        const int64_t o = ((int64_t)gy * a.width + gx) * 3 + c;
-        v = im[o] - kShift;
-        vy = tg[o] - kShift;
+  if (px < a.width && py < a.height) {
+    float mp[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
+#pragma unroll
+      for (int d = 0; d <= 2 * kSsimR; ++d) {
+        const int q = (oy + d) * 16 + ox;
+        const float wd = W.w[d];
+        mx = fmaf(wd, hs[c][0][q], mx);
+        my = fmaf(wd, hs[c][1][q], my);
+        exx = fmaf(wd, hs[c][2][q], exx);
+        eyy = fmaf(wd, hs[c][3][q], eyy);
+        exy = fmaf(wd, hs[c][4][q], exy);
       }
-      L.x[0][q] = v;
-      L.y[q] = vy;
-    }
-    __syncthreads();
-    float mu[1], muy, ekk[1], eyy, eky[1];
-    ssim_moments<1, 16, 16>(L, W, mu, muy, ekk, eyy, eky);
-    if (in) {
-      const int q = (oy + kSsimR) * SL::AW + ox + kSsimR;
-      const float dv = L.x[0][q] - L.y[q];
+      const int ai = (oy + kSsimR) * kObjAW + ox + kSsimR;
+      const float dv = xs[c][ai] - ys[c][ai];
       se += dv * dv;
-      const float mx = mu[0], my = muy;
-      const float sxx = ekk[0] - mx * mx, syy = eyy - my * my, sxy = eky[0] - mx * my;
+      const float sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
       const float ux = mx + kShift, uy = my + kShift;
       const float A1 = 2.0f * ux * uy + kSsimC1, A2 = 2.0f * sxy + kSsimC2;
       const float B1 = ux * ux + uy * uy + kSsimC1, B2 = sxx + syy + kSsimC2;
-      const float s = (A1 * A2) / (B1 * B2);
-      ss += s;
+      const float sv = (A1 * A2) / (B1 * B2);
+      ss += sv;
       const float inv = 1.0f / (B1 * B2);
-      const float ds_ux = 2.0f * uy * A2 * inv - s * (2.0f * ux) / B1;
-      const float ds_sxx = -s / B2;
+      const float ds_ux = 2.0f * uy * A2 * inv - sv * (2.0f * ux) / B1;
+      const float ds_sxx = -sv / B2;
       const float ds_sxy = 2.0f * A1 * inv;
-      float *mp = a.maps + ((int64_t)k * 9 + 3 * c) * plane + (int64_t)py * a.width + px;
-      mp[0] = ds_ux - 2.0f * mx * ds_sxx - my * ds_sxy;
-      mp[plane] = ds_sxx;
-      mp[2 * plane] = ds_sxy;
+      mp[3 * c] = ds_ux - 2.0f * mx * ds_sxx - my * ds_sxy;
+      mp[3 * c + 1] = ds_sxx;
+      mp[3 * c + 2] = ds_sxy;
     }
-    __syncthreads();
+    float *dst = a.maps + ((int64_t)k * plane + (int64_t)py * a.width + px) * 9;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) dst[j] = mp[j];
   }
   const float tse = block_sum(se, red);
   const float tss = block_sum(ss, red);
@@ -363,10 +424,13 @@ __global__ void __launch_bounds__(kBlock) k_obj_weights(ObjArgs a) {
 }
 
 // --------------------------------------------------------------- gradient
+// One 16x16 block of one image: the nine coefficient maps of the apron at
+// once (36 contiguous bytes per pixel), the horizontal pass of all nine with
+// two output columns per task, then per channel the vertical pass and the
+// gradient.  Two barriers.
 __global__ void __launch_bounds__(kBlock) k_obj_grad(ObjArgs a, SsimWeights W, const uint32_t *__restrict__ tvals) {
-  constexpr int AW = 16 + 2 * kSsimR, AH = 16 + 2 * kSsimR;
-  __shared__ float m[3][AW * AH];
-  __shared__ float hp[3][AH * 16];
+  __shared__ float m[9][kObjA];
+  __shared__ float hp[9][kObjAH * 16];
   const int blk = blockIdx.x, k = blockIdx.y;
   const int tx = blk % a.bx, ty = blk / a.bx;
   const int64_t plane = (int64_t)a.width * a.height;
@@ -383,71 +447,69 @@ __global__ void __launch_bounds__(kBlock) k_obj_grad(ObjArgs a, SsimWeights W, c
   const float inv3n = (float)(1.0 / n3);
   const float ct = a.n_temporal ? (float)(2.0 * (double)a.w.lambda_t / ((double)a.n_temporal * n3)) : 0.0f;
   const int x0 = tx * 16 - kSsimR, y0 = ty * 16 - kSsimR;
-  for (int c = 0; c < 3; ++c) {
-    float g = 0.0f;
-    if (ssim_part) {  // uniform over the workgroup
-      for (int q = threadIdx.x; q < AW * AH; q += kBlock) {
-        const int gx = x0 + q % AW, gy = y0 + q / AW;
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-        if (gx >= 0 && gx < a.width && gy >= 0 && gy < a.height) {
-          const float *mp = a.maps + ((int64_t)k * 9 + 3 * c) * plane + (int64_t)gy * a.width + gx;
-          v0 = mp[0];
-          v1 = mp[plane];
-          v2 = mp[2 * plane];
-        }
-        m[0][q] = v0;
-        m[1][q] = v1;
-        m[2][q] = v2;
+  float g[3] = {0.0f, 0.0f, 0.0f};
+  if (ssim_part) {  // uniform over the workgroup
+    for (int q = threadIdx.x; q < kObjA; q += kBlock) {
+      const int gx = x0 + q % kObjAW, gy = y0 + q / kObjAW;
+      float v[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) v[j] = 0.0f;
+      if (gx >= 0 && gx < a.width && gy >= 0 && gy < a.height) {
+        const float *src = a.maps + ((int64_t)k * plane + (int64_t)gy * a.width + gx) * 9;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = src[j];
       }
-      __syncthreads();
-      for (int q = threadIdx.x; q < AH * 16; q += kBlock) {
-        const int r = q / 16, cx = q % 16;
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) m[j][q] = v[j];
+    }
+    __syncthreads();
+    for (int task = threadIdx.x; task < 9 * kObjAH * 8; task += kBlock) {
+      const int j = task / (kObjAH * 8), rem = task % (kObjAH * 8), r = rem / 8, cx = (rem % 8) * 2;
+      float h0, h1;
+      hpass2(m[j], W, r, cx, h0, h1);
+      hp[j][r * 16 + cx] = h0;
+      hp[j][r * 16 + cx + 1] = h1;
+    }
+    __syncthreads();
+    if (in && tok) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float wa = 0.0f, wb = 0.0f, wc = 0.0f;
 #pragma unroll
         for (int d = 0; d <= 2 * kSsimR; ++d) {
-          const int i = r * AW + cx + d;
-          s0 = fmaf(W.w[d], m[0][i], s0);
-          s1 = fmaf(W.w[d], m[1][i], s1);
-          s2 = fmaf(W.w[d], m[2][i], s2);
+          const int q = (oy + d) * 16 + ox;
+          wa = fmaf(W.w[d], hp[3 * c][q], wa);
+          wb = fmaf(W.w[d], hp[3 * c + 1][q], wb);
+          wc = fmaf(W.w[d], hp[3 * c + 2][q], wc);
         }
-        hp[0][q] = s0;
-        hp[1][q] = s1;
-        hp[2][q] = s2;
-      }
-      __syncthreads();
-      float wa = 0.0f, wb = 0.0f, wc = 0.0f;
-#pragma unroll
-      for (int d = 0; d <= 2 * kSsimR; ++d) {
-        const int q = (oy + d) * 16 + ox;
-        wa = fmaf(W.w[d], hp[0][q], wa);
-        wb = fmaf(W.w[d], hp[1][q], wb);
-        wc = fmaf(W.w[d], hp[2][q], wc);
-      }
-      if (in && tok) {
         const float x = a.images[((int64_t)k * plane + o) * 3 + c];
         const float y = a.targets[((int64_t)t * plane + o) * 3 + c];
         const float xs = x - kShift, ys = y - kShift;
         const float dssim = (wa + 2.0f * xs * wb + ys * wc) * inv3n;
-        g = ck * (2.0f * (x - y) * inv3n - a.w.lambda_ssim * dssim);
-      } else if (in) {
-        g = ck;  // invalid target: NaN like the loss
+        g[c] = ck * (2.0f * (x - y) * inv3n - a.w.lambda_ssim * dssim);
       }
-      __syncthreads();  // LDS reused by the next channel
-    }
-    if (in) {
-      for (int e = e0; e < e1; ++e) {
-        const uint32_t v = tvals[e];
-        const int j = (int)(v >> 1);
-        const int ia = a.temporal[2 * j], ib = a.temporal[2 * j + 1];
-        const int ta = a.target_of[ia], tb = a.target_of[ib];
-        const float xa = a.images[((int64_t)ia * plane + o) * 3 + c], xb = a.images[((int64_t)ib * plane + o) * 3 + c];
-        const float ga = a.targets[((int64_t)ta * plane + o) * 3 + c], gb = a.targets[((int64_t)tb * plane + o) * 3 + c];
-        const float ev = (xb - xa) - (gb - ga);
-        g += (v & 1u) ? ct * ev : -ct * ev;
-      }
-      a.grad[((int64_t)k * plane + o) * 3 + c] = g;
+    } else if (in) {
+      g[0] = g[1] = g[2] = ck;  // invalid target: NaN like the loss
     }
   }
+  if (!in) return;
+  for (int e = e0; e < e1; ++e) {
+    const uint32_t v = tvals[e];
+    const int j = (int)(v >> 1);
+    const int ia = a.temporal[2 * j], ib = a.temporal[2 * j + 1];
+    const int ta = a.target_of[ia], tb = a.target_of[ib];
+    const float *xa = a.images + ((int64_t)ia * plane + o) * 3, *xb = a.images + ((int64_t)ib * plane + o) * 3;
+    const float *ga = a.targets + ((int64_t)ta * plane + o) * 3, *gb = a.targets + ((int64_t)tb * plane + o) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float ev = (xb[c] - xa[c]) - (gb[c] - ga[c]);
+      g[c] += (v & 1u) ? ct * ev : -ct * ev;
+    }
+  }
+  float *dst = a.grad + ((int64_t)k * plane + o) * 3;
+  dst[0] = g[0];
+  dst[1] = g[1];
+  dst[2] = g[2];
 }
 
 __global__ void k_obj_clear(ObjHeader *h) {
