@@ -330,6 +330,8 @@ int utility_prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_sta
   u->group_base = at<uint32_t>(uws, U.group_base);
   u->icount = at<uint32_t>(uws, U.icount);
   u->item_base = at<uint32_t>(uws, U.item_base);
+  u->bcount = at<uint32_t>(uws, U.bcount);
+  u->bbase = at<uint32_t>(uws, U.bbase);
   u->bad = at<uint32_t>(uws, U.bad);
   u->pvis = at<uint32_t>(uws, U.pvis);
   u->parts = at<unsigned long long>(uws, U.parts);
@@ -735,6 +737,9 @@ int dgs_utility(const dgs_scene *scene, const dgs_camera *cam, const dgs_states 
   a.pair.context_group = context_group;
   a.pair.group_base = u.group_base;
   a.pair.region_tiles = u.region_tiles;
+  a.pair.bundle_total = &u.hdr->bundle_items;
+  a.pair.bundle_base = u.bbase;
+  a.pair.bad = u.bad;
   const int cus = device_cus();
   if (launch_composite_pairs(a, cl.tiling.tw, cl.tiling.th, cus * 8, st))
     return fail(DGS_ERR_UNSUPPORTED, "no pair compositing variant for this tile shape");

@@ -99,13 +99,18 @@ struct Stage {
 // 28 bits and, in bits 28..31, whether the entry can reach alpha >= 1/255 in
 // each of the tile's four 8x8 wave blocks (decided once at emission).  Per wave
 // the stage holds the entry's delivery bits, or 0 for a block it cannot reach.
+// In pair mode `nvis` contexts' two-bit tables, `vstride` words apart, are
+// merged: bits 2c and 2c + 1 belong to the bundle's context c.
 template <int TW, int TH>
 __device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, const float4 *rec0,
-                                            const float4 *rec1, const float4 *rec2, const uint32_t *vis) {
+                                            const float4 *rec1, const float4 *rec2, const uint32_t *vis,
+                                            int nvis = 1, int64_t vstride = 0) {
   const uint32_t id = val & kIdMask;
   const float4 r0 = rec0[id];
   const float4 r1 = rec1[id];
-  const uint32_t vb = vis ? vis[__float_as_uint(r0.w)] : 1u;
+  const uint32_t pl = __float_as_uint(r0.w);
+  uint32_t vb = vis ? vis[pl] : 1u;
+  for (int c = 1; c < nvis; ++c) vb |= vis[c * vstride + pl] << (2 * c);
 #pragma unroll
   for (int w = 0; w < 4; ++w) st.vis[w][slot] = ((val >> (kMaskShift + w)) & 1u) ? vb : 0u;
   st.rec[slot].p0 = make_float4(r0.x, r0.y, r0.z, r1.x);
@@ -119,12 +124,20 @@ __device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, c
 template <int S>
 constexpr int waves_per_eu() { return S <= 8 ? 8 : (S <= 16 ? 5 : 2); }
 
+// Pair mode: a bundle of contexts (their delivery tables `vstride` words
+// apart from `vis`) and the work item of each context's patch.
+struct PairOut {
+  int pairs;
+  int64_t vstride;
+  uint32_t item[4];
+};
+
 // Composites one tile for the S states of one group.  `vis` holds the
 // group's delivery bits per (packet, layer); `grp` indexes the outputs (the
-// state group, or in pair mode the work item).
+// state group); in pair mode `po` names the bundle's patches instead.
 template <int S, int TW, int TH, int MODE>
 __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st, int tile, int grp,
-                                               const uint32_t *vis) {
+                                               const uint32_t *vis, const PairOut *po = nullptr) {
   static_assert(TW * TH == kBlock, "one pixel per thread");
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -134,9 +147,10 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
 
   float T[S], cr[S], cg[S], cb[S];
+  const int nact = MODE == 3 ? 2 * po->pairs : S;  // states of the bundle's contexts
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    T[s] = inside ? 1.0f : -1.0f;
+    T[s] = (inside && s < nact) ? 1.0f : -1.0f;
     cr[s] = cg[s] = cb[s] = 0.0f;
   }
 
@@ -148,7 +162,12 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
     for (int s = 0; s < S; ++s) alive |= T[s] > 0.0f;
     if (!__syncthreads_or(alive)) break;
     const uint32_t e = b0 + tid;
-    if (e < rg.y) stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
+    if (e < rg.y) {
+      if (MODE == 3)
+        stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis, po->pairs, po->vstride);
+      else
+        stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
+    }
     __syncthreads();
     // entries of this batch; wave-uniform, kept in scalar registers
     const int cnt = __builtin_amdgcn_readfirstlane(
@@ -219,15 +238,18 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
   }
 
   if (MODE == 3) {
-    // pair mode: the tile's pixels of both states into the work item's patch
+    // pair mode: the tile's pixels of both states of each context into that
+    // context's work-item patch [item][2][TW * TH][3]
     if (!inside) return;
-    float *o = a.image + ((int64_t)grp * S * kBlock + (int64_t)(py - tpy) * TW + (px - tpx)) * 3;
+    const int64_t pix = (int64_t)(py - tpy) * TW + (px - tpx);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+      if (s >= nact) break;
       const float Tf = fabsf(T[s]);
-      o[(int64_t)s * kBlock * 3 + 0] = fmaf(Tf, a.bg[0], cr[s]);
-      o[(int64_t)s * kBlock * 3 + 1] = fmaf(Tf, a.bg[1], cg[s]);
-      o[(int64_t)s * kBlock * 3 + 2] = fmaf(Tf, a.bg[2], cb[s]);
+      float *o = a.image + (((int64_t)po->item[s >> 1] * 2 + (s & 1)) * kBlock + pix) * 3;
+      o[0] = fmaf(Tf, a.bg[0], cr[s]);
+      o[1] = fmaf(Tf, a.bg[1], cg[s]);
+      o[2] = fmaf(Tf, a.bg[2], cb[s]);
     }
     return;
   }
@@ -327,34 +349,47 @@ k_composite(CompositeArgs a) {
   }
 }
 
-// Paired states of the counterfactual utility: each work item is (context j,
-// slot of a tile in the region of j's completion group); both states (the
-// context m and m u g) are composited together as one S = 2 group and written
-// to the item's patch.  Resident workgroups take items from one queue.
+// Paired states of the counterfactual utility.  Each context j has one work
+// item per tile of its group's region; the states of a pair (the context m
+// and m u g) differ only in g.  Up to four consecutive contexts of one group
+// (a bundle) are composited together at one tile as one 8-state group, so
+// each splat's alpha serves all eight states; every context's two states go
+// to its own item's patch.  Resident workgroups take (bundle, region tile)
+// items from one queue.
 template <int TW, int TH>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_composite_pairs(CompositeArgs a) {
   __shared__ Stage st;
   __shared__ int s_item;
   // after an overflow nothing is composited (every delta becomes NaN)
-  const unsigned long long total = *a.pair.item_total;
-  const uint32_t n_items = total <= a.pair.item_capacity ? (uint32_t)total : 0u;
+  const bool over = *a.pair.item_total > a.pair.item_capacity;
+  const unsigned long long total = *a.pair.bundle_total;
+  const uint32_t n_items = over ? 0u : (uint32_t)total;
+  const int J = a.pair.num_contexts;
   for (;;) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(a.queues, 1u);
     __syncthreads();
     const uint32_t item = (uint32_t)s_item;
     __syncthreads();
     if (item >= n_items) break;
-    // context of the item: the last j with item_base[j] <= item
-    int lo = 0, hi = a.pair.num_contexts - 1;
+    // bundle of the item: the last context b with bundle_base[b] <= item
+    int lo = 0, hi = J - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (a.pair.item_base[mid] <= item) lo = mid; else hi = mid - 1;
+      if (a.pair.bundle_base[mid] <= item) lo = mid; else hi = mid - 1;
     }
-    const int j = lo;
-    const int g = a.pair.context_group[j];
-    const int tile = (int)a.pair.region_tiles[a.pair.group_base[g] + (item - a.pair.item_base[j])];
-    composite_item<2, TW, TH, 3>(a, st, tile, (int)item, a.visbits + (int64_t)j * a.P4);
+    const int b = lo;
+    const int g = a.pair.context_group[b];
+    const uint32_t slot = item - a.pair.bundle_base[b];
+    PairOut po;
+    po.pairs = 1;
+    while (po.pairs < 4 && b + po.pairs < J && !bundle_start(a.pair.context_group, a.pair.bad, b + po.pairs))
+      ++po.pairs;
+    po.vstride = a.P4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) po.item[c] = c < po.pairs ? a.pair.item_base[b + c] + slot : 0u;
+    const int tile = (int)a.pair.region_tiles[a.pair.group_base[g] + slot];
+    composite_item<8, TW, TH, 3>(a, st, tile, 0, a.visbits + (int64_t)b * a.P4, &po);
     __syncthreads();
   }
 }

@@ -88,6 +88,9 @@ struct CompositeArgs {
     const int32_t *context_group;  // [J]
     const uint32_t *group_base;    // [G + 1] first region tile of each group
     const uint32_t *region_tiles;  // tiles of each group's region, by group
+    const unsigned long long *bundle_total;  // compositing work items over all bundles (device)
+    const uint32_t *bundle_base;   // [J] first compositing item of the bundle context j starts
+    const uint32_t *bad;           // [J] context without work items
   } pair;
 };
 // mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only.
@@ -98,6 +101,8 @@ void launch_zero_queues(unsigned int *queues, hipStream_t st);
 // Pair mode: composites every (context, region tile) work item for the
 // context and the context plus its group into a.image patches
 // [item][2][tile_w * tile_h][3]; a.visbits holds [J][P*4] two-bit words.
+// Up to four consecutive contexts of one group ("a bundle") are composited
+// together at one tile as one 8-state group.
 int launch_composite_pairs(const CompositeArgs &a, int tile_w, int tile_h, int workgroups, hipStream_t st);
 // How launch_composite runs image mode for `groups` state groups (host only).
 struct CompositePlan {
@@ -126,19 +131,19 @@ int launch_composite_bwd(const CompositeBwdArgs &a, int S, int tile_w, int tile_
 
 // utility.hip: counterfactual render utility, distortion, risk adjustment
 struct UtilHeader {
-  unsigned long long regions;  // region tiles over all groups
-  unsigned long long items;    // work items over all contexts
+  unsigned long long regions;       // region tiles over all groups
+  unsigned long long items;         // work items over all contexts
+  unsigned long long bundle_items;  // compositing work items over all bundles
   unsigned int bad_group;      // 1: a group's packet is out of range; 2: two groups name one (packet, layer)
   unsigned int bad_context;    // 1: a context lacks its group's packet at exactly the group's layer
   unsigned int queue[8];
-  unsigned int pad[2];
 };
 
 constexpr int kMaxRiskValues = 4096;  // contexts per group in dgs_risk_adjusted
 
 struct UtilLayout {
   size_t hdr, pl2g, core, region, wcount, wprefix, region_tiles, group_base, icount, item_base, bad, pvis, parts,
-      partial, patches, total;
+      partial, patches, bcount, bbase, total;
   int64_t words;
 };
 
@@ -164,6 +169,8 @@ inline UtilLayout make_util_layout(int64_t P, int64_t tiles, int64_t G, int64_t 
   L.parts = take(8 * (ceil_div(scan_n, kScanTile) + 1));
   L.partial = take(4 * cap);
   L.patches = take((size_t)4 * cap * 2 * kBlock * 3);
+  L.bcount = take(4 * J);
+  L.bbase = take(4 * J);
   L.total = o;
   return L;
 }
@@ -172,6 +179,7 @@ struct UtilArgs {
   UtilHeader *hdr;
   int *pl2g;
   uint32_t *core, *region, *wcount, *wprefix, *region_tiles, *group_base, *icount, *item_base, *bad, *pvis;
+  uint32_t *bcount, *bbase;  // work items of the bundle a context starts (0 if none), and their prefix
   unsigned long long *parts;
   float *partial, *patches, *delta;
   const unsigned long long *item_total;  // &hdr->items
@@ -182,6 +190,13 @@ struct UtilArgs {
   const float *reference;
   float lambda;
 };
+
+// A context starts a compositing bundle unless it continues the previous
+// context's: same group, both with work items, and not at a multiple of four
+// (so a bundle holds one to four contexts of one group).
+__device__ inline bool bundle_start(const int32_t *context_group, const uint32_t *bad, int j) {
+  return j == 0 || (j & 3) == 0 || context_group[j] != context_group[j - 1] || bad[j] != 0u || bad[j - 1] != 0u;
+}
 
 void launch_clear_util_header(UtilHeader *h, hipStream_t st);
 // Group tables, core tiles, regions (core dilated by rx, ry tiles) and the

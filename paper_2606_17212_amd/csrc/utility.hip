@@ -150,6 +150,16 @@ k_pair_setup(const uint8_t *__restrict__ codes, const int32_t *__restrict__ cont
   }
 }
 
+// Compositing items of each bundle: its group's region tiles, counted at the
+// context that starts it.
+__global__ void __launch_bounds__(kBlock)
+k_bundle_setup(const int32_t *__restrict__ context_group, const uint32_t *__restrict__ bad,
+               const uint32_t *__restrict__ icount, int J, uint32_t *__restrict__ bcount) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= J) return;
+  bcount[j] = (bad[j] == 0u && bundle_start(context_group, bad, j)) ? icount[j] : 0u;
+}
+
 // Pair items: per-pixel  sum_c (x1 - y)^2 - (x2 - y)^2 - lambda (ssim1 - ssim2)
 // over the item's tile, for items whose 3x3 tile neighbourhood meets the core.
 template <int TW, int TH>
@@ -418,6 +428,9 @@ void launch_pair_setup(const UtilArgs &u, const uint8_t *codes, const uint16_t *
   k_pair_setup<<<u.num_contexts, kBlock, 0, st>>>(codes, u.context_group, group_pl, u.group_base, u.num_contexts,
                                                   G, P, u.icount, u.pvis, u.bad, u.hdr);
   launch_scan_u32(u.icount, u.item_base, u.num_contexts, u.parts, &u.hdr->items, st);
+  k_bundle_setup<<<(unsigned)ceil_div(u.num_contexts, kBlock), kBlock, 0, st>>>(u.context_group, u.bad, u.icount,
+                                                                              u.num_contexts, u.bcount);
+  launch_scan_u32(u.bcount, u.bbase, u.num_contexts, u.parts, &u.hdr->bundle_items, st);
 }
 
 int launch_pair_ssim(const UtilArgs &u, int tile_w, int tile_h, int workgroups, hipStream_t st) {

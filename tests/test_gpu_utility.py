@@ -158,3 +158,36 @@ def test_utility_edge_cases_and_errors():
     z = r2.utility(sf, c, _dev(np.zeros((2, 1), np.uint8)), _dev(np.zeros(2, np.int32)),
                    _dev(np.zeros(1, np.int16)), basis, _dev(ref), BG)
     assert r2.utility_check() == 0 and torch.equal(z, torch.zeros_like(z))
+
+
+def test_utility_bundles_do_not_change_deltas():
+    """Contexts of one group are composited four at a time; the deltas are
+    the same bit for bit whatever the context order (runs of one group, mixed
+    groups, a bad context in the middle)."""
+    dgs = _dgs()
+    scene, cam, basis, groups, ctx, cg, ref = _utility_case(n=2000, J_per=8)
+    dev = torch.device("cuda:0")
+    s = dgs.GaussianScene.from_arrays(scene, dev)
+    c = dgs.Camera.from_arrays(cam)
+    gpl = np.array([(p << 2) | l for p, l in groups], np.uint16).view(np.int16)
+    r = dgs.Renderer(dev)
+    r.plan(s, c, basis, 1)
+    r.bin(s, c, basis)
+    base = r.utility(s, c, _dev(ctx), _dev(cg), _dev(gpl), basis, _dev(ref), BG).cpu().numpy()
+    n_items = r.utility_check()
+    assert n_items > 0 and np.isfinite(base).all()
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        perm = rng.permutation(len(ctx))
+        d = r.utility(s, c, _dev(ctx[perm]), _dev(cg[perm]), _dev(gpl), basis, _dev(ref), BG).cpu().numpy()
+        r.utility_check()
+        assert np.array_equal(d, base[perm])
+    # a context without its group's packet at the group's layer inside a run
+    bad = ctx.copy()
+    p0, l0 = groups[cg[5]]
+    bad[5, p0] = l0 + 1
+    d = r.utility(s, c, _dev(bad), _dev(cg), _dev(gpl), basis, _dev(ref), BG, item_capacity=n_items)
+    with pytest.raises(dgs.DgsError):
+        r.utility_check()
+    d = d.cpu().numpy()
+    assert np.isnan(d[5]) and np.array_equal(np.delete(d, 5), np.delete(base, 5))
