@@ -231,17 +231,6 @@ __global__ void __launch_bounds__(kBlock) k_obj_temporal(ObjArgs a) {
   if (threadIdx.x == 0) a.tpart[(int64_t)j * a.bx * a.by + blk] = (double)tot;
 }
 
-// Sum over the workgroup in a fixed order (FP64).
-__device__ double block_sum_f64(double v, double *red) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const double r = (red[0] + red[1]) + (red[2] + red[3]);
-  __syncthreads();
-  return r;
-}
-
 // D per image (workgroups 0..K-1) and the squared temporal-change error per
 // pair (workgroups K..K+Q-1), each summed over the 16x16 blocks in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_obj_dfinal(ObjArgs a) {

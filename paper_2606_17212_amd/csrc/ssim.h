@@ -108,6 +108,17 @@ __device__ __forceinline__ float block_sum(float v, float *red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// Sum over the workgroup in a fixed order (FP64).
+__device__ inline double block_sum_f64(double v, double *red) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
 // Normalised window taps (host).
 inline SsimWeights ssim_weights() {
   SsimWeights W;

@@ -43,22 +43,46 @@ __global__ void k_group_table(const uint16_t *__restrict__ group_pl, int G, int 
   if (atomicCAS(&pl2g[pl], -1, k) != -1) atomicOr(&h->bad_group, 2u);  // two groups name one (packet, layer)
 }
 
-// Core tiles of every group: the tile rectangles of its Gaussians.
+// Core tiles of every group: the tile rectangles of its Gaussians.  Each row
+// of a rectangle is a run of consecutive tile bits, set with one OR per
+// bitmap word it touches.  LDS: the group bitmaps of all groups, privatised
+// per workgroup and merged into the global ones once (when they fit).
+constexpr int kCoreLdsWords = 8192;
+
+__device__ __forceinline__ void mark_rect_rows(uint32_t *row, int tiles_x, int x0, int y0, int x1, int y1) {
+  for (int y = y0; y < y1; ++y) {
+    const int t0 = y * tiles_x + x0, t1 = y * tiles_x + x1 - 1;  // inclusive bit range
+    for (int w = t0 >> 5; w <= (t1 >> 5); ++w) {
+      const int lo = w == (t0 >> 5) ? (t0 & 31) : 0, hi = w == (t1 >> 5) ? (t1 & 31) : 31;
+      const uint32_t m = (hi == 31 ? 0xFFFFFFFFu : ((1u << (hi + 1)) - 1u)) & ~((1u << lo) - 1u);
+      atomicOr(row + w, m);
+    }
+  }
+}
+
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
 k_group_core(const float4 *__restrict__ rec0, const uint2 *__restrict__ rect, int n, const int *__restrict__ pl2g,
-             int tiles_x, int words, uint32_t *__restrict__ core) {
+             int tiles_x, int words, int gw, uint32_t *__restrict__ core) {
+  __shared__ uint32_t bm[LDS ? kCoreLdsWords : 1];
+  if (LDS) {
+    for (int i = threadIdx.x; i < gw; i += kBlock) bm[i] = 0u;
+    __syncthreads();
+  }
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     const uint2 r = rect[i];
     const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
     if (x1 <= x0 || y1 <= y0) continue;
     const int g = pl2g[__float_as_uint(rec0[i].w) & 0xFFFFu];
     if (g < 0) continue;
-    uint32_t *row = core + (int64_t)g * words;
-    for (int y = y0; y < y1; ++y)
-      for (int x = x0; x < x1; ++x) {
-        const int t = y * tiles_x + x;
-        atomicOr(row + (t >> 5), 1u << (t & 31));
-      }
+    mark_rect_rows((LDS ? bm : core) + (int64_t)g * words, tiles_x, x0, y0, x1, y1);
+  }
+  if (LDS) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < gw; i += kBlock) {
+      const uint32_t v = bm[i];
+      if (v) atomicOr(core + i, v);
+    }
   }
 }
 
@@ -162,13 +186,20 @@ k_bundle_setup(const int32_t *__restrict__ context_group, const uint32_t *__rest
 
 // Pair items: per-pixel  sum_c (x1 - y)^2 - (x2 - y)^2 - lambda (ssim1 - ssim2)
 // over the item's tile, for items whose 3x3 tile neighbourhood meets the core.
+// One pass reads the apron of both states (from the neighbouring items'
+// patches) and of the reference for all three channels; the horizontal
+// 11-tap pass of the eight window sums runs per channel with two output
+// columns per task.
 template <int TW, int TH>
 __global__ void __launch_bounds__(kBlock)
 k_pair_ssim(UtilArgs u, SsimWeights W) {
-  __shared__ SsimLds<2, TW, TH> L;
+  constexpr int AW = TW + 2 * kSsimR, AH = TH + 2 * kSsimR, A = AW * AH;
+  __shared__ float xs[2][3][A];  // both states, shifted
+  __shared__ float ys[3][A];     // reference, shifted
+  // horizontal sums of one channel: x1, x2, y, x1^2, x2^2, y^2, x1 y, x2 y
+  __shared__ float hs[8][AH * TW];
   __shared__ float red[4];
   __shared__ int s_item;
-  using SL = SsimLds<2, TW, TH>;
   const unsigned long long total = *u.item_total;
   const uint32_t n_items = total <= u.item_capacity ? (uint32_t)total : 0u;  // nothing after an overflow
   for (;;) {
@@ -204,12 +235,15 @@ k_pair_ssim(UtilArgs u, SsimWeights W) {
     near = __builtin_amdgcn_readfirstlane(near);
     const int x0 = tx * TW - kSsimR, y0 = ty * TH - kSsimR;
     float acc = 0.0f;
-    for (int c = 0; c < (near ? 3 : 0); ++c) {
-      for (int a = threadIdx.x; a < SL::A; a += kBlock) {
-        const int gx = x0 + a % SL::AW, gy = y0 + a / SL::AW;
-        float v1 = -kShift, v2 = -kShift, vy = -kShift;  // zero outside the image
+    if (near) {
+      for (int q = threadIdx.x; q < A; q += kBlock) {
+        const int gx = x0 + q % AW, gy = y0 + q / AW;
+        float v1[3] = {-kShift, -kShift, -kShift}, v2[3] = {-kShift, -kShift, -kShift};  // zero outside
+        float vy[3] = {-kShift, -kShift, -kShift};
         if (gx >= 0 && gx < u.width && gy >= 0 && gy < u.height) {
-          vy = u.reference[((int64_t)gy * u.width + gx) * 3 + c] - kShift;
+          const float *rp = u.reference + ((int64_t)gy * u.width + gx) * 3;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) vy[c] = rp[c] - kShift;
           const int nt = (gy / TH) * u.tiles_x + gx / TW;
           if (bit_at(rrow, nt)) {  // outside the region: the same value in both states
             // slot of tile nt within group g's region (the word prefix counts every group)
@@ -217,28 +251,69 @@ k_pair_ssim(UtilArgs u, SsimWeights W) {
             const uint32_t slot = rpre[w] - u.group_base[g] + (uint32_t)__popc(rrow[w] & ((1u << b) - 1u));
             const int64_t it = (int64_t)u.item_base[j] + slot;
             const int lp = (gy - (gy / TH) * TH) * TW + (gx - (gx / TW) * TW);
-            const float *pp = u.patches + (it * 2 * kBlock + lp) * 3 + c;
-            v1 = pp[0] - kShift;
-            v2 = pp[kBlock * 3] - kShift;
+            const float *pp = u.patches + (it * 2 * kBlock + lp) * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              v1[c] = pp[c] - kShift;
+              v2[c] = pp[kBlock * 3 + c] - kShift;
+            }
           }
         }
-        L.x[0][a] = v1;
-        L.x[1][a] = v2;
-        L.y[a] = vy;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xs[0][c][q] = v1[c];
+          xs[1][c][q] = v2[c];
+          ys[c][q] = vy[c];
+        }
       }
       __syncthreads();
-      float mu[2], muy, ekk[2], eyy, eky[2];
-      ssim_moments<2, TW, TH>(L, W, mu, muy, ekk, eyy, eky);
       const int ox = threadIdx.x % TW, oy = threadIdx.x / TW;
-      const int px = tx * TW + ox, py = ty * TH + oy;
-      if (px < u.width && py < u.height) {
-        const int a = (oy + kSsimR) * SL::AW + ox + kSsimR;
-        const float d1 = L.x[0][a] - L.y[a], d2 = L.x[1][a] - L.y[a];
-        const float s1 = ssim_value(mu[0], muy, ekk[0], eyy, eky[0]);
-        const float s2 = ssim_value(mu[1], muy, ekk[1], eyy, eky[1]);
-        acc += (d1 * d1 - d2 * d2) - u.lambda * (s1 - s2);
+      const bool in = tx * TW + ox < u.width && ty * TH + oy < u.height;
+      for (int c = 0; c < 3; ++c) {
+        for (int task = threadIdx.x; task < AH * (TW / 2); task += kBlock) {
+          const int r = task / (TW / 2), cx = (task % (TW / 2)) * 2;
+          const float *ar = &xs[0][c][r * AW + cx], *br = &xs[1][c][r * AW + cx], *yr = &ys[c][r * AW + cx];
+          float t0[8], t1[8];
+#pragma unroll
+          for (int m = 0; m < 8; ++m) t0[m] = t1[m] = 0.0f;
+#pragma unroll
+          for (int d = 0; d <= 2 * kSsimR + 1; ++d) {
+            const float a = ar[d], bb = br[d], y = yr[d];
+            const float v[8] = {a, bb, y, a * a, bb * bb, y * y, a * y, bb * y};
+            if (d <= 2 * kSsimR) {
+#pragma unroll
+              for (int m = 0; m < 8; ++m) t0[m] = fmaf(W.w[d], v[m], t0[m]);
+            }
+            if (d >= 1) {
+#pragma unroll
+              for (int m = 0; m < 8; ++m) t1[m] = fmaf(W.w[d - 1], v[m], t1[m]);
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            hs[m][r * TW + cx] = t0[m];
+            hs[m][r * TW + cx + 1] = t1[m];
+          }
+        }
+        __syncthreads();
+        if (in) {
+          float mo[8];
+#pragma unroll
+          for (int m = 0; m < 8; ++m) mo[m] = 0.0f;
+#pragma unroll
+          for (int d = 0; d <= 2 * kSsimR; ++d) {
+            const int q = (oy + d) * TW + ox;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) mo[m] = fmaf(W.w[d], hs[m][q], mo[m]);
+          }
+          const int q = (oy + kSsimR) * AW + ox + kSsimR;
+          const float d1 = xs[0][c][q] - ys[c][q], d2 = xs[1][c][q] - ys[c][q];
+          const float s1 = ssim_value(mo[0], mo[2], mo[3], mo[5], mo[6]);
+          const float s2 = ssim_value(mo[1], mo[2], mo[4], mo[5], mo[7]);
+          acc += (d1 * d1 - d2 * d2) - u.lambda * (s1 - s2);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     const float tot = block_sum(acc, red);
     if (threadIdx.x == 0) u.partial[item] = tot;
@@ -248,18 +323,22 @@ k_pair_ssim(UtilArgs u, SsimWeights W) {
 
 // Delta per context: its items' partial sums (in FP64, in item order) / 3HW;
 // NaN for an invalid context or after an item overflow.
-__global__ void k_context_delta(UtilArgs u, const uint32_t *__restrict__ bad, float *__restrict__ delta) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= u.num_contexts) return;
+// Delta per context: its items' sums in a fixed order (one workgroup per
+// context, FP64).
+__global__ void __launch_bounds__(kBlock)
+k_context_delta(UtilArgs u, const uint32_t *__restrict__ bad, float *__restrict__ delta) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
   const unsigned long long total = *u.item_total;
-  if (bad[j] || total > u.item_capacity) {
-    delta[j] = __int_as_float(0x7FC00000);
+  if (bad[j] || total > u.item_capacity) {  // uniform over the workgroup
+    if (threadIdx.x == 0) delta[j] = __int_as_float(0x7FC00000);
     return;
   }
   const uint32_t b = u.item_base[j], e = j + 1 < u.num_contexts ? u.item_base[j + 1] : (uint32_t)total;
   double s = 0.0;
-  for (uint32_t i = b; i < e; ++i) s += (double)u.partial[i];
-  delta[j] = (float)(s / (3.0 * (double)u.width * (double)u.height));
+  for (uint32_t i = b + threadIdx.x; i < e; i += kBlock) s += (double)u.partial[i];
+  s = block_sum_f64(s, red);
+  if (threadIdx.x == 0) delta[j] = (float)(s / (3.0 * (double)u.width * (double)u.height));
 }
 
 // Full images: per (image, 16x16 block) sums of squared error and SSIM.
@@ -411,8 +490,13 @@ void launch_group_setup(const UtilArgs &u, const uint16_t *group_pl, int G, int 
   k_fill_i32<<<(unsigned)std::min<int64_t>(ceil_div(gw, kBlock), 4096), kBlock, 0, st>>>(reinterpret_cast<int *>(u.core), gw, 0);
   k_group_table<<<(unsigned)ceil_div(G, kBlock), kBlock, 0, st>>>(group_pl, G, P, u.pl2g, u.hdr);
   if (n > 0) {
-    const int blocks = (int)std::min<int64_t>(ceil_div(n, kBlock), 4096);
-    k_group_core<<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, u.core);
+    if (gw <= kCoreLdsWords) {
+      const int blocks = (int)std::min<int64_t>(ceil_div(n, kBlock), 128);
+      k_group_core<true><<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, (int)gw, u.core);
+    } else {
+      const int blocks = (int)std::min<int64_t>(ceil_div(n, kBlock), 4096);
+      k_group_core<false><<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, (int)gw, u.core);
+    }
   }
   k_group_region<<<(unsigned)ceil_div(gw, kBlock), kBlock, 0, st>>>(u.core, G, u.tiles_x, u.tiles_y, u.words,
                                                                     rx, ry, u.region, u.wcount);
@@ -442,7 +526,7 @@ int launch_pair_ssim(const UtilArgs &u, int tile_w, int tile_h, int workgroups, 
     k_pair_ssim<32, 8><<<workgroups, kBlock, 0, st>>>(u, W);
   else
     return 1;
-  k_context_delta<<<(unsigned)ceil_div(u.num_contexts, kBlock), kBlock, 0, st>>>(u, u.bad, u.delta);
+  k_context_delta<<<(unsigned)u.num_contexts, kBlock, 0, st>>>(u, u.bad, u.delta);
   return 0;
 }
 
