@@ -341,39 +341,80 @@ k_context_delta(UtilArgs u, const uint32_t *__restrict__ bad, float *__restrict_
   if (threadIdx.x == 0) delta[j] = (float)(s / (3.0 * (double)u.width * (double)u.height));
 }
 
-// Full images: per (image, 16x16 block) sums of squared error and SSIM.
+// Full images: per (image, 16x16 block) sums of squared error and SSIM.  One
+// pass reads the apron of all three channels; the horizontal 11-tap pass of
+// the five window sums runs per channel with two output columns per task.
 __global__ void __launch_bounds__(kBlock)
 k_distortion_tiles(const float *__restrict__ images, const float *__restrict__ reference, int width, int height,
                    int bx, int by, SsimWeights W, double *__restrict__ part) {
-  __shared__ SsimLds<1, 16, 16> L;
+  constexpr int AW = 16 + 2 * kSsimR, AH = 16 + 2 * kSsimR, A = AW * AH;
+  __shared__ float xs[3][A], ys[3][A];
+  __shared__ float hs[5][AH * 16];
   __shared__ float red[4];
-  using SL = SsimLds<1, 16, 16>;
   const int blk = blockIdx.x, img = blockIdx.y;
   const int tx = blk % bx, ty = blk / bx;
   const float *im = images + (int64_t)img * width * height * 3;
   const int x0 = tx * 16 - kSsimR, y0 = ty * 16 - kSsimR;
+  for (int q = threadIdx.x; q < A; q += kBlock) {
+    const int gx = x0 + q % AW, gy = y0 + q / AW;
+    float v[3] = {-kShift, -kShift, -kShift}, w[3] = {-kShift, -kShift, -kShift};
+    if (gx >= 0 && gx < width && gy >= 0 && gy < height) {
+      const int64_t o = ((int64_t)gy * width + gx) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v[c] = im[o + c] - kShift;
+        w[c] = reference[o + c] - kShift;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xs[c][q] = v[c];
+      ys[c][q] = w[c];
+    }
+  }
+  __syncthreads();
+  const int ox = threadIdx.x % 16, oy = threadIdx.x / 16;
+  const bool in = tx * 16 + ox < width && ty * 16 + oy < height;
   float se = 0.0f, ss = 0.0f;
   for (int c = 0; c < 3; ++c) {
-    for (int a = threadIdx.x; a < SL::A; a += kBlock) {
-      const int gx = x0 + a % SL::AW, gy = y0 + a / SL::AW;
-      float v = -kShift, vy = -kShift;
-      if (gx >= 0 && gx < width && gy >= 0 && gy < height) {
-        const int64_t o = ((int64_t)gy * width + gx) * 3 + c;
-        v = im[o] - kShift;
-        vy = reference[o] - kShift;
+    for (int task = threadIdx.x; task < AH * 8; task += kBlock) {
+      const int r = task / 8, cx = (task % 8) * 2;
+      const float *xr = &xs[c][r * AW + cx], *yr = &ys[c][r * AW + cx];
+      float t0[5], t1[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) t0[m] = t1[m] = 0.0f;
+#pragma unroll
+      for (int d = 0; d <= 2 * kSsimR + 1; ++d) {
+        const float x = xr[d], y = yr[d];
+        const float vals[5] = {x, y, x * x, y * y, x * y};
+        if (d <= 2 * kSsimR) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) t0[m] = fmaf(W.w[d], vals[m], t0[m]);
+        }
+        if (d >= 1) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) t1[m] = fmaf(W.w[d - 1], vals[m], t1[m]);
+        }
       }
-      L.x[0][a] = v;
-      L.y[a] = vy;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        hs[m][r * 16 + cx] = t0[m];
+        hs[m][r * 16 + cx + 1] = t1[m];
+      }
     }
     __syncthreads();
-    float mu[1], muy, ekk[1], eyy, eky[1];
-    ssim_moments<1, 16, 16>(L, W, mu, muy, ekk, eyy, eky);
-    const int ox = threadIdx.x % 16, oy = threadIdx.x / 16;
-    if (tx * 16 + ox < width && ty * 16 + oy < height) {
-      const int a = (oy + kSsimR) * SL::AW + ox + kSsimR;
-      const float d = L.x[0][a] - L.y[a];
-      se += d * d;
-      ss += ssim_value(mu[0], muy, ekk[0], eyy, eky[0]);
+    if (in) {
+      float mo[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int d = 0; d <= 2 * kSsimR; ++d) {
+        const int q = (oy + d) * 16 + ox;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) mo[m] = fmaf(W.w[d], hs[m][q], mo[m]);
+      }
+      const int q = (oy + kSsimR) * AW + ox + kSsimR;
+      const float dv = xs[c][q] - ys[c][q];
+      se += dv * dv;
+      ss += ssim_value(mo[0], mo[1], mo[2], mo[3], mo[4]);
     }
     __syncthreads();
   }
