@@ -9,8 +9,9 @@
 // it, so the SSIM term can change only within 5 px of the core, and those
 // pixels' windows lie within 10 px of the core.  The paired renderer
 // therefore composites, for each context, only the "region" = core dilated by
-// enough tiles to cover 10 px, both states at once (one S = 2 group), and
-// sums the per-pixel differences there.  Pixels of the region whose window
+// enough tiles to cover 10 px, both states at once (up to four contexts of one
+// group share a workgroup as one 8-state group), and sums the per-pixel
+// differences there.  Pixels of the region whose window
 // reaches outside it see the same (zero) values in both states and so add
 // exactly zero.  Delta is that sum over all pixels and channels divided by
 // 3 H W.
