@@ -427,16 +427,20 @@ k_distortion_tiles(const float *__restrict__ images, const float *__restrict__ r
   }
 }
 
-__global__ void k_distortion_finalize(const double *__restrict__ part, int num_images, int blocks, int64_t values,
-                                      float lambda, float *__restrict__ d) {
-  const int img = blockIdx.x * blockDim.x + threadIdx.x;
-  if (img >= num_images) return;
+// D per image from its blocks' sums (one workgroup per image, fixed order, FP64).
+__global__ void __launch_bounds__(kBlock)
+k_distortion_finalize(const double *__restrict__ part, int num_images, int blocks, int64_t values, float lambda,
+                      float *__restrict__ d) {
+  __shared__ double red[4];
+  const int img = blockIdx.x;
   double se = 0.0, ss = 0.0;
-  for (int b = 0; b < blocks; ++b) {
+  for (int b = threadIdx.x; b < blocks; b += kBlock) {
     se += part[((int64_t)img * blocks + b) * 2 + 0];
     ss += part[((int64_t)img * blocks + b) * 2 + 1];
   }
-  d[img] = (float)(se / (double)values + (double)lambda * (1.0 - ss / (double)values));
+  se = block_sum_f64(se, red);
+  ss = block_sum_f64(ss, red);
+  if (threadIdx.x == 0) d[img] = (float)(se / (double)values + (double)lambda * (1.0 - ss / (double)values));
 }
 
 // ------------------------------------------------------------ Eq. (4)
@@ -577,8 +581,8 @@ void launch_distortion(const float *images, int num_images, int width, int heigh
   const int bx = (int)ceil_div(width, 16), by = (int)ceil_div(height, 16);
   k_distortion_tiles<<<dim3(bx * by, num_images), kBlock, 0, st>>>(images, reference, width, height, bx, by,
                                                                   ssim_weights(), part);
-  k_distortion_finalize<<<(unsigned)ceil_div(num_images, kBlock), kBlock, 0, st>>>(
-      part, num_images, bx * by, (int64_t)width * height * 3, lambda, d);
+  k_distortion_finalize<<<(unsigned)num_images, kBlock, 0, st>>>(part, num_images, bx * by,
+                                                                 (int64_t)width * height * 3, lambda, d);
 }
 
 void launch_risk_adjusted(const float *values, const int32_t *offsets, int G, float alpha, float beta, float q,
