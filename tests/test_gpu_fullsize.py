@@ -123,3 +123,50 @@ def test_full_size_250k_800px_64states_refined():
     ref = oracle.render_refined(w.scene, levels, w.camera, w.basis, w.codes, w.background, pixels=pix)
     ex = np.abs(host.astype(np.float64) - ref["image"]).max(-1) - ref["budget"]
     assert ex.max() <= TOL, f"excess {ex.max():.3g}"
+
+
+def test_full_size_utility_1m_540p_64groups_16contexts():
+    """Eq. (3) at the utility bench's size and launch shape: every delta of
+    the paired incremental renderer equals the difference of the on-device
+    distortions of full-frame renders of both states (whose images the
+    parity tests pin to the oracle), and Eq. (4) of the device deltas equals
+    the oracle's risk adjustment of the same values."""
+    import paper_2606_17212_amd as dgs
+    from oracle import utility as U
+    uw = synth.make_utility_workload("g1m_540p_utility_64groups_16contexts")
+    w = uw.base
+    dev = torch.device("cuda:0")
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    bg = tuple(float(x) for x in w.background)
+    ctx = torch.from_numpy(uw.codes).to(dev)
+    cg = torch.from_numpy(uw.context_group).to(dev)
+    gpl = torch.from_numpy(uw.group_pl.view(np.int16)).to(dev)
+    G, J = int(gpl.shape[0]), int(ctx.shape[0])
+    r = dgs.Renderer(dev, tile=(16, 16), states_per_group=8)
+    r.plan(scene, cam, w.basis, 512)
+    ref = r.render(scene, cam, torch.full_like(ctx[:1], 4), w.basis, bg)[0].contiguous()
+    r.bin(scene, cam, w.basis)
+    delta = r.utility(scene, cam, ctx, cg, gpl, w.basis, ref, bg)
+    assert r.utility_check() > 0
+    mg = uw.codes.copy()
+    p = (uw.group_pl >> 2).astype(np.int64)[uw.context_group]
+    mg[np.arange(J), p] = (uw.group_pl & 3).astype(np.uint8)[uw.context_group] + 1
+    mg = torch.from_numpy(mg).to(dev)
+    full = np.zeros(J)
+    for b in range(0, J, 256):
+        e = min(J, b + 256)
+        imgs = r.render(scene, cam, torch.cat([ctx[b:e], mg[b:e]]).contiguous(), w.basis, bg)
+        d = dgs.distortion(imgs, ref).double().cpu().numpy()
+        full[b:e] = d[:e - b] - d[e - b:]
+    dl = delta.double().cpu().numpy()
+    assert np.abs(dl - full).max() <= 1e-6, np.abs(dl - full).max()
+    assert np.abs(full).max() > 1e-5
+    offsets = np.searchsorted(uw.context_group, np.arange(G + 1)).astype(np.int32)
+    stats = dgs.risk_adjusted(delta, torch.from_numpy(offsets).to(dev)).cpu().numpy().astype(np.float64)
+    vals = delta.cpu().numpy().astype(np.float64)
+    for g in range(G):
+        want = U.risk_adjusted(vals[offsets[g]:offsets[g + 1]])
+        got = stats[g]
+        assert np.allclose(got, [want["mean"], want["quantile"], want["std"], want["risk_adjusted"]],
+                           rtol=1e-5, atol=1e-9), (g, got, want)
