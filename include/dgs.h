@@ -82,8 +82,9 @@ typedef enum {
  * The renderer projects one record per (Gaussian, depth) - 4n records, size
  * the workspace for n_records = 4n - and each state draws the record of the
  * depth it delivers.  dgs_backward also returns the levels' gradients
- * (dgs_scene_grad.refine).  dgs_render_per_state and the utility calls return
- * DGS_ERR_UNSUPPORTED for such scenes.
+ * (dgs_scene_grad.refine); the utility calls take such scenes (adding group
+ * (p, l) moves packet p from depth l - 1 to depth l).  dgs_render_per_state
+ * returns DGS_ERR_UNSUPPORTED for them.
  */
 typedef struct {
   int32_t n;

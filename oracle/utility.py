@@ -85,13 +85,21 @@ def paired_states(contexts: np.ndarray, packet: int, layer: int):
     return m, mg
 
 
-def deltas(scene, cam, basis, contexts, packet: int, layer: int, reference, background, lam: float = 0.20):
-    """Delta_g(m) of Eq. (3) for every context row (FP64 oracle renders)."""
-    from . import render
+def deltas(scene, cam, basis, contexts, packet: int, layer: int, reference, background, lam: float = 0.20,
+           refine=None):
+    """Delta_g(m) of Eq. (3) for every context row (FP64 oracle renders).
+    With ``refine`` (attribute refinement levels, Sec. 3) each state renders
+    its decoded scene (``oracle.render_refined``): adding g moves the packet's
+    Gaussians from depth ``layer - 1`` to depth ``layer``."""
+    from . import render, render_refined
 
     m, mg = paired_states(contexts, packet, layer)
-    a = render(scene, cam, basis, m, background)["image"]
-    b = render(scene, cam, basis, mg, background)["image"]
+    if refine is None:
+        a = render(scene, cam, basis, m, background)["image"]
+        b = render(scene, cam, basis, mg, background)["image"]
+    else:
+        a = render_refined(scene, refine, cam, basis, m, background)["image"]
+        b = render_refined(scene, refine, cam, basis, mg, background)["image"]
     return np.array([distortion(a[j], reference, lam) - distortion(b[j], reference, lam) for j in range(len(m))])
 
 

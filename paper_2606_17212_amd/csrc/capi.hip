@@ -302,7 +302,6 @@ int utility_prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_sta
                     int64_t item_capacity, Call *cl, UtilArgs *u) {
   // the render workspace is read only in its state-independent sections
   if (!contexts) return fail(DGS_ERR_INVALID_ARG, "contexts is NULL");
-  if (int rc0 = reject_refined(scene, "counterfactual utility")) return rc0;
   dgs_states none = *contexts;
   none.num_states = 0;
   int rc = prepare(scene, cam, &none, tun, ws, ws_bytes, cap, 0, cl);
@@ -341,6 +340,7 @@ int utility_prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_sta
   u->queue = u->hdr->queue;
   u->item_capacity = (uint64_t)item_capacity;
   u->num_contexts = contexts->num_states;
+  u->refined = scene->refine != nullptr;
   u->words = (int)U.words;
   u->tiles_x = cl->tiling.tiles_x;
   u->tiles_y = cl->tiling.tiles_y;
@@ -355,7 +355,8 @@ void utility_setup(const Call &cl, void *ws, const UtilArgs &u, const dgs_states
                    int G, hipStream_t st) {
   launch_clear_util_header(u.hdr, st);
   const int rx = (10 + cl.tiling.tw - 1) / cl.tiling.tw, ry = (10 + cl.tiling.th - 1) / cl.tiling.th;
-  launch_group_setup(u, group_pl, G, cl.P, at<float4>(ws, cl.L.rec0), at<uint2>(ws, cl.L.rect), cl.s.n, rx, ry, st);
+  launch_group_setup(u, group_pl, G, cl.P, at<float4>(ws, cl.L.rec0), at<uint2>(ws, cl.L.rect), cl.records, rx, ry,
+                     st);
   if (u.num_contexts > 0) launch_pair_setup(u, contexts->codes, group_pl, G, cl.P, st);
 }
 

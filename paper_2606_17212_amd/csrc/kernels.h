@@ -186,6 +186,7 @@ struct UtilArgs {
   unsigned int *queue;                   // hdr->queue
   uint64_t item_capacity;
   int num_contexts, words, tiles_x, tiles_y, width, height;
+  int refined;  // the scene has refinement levels: records are (Gaussian, delivered depth)
   const int32_t *context_group;
   const float *reference;
   float lambda;

@@ -44,7 +44,9 @@ __global__ void k_group_table(const uint16_t *__restrict__ group_pl, int G, int 
   if (atomicCAS(&pl2g[pl], -1, k) != -1) atomicOr(&h->bad_group, 2u);  // two groups name one (packet, layer)
 }
 
-// Core tiles of every group: the tile rectangles of its Gaussians.  Each row
+// Core tiles of every group: the tile rectangles of its Gaussians (with
+// refinement levels: of its packet's records at depths layer - 1 and layer,
+// the records that adding the group hides and shows).  Each row
 // of a rectangle is a run of consecutive tile bits, set with one OR per
 // bitmap word it touches.  LDS: the group bitmaps of all groups, privatised
 // per workgroup and merged into the global ones once (when they fit).
@@ -64,7 +66,7 @@ __device__ __forceinline__ void mark_rect_rows(uint32_t *row, int tiles_x, int x
 template <bool LDS>
 __global__ void __launch_bounds__(kBlock)
 k_group_core(const float4 *__restrict__ rec0, const uint2 *__restrict__ rect, int n, const int *__restrict__ pl2g,
-             int tiles_x, int words, int gw, uint32_t *__restrict__ core) {
+             int tiles_x, int words, int gw, int refined, uint32_t *__restrict__ core) {
   __shared__ uint32_t bm[LDS ? kCoreLdsWords : 1];
   if (LDS) {
     for (int i = threadIdx.x; i < gw; i += kBlock) bm[i] = 0u;
@@ -74,9 +76,12 @@ k_group_core(const float4 *__restrict__ rec0, const uint2 *__restrict__ rect, in
     const uint2 r = rect[i];
     const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
     if (x1 <= x0 || y1 <= y0) continue;
-    const int g = pl2g[__float_as_uint(rec0[i].w) & 0xFFFFu];
-    if (g < 0) continue;
-    mark_rect_rows((LDS ? bm : core) + (int64_t)g * words, tiles_x, x0, y0, x1, y1);
+    const uint32_t pl = __float_as_uint(rec0[i].w) & 0xFFFFu;
+    const int g = pl2g[pl];
+    // a record of depth d also changes when group (packet, d + 1) is added
+    const int g2 = (refined && (pl & 3u) < 3u) ? pl2g[pl + 1] : -1;
+    if (g >= 0) mark_rect_rows((LDS ? bm : core) + (int64_t)g * words, tiles_x, x0, y0, x1, y1);
+    if (g2 >= 0) mark_rect_rows((LDS ? bm : core) + (int64_t)g2 * words, tiles_x, x0, y0, x1, y1);
   }
   if (LDS) {
     __syncthreads();
@@ -152,7 +157,7 @@ __global__ void __launch_bounds__(kBlock)
 k_pair_setup(const uint8_t *__restrict__ codes, const int32_t *__restrict__ context_group,
              const uint16_t *__restrict__ group_pl, const uint32_t *__restrict__ gbase, int J, int G, int P,
              uint32_t *__restrict__ icount, uint32_t *__restrict__ pvis, uint32_t *__restrict__ bad,
-             UtilHeader *h) {
+             UtilHeader *h, int exact) {
   const int j = blockIdx.x;
   if (j >= J) return;
   const int g = context_group[j];
@@ -171,7 +176,10 @@ k_pair_setup(const uint8_t *__restrict__ codes, const int32_t *__restrict__ cont
     const int p = e >> 2, l = e & 3;
     const int c = row[p];
     const int cg = (ok && p == gp) ? gl + 1 : c;
-    out[e] = (l < c ? 1u : 0u) | (l < cg ? 2u : 0u);
+    if (exact)  // records at delivered depth l: shown where the state delivers exactly depth l
+      out[e] = ((c < 4 ? c : 4) == l + 1 ? 1u : 0u) | ((cg < 4 ? cg : 4) == l + 1 ? 2u : 0u);
+    else
+      out[e] = (l < c ? 1u : 0u) | (l < cg ? 2u : 0u);
   }
 }
 
@@ -538,10 +546,12 @@ void launch_group_setup(const UtilArgs &u, const uint16_t *group_pl, int G, int 
   if (n > 0) {
     if (gw <= kCoreLdsWords) {
       const int blocks = (int)std::min<int64_t>(ceil_div(n, kBlock), 128);
-      k_group_core<true><<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, (int)gw, u.core);
+      k_group_core<true><<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, (int)gw, u.refined,
+                                                    u.core);
     } else {
       const int blocks = (int)std::min<int64_t>(ceil_div(n, kBlock), 4096);
-      k_group_core<false><<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, (int)gw, u.core);
+      k_group_core<false><<<blocks, kBlock, 0, st>>>(rec0, rect, n, u.pl2g, u.tiles_x, u.words, (int)gw, u.refined,
+                                                     u.core);
     }
   }
   k_group_region<<<(unsigned)ceil_div(gw, kBlock), kBlock, 0, st>>>(u.core, G, u.tiles_x, u.tiles_y, u.words,
@@ -556,7 +566,7 @@ void launch_group_setup(const UtilArgs &u, const uint16_t *group_pl, int G, int 
 void launch_pair_setup(const UtilArgs &u, const uint8_t *codes, const uint16_t *group_pl, int G, int P,
                        hipStream_t st) {
   k_pair_setup<<<u.num_contexts, kBlock, 0, st>>>(codes, u.context_group, group_pl, u.group_base, u.num_contexts,
-                                                  G, P, u.icount, u.pvis, u.bad, u.hdr);
+                                                  G, P, u.icount, u.pvis, u.bad, u.hdr, u.refined);
   launch_scan_u32(u.icount, u.item_base, u.num_contexts, u.parts, &u.hdr->items, st);
   k_bundle_setup<<<(unsigned)ceil_div(u.num_contexts, kBlock), kBlock, 0, st>>>(u.context_group, u.bad, u.icount,
                                                                               u.num_contexts, u.bcount);

@@ -191,3 +191,38 @@ def test_utility_bundles_do_not_change_deltas():
         r.utility_check()
     d = d.cpu().numpy()
     assert np.isnan(d[5]) and np.array_equal(np.delete(d, 5), np.delete(base, 5))
+
+
+def test_utility_with_refinement_levels():
+    """Scenes with refinement levels: adding group (p, l) moves packet p from
+    depth l - 1 to depth l; the paired renderer against the oracle's refined
+    renders and against the GPU's own refined full-frame path."""
+    dgs = _dgs()
+    scene, cam, basis, groups, ctx, cg, _ = _utility_case(J_per=3)
+    levels = synth.make_refinement(scene, index=7)
+    P = scene.num_packets
+    ref = oracle.render_refined(scene, levels, cam, basis, np.full((1, P), 4, np.uint8),
+                                np.asarray(BG))["image"][0].astype(np.float32)
+    dev = torch.device("cuda:0")
+    s = dgs.GaussianScene.from_arrays(scene, dev, refine=levels)
+    c = dgs.Camera.from_arrays(cam)
+    gpl = np.array([(p << 2) | l for p, l in groups], np.uint16).view(np.int16)
+    for tile in ((16, 16), (32, 8)):
+        r = dgs.Renderer(dev, tile=tile, states_per_group=8)
+        r.plan(s, c, basis, 2 * len(ctx))
+        r.bin(s, c, basis)
+        delta = r.utility(s, c, _dev(ctx), _dev(cg), _dev(gpl), basis, _dev(ref), BG).cpu().numpy()
+        assert r.utility_check() > 0
+        mg = ctx.copy()
+        for j in range(len(ctx)):
+            p, l = groups[cg[j]]
+            mg[j, p] = l + 1
+        both = r.render(s, c, _dev(np.concatenate([ctx, mg])), basis, BG)
+        d = dgs.distortion(both, _dev(ref)).double().cpu().numpy()
+        full = d[: len(ctx)] - d[len(ctx):]
+        assert np.abs(delta - full).max() <= 1e-6, (tile, np.abs(delta - full).max())
+        want = np.concatenate([U.deltas(scene, cam, basis, ctx[cg == k], p, l, ref, np.asarray(BG), refine=levels)
+                               for k, (p, l) in enumerate(groups)])
+        err = np.abs(delta.astype(np.float64) - want)
+        assert err.max() <= 1e-5 + 1e-3 * np.abs(want).max(), (tile, err.max(), np.abs(want).max())
+        assert np.abs(want).max() > 1e-4

@@ -136,3 +136,20 @@ def test_delta_is_local_to_the_group():
     outside = np.ones_like(changed)
     outside[y0:y1, x0:x1] = False
     assert np.all((sa == sb)[outside])
+
+
+def test_refined_deltas_reduce_to_plain_with_zero_levels():
+    """Refinement levels of zero leave every state's render, so every delta,
+    unchanged; non-zero levels of the group's packet change the delta."""
+    import synth
+    sc = synth.make_scene(300, 2, 2, 4, "rgb", index=8, stream=0)
+    cam = centred_camera(24, 20)
+    basis = synth.temporal_basis(0.5, sc.rank)
+    ref = np.random.default_rng(1).uniform(0, 1, (20, 24, 3))
+    ctx = np.array([[2, 1, 4, 0], [2, 3, 1, 1], [2, 0, 0, 4]], np.uint8)
+    plain = U.deltas(sc, cam, basis, ctx, 0, 2, ref, BG)
+    zero = U.deltas(sc, cam, basis, ctx, 0, 2, ref, BG, refine=np.zeros((3, oracle.refine_rows(0), sc.n), np.float32))
+    assert np.array_equal(plain, zero)
+    lv = synth.make_refinement(sc, index=8)
+    refined = U.deltas(sc, cam, basis, ctx, 0, 2, ref, BG, refine=lv)
+    assert np.abs(refined - plain).max() > 1e-6
