@@ -417,11 +417,30 @@ def refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg):
     value = W * args.steps / (total_ms / 1e3)
     log(f"[bench] refined: {total_ms / args.steps:.3f} ms/step (bin {bin_ms:.3f}, composite {comp_ms:.3f}) "
         f"-> {value:.1f} states/s; {M} instances")
-    return {"workload": args.workload + "_refined", "value": round(value, 2), "unit": "states/s",
-            "records": scene.records, "instances": M, "ms_per_step": round(total_ms / args.steps, 4),
-            "bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4),
-            "achieved_tflops": round(flops / (comp_ms / 1e3) / 1e12, 3),
-            "alpha_evals": alpha_evals, "blends": blends}
+    out = {"workload": args.workload + "_refined", "value": round(value, 2), "unit": "states/s",
+           "records": scene.records, "instances": M, "ms_per_step": round(total_ms / args.steps, 4),
+           "bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4),
+           "achieved_tflops": round(flops / (comp_ms / 1e3) / 1e12, 3),
+           "alpha_evals": alpha_evals, "blends": blends}
+    if not args.no_per_state:
+        # the per-state baseline of the same states (each state's delivered records)
+        r.bin(scene, cam, w.basis)
+        r.composite(scene, cam, codes, w.basis, bg, out=img)
+        one = torch.empty((1, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+        for k in range(min(4, W)):
+            r.render(scene, cam, codes[k:k + 1], w.basis, bg, per_state=True, out=one)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(W):
+            r.render(scene, cam, codes[k:k + 1], w.basis, bg, per_state=True, out=one)
+            torch.cuda.synchronize()
+        ps_s = time.perf_counter() - t0
+        r.check()
+        same = bool(torch.equal(one[0], img[W - 1]))
+        out["per_state"] = {"value": round(W / ps_s, 2), "unit": "states/s", "bit_identical_to_batched": same}
+        out["speedup_batched_vs_per_state"] = round(value / (W / ps_s), 3)
+        log(f"[bench] refined per-state: {1e3 * ps_s / W:.3f} ms/state -> {W / ps_s:.1f} states/s; identical={same}")
+    return out
 
 
 def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):

@@ -45,8 +45,7 @@ typedef enum {
   DGS_ERR_WORKSPACE = 2,   /* workspace smaller than dgs_workspace_bytes() */
   DGS_ERR_OVERFLOW = 3,    /* tile instances exceeded the capacity (dgs_check) */
   DGS_ERR_HIP = 4,         /* a HIP runtime call failed (message in dgs_last_error) */
-  DGS_ERR_UNSUPPORTED = 5  /* tuning outside the compiled variants, or a call
-                              that does not take refinement levels */
+  DGS_ERR_UNSUPPORTED = 5  /* tuning outside the compiled variants */
 } dgs_status;
 
 /*
@@ -83,8 +82,8 @@ typedef enum {
  * the workspace for n_records = 4n - and each state draws the record of the
  * depth it delivers.  dgs_backward also returns the levels' gradients
  * (dgs_scene_grad.refine); the utility calls take such scenes (adding group
- * (p, l) moves packet p from depth l - 1 to depth l).  dgs_render_per_state
- * returns DGS_ERR_UNSUPPORTED for them.
+ * (p, l) moves packet p from depth l - 1 to depth l), and so does
+ * dgs_render_per_state (each state's delivered records).
  */
 typedef struct {
   int32_t n;

@@ -662,18 +662,29 @@ void launch_present_flags(const uint8_t *codes_row, const uint16_t *packet_layer
   k_present_flags<<<(unsigned)ceil_div(n, kBlock), kBlock, 0, st>>>(codes_row, packet_layer, n, P, flags);
 }
 
+// The list holds record ids: the Gaussian i, or with refinement levels its
+// record 4 i + d at the delivered depth d (codes above 4 act as 4).
 __global__ void __launch_bounds__(kBlock)
 k_present_scatter(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ off, int n,
+                  const uint8_t *__restrict__ codes_row, const uint16_t *__restrict__ packet_layer, int refined,
                   uint32_t *__restrict__ list, const unsigned long long *__restrict__ total, Header *h) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i == 0) h->n_active = (unsigned)*total;
   if (i >= n) return;
-  if (flags[i]) list[off[i]] = (uint32_t)i;
+  if (!flags[i]) return;
+  uint32_t v = (uint32_t)i;
+  if (refined) {
+    const int c = codes_row[packet_layer[i] >> 2];  // present: the packet is in range and c > layer
+    v = 4u * (uint32_t)i + (uint32_t)((c < 4 ? c : 4) - 1);
+  }
+  list[off[i]] = v;
 }
 
-void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, uint32_t *list,
+void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, const uint8_t *codes_row,
+                            const uint16_t *packet_layer, bool refined, uint32_t *list,
                             const unsigned long long *total, Header *h, hipStream_t st) {
-  k_present_scatter<<<(unsigned)ceil_div(n > 0 ? n : 1, kBlock), kBlock, 0, st>>>(flags, off, n, list, total, h);
+  k_present_scatter<<<(unsigned)ceil_div(n > 0 ? n : 1, kBlock), kBlock, 0, st>>>(
+      flags, off, n, codes_row, packet_layer, refined ? 1 : 0, list, total, h);
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_f32(float *p, int64_t n, float v) {

@@ -150,12 +150,6 @@ struct Call {
   int records;  // projected records: n, or 4n (one per delivered depth) with refinement levels
 };
 
-// Entry points that need one record per Gaussian.
-int reject_refined(const dgs_scene *scene, const char *what) {
-  if (scene && scene->refine) return fail(DGS_ERR_UNSUPPORTED, "%s: scenes with refinement levels are not supported", what);
-  return DGS_OK;
-}
-
 int prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
             const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t cap, int need_codes, Call *call) {
   int rc;
@@ -522,8 +516,8 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
                          float *tfinal, void *stream) {
   g_err.clear();
   Call cl;
-  int rc = reject_refined(scene, "dgs_render_per_state");
-  if (rc || (rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl))) return rc;
+  int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 1, &cl);
+  if (rc) return rc;
   if (states->num_states > 0 && !image) return fail(DGS_ERR_INVALID_ARG, "image is NULL");
   hipStream_t st = (hipStream_t)stream;
   const int W = states->num_states;
@@ -537,6 +531,7 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
     launch_scan_u32(at<uint32_t>(ws, cl.L.cnt), at<uint32_t>(ws, cl.L.dkey1), n,
                     at<unsigned long long>(ws, cl.L.part), &h->instances, st);
     launch_present_scatter(at<uint32_t>(ws, cl.L.cnt), at<uint32_t>(ws, cl.L.dkey1), n,
+                           states->codes + (int64_t)w * cl.P, scene->packet_layer, scene->refine != nullptr,
                            at<uint32_t>(ws, cl.L.present), &h->instances, h, st);
     project_and_count(cl, ws, true, st);
     const uint32_t *vals = emit_and_sort(cl, ws, true, cap, st);

@@ -56,7 +56,8 @@ void launch_state_order(const uint8_t *codes, const uint32_t *hist, int num_stat
 void launch_tile_order(const uint2 *ranges, int tiles, uint32_t *order, hipStream_t st);
 void launch_present_flags(const uint8_t *codes_row, const uint16_t *packet_layer, int n, int P,
                           uint32_t *flags, hipStream_t st);
-void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, uint32_t *list,
+void launch_present_scatter(const uint32_t *flags, const uint32_t *off, int n, const uint8_t *codes_row,
+                            const uint16_t *packet_layer, bool refined, uint32_t *list,
                             const unsigned long long *total, Header *h, hipStream_t st);
 void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 void launch_fill_u64(unsigned long long *p, int n, hipStream_t st);  // zero n <= 64 counters

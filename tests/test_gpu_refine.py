@@ -7,8 +7,8 @@ its plain scene.
 Bars: images within 1e-4 of the FP64 oracle plus its ambiguity budget; every
 record's depth key and tile rectangle bit-exact with the FP32 mirror of the
 decoded scene at that depth; group size and tile shape change no pixel;
-all-zero levels give the plain renderer's images bit for bit; calls that take
-no refinement levels raise DGS_ERR_UNSUPPORTED.  Gradients of the base
+all-zero levels give the plain renderer's images bit for bit; the per-state
+baseline gives the batched images bit for bit.  Gradients of the base
 parameters and of the levels against the FP64 oracle with the bar of the plain
 backward (per tensor relative norm <= 1e-3, elementwise <= 1e-3 (|g*| +
 rms g*) outside Gaussians that touch an ambiguous pixel).
@@ -138,7 +138,7 @@ def test_zero_levels_equal_plain_render_bit_for_bit():
         assert np.array_equal(a, b), tile
 
 
-def test_refined_psnr_and_unsupported_calls(case):
+def test_refined_psnr_per_state_and_bad_shapes(case):
     dgs = _dgs()
     scene, cam, basis, levels, codes, ref = case
     dev = torch.device("cuda:0")
@@ -151,9 +151,10 @@ def test_refined_psnr_and_unsupported_calls(case):
     want = oracle.psnr(ref["image"], ref["image"][1])
     fin = np.isfinite(want) & (want < 90)
     assert np.allclose(ps[fin], want[fin], atol=2e-2), (ps, want)
-    with pytest.raises(dgs.DgsError) as e:
-        r.render(s, c, cd, basis, BG, per_state=True)
-    assert e.value.status == 5
+    # the per-state baseline renders each state's delivered records: the batched images bit for bit
+    batched = r.render(s, c, cd, basis, BG)
+    per_state = r.render(s, c, cd[:6].contiguous(), basis, BG, per_state=True)
+    assert torch.equal(per_state, batched[:6])
     # a refine array of the wrong shape is refused before any launch
     bad = s.with_params(refine=s.refine[:, :5].contiguous())
     with pytest.raises(ValueError):
