@@ -54,7 +54,10 @@ def parse():
                     help="counterfactual-utility workload timed beside the main metric")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true", help="time replays of one captured HIP graph")
-    ap.add_argument("--tune", action="store_true", help="pick tile shape and states per group by timing")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick tile shape, states per group, launch and LDS batch by timing")
+    ap.add_argument("--lds-batch", type=int, default=256, choices=(128, 256, 512),
+                    help="list entries staged in LDS per compositing batch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -94,9 +97,12 @@ def main():
         res = dgs.Autotuner().tune(scene, cam, codes, w.basis, bg, reps=3)
         (tw, th), args.states_per_group = res.tile, res.states_per_group
         args.launch = "persistent" if res.persistent else "grid"
-        log(f"[bench] autotuner: {tw}x{th}, S={args.states_per_group}, {args.launch} ({res.ms:.3f} ms); "
+        args.lds_batch = res.lds_batch
+        log(f"[bench] autotuner: {tw}x{th}, S={args.states_per_group}, {args.launch}, LDS batch {args.lds_batch} "
+            f"({res.ms:.3f} ms); "
             f"table {res.table}")
-    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch])
+    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch],
+                     lds_batch=args.lds_batch)
     M = r.plan(scene, cam, w.basis, W)
     log(f"[bench] {args.workload}: N={scene.n} {cam.width}x{cam.height} W={W} instances={M}")
     img = torch.empty((W, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
@@ -153,7 +159,8 @@ def main():
     flops = FLOPS_PER_ALPHA * alpha_evals + FLOPS_PER_BLEND * blends
     achieved = flops / (comp_ms / 1e3) / 1e12
     plan = r.launch_plan(cam, W)
-    kernel = f"k_composite<{plan['states_per_group']},{tw},{th},0,{'true' if plan['persistent'] else 'false'}>"
+    kernel = (f"k_composite<{plan['states_per_group']},{tw},{th},0,{'true' if plan['persistent'] else 'false'},"
+              f"{plan['lds_batch']}>")
     traffic = profile_summary.measured_traffic(kernel, args.workload, ROOT)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
@@ -454,7 +461,8 @@ def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
     codes_all = torch.from_numpy(synth.make_codes(kind, lo, hi, total, w.scene.num_packets, rec["layers"],
                                                   index=w.index)).to(dev)
     bg = tuple(float(x) for x in w.background)
-    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch])
+    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch],
+                       lds_batch=args.lds_batch)
     ren.plan(scene, cam, w.basis, batch)
     ref = ren.render(scene, cam, torch.ones_like(codes_all[:1]), w.basis, bg)[0].contiguous()
     psnr = torch.empty(total, dtype=torch.float32, device=dev)
@@ -517,7 +525,8 @@ def utility_bench(args, dgs, synth, torch, np, dev, tw, th):
     gpl = torch.from_numpy(uw.group_pl.view(np.int16)).to(dev)
     G, J = int(gpl.shape[0]), int(ctx.shape[0])
     offsets = torch.from_numpy(np.searchsorted(uw.context_group, np.arange(G + 1)).astype(np.int32)).to(dev)
-    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch])
+    r = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch],
+                     lds_batch=args.lds_batch)
     r.plan(scene, cam, w.basis, 512)
     # the reference I: full delivery (code 4 = every layer of every packet)
     ref = r.render(scene, cam, torch.full_like(ctx[:1], 4), w.basis, bg)[0].contiguous()

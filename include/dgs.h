@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define DGS_ABI_VERSION 2
+#define DGS_ABI_VERSION 3
 
 typedef enum {
   DGS_OK = 0,
@@ -141,6 +141,8 @@ typedef struct {
   int32_t tile_h;
   int32_t states_per_group;
   int32_t flags;
+  int32_t lds_batch;  /* list entries staged in LDS per batch: 128, 256 or 512 (0 = 256);
+                         used for states_per_group >= 4 in image and PSNR mode */
 } dgs_tuning;
 
 /* Parameter gradients, device pointers with the scene's shapes; overwritten.
@@ -231,11 +233,12 @@ int dgs_composite_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_
  * current, for the occupancy query).  Outputs (host): *states_per_group = S
  * used; *persistent = 1 for the persistent launch, 0 for the grid launch;
  * *workgroups = workgroups launched; *work_items = (tile, state group) work
- * items.  Returns DGS_OK, DGS_ERR_INVALID_ARG, DGS_ERR_UNSUPPORTED or
+ * items; *lds_batch = list entries staged per LDS batch by the variant that
+ * runs (the tuning's, or 256 where S < 4).  Returns DGS_OK, DGS_ERR_INVALID_ARG, DGS_ERR_UNSUPPORTED or
  * DGS_ERR_HIP.
  */
 int dgs_composite_launch(const dgs_camera *cam, const dgs_tuning *tun, int32_t num_states, int32_t *states_per_group,
-                         int32_t *persistent, int64_t *workgroups, int64_t *work_items);
+                         int32_t *persistent, int64_t *workgroups, int64_t *work_items, int32_t *lds_batch);
 
 /*
  * Work counters of dgs_composite for the same arguments, nothing rendered:

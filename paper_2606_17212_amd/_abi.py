@@ -58,7 +58,8 @@ TUNE_GRID = 2        # dgs_tuning.flags: one workgroup per work item (0 = automa
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("states_per_group", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("states_per_group", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("lds_batch", ctypes.c_int32)]
 
 
 class SceneGrad(ctypes.Structure):
@@ -73,7 +74,7 @@ class WorkspaceView(ctypes.Structure):
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32)]
 
 
-ABI_VERSION = 2  # the structs below match include/dgs.h of this version
+ABI_VERSION = 3  # the structs below match include/dgs.h of this version
 
 
 class DgsError(RuntimeError):
@@ -113,7 +114,7 @@ def lib():
         f.restype = ctypes.c_int
         f.argtypes = common + [i64, vp, vp, vp]
     L.dgs_composite_launch.restype = ctypes.c_int
-    L.dgs_composite_launch.argtypes = [P(Camera), P(Tuning), i32, P(i32), P(i32), P(i64), P(i64)]
+    L.dgs_composite_launch.argtypes = [P(Camera), P(Tuning), i32, P(i32), P(i32), P(i64), P(i64), P(i32)]
     L.dgs_bin.restype = ctypes.c_int
     L.dgs_bin.argtypes = common + [i64, vp]
     L.dgs_composite.restype = ctypes.c_int

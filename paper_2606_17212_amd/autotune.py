@@ -1,9 +1,10 @@
 """Launch-shape autotuner and memory-probed state-batch sizing.
 
 * ``tune``: times ``bin + composite`` for every tile shape (16x16, 32x8),
-  states-per-group S in {2, 4, 8, 16, 32} and compositing launch (grid or
-  persistent) on the caller's own scene, camera and states, and keeps the
-  fastest.  Results are cached in a JSON file keyed by
+  states-per-group S in {2, 4, 8, 16, 32}, compositing launch (grid or
+  persistent) and list entries staged in LDS per batch (128, 256, 512; groups
+  of 4 or more states) on the caller's own scene, camera and states, and keeps
+  the fastest.  Results are cached in a JSON file keyed by
   the device name and the workload's shape.
 * ``probe_state_batch``: the largest number of states whose images and
   workspace fit a memory budget.  Like the paper's probe-based world-batch
@@ -24,6 +25,8 @@ from typing import Callable, Dict, Iterable, Optional, Tuple
 TILES = ((16, 16), (32, 8))
 GROUP_SIZES = (2, 4, 8, 16, 32)
 LAUNCHES = (False, True)  # persistent compositing launch off / on
+LDS_BATCHES = (128, 256, 512)  # list entries per LDS batch (variants exist for S >= 4)
+DEFAULT_LDS_BATCH = 256
 
 
 @dataclass
@@ -33,42 +36,47 @@ class TuneResult:
     persistent: bool
     ms: float
     table: Dict[str, float]
+    lds_batch: int = DEFAULT_LDS_BATCH
 
     def as_dict(self):
         return {"tile": list(self.tile), "states_per_group": self.states_per_group,
-                "persistent": self.persistent, "ms": self.ms, "table": self.table}
+                "persistent": self.persistent, "lds_batch": self.lds_batch, "ms": self.ms, "table": self.table}
 
 
 def _key(device_name: str, n: int, width: int, height: int, num_states: int, packets: int) -> str:
     return f"{device_name}|n={n}|{width}x{height}|W={num_states}|P={packets}"
 
 
-def search(timer: Callable[[Tuple[int, int], int, bool], float], num_states: int,
+def search(timer: Callable[[Tuple[int, int], int, bool, int], float], num_states: int,
            tiles: Iterable[Tuple[int, int]] = TILES, group_sizes: Iterable[int] = GROUP_SIZES,
-           launches: Iterable[bool] = LAUNCHES) -> TuneResult:
-    """Exhaustive search: ``timer(tile, S, persistent)`` returns milliseconds
-    (may raise to reject a candidate).  Group sizes above the state count add
-    nothing and are skipped."""
+           launches: Iterable[bool] = LAUNCHES, lds_batches: Iterable[int] = LDS_BATCHES) -> TuneResult:
+    """Exhaustive search: ``timer(tile, S, persistent, lds_batch)`` returns
+    milliseconds (may raise to reject a candidate).  Group sizes above the
+    state count add nothing and are skipped; groups of fewer than 4 states have
+    only the default LDS batch, so they are timed once."""
     table = {}
     best = None
     cap = 1
     while cap < max(num_states, 1):
         cap *= 2
     group_sizes = tuple(group_sizes)
+    lds_batches = tuple(lds_batches)
     for tile in tiles:
         for S in group_sizes:
             if S > cap and S != min(group_sizes):
                 continue
+            batches = lds_batches if S >= 4 else (DEFAULT_LDS_BATCH,)
             for pers in launches:
-                name = f"{tile[0]}x{tile[1]}/S{S}/{'persistent' if pers else 'grid'}"
-                try:
-                    ms = float(timer(tile, S, pers))
-                except Exception as e:  # a candidate that fails (e.g. out of memory) is skipped
-                    table[name] = f"failed: {type(e).__name__}"
-                    continue
-                table[name] = ms
-                if best is None or ms < best.ms:
-                    best = TuneResult(tile, S, bool(pers), ms, table)
+                for B in batches:
+                    name = f"{tile[0]}x{tile[1]}/S{S}/{'persistent' if pers else 'grid'}/B{B}"
+                    try:
+                        ms = float(timer(tile, S, pers, B))
+                    except Exception as e:  # a candidate that fails (e.g. out of memory) is skipped
+                        table[name] = f"failed: {type(e).__name__}"
+                        continue
+                    table[name] = ms
+                    if best is None or ms < best.ms:
+                        best = TuneResult(tile, S, bool(pers), ms, table, B)
     if best is None:
         raise RuntimeError("no launch shape could be timed")
     best.table = table
@@ -123,7 +131,7 @@ class Autotuner:
                 self.cache = json.load(f)
 
     def tune(self, scene, camera, codes, basis, background=(0, 0, 0), reps: int = 5,
-             tiles=TILES, group_sizes=GROUP_SIZES, launches=LAUNCHES) -> TuneResult:
+             tiles=TILES, group_sizes=GROUP_SIZES, launches=LAUNCHES, lds_batches=LDS_BATCHES) -> TuneResult:
         import torch
 
         from .render import Renderer
@@ -134,12 +142,12 @@ class Autotuner:
         if key in self.cache:
             c = self.cache[key]
             return TuneResult(tuple(c["tile"]), int(c["states_per_group"]), bool(c.get("persistent", False)),
-                              float(c["ms"]), c["table"])
+                              float(c["ms"]), c["table"], int(c.get("lds_batch", DEFAULT_LDS_BATCH)))
         W = int(codes.shape[0])
         img = torch.empty((W, camera.height, camera.width, 3), dtype=torch.float32, device=dev)
 
-        def timer(tile, S, persistent):
-            r = Renderer(dev, tile=tile, states_per_group=S, persistent=persistent)
+        def timer(tile, S, persistent, lds_batch):
+            r = Renderer(dev, tile=tile, states_per_group=S, persistent=persistent, lds_batch=lds_batch)
             r.plan(scene, camera, basis, W)
             for _ in range(2):
                 r.bin(scene, camera, basis)
@@ -155,7 +163,7 @@ class Autotuner:
             del r
             return e0.elapsed_time(e1) / reps
 
-        res = search(timer, W, tiles, group_sizes, launches)
+        res = search(timer, W, tiles, group_sizes, launches, lds_batches)
         self.cache[key] = res.as_dict()
         if self.cache_path:
             with open(self.cache_path, "w") as f:

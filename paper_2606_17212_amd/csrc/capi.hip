@@ -50,6 +50,8 @@ int check_tuning(const dgs_camera *cam, const dgs_tuning *tun, Tiling *t) {
     return fail(DGS_ERR_INVALID_ARG, "unknown tuning flags");
   if (tun && (tun->flags & DGS_TUNE_PERSISTENT) && (tun->flags & DGS_TUNE_GRID))
     return fail(DGS_ERR_INVALID_ARG, "tuning flags: persistent and grid are exclusive");
+  if (tun && tun->lds_batch != 0 && tun->lds_batch != 128 && tun->lds_batch != 256 && tun->lds_batch != 512)
+    return fail(DGS_ERR_UNSUPPORTED, "lds_batch %d not supported (128, 256 or 512)", tun->lds_batch);
   t->tw = tw;
   t->th = th;
   t->tiles_x = (cam->width + tw - 1) / tw;
@@ -240,6 +242,9 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
   return r ? at<uint32_t>(ws, L.tval1) : at<uint32_t>(ws, L.tval0);
 }
 
+
+// List entries per LDS batch (validated by check_tuning).
+int lds_batch(const dgs_tuning *tun) { return (tun && tun->lds_batch) ? tun->lds_batch : 256; }
 
 // 0 automatic, 1 persistent, 2 grid (validated by check_tuning)
 int launch_kind(const dgs_tuning *tun) {
@@ -466,7 +471,7 @@ int composite_call(const dgs_scene *scene, const dgs_camera *cam, const dgs_stat
   a.psnr_part = at<float>(ws, cl.L.psnr_part);
   a.counters = counters;
   a.queues = at<unsigned int>(ws, cl.L.queues);
-  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, launch_kind(tun), st))
+  if (launch_composite(a, S, cl.tiling.tw, cl.tiling.th, mode, launch_kind(tun), lds_batch(tun), st))
     return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
   if (mode == 1)
     launch_psnr_finalize(a.psnr_part, W, cl.tiling.tiles, (int64_t)cl.c.width * cl.c.height, psnr, st);
@@ -541,7 +546,7 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
     a.tfinal = tfinal;
     a.state_offset = w;
     a.launch_states = 1;
-    if (launch_composite(a, 1, cl.tiling.tw, cl.tiling.th, 0, 2, st))
+    if (launch_composite(a, 1, cl.tiling.tw, cl.tiling.th, 0, 2, 256, st))
       return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=1");
   }
   return hip_check("render_per_state launch");
@@ -638,22 +643,23 @@ int dgs_workspace_sections(int32_t n, int32_t num_packets, const dgs_camera *cam
 }
 
 int dgs_composite_launch(const dgs_camera *cam, const dgs_tuning *tun, int32_t num_states, int32_t *states_per_group,
-                         int32_t *persistent, int64_t *workgroups, int64_t *work_items) {
+                         int32_t *persistent, int64_t *workgroups, int64_t *work_items, int32_t *lds_batch_out) {
   g_err.clear();
   Tiling t;
   int rc;
-  if (!states_per_group || !persistent || !workgroups || !work_items)
+  if (!states_per_group || !persistent || !workgroups || !work_items || !lds_batch_out)
     return fail(DGS_ERR_INVALID_ARG, "output pointer is NULL");
   if (num_states < 0) return fail(DGS_ERR_INVALID_ARG, "num_states < 0");
   if ((rc = check_camera(cam)) || (rc = check_tuning(cam, tun, &t))) return rc;
   const int S = group_size(tun, num_states, 32);
   CompositePlan p;
-  if (plan_composite(S, t.tw, t.th, t.tiles, (num_states + S - 1) / S, launch_kind(tun), &p))
+  if (plan_composite(S, t.tw, t.th, t.tiles, (num_states + S - 1) / S, launch_kind(tun), lds_batch(tun), &p))
     return fail(DGS_ERR_UNSUPPORTED, "no composite variant for S=%d", S);
   *states_per_group = S;
   *persistent = p.persistent ? 1 : 0;
   *workgroups = p.workgroups;
   *work_items = p.items;
+  *lds_batch_out = p.lds_batch;
   return hip_check("occupancy query");
 }
 

@@ -89,11 +89,14 @@ template <typename T>
 __device__ __forceinline__ const T *vgpr_lds_ptr(const T *p) { return p; }
 #endif
 
-struct Stage {
-  uint32_t vis[4][kBlock];  // per wave: delivery bits of the entry, 0 if it misses the wave's block
-  StageRec rec[kBlock];     // one 48-byte record per entry: one LDS base address per entry
-  uint32_t id[kBlock];      // Gaussian id (backward)
+// One LDS batch of B list entries.
+template <int B>
+struct StageT {
+  uint32_t vis[4][B];  // per wave: delivery bits of the entry, 0 if it misses the wave's block
+  StageRec rec[B];     // one 48-byte record per entry: one LDS base address per entry
+  uint32_t id[B];      // Gaussian id (backward)
 };
+using Stage = StageT<kBlock>;
 
 // Stages one list entry.  The sorted value carries the Gaussian id in its low
 // 28 bits and, in bits 28..31, whether the entry can reach alpha >= 1/255 in
@@ -101,8 +104,8 @@ struct Stage {
 // the stage holds the entry's delivery bits, or 0 for a block it cannot reach.
 // In pair mode `nvis` contexts' two-bit tables, `vstride` words apart, are
 // merged: bits 2c and 2c + 1 belong to the bundle's context c.
-template <int TW, int TH>
-__device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, const float4 *rec0,
+template <int TW, int TH, typename ST>
+__device__ __forceinline__ void stage_entry(ST &st, int slot, uint32_t val, const float4 *rec0,
                                             const float4 *rec1, const float4 *rec2, const uint32_t *vis,
                                             int nvis = 1, int64_t vstride = 0) {
   const uint32_t id = val & kIdMask;
@@ -120,9 +123,14 @@ __device__ __forceinline__ void stage_entry(Stage &st, int slot, uint32_t val, c
 }
 
 // Occupancy requested from the register allocator: the state registers
-// (4 per state) dominate, so small groups can keep 8 waves per SIMD.
-template <int S>
-constexpr int waves_per_eu() { return S <= 8 ? 8 : (S <= 16 ? 5 : 2); }
+// (4 per state) dominate, so small groups can keep 8 waves per SIMD; a
+// 512-entry LDS batch (~35 KB) leaves room for 4 workgroups per CU.
+template <int S, int B = kBlock>
+constexpr int waves_per_eu() {
+  constexpr int by_regs = S <= 8 ? 8 : (S <= 16 ? 5 : 2);
+  constexpr int by_lds = B > kBlock ? 4 : 8;
+  return by_regs < by_lds ? by_regs : by_lds;
+}
 
 // Pair mode: a bundle of contexts (their delivery tables `vstride` words
 // apart from `vis`) and the work item of each context's patch.
@@ -135,8 +143,8 @@ struct PairOut {
 // Composites one tile for the S states of one group.  `vis` holds the
 // group's delivery bits per (packet, layer); `grp` indexes the outputs (the
 // state group); in pair mode `po` names the bundle's patches instead.
-template <int S, int TW, int TH, int MODE>
-__device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st, int tile, int grp,
+template <int S, int TW, int TH, int MODE, int B = kBlock>
+__device__ __forceinline__ void composite_item(const CompositeArgs &a, StageT<B> &st, int tile, int grp,
                                                const uint32_t *vis, const PairOut *po = nullptr) {
   static_assert(TW * TH == kBlock, "one pixel per thread");
   const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
@@ -156,22 +164,25 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
 
   const uint2 rg = a.ranges[tile];
   uint32_t n_alpha = 0, n_blend = 0, n_wave_alpha = 0, n_wave_miss = 0;  // MODE 2 only
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
+  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += B) {
     int alive = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) alive |= T[s] > 0.0f;
     if (!__syncthreads_or(alive)) break;
-    const uint32_t e = b0 + tid;
-    if (e < rg.y) {
-      if (MODE == 3)
-        stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis, po->pairs, po->vstride);
-      else
-        stage_entry<TW, TH>(st, tid, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
+#pragma unroll
+    for (int off = tid; off < B; off += kBlock) {
+      const uint32_t e = b0 + off;
+      if (e < rg.y) {
+        if (MODE == 3)
+          stage_entry<TW, TH>(st, off, a.vals[e], a.rec0, a.rec1, a.rec2, vis, po->pairs, po->vstride);
+        else
+          stage_entry<TW, TH>(st, off, a.vals[e], a.rec0, a.rec1, a.rec2, vis);
+      }
     }
     __syncthreads();
     // entries of this batch; wave-uniform, kept in scalar registers
     const int cnt = __builtin_amdgcn_readfirstlane(
-        (int)((rg.y - b0) < (uint32_t)kBlock ? (rg.y - b0) : (uint32_t)kBlock));
+        (int)((rg.y - b0) < (uint32_t)B ? (rg.y - b0) : (uint32_t)B));
     uint32_t wave_alive = 0;
     // four entries per step: one 16-byte read of their delivery bits and
     // constant offsets from one record address
@@ -308,15 +319,15 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, Stage &st
 // launch: one workgroup per resident slot; each drains its XCD's queue of
 // work items in the same heavy-first order, then steals from the other XCDs'
 // queues.  Every workgroup leaves once all eight queues are exhausted.
-template <int S, int TW, int TH, int MODE, bool PERSISTENT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), 8)))
+template <int S, int TW, int TH, int MODE, bool PERSISTENT, int B = kBlock>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_per_eu<S, B>(), 8)))
 k_composite(CompositeArgs a) {
-  __shared__ Stage st;
+  __shared__ StageT<B> st;
   const int tiles = a.tiles_x * a.tiles_y;
   int kpos, grp;
   if (!PERSISTENT) {
     if (work_item(blockIdx.x, a.groups, tiles, kpos, grp))
-      composite_item<S, TW, TH, MODE>(a, st, (int)a.tile_order[kpos], grp,
+      composite_item<S, TW, TH, MODE, B>(a, st, (int)a.tile_order[kpos], grp,
                                       a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr);
     return;
   }
@@ -343,7 +354,7 @@ k_composite(CompositeArgs a) {
     __syncthreads();
     if (L < 0) break;
     work_item(L, a.groups, tiles, kpos, grp);
-    composite_item<S, TW, TH, MODE>(a, st, (int)a.tile_order[kpos], grp,
+    composite_item<S, TW, TH, MODE, B>(a, st, (int)a.tile_order[kpos], grp,
                                     a.visbits ? a.visbits + (int64_t)grp * a.P4 : nullptr);
     __syncthreads();  // the stage is reused by the next item
   }
@@ -611,95 +622,111 @@ constexpr int kPersistentItemsPerSlot = 32;
 
 // Resident workgroups of the persistent kernel, cached per instantiation
 // (host-side queries only, so a launch can be captured in a graph).
-template <int S, int TW, int TH, int MODE>
+template <int S, int TW, int TH, int MODE, int B>
 static int resident_slots() {
   static int resident = 0;
   if (!resident) {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_composite<S, TW, TH, MODE, true>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_composite<S, TW, TH, MODE, true, B>, kBlock, 0);
     resident = (cus > 0 ? cus : 256) * (per_cu > 0 ? per_cu : 1);
   }
   return resident;
 }
 
-template <int S, int TW, int TH, int MODE>
+template <int S, int TW, int TH, int MODE, int B>
 static CompositePlan plan_fwd_m(int launch, int64_t items) {
-  const int64_t resident = resident_slots<S, TW, TH, MODE>();
+  const int64_t resident = resident_slots<S, TW, TH, MODE, B>();
   CompositePlan p;
   p.items = items;
   p.persistent = launch == 1 || (launch == 0 && items >= kPersistentItemsPerSlot * resident);
   p.workgroups = p.persistent ? (resident < items ? resident : items) : items;
+  p.lds_batch = B;
   return p;
 }
 
-template <int S, int TW, int TH, int MODE>
+template <int S, int TW, int TH, int MODE, int B>
 static void launch_fwd_m(const CompositeArgs &a, int launch, int64_t items, hipStream_t st) {
-  const CompositePlan p = plan_fwd_m<S, TW, TH, MODE>(launch, items);
+  const CompositePlan p = plan_fwd_m<S, TW, TH, MODE, B>(launch, items);
   if (!p.persistent) {
-    k_composite<S, TW, TH, MODE, false><<<(unsigned)p.workgroups, kBlock, 0, st>>>(a);
+    k_composite<S, TW, TH, MODE, false, B><<<(unsigned)p.workgroups, kBlock, 0, st>>>(a);
     return;
   }
   launch_zero_queues(a.queues, st);
-  k_composite<S, TW, TH, MODE, true><<<(unsigned)p.workgroups, kBlock, 0, st>>>(a);
+  k_composite<S, TW, TH, MODE, true, B><<<(unsigned)p.workgroups, kBlock, 0, st>>>(a);
 }
 
-// Calls F::run<S, TW, TH, MODE>(args...) for the runtime shape; false if unsupported.
+// LDS batch variants: 128, 256 and 512 entries for groups of 4 or more states
+// in image and PSNR mode; 256 everywhere else (results do not depend on it).
+template <int S, int MODE>
+constexpr bool has_batch_variants() { return S >= 4 && (MODE == 0 || MODE == 1); }
+
+template <typename F, int TW, int TH, int MODE, int S, typename... A>
+static void run_b(int B, A &&...args) {
+  if constexpr (has_batch_variants<S, MODE>()) {
+    if (B == 128) { F::template run<S, TW, TH, MODE, 128>(args...); return; }
+    if (B == 512) { F::template run<S, TW, TH, MODE, 512>(args...); return; }
+  }
+  F::template run<S, TW, TH, MODE, kBlock>(args...);
+}
+
+// Calls F::run<S, TW, TH, MODE, B>(args...) for the runtime shape; false if unsupported.
 template <typename F, int TW, int TH, int MODE, typename... A>
-static bool dispatch_s(int S, A &&...args) {
+static bool dispatch_s(int S, int B, A &&...args) {
   switch (S) {
-    case 1: F::template run<1, TW, TH, MODE>(args...); return true;
-    case 2: F::template run<2, TW, TH, MODE>(args...); return true;
-    case 4: F::template run<4, TW, TH, MODE>(args...); return true;
-    case 8: F::template run<8, TW, TH, MODE>(args...); return true;
-    case 16: F::template run<16, TW, TH, MODE>(args...); return true;
-    case 32: F::template run<32, TW, TH, MODE>(args...); return true;
+    case 1: run_b<F, TW, TH, MODE, 1>(B, args...); return true;
+    case 2: run_b<F, TW, TH, MODE, 2>(B, args...); return true;
+    case 4: run_b<F, TW, TH, MODE, 4>(B, args...); return true;
+    case 8: run_b<F, TW, TH, MODE, 8>(B, args...); return true;
+    case 16: run_b<F, TW, TH, MODE, 16>(B, args...); return true;
+    case 32: run_b<F, TW, TH, MODE, 32>(B, args...); return true;
     default: return false;
   }
 }
 
 template <typename F, int TW, int TH, typename... A>
-static bool dispatch_m(int S, int mode, A &&...args) {
-  if (mode == 0) return dispatch_s<F, TW, TH, 0>(S, args...);
-  if (mode == 1) return dispatch_s<F, TW, TH, 1>(S, args...);
-  return dispatch_s<F, TW, TH, 2>(S, args...);
+static bool dispatch_m(int S, int B, int mode, A &&...args) {
+  if (mode == 0) return dispatch_s<F, TW, TH, 0>(S, B, args...);
+  if (mode == 1) return dispatch_s<F, TW, TH, 1>(S, B, args...);
+  return dispatch_s<F, TW, TH, 2>(S, B, args...);
 }
 
 template <typename F, typename... A>
-static bool dispatch_shape(int S, int tile_w, int tile_h, int mode, A &&...args) {
-  if (tile_w == 16 && tile_h == 16) return dispatch_m<F, 16, 16>(S, mode, args...);
-  if (tile_w == 32 && tile_h == 8) return dispatch_m<F, 32, 8>(S, mode, args...);
+static bool dispatch_shape(int S, int B, int tile_w, int tile_h, int mode, A &&...args) {
+  if (tile_w == 16 && tile_h == 16) return dispatch_m<F, 16, 16>(S, B, mode, args...);
+  if (tile_w == 32 && tile_h == 8) return dispatch_m<F, 32, 8>(S, B, mode, args...);
   return false;
 }
 
 struct LaunchFwd {
-  template <int S, int TW, int TH, int MODE>
+  template <int S, int TW, int TH, int MODE, int B>
   static void run(const CompositeArgs &a, int launch, int64_t items, hipStream_t st) {
-    launch_fwd_m<S, TW, TH, MODE>(a, launch, items, st);
+    launch_fwd_m<S, TW, TH, MODE, B>(a, launch, items, st);
   }
 };
 
 struct PlanFwd {
-  template <int S, int TW, int TH, int MODE>
+  template <int S, int TW, int TH, int MODE, int B>
   static void run(int launch, int64_t items, CompositePlan *out) {
-    *out = plan_fwd_m<S, TW, TH, MODE>(launch, items);
+    *out = plan_fwd_m<S, TW, TH, MODE, B>(launch, items);
   }
 };
 
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch,
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch, int lds_batch,
                      hipStream_t st) {
   const int64_t items = work_items(a.tiles_x * a.tiles_y, a.groups);
   if (items <= 0) return 0;
   if (launch != 2 && !a.queues) return 1;
-  return dispatch_shape<LaunchFwd>(S, tile_w, tile_h, mode, a, launch, items, st) ? 0 : 1;
+  return dispatch_shape<LaunchFwd>(S, lds_batch, tile_w, tile_h, mode, a, launch, items, st) ? 0 : 1;
 }
 
-int plan_composite(int S, int tile_w, int tile_h, int tiles, int groups, int launch, CompositePlan *out) {
+int plan_composite(int S, int tile_w, int tile_h, int tiles, int groups, int launch, int lds_batch,
+                   CompositePlan *out) {
   const int64_t items = work_items(tiles, groups);
-  *out = CompositePlan{false, 0, 0};
+  *out = CompositePlan{false, 0, 0, kBlock};
   if (items <= 0) return 0;
-  return dispatch_shape<PlanFwd>(S, tile_w, tile_h, 0, launch, items, out) ? 0 : 1;
+  return dispatch_shape<PlanFwd>(S, lds_batch, tile_w, tile_h, 0, launch, items, out) ? 0 : 1;
 }
 
 template <int TW, int TH>

@@ -95,8 +95,10 @@ struct CompositeArgs {
   } pair;
 };
 // mode 0: images, 1: per-tile squared error for PSNR, 2: work counters only.
-// launch 0: automatic, 1: persistent, 2: grid.
-int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch,
+// launch 0: automatic, 1: persistent, 2: grid.  lds_batch: list entries staged
+// per batch (128, 256 or 512; variants exist for S >= 4 in modes 0 and 1, 256
+// is used otherwise).
+int launch_composite(const CompositeArgs &a, int S, int tile_w, int tile_h, int mode, int launch, int lds_batch,
                      hipStream_t st);
 void launch_zero_queues(unsigned int *queues, hipStream_t st);
 // Pair mode: composites every (context, region tile) work item for the
@@ -110,8 +112,10 @@ struct CompositePlan {
   bool persistent;
   int64_t workgroups;  // workgroups launched
   int64_t items;       // (tile, state group) work items
+  int lds_batch;       // list entries staged per LDS batch by the chosen variant
 };
-int plan_composite(int S, int tile_w, int tile_h, int tiles, int groups, int launch, CompositePlan *out);
+int plan_composite(int S, int tile_w, int tile_h, int tiles, int groups, int launch, int lds_batch,
+                   CompositePlan *out);
 void launch_psnr_finalize(const float *psnr_part, int num_states, int tiles, int64_t pixels,
                           float *psnr, hipStream_t st);
 

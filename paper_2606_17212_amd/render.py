@@ -159,14 +159,16 @@ class Renderer:
     ``check()`` reports an overflow.
     """
 
-    def __init__(self, device="cuda", tile=(16, 16), states_per_group=16, slack=1.25, persistent=None):
+    def __init__(self, device="cuda", tile=(16, 16), states_per_group=16, slack=1.25, persistent=None,
+                 lds_batch=256):
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         # compositing launch: True persistent, False grid, None chosen by the library
         flags = 0 if persistent is None else (_abi.TUNE_PERSISTENT if persistent else _abi.TUNE_GRID)
-        self.tuning = _abi.Tuning(int(tile[0]), int(tile[1]), int(states_per_group), flags)
+        # list entries staged in LDS per batch (128, 256 or 512; images do not depend on it)
+        self.tuning = _abi.Tuning(int(tile[0]), int(tile[1]), int(states_per_group), flags, int(lds_batch))
         self.slack = float(slack)
         self.ws = None
         self.ws_bytes = 0
@@ -191,7 +193,8 @@ class Renderer:
         b = _abi.lib().dgs_workspace_bytes(scene.records, scene.num_packets, ctypes.byref(_c_camera(camera)),
                                            ctypes.byref(self.tuning), int(max_states), int(capacity))
         if b == 0:
-            raise ValueError("invalid arguments for dgs_workspace_bytes")
+            raise ValueError("invalid arguments for dgs_workspace_bytes: "
+                             + _abi.lib().dgs_last_error().decode())
         return int(b)
 
     def count_instances(self, scene: GaussianScene, camera: Camera, basis, params=None) -> int:
@@ -326,15 +329,16 @@ class Renderer:
 
     def launch_plan(self, camera: Camera, num_states: int):
         """How ``composite`` launches for ``num_states`` states: dict with
-        ``states_per_group``, ``persistent``, ``workgroups``, ``work_items``."""
+        ``states_per_group``, ``persistent``, ``workgroups``, ``work_items``,
+        ``lds_batch``."""
         with torch.cuda.device(self.device):
             S, pers = ctypes.c_int32(), ctypes.c_int32()
-            wg, items = ctypes.c_int64(), ctypes.c_int64()
+            wg, items, lb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
             _abi.check(_abi.lib().dgs_composite_launch(ctypes.byref(_c_camera(camera)), ctypes.byref(self.tuning),
                                                        int(num_states), ctypes.byref(S), ctypes.byref(pers),
-                                                       ctypes.byref(wg), ctypes.byref(items)))
+                                                       ctypes.byref(wg), ctypes.byref(items), ctypes.byref(lb)))
         return {"states_per_group": S.value, "persistent": bool(pers.value), "workgroups": wg.value,
-                "work_items": items.value}
+                "work_items": items.value, "lds_batch": lb.value}
 
     # ------------------------------------------------- counterfactual utility
     def _utility_args(self, scene, camera, contexts, context_group, group_pl):

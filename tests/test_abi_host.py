@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
     assert sorted(abi.EXPORTS) == decl
     for name in decl:
         assert hasattr(L, name), name
-    assert L.dgs_abi_version() == 2
+    assert L.dgs_abi_version() == 3
     assert L.dgs_status_string(3) == b"instance capacity exceeded"
 
 
@@ -60,6 +60,9 @@ def test_workspace_bytes_and_sections():
                       (abi.TUNE_PERSISTENT | abi.TUNE_GRID, False), (4, False)):
         t = abi.Tuning(16, 16, 16, flags)
         assert (L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(t), 16, 0) == b0) == ok, flags
+    for batch, ok in ((0, True), (128, True), (256, True), (512, True), (64, False), (384, False), (1024, False)):
+        t = abi.Tuning(16, 16, 16, 0, batch)
+        assert (L.dgs_workspace_bytes(1000, 32, ctypes.byref(cam), ctypes.byref(t), 16, 0) == b0) == ok, batch
     v = abi.WorkspaceView()
     assert L.dgs_workspace_sections(1000, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 100000,
                                     ctypes.byref(v)) == 0

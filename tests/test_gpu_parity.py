@@ -321,3 +321,43 @@ def test_bin_once_composite_many_and_work_counters(tiny):
     ps = r.composite_psnr(scene, cam, codes, w.basis, full[0].contiguous(), BG).cpu().numpy()
     host = oracle.psnr(full.cpu().numpy(), full[0].cpu().numpy())
     assert np.max(np.abs(ps - host)) <= 1e-3
+
+
+def test_lds_batch_sizes_give_identical_results():
+    """Staging 128, 256 or 512 list entries per LDS batch changes the batch
+    boundaries only: with tile lists of ~500 to ~5700 entries (ragged against
+    every batch size), images and final transmittances are bit-identical for
+    every tile shape, group size and launch, and match the oracle; PSNR is
+    bit-identical for a given tile shape.  Groups
+    of fewer than 4 states run the 256-entry variant whatever is asked."""
+    dgs = _dgs()
+    w = synth.subscene(12000, 96, 80, states=12, log_scale_mean=-2.2, index=9, background=BG)
+    ref = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background)
+    scene, cam, codes = on_device(w)
+    base = dgs.Renderer(tile=(16, 16), states_per_group=8)
+    bi, bt = base.render(scene, cam, codes, w.basis, BG, tfinal=True)
+    base.check()
+    ex = image_excess(bi.cpu().numpy(), ref)
+    assert ex.max() <= TOL, ex.max()
+    rng = base.sections(scene, cam, codes.shape[0])["ranges"].numpy().astype(np.int64)
+    lens = rng[:, 1] - rng[:, 0]
+    assert lens.max() > 4 * 512 and np.any(lens % 512 != 0) and np.any(lens % 128 != 0)
+    target = bi[0].contiguous()
+    for tile in ((16, 16), (32, 8)):
+        # PSNR sums per-tile partials, so its last bits depend on the tile shape only
+        bp = dgs.Renderer(tile=tile, states_per_group=8).render_psnr(scene, cam, codes, w.basis, target, BG)
+        for S in (4, 8, 32):
+            for pers in (False, True):
+                for B in (128, 512, 256):
+                    r = dgs.Renderer(tile=tile, states_per_group=S, persistent=pers, lds_batch=B)
+                    assert r.launch_plan(cam, codes.shape[0])["lds_batch"] == B
+                    img, tf = r.render(scene, cam, codes, w.basis, BG, tfinal=True)
+                    assert torch.equal(img, bi) and torch.equal(tf, bt), (tile, S, pers, B)
+                    assert torch.equal(r.render_psnr(scene, cam, codes, w.basis, target, BG), bp), (tile, S, pers, B)
+                    r.check()
+    for S in (1, 2):
+        r = dgs.Renderer(states_per_group=S, lds_batch=512)
+        assert r.launch_plan(cam, codes.shape[0])["lds_batch"] == 256
+        assert torch.equal(r.render(scene, cam, codes, w.basis, BG), bi), S
+    with pytest.raises(ValueError, match="lds_batch"):
+        dgs.Renderer(lds_batch=64).render(scene, cam, codes, w.basis, BG)
