@@ -336,7 +336,7 @@ __device__ __forceinline__ float readlane_f(float v, int g) {
 }
 
 // Instances per tile of chunk c (kChunk depth-ordered Gaussians, four waves
-// of 64), counted with LDS atomics.
+// of kWaveGauss), counted with LDS atomics.
 __global__ void __launch_bounds__(kBlock)
 k_chunk_hist(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
              const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles, uint32_t *__restrict__ chist) {
@@ -344,12 +344,12 @@ k_chunk_hist(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dva
   const int nact = n_active ? (int)*n_active : grid_n;
   for (int t = threadIdx.x; t < tiles; t += kBlock) cnt[t] = 0u;
   __syncthreads();
-  const int jb = blockIdx.x * kChunk + (threadIdx.x >> 6) * kWave;
-  const int j1 = (blockIdx.x * kChunk + kChunk) < nact ? (blockIdx.x * kChunk + kChunk) : nact;
+  const int jb = blockIdx.x * kChunk + (threadIdx.x >> 6) * kWaveGauss;
+  const int j1 = (jb + kWaveGauss) < nact ? (jb + kWaveGauss) : nact;
   if (jb < j1) {
     const WaveGaussians q = load_wave_gaussians<false>(dkey, dval, rect, jb + __lane_id(), j1, nullptr, nullptr,
                                                        nullptr);
-    const int ng = (j1 - jb) < kWave ? (j1 - jb) : kWave;
+    const int ng = j1 - jb;
     for_wave_instances(q, ng, tiles_x, [&](int, uint32_t t, uint32_t, uint32_t) { atomicAdd(&cnt[t], 1u); });
   }
   __syncthreads();
@@ -384,19 +384,19 @@ k_chunk_offsets(uint32_t *__restrict__ chist, const uint32_t *__restrict__ segsu
   }
 }
 
-// Scatter of chunk c: wave w owns Gaussians [c kChunk + 64 w, +64).  Its
+// Scatter of chunk c: wave w owns Gaussians [c kChunk + w kWaveGauss, +kWaveGauss).  Its
 // instances of tile t go after the chunk's first slot choff[c][t] and the
-// instances of tile t owned by waves < w.  ABS: the four waves' absolute next
-// slots per tile live in LDS (u32, grids up to kChunkTilesAbs tiles);
-// otherwise 16-bit relative counts (at most 64 per wave and tile) are added
-// to choff[c][t] read per instance.
-template <bool ABS>
+// instances of tile t owned by waves < w.  The four waves' next slots per tile
+// live in LDS as 16-bit counts relative to choff[c][t] (at most kWaveGauss per
+// wave and tile, so the prefix over the waves fits), which is read per
+// instance: half the LDS of absolute 32-bit slots, so twice the resident
+// workgroups (measured faster at 2,500 tiles as well as at 8,160).
 __global__ void __launch_bounds__(kBlock)
 k_chunk_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
                 const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles, int tile_w, int tile_h,
                 const float4 *__restrict__ rec0, const float4 *__restrict__ rec1, const uint2 *__restrict__ pbox,
                 const uint32_t *__restrict__ choff, const Header *__restrict__ h, uint32_t *__restrict__ tval) {
-  using Slot = typename std::conditional<ABS, uint32_t, uint16_t>::type;
+  using Slot = uint16_t;
   extern __shared__ uint32_t lds_raw[];
   Slot *rel = reinterpret_cast<Slot *>(lds_raw);  // [4][tiles]
   if (h->overflow) return;  // the ranges are empty; nothing may be written past the capacity
@@ -404,9 +404,9 @@ k_chunk_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ 
   const int w = threadIdx.x >> 6;
   for (int t = threadIdx.x; t < 4 * tiles; t += kBlock) rel[t] = 0;
   __syncthreads();
-  const int jb = blockIdx.x * kChunk + w * kWave;
-  const int j1 = (blockIdx.x * kChunk + kChunk) < nact ? (blockIdx.x * kChunk + kChunk) : nact;
-  const int ng = jb < j1 ? ((j1 - jb) < kWave ? (j1 - jb) : kWave) : 0;
+  const int jb = blockIdx.x * kChunk + w * kWaveGauss;
+  const int j1 = (jb + kWaveGauss) < nact ? (jb + kWaveGauss) : nact;
+  const int ng = jb < j1 ? j1 - jb : 0;
   const WaveGaussians q = load_wave_gaussians<true>(dkey, dval, rect, jb + __lane_id(), j1, rec0, rec1, pbox);
   Slot *mine = rel + w * tiles;
   // per-wave counts (each Gaussian's tiles are distinct; Gaussians in program order)
@@ -415,11 +415,10 @@ k_chunk_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ 
   const uint32_t *row = choff + (int64_t)blockIdx.x * tiles;
   for (int t = threadIdx.x; t < tiles; t += kBlock) {  // counts -> first slot of each wave
     const uint32_t a = rel[t], b = rel[tiles + t], c = rel[2 * tiles + t];
-    const uint32_t base = ABS ? row[t] : 0u;
-    rel[t] = (Slot)base;
-    rel[tiles + t] = (Slot)(base + a);
-    rel[2 * tiles + t] = (Slot)(base + a + b);
-    rel[3 * tiles + t] = (Slot)(base + a + b + c);
+    rel[t] = 0;
+    rel[tiles + t] = (Slot)a;
+    rel[2 * tiles + t] = (Slot)(a + b);
+    rel[3 * tiles + t] = (Slot)(a + b + c);
   }
   __syncthreads();
   // per Gaussian of the wave: the reciprocals of the reach test, once
@@ -438,7 +437,7 @@ k_chunk_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ 
     for (uint32_t k = __lane_id(); k < area; k += kWave) {
       const uint32_t dy = k / nx, tx = x0 + (k - dy * nx), ty = y0 + dy;
       const uint32_t t = ty * (uint32_t)tiles_x + tx;
-      const uint32_t slot = ABS ? (uint32_t)mine[t] : row[t] + (uint32_t)mine[t];
+      const uint32_t slot = row[t] + (uint32_t)mine[t];
       mine[t] = (Slot)(mine[t] + 1);
       // which of the tile's four 8x8 wave blocks the Gaussian reaches (as block_reach_mask)
       const int tpx = (int)tx * tile_w, tpy = (int)ty * tile_h;
@@ -477,12 +476,8 @@ void launch_chunk_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
                                                                        tiles_x, tiles, chist);
   k_chunk_segsum<<<tg, kBlock, 0, st>>>(chist, chunks, tiles, segsum);
   k_chunk_offsets<<<tg, kBlock, 0, st>>>(chist, segsum, ranges, chunks, tiles);
-  if (tiles <= kChunkTilesAbs)
-    k_chunk_scatter<true><<<chunks, kBlock, sizeof(uint32_t) * 4 * (size_t)tiles, st>>>(
-        dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
-  else
-    k_chunk_scatter<false><<<chunks, kBlock, sizeof(uint16_t) * 4 * (size_t)tiles, st>>>(
-        dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
+  k_chunk_scatter<<<chunks, kBlock, sizeof(uint16_t) * 4 * (size_t)tiles, st>>>(
+      dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
 
 }
 

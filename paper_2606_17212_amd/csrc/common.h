@@ -140,8 +140,9 @@ struct Layout {
 
 constexpr int kDiffLds = 12288;   // tile-coverage entries held in LDS (48 KB): (tiles_x + 1) (tiles_y + 1)
 constexpr int kChunk = 256;       // depth-ordered Gaussians per workgroup of the one-pass instance scatter
+constexpr int kWaveGauss = kChunk / 4;  // of them per wave (at most one per lane)
+static_assert(kWaveGauss <= 64, "one Gaussian per lane");
 constexpr int kChunkTiles = 8192; // tiles whose per-wave 16-bit counts fit one workgroup's LDS (64 KB)
-constexpr int kChunkTilesAbs = 4096;  // tiles whose per-wave 32-bit slots fit it
 constexpr int kSegChunks = 32;    // chunks per segment of its offset scan
 constexpr int kSortIpt = 16;
 constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per radix workgroup

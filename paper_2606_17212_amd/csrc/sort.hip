@@ -130,10 +130,17 @@ k_radix_up(const uint32_t *__restrict__ keys, const void *count_dev, int is_u64,
   const uint32_t mask = (1u << nbits) - 1u;
   const int64_t wbase = (int64_t)blockIdx.x * kSortTile + w * 1024;
   if (wbase < n) {
+    // all sixteen loads in flight before the first digit is ranked
+    uint32_t key[16];
+#pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t idx = wbase + r * kWave + lane;
-      const bool valid = idx < n;
-      const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
+      key[r] = idx < n ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const bool valid = wbase + r * kWave + lane < n;
+      const uint32_t d = valid ? (key[r] >> shift) & mask : 0u;
       const unsigned long long peers = match_digit(d, nbits, __ballot(valid));
       if (valid && (peers & lanemask_gt()) == 0ull) wc[w][d] += (uint32_t)__popcll(peers);
     }
@@ -165,9 +172,12 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int64_t idx = wbase + r * kWave + lane;
-    const bool valid = idx < n;
-    key[r] = valid ? kin[idx] : 0u;
-    val[r] = valid ? vin[idx] : 0u;
+    key[r] = idx < n ? kin[idx] : 0u;
+    val[r] = idx < n ? vin[idx] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const bool valid = wbase + r * kWave + lane < n;
     const uint32_t d = (key[r] >> shift) & mask;
     const unsigned long long peers = match_digit(d, nbits, __ballot(valid));
     const uint32_t before = wc[w][d];
@@ -199,7 +209,7 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t tot = 0, before = 0;
     if (d <= (int)mask) {
       const uint32_t *row = hist + (int64_t)d * nblocks;
-#pragma unroll 8
+#pragma unroll 16
       for (int b = 0; b < nblocks; ++b) {
         const uint32_t c = row[b];
         tot += c;
