@@ -517,6 +517,32 @@ int dgs_objective(const float *images, int32_t num_images, int32_t width, int32_
  * this scratch met an index out of range, else DGS_OK. */
 int dgs_objective_check(void *scratch, size_t scratch_bytes, void *stream);
 
+/*
+ * Plain photometric L1 loss, for training on a target without the Eq. (2)
+ * terms (whose distortion D, Sec. 4, is MSE + SSIM): the mean over all
+ * num_images * height * width * 3 elements of |images - targets[target_of[k]]|
+ * (target_of device int32 [num_images], or NULL: every image against target 0).
+ * dgs_l1_loss writes the loss (device float [1]; 0 for an empty batch).  Its
+ * scratch (device, 256-byte aligned, dgs_l1_scratch_bytes, 0 on invalid
+ * sizes) starts with the flag dgs_objective_check reads: a target index
+ * outside 0..num_targets-1 makes the loss NaN, and dgs_objective_check then
+ * returns DGS_ERR_INVALID_ARG.  The sum is formed in FP64 partials in a fixed
+ * order (reproducible bit for bit).
+ * dgs_l1_loss_grad writes grad [num_images][height][width][3] =
+ * dloss * sign(image - target) / (num_images * height * width * 3), sign(0) = 0,
+ * with dloss a device float [1] (the upstream gradient of the loss) or NULL
+ * for 1; NaN for an image whose target index is out of range.  Both are
+ * asynchronous on `stream`; num_images <= 65535.  Returns DGS_OK,
+ * DGS_ERR_INVALID_ARG, DGS_ERR_WORKSPACE or DGS_ERR_HIP.
+ */
+size_t dgs_l1_scratch_bytes(int32_t num_images, int32_t width, int32_t height);
+int dgs_l1_loss(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                int32_t num_targets, const int32_t *target_of, float *loss, void *scratch, size_t scratch_bytes,
+                void *stream);
+int dgs_l1_loss_grad(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                     int32_t num_targets, const int32_t *target_of, const float *dloss, float *grad, void *stream);
+
+
 #ifdef __cplusplus
 }
 #endif

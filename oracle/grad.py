@@ -243,6 +243,13 @@ def gradients_refined(scene, refine, cam, basis, codes, background, grad_image, 
     return out
 
 
+def l1_loss(image, target) -> float:
+    """Mean |C - target| over every element (the plain L1 training loss), in
+    FP64; ``target`` broadcasts against ``image``."""
+    d = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    return float(np.abs(d).mean())
+
+
 def l1_loss_grad(image, target) -> np.ndarray:
     """d/dC of mean |C - target| over every element (sign(0) = 0)."""
     d = np.asarray(image, np.float64) - np.asarray(target, np.float64)

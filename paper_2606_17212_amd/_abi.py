@@ -23,7 +23,7 @@ EXPORTS = (
     "dgs_composite_psnr", "dgs_composite_stats", "dgs_composite_launch", "dgs_utility_workspace_bytes",
     "dgs_utility_count", "dgs_utility", "dgs_utility_check", "dgs_distortion_scratch_bytes", "dgs_distortion",
     "dgs_risk_adjusted", "dgs_sample_states", "dgs_objective_scratch_bytes", "dgs_objective",
-    "dgs_objective_check",
+    "dgs_objective_check", "dgs_l1_scratch_bytes", "dgs_l1_loss", "dgs_l1_loss_grad",
 )
 
 
@@ -155,6 +155,12 @@ def lib():
                                 P(ObjectiveWeights), vp, vp, vp, vp, sz, vp]
     L.dgs_objective_check.restype = ctypes.c_int
     L.dgs_objective_check.argtypes = [vp, sz, vp]
+    L.dgs_l1_scratch_bytes.restype = sz
+    L.dgs_l1_scratch_bytes.argtypes = [i32, i32, i32]
+    L.dgs_l1_loss.restype = ctypes.c_int
+    L.dgs_l1_loss.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, vp, sz, vp]
+    L.dgs_l1_loss_grad.restype = ctypes.c_int
+    L.dgs_l1_loss_grad.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, vp, vp]
     _lib = L
     return L
 

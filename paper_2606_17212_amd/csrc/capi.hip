@@ -895,6 +895,48 @@ int dgs_objective(const float *images, int32_t num_images, int32_t width, int32_
   return hip_check("objective launch");
 }
 
+size_t dgs_l1_scratch_bytes(int32_t num_images, int32_t width, int32_t height) {
+  if (num_images < 0 || num_images > 65535 || width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
+  return l1_scratch_bytes(num_images, width, height);
+}
+
+static int check_l1(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                    int32_t num_targets) {
+  if (num_images < 0 || num_images > 65535) return fail(DGS_ERR_INVALID_ARG, "num_images %d outside 0..65535", num_images);
+  if (width < 1 || height < 1 || width > 16384 || height > 16384)
+    return fail(DGS_ERR_INVALID_ARG, "image size %dx%d outside 1..16384", width, height);
+  if (num_images > 0 && (!images || !targets || num_targets < 1))
+    return fail(DGS_ERR_INVALID_ARG, "images / targets missing");
+  return DGS_OK;
+}
+
+int dgs_l1_loss(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                int32_t num_targets, const int32_t *target_of, float *loss, void *scratch, size_t scratch_bytes,
+                void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = check_l1(images, num_images, width, height, targets, num_targets))) return rc;
+  if (!loss) return fail(DGS_ERR_INVALID_ARG, "loss is NULL");
+  if (!scratch) return fail(DGS_ERR_INVALID_ARG, "scratch is NULL");
+  if (((uintptr_t)scratch) & 255u) return fail(DGS_ERR_INVALID_ARG, "scratch not 256-byte aligned");
+  const size_t need = l1_scratch_bytes(num_images, width, height);
+  if (scratch_bytes < need) return fail(DGS_ERR_WORKSPACE, "scratch %zu bytes < %zu needed", scratch_bytes, need);
+  launch_l1_loss(images, num_images, (int64_t)width * height * 3, targets, num_targets, target_of, loss, scratch,
+                 (hipStream_t)stream);
+  return hip_check("l1 loss launch");
+}
+
+int dgs_l1_loss_grad(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
+                     int32_t num_targets, const int32_t *target_of, const float *dloss, float *grad, void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = check_l1(images, num_images, width, height, targets, num_targets))) return rc;
+  if (num_images > 0 && !grad) return fail(DGS_ERR_INVALID_ARG, "grad is NULL");
+  launch_l1_grad(images, num_images, (int64_t)width * height * 3, targets, num_targets, target_of, dloss, grad,
+                 (hipStream_t)stream);
+  return hip_check("l1 grad launch");
+}
+
 int dgs_objective_check(void *scratch, size_t scratch_bytes, void *stream) {
   g_err.clear();
   if (!scratch || scratch_bytes < sizeof(ObjHeader)) return fail(DGS_ERR_INVALID_ARG, "objective scratch missing");

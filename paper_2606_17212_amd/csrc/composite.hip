@@ -553,7 +553,9 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
         if (hit) {
           const float alpha = alpha_of(q);
           const float4 C = st.rec[k].col;
-          const float inv1ma = 1.0f / (1.0f - alpha);
+          // hardware reciprocal (about 1 ulp; 1 - alpha >= 0.01 under the cap)
+          // instead of the IEEE division sequence
+          const float inv1ma = __builtin_amdgcn_rcpf(1.0f - alpha);
           float d_alpha = 0.0f;
 #pragma unroll
           for (int s = 0; s < S; ++s) {

@@ -57,4 +57,14 @@ struct ObjArgs {
 
 void launch_objective(const ObjArgs &a, hipStream_t st);
 
+// Mean absolute error of images against their targets (the L1 training
+// loss): scratch holds an ObjHeader, then one FP64 partial per
+// (image, kL1Chunk elements).
+constexpr int kL1Chunk = 4096;  // elements per workgroup (16 per thread)
+size_t l1_scratch_bytes(int64_t K, int64_t width, int64_t height);
+void launch_l1_loss(const float *images, int K, int64_t per_image, const float *targets, int T,
+                    const int32_t *target_of, float *loss, void *scratch, hipStream_t st);
+void launch_l1_grad(const float *images, int K, int64_t per_image, const float *targets, int T,
+                    const int32_t *target_of, const float *dloss, float *grad, hipStream_t st);
+
 }  // namespace dgs

@@ -505,6 +505,113 @@ __global__ void k_obj_clear(ObjHeader *h) {
   if (threadIdx.x == 0) h->bad = 0u;
 }
 
+// ------------------------------------------------------------------ L1 loss
+// L = sum_k sum_j |x_kj - t_{target_of[k], j}| / (K n), n = H W 3 elements per
+// image.  Partials in FP64, summed in a fixed order: the loss does not depend
+// on scheduling.  An out-of-range target index sets the header's flag and
+// makes the loss (and that image's gradient) NaN; nothing is read out of
+// bounds.
+
+size_t l1_scratch_bytes(int64_t K, int64_t width, int64_t height) {
+  const int64_t chunks = ceil_div(width * height * 3, kL1Chunk);
+  return align256(sizeof(ObjHeader)) + align256(8 * (K > 0 ? K : 1) * chunks);
+}
+
+__device__ inline bool l1_target(const int32_t *target_of, int k, int T, int &t) {
+  t = target_of ? target_of[k] : 0;
+  return t >= 0 && t < T;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_l1_partial(const float *__restrict__ x, int64_t n, const float *__restrict__ tg, int T,
+             const int32_t *__restrict__ target_of, ObjHeader *h, double *__restrict__ part) {
+  const int k = blockIdx.y;
+  int t;
+  const bool ok = l1_target(target_of, k, T, t);
+  const int64_t j0 = (int64_t)blockIdx.x * kL1Chunk;
+  float s = 0.0f;
+  if (ok) {
+    const float *xi = x + (int64_t)k * n, *ti = tg + (int64_t)t * n;
+#pragma unroll 4
+    for (int64_t j = j0 + threadIdx.x; j < j0 + kL1Chunk && j < n; j += kBlock) s += fabsf(xi[j] - ti[j]);
+  }
+  double d = s;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, kWave);
+  __shared__ double w[4];
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[(int64_t)k * gridDim.x + blockIdx.x] = ok ? ((w[0] + w[1]) + (w[2] + w[3])) : __longlong_as_double(0x7FF8000000000000LL);
+    if (!ok) atomicOr(&h->bad, 1u);
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_l1_finalize(const double *__restrict__ part, int64_t np, double inv,
+                                                      float *loss) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += 1024) s += part[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+  __shared__ double w[16];
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += w[i];
+    loss[0] = (float)(t * inv);
+  }
+}
+
+__global__ void k_l1_clear(ObjHeader *h, float *loss, int empty) {
+  if (threadIdx.x == 0) {
+    h->bad = 0u;
+    if (empty) loss[0] = 0.0f;
+  }
+}
+
+void launch_l1_loss(const float *images, int K, int64_t per_image, const float *targets, int T,
+                    const int32_t *target_of, float *loss, void *scratch, hipStream_t st) {
+  ObjHeader *h = reinterpret_cast<ObjHeader *>(scratch);
+  double *part = reinterpret_cast<double *>(reinterpret_cast<char *>(scratch) + align256(sizeof(ObjHeader)));
+  const int64_t chunks = ceil_div(per_image, kL1Chunk);
+  k_l1_clear<<<1, 64, 0, st>>>(h, loss, K == 0 ? 1 : 0);
+  if (K == 0) return;
+  k_l1_partial<<<dim3((unsigned)chunks, (unsigned)K), kBlock, 0, st>>>(images, per_image, targets, T, target_of, h,
+                                                                         part);
+  k_l1_finalize<<<1, 1024, 0, st>>>(part, chunks * K, 1.0 / ((double)K * (double)per_image), loss);
+}
+
+// dL/dx = dloss sign(x - t) / (K n), sign(0) = 0; dloss NULL means 1.
+__global__ void __launch_bounds__(kBlock)
+k_l1_grad(const float *__restrict__ x, int64_t n, const float *__restrict__ tg, int T,
+          const int32_t *__restrict__ target_of, const float *dloss, float inv, float *__restrict__ g) {
+  const int k = blockIdx.y;
+  int t;
+  const bool ok = l1_target(target_of, k, T, t);
+  const float sc = (dloss ? dloss[0] : 1.0f) * inv;
+  const int64_t j0 = (int64_t)blockIdx.x * kL1Chunk;
+  const float *xi = x + (int64_t)k * n, *ti = tg + (int64_t)(ok ? t : 0) * n;
+  float *gi = g + (int64_t)k * n;
+#pragma unroll 4
+  for (int64_t j = j0 + threadIdx.x; j < j0 + kL1Chunk && j < n; j += kBlock) {
+    if (!ok) {
+      gi[j] = __int_as_float(0x7FC00000);
+      continue;
+    }
+    const float d = xi[j] - ti[j];
+    gi[j] = d > 0.0f ? sc : (d < 0.0f ? -sc : 0.0f);
+  }
+}
+
+void launch_l1_grad(const float *images, int K, int64_t per_image, const float *targets, int T,
+                    const int32_t *target_of, const float *dloss, float *grad, hipStream_t st) {
+  if (K == 0) return;
+  const int64_t chunks = ceil_div(per_image, kL1Chunk);
+  k_l1_grad<<<dim3((unsigned)chunks, (unsigned)K), kBlock, 0, st>>>(
+      images, per_image, targets, T, target_of, dloss, (float)(1.0 / ((double)K * (double)per_image)), grad);
+}
+
 // ---------------------------------------------------------------- launcher
 void launch_objective(const ObjArgs &a, hipStream_t st) {
   const SsimWeights W = ssim_weights();

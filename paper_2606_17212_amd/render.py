@@ -616,6 +616,93 @@ class ObjectiveFunction(torch.autograd.Function):
         return (None, ctx.image_grad * grad_loss, None, None, None, None, None, None)
 
 
+class L1Loss:
+    """Mean absolute error of images [K, H, W, 3] against targets [T, H, W, 3]
+    (image k against ``targets[target_of[k]]``, default all target 0) on the
+    device; keeps its scratch buffer between calls.  ``loss`` returns the
+    scalar, ``grad`` dL/d images scaled by ``dloss`` (a device scalar or
+    None for 1)."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.scratch = None
+        self.scratch_bytes = 0
+
+    def _args(self, images, targets, target_of):
+        dev = self.device
+        _check_tensor(images, "images", torch.float32, dev)
+        _check_tensor(targets, "targets", torch.float32, dev)
+        if images.dim() != 4 or images.shape[-1] != 3 or targets.dim() != 4 or \
+                tuple(targets.shape[1:]) != tuple(images.shape[1:]):
+            raise ValueError("images [K, H, W, 3] and targets [T, H, W, 3] of one image size")
+        K, H, Wd = (int(x) for x in images.shape[:3])
+        tof = None
+        if target_of is not None:
+            tof, nt = _index_tensor(target_of, "target_of", dev)
+            if nt != K:
+                raise ValueError("target_of needs one entry per image")
+        return K, H, Wd, tof
+
+    def loss(self, images, targets, target_of=None):
+        K, H, Wd, tof = self._args(images, targets, target_of)
+        L = _abi.lib()
+        nbytes = int(L.dgs_l1_scratch_bytes(K, Wd, H))
+        if nbytes == 0:
+            raise ValueError("invalid sizes for dgs_l1_loss")
+        if nbytes > self.scratch_bytes:
+            self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.scratch_bytes = nbytes
+        out = torch.empty((), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            _abi.check(L.dgs_l1_loss(_ptr(images), K, Wd, H, _ptr(targets), int(targets.shape[0]), _ptr(tof),
+                                     _ptr(out), _ptr(self.scratch), self.scratch_bytes, st))
+        return out
+
+    def grad(self, images, targets, target_of=None, dloss=None):
+        K, H, Wd, tof = self._args(images, targets, target_of)
+        if dloss is not None:
+            _check_tensor(dloss, "dloss", torch.float32, self.device)
+            if dloss.numel() != 1:
+                raise ValueError("dloss must hold one value")
+        g = torch.empty_like(images)
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            _abi.check(_abi.lib().dgs_l1_loss_grad(_ptr(images), K, Wd, H, _ptr(targets), int(targets.shape[0]),
+                                                   _ptr(tof), _ptr(dloss), _ptr(g), st))
+        return g
+
+    def check(self):
+        """Synchronise; raises DgsError if the last loss met a target index out of range."""
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            _abi.check(_abi.lib().dgs_objective_check(_ptr(self.scratch), self.scratch_bytes, st))
+
+
+class L1Function(torch.autograd.Function):
+    """The L1 loss as a differentiable function of the images: one device
+    pass for the loss, one for the gradient (scaled by the upstream
+    gradient on the device, no host synchronisation)."""
+
+    @staticmethod
+    def forward(ctx, l1, images, targets, target_of):
+        x = images.detach().contiguous()
+        ctx.l1, ctx.target_of = l1, target_of
+        ctx.save_for_backward(x, targets)
+        return l1.loss(x, targets, target_of)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        x, targets = ctx.saved_tensors
+        dl = grad_loss.detach().to(torch.float32).contiguous().reshape(1)
+        return None, ctx.l1.grad(x, targets, ctx.target_of, dl), None, None
+
+
+def l1_loss(images, targets, target_of=None, l1: Optional[L1Loss] = None):
+    """Differentiable mean |images - targets[target_of]| on the device."""
+    return L1Function.apply(l1 if l1 is not None else L1Loss(images.device), images, targets, target_of)
+
+
 def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
            background=(0, 0, 0)):
     """Differentiable render of every state in ``codes`` -> [W, H, Wd, 3]

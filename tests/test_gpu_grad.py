@@ -109,3 +109,32 @@ def test_gradients_full_size_720p_window():
     rpix = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background, pixels=pix)
     amb = pix[rpix["budget"].max(0) > 0]
     _compare(got, ref, exclude=_ambiguous_gaussians(w, amb))
+
+
+def test_batched_gradients_equal_sum_of_single_state_calls():
+    """The backward of one batched call over 8 states equals the gradients
+    accumulated over 8 calls with one state each (the batched/serial
+    equivalence of the forward, carried to the backward), up to the order of
+    the FP32 atomic sums."""
+    import paper_2606_17212_amd as dgs
+    from paper_2606_17212_amd.render import PARAMS
+    w = synth.subscene(2000, 96, 64, states=8, log_scale_mean=-2.0, background=BG)
+    dev = torch.device("cuda:0")
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(np.ascontiguousarray(w.codes)).to(dev)
+    g = torch.from_numpy(np.random.default_rng(5).normal(size=(8, 64, 96, 3)).astype(np.float32)).to(dev)
+    r = dgs.Renderer(dev, states_per_group=8)
+    p = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    sc = scene.with_params(**p)
+    (dgs.render(r, sc, cam, codes, w.basis, BG) * g).sum().backward()
+    batched = {k: v.grad.clone() for k, v in p.items()}
+    for v in p.values():
+        v.grad = None
+    for k in range(8):
+        (dgs.render(r, sc, cam, codes[k:k + 1], w.basis, BG) * g[k:k + 1]).sum().backward()
+    r.check()
+    for k in PARAMS:
+        nb = float(batched[k].norm())
+        assert nb > 0, k
+        assert float((p[k].grad - batched[k]).norm()) <= 1e-5 * nb, k

@@ -163,3 +163,61 @@ def test_training_step_gradient_flows_through_the_renderer():
                        list(range(6)), [6], [tuple(m) for m in mono])
     _compare((torch.tensor([want["loss"], want["E"], want["cvar"], want["F"], want["M"], want["anchor"]]),
               torch.tensor(want["D"]), g), want)
+
+
+def test_l1_loss_and_gradient_match_oracle():
+    """Plain L1 loss on the device against the FP64 oracle: ragged chunking
+    (37 x 53 x 3 elements per image), several targets, exact ties (sign 0),
+    an upstream scale, the autograd wrapper, an empty batch and an invalid
+    target index; reproducible bit for bit."""
+    import oracle.grad as og
+    dgs = _dgs()
+    x, t, tof = _batch(K=5, H=37, W=53, T=2, seed=11)
+    x[1, :5] = t[tof[1], :5]  # exact ties
+    l1 = dgs.L1Loss("cuda:0")
+    X, Tt = _dev(x), _dev(t)
+    loss = l1.loss(X, Tt, tof)
+    l1.check()
+    want = og.l1_loss(x, t[tof])
+    assert abs(float(loss) - want) <= 1e-6 * want
+    assert torch.equal(loss, l1.loss(X, Tt, tof))
+    g = l1.grad(X, Tt, tof).cpu().numpy().astype(np.float64)
+    gw = og.l1_loss_grad(x, t[tof])
+    assert np.array_equal(np.sign(g), np.sign(gw))
+    assert np.allclose(g, gw, rtol=1e-6, atol=0)
+    assert np.all(g[1, :5] == 0.0)
+    scale = torch.tensor([2.5], device="cuda:0")
+    assert np.allclose(l1.grad(X, Tt, tof, dloss=scale).cpu().numpy(), 2.5 * gw, rtol=1e-6, atol=0)
+    # default target_of: every image against target 0
+    assert abs(float(l1.loss(X, Tt)) - og.l1_loss(x, t[:1])) <= 1e-6 * og.l1_loss(x, t[:1])
+    # autograd: the image gradient of 3 L equals 3 dL/dx
+    Xr = X.clone().requires_grad_(True)
+    (3.0 * dgs.l1_loss(Xr, Tt, tof, l1)).backward()
+    assert np.allclose(Xr.grad.cpu().numpy(), 3.0 * gw, rtol=1e-6, atol=0)
+    # empty batch
+    assert float(l1.loss(X[:0], Tt, np.zeros(0, np.int32))) == 0.0
+    # invalid target index: NaN loss and gradient for that image, reported by check
+    bad = tof.copy()
+    bad[2] = 7
+    assert torch.isnan(l1.loss(X, Tt, bad))
+    with pytest.raises(dgs.DgsError):
+        l1.check()
+    gb = l1.grad(X, Tt, bad).cpu().numpy()
+    assert np.isnan(gb[2]).all() and np.isfinite(gb[[0, 1, 3, 4]]).all()
+
+
+def test_l1_loss_at_training_size():
+    """8 images of 1280x720 against one target: loss within 1e-6 relative of
+    the FP64 oracle, gradient signs exact."""
+    import oracle.grad as og
+    dgs = _dgs()
+    rng = np.random.default_rng(21)
+    t = rng.uniform(0, 1, (1, 720, 1280, 3)).astype(np.float32)
+    x = np.clip(t + rng.normal(0, 0.05, (8, 720, 1280, 3)), 0, 1).astype(np.float32)
+    l1 = dgs.L1Loss("cuda:0")
+    X, Tt = _dev(x), _dev(t)
+    want = og.l1_loss(x, t)
+    assert abs(float(l1.loss(X, Tt)) - want) <= 1e-6 * want
+    g = l1.grad(X, Tt)
+    d = X - Tt
+    assert torch.equal(torch.sign(g), torch.sign(d))

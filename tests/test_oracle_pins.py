@@ -468,6 +468,28 @@ def test_psnr_definition():
     assert p[2] == pytest.approx(40.0)
 
 
+def test_l1_loss_and_gradient():
+    """Plain L1 loss: a hand-computed value, sign(0) = 0 in the gradient, and
+    the gradient against central differences of the value away from ties."""
+    import oracle.grad as og
+    img = np.array([[[[0.5, 0.25, 1.0]], [[0.0, 0.75, 0.5]]]])  # [1, 2, 1, 3]
+    tgt = np.array([[[[0.25, 0.25, 0.0]], [[0.5, 0.5, 0.5]]]])
+    # |d| = 0.25, 0, 1, 0.5, 0.25, 0 -> mean 2 / 6
+    assert og.l1_loss(img, tgt) == pytest.approx(2.0 / 6.0, abs=1e-15)
+    g = og.l1_loss_grad(img, tgt)
+    assert np.array_equal(g.reshape(-1) * 6, [1, 0, 1, -1, 1, 0])
+    rng = np.random.default_rng(2)
+    x, t = rng.uniform(0, 1, (3, 4, 5, 3)), rng.uniform(0, 1, (1, 4, 5, 3))
+    g = og.l1_loss_grad(x, t)
+    h = 1e-7
+    for idx in [(0, 0, 0, 0), (1, 2, 3, 1), (2, 3, 4, 2)]:
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (og.l1_loss(xp, t) - og.l1_loss(xm, t)) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6)
+
+
 # --------------------------------------------------------- stored fixtures
 
 def test_golden_oracle_regression():
