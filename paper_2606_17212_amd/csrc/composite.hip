@@ -474,9 +474,11 @@ __device__ __forceinline__ float row_sum_to_lane15(float x) {
 
 // Per tile the forward is replayed front to back with bit-identical
 // arithmetic (same alphas, same transmittance updates, same stop), so no
-// per-pixel list is stored.  The colour behind entry k comes from the final
-// colour minus the running prefix: rem_k = C_final - sum_{j<=k} T_j a_j c_j,
-// which includes T_final * background.  Per state and entry:
+// per-pixel list is stored.  The colour behind entry k is the final colour
+// minus the running prefix, rem_k = C_final - sum_{j<=k} T_j a_j c_j (which
+// includes T_final * background); only its dot product with g = dL/dC enters,
+// so each state keeps the scalar g . rem_k, starting from g . C_final and
+// lowered by T_k a_k (g . c_k) at each entry.  Per state and entry:
 //   dL/dc_k     = g T_k a_k
 //   dL/da_k     = T_k (g . c_k) - (g . rem_k) / (1 - a_k)
 // summed over the group's states; then, below the 0.99 cap, through
@@ -501,19 +503,21 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
   const int64_t plane = (int64_t)a.width * a.height;
   const int64_t pix = (int64_t)py * a.width + px;
 
-  float T[S], rr[S], rgn[S], rb[S], gr[S], gg[S], gb[S];
+  // per state: transmittance, dL/dC, and g . rem (the colour still to come
+  // behind the current entry, dotted with dL/dC) as one scalar
+  float T[S], grem[S], gr[S], gg[S], gb[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int slot = grp * S + s;
     const bool ok = inside && slot < a.num_states;
     const int w = ok ? (a.state_order ? (int)a.state_order[slot] : slot) : 0;
     T[s] = ok ? 1.0f : -1.0f;
-    rr[s] = rgn[s] = rb[s] = gr[s] = gg[s] = gb[s] = 0.0f;
+    grem[s] = gr[s] = gg[s] = gb[s] = 0.0f;
     if (ok) {
       const float *im = a.image + ((int64_t)w * plane + pix) * 3;
       const float *gi = a.grad_image + ((int64_t)w * plane + pix) * 3;
-      rr[s] = im[0]; rgn[s] = im[1]; rb[s] = im[2];
       gr[s] = gi[0]; gg[s] = gi[1]; gb[s] = gi[2];
+      grem[s] = fmaf(gr[s], im[0], fmaf(gg[s], im[1], gb[s] * im[2]));
     }
   }
 
@@ -561,13 +565,9 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
           for (int s = 0; s < S; ++s) {
             if (uv & (1u << s)) {
               const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
-              rr[s] = fmaf(-ta, C.x, rr[s]);
-              rgn[s] = fmaf(-ta, C.y, rgn[s]);
-              rb[s] = fmaf(-ta, C.z, rb[s]);
-              const float gcol = gr[s] * C.x + gg[s] * C.y + gb[s] * C.z;
-              const float grem = gr[s] * rr[s] + gg[s] * rgn[s] + gb[s] * rb[s];
-              const float Tp = fmaxf(T[s], 0.0f);
-              const float da = Tp * gcol - grem * inv1ma;
+              const float gcol = fmaf(gr[s], C.x, fmaf(gg[s], C.y, gb[s] * C.z));
+              grem[s] = fmaf(-ta, gcol, grem[s]);  // g . rem_k
+              const float da = fmaf(fmaxf(T[s], 0.0f), gcol, -grem[s] * inv1ma);
               d_alpha += (T[s] > 0.0f) ? da : 0.0f;
               dcr = fmaf(gr[s], ta, dcr);
               dcg = fmaf(gg[s], ta, dcg);
