@@ -487,10 +487,13 @@ __device__ __forceinline__ float row_sum_to_lane15(float x) {
 // waves and added to the Gaussian's 2D gradient with one atomic per value
 // and entry.
 constexpr int kBwdWindow = 64;  // entries per fold of the backward's per-wave gradient sums
-constexpr int kBwdVals = 12;    // nine values, padded to a 16-byte multiple
+constexpr int kBwdVals = 9;     // nine values per entry
+// Six waves per SIMD: the stage (17 KB) and the window sums (9 KB) let six
+// workgroups share a CU's 160 KB of LDS, and at most 80 VGPRs fit six waves.
 
 template <int S, int TW, int TH>
-__global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_composite_bwd(CompositeBwdArgs a) {
   int kpos, grp;
   if (!work_item(blockIdx.x, a.groups, a.tiles_x * a.tiles_y, kpos, grp)) return;
   const int tile = (int)a.tile_order[kpos];
@@ -567,13 +570,15 @@ __global__ void __launch_bounds__(kBlock) k_composite_bwd(CompositeBwdArgs a) {
               const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
               const float gcol = fmaf(gr[s], C.x, fmaf(gg[s], C.y, gb[s] * C.z));
               grem[s] = fmaf(-ta, gcol, grem[s]);  // g . rem_k
-              const float da = fmaf(fmaxf(T[s], 0.0f), gcol, -grem[s] * inv1ma);
-              d_alpha += (T[s] > 0.0f) ? da : 0.0f;
+              // zero for a stopped state: T <= 0, and its g . rem was cleared at the stop
+              d_alpha += fmaf(fmaxf(T[s], 0.0f), gcol, -grem[s] * inv1ma);
               dcr = fmaf(gr[s], ta, dcr);
               dcg = fmaf(gg[s], ta, dcg);
               dcb = fmaf(gb[s], ta, dcb);
               const float Tn = T[s] - ta;
-              T[s] = (Tn < kTStop) ? -fabsf(Tn) : Tn;
+              const bool stop = Tn < kTStop;
+              T[s] = stop ? -fabsf(Tn) : Tn;
+              grem[s] = stop ? 0.0f : grem[s];
             }
           }
           // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap passes nothing
