@@ -46,6 +46,7 @@ def parse():
                          "draining per-XCD work queues (auto: the library decides)")
     ap.add_argument("--no-per-state", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
+    ap.add_argument("--no-train-step", action="store_true", help="skip the Eq. (2) training-step leg")
     ap.add_argument("--no-serial-fwdbwd", action="store_true",
                     help="skip the 2.7M-Gaussian fwd+bwd leg: 32 states batched vs one state per call")
     ap.add_argument("--no-cpu", action="store_true")
@@ -219,7 +220,8 @@ def main():
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)
-        out["train_step"] = train_step(dgs, synth, torch, np, dev, args)
+        if not args.no_train_step:
+            out["train_step"] = train_step(dgs, synth, torch, np, dev, args)
         if not args.no_serial_fwdbwd:
             out["fwd_bwd_batched_vs_serial"] = fwd_bwd_batched_vs_serial(dgs, synth, torch, np, dev)
 
@@ -286,6 +288,8 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
            "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
            "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
 
+    if args.no_refined:
+        return out
     # the same step with three refinement levels (gradients for base and levels)
     levels = synth.make_refinement(w.scene, index=w.index)
     rs = dgs.GaussianScene.from_arrays(w.scene, dev, refine=levels)
