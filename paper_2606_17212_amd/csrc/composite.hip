@@ -570,26 +570,32 @@ k_composite_bwd(CompositeBwdArgs a) {
               const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
               const float gcol = fmaf(gr[s], C.x, fmaf(gg[s], C.y, gb[s] * C.z));
               grem[s] = fmaf(-ta, gcol, grem[s]);  // g . rem_k
-              // zero for a stopped state: T <= 0, and its g . rem was cleared at the stop
-              d_alpha += fmaf(fmaxf(T[s], 0.0f), gcol, -grem[s] * inv1ma);
+              // zero for a stopped state (T and g . rem both cleared at the stop)
+              // and for a lane outside the image (T = -1, g = 0)
+              d_alpha += fmaf(T[s], gcol, -grem[s] * inv1ma);
               dcr = fmaf(gr[s], ta, dcr);
               dcg = fmaf(gg[s], ta, dcg);
               dcb = fmaf(gb[s], ta, dcb);
               const float Tn = T[s] - ta;
               const bool stop = Tn < kTStop;
-              T[s] = stop ? -fabsf(Tn) : Tn;
+              // the replay needs T only for T alpha (zero once stopped, as in
+              // the forward's -T_final) and the liveness tests
+              T[s] = stop ? 0.0f : Tn;
               grem[s] = stop ? 0.0f : grem[s];
             }
           }
-          // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap passes nothing
+          // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap
+          // passes nothing.  dq'/du = 2 A' dx + B' dy and dq'/dv = B' dx + 2 C' dy
+          // are linear in (dx, dy) with entry constants, so the lanes sum
+          // dq dx and dq dy (in the gu, gv slots) and the fold applies A', B', C'.
           if (alpha < kAlphaMax) {
             const float dq = d_alpha * alpha * 0.69314718055994531f;
             const float dx = P0.x - fpx, dy = P0.y - fpy;
-            gu = dq * (2.0f * P0.w * dx + P1.x * dy);
-            gv = dq * (P1.x * dx + 2.0f * P1.y * dy);
-            gA = dq * dx * dx;
-            gB = dq * dx * dy;
-            gC = dq * dy * dy;
+            gu = dq * dx;
+            gv = dq * dy;
+            gA = gu * dx;
+            gB = gu * dy;
+            gC = gv * dy;
             glo = dq;
           }
         }
@@ -611,9 +617,17 @@ k_composite_bwd(CompositeBwdArgs a) {
       }
       __syncthreads();
       // fold the four waves; one atomic per value and entry for the workgroup
+      // (values 0 and 1 from the sums of dq dx and dq dy)
       for (int i = tid; i < (w1 - w0) * 9; i += kBlock) {
         const int k = i / 9, v = i - k * 9;
-        const float sum = red[0][k][v] + red[1][k][v] + red[2][k][v] + red[3][k][v];
+        float sum = red[0][k][v] + red[1][k][v] + red[2][k][v] + red[3][k][v];
+        if (v < 2) {
+          const int o = v ^ 1;
+          const float other = red[0][k][o] + red[1][k][o] + red[2][k][o] + red[3][k][o];
+          const StageRec &r = st.rec[w0 + k];
+          // v = 0: 2 A' Sx + B' Sy;  v = 1: B' Sx + 2 C' Sy
+          sum = v == 0 ? fmaf(2.0f * r.p0.w, sum, r.p1.x * other) : fmaf(r.p1.x, other, 2.0f * r.p1.y * sum);
+        }
         if (sum != 0.0f) unsafeAtomicAdd(a.g2d + (int64_t)v * a.n + st.id[w0 + k], sum);
       }
       __syncthreads();  // sums read before the next window clears them
