@@ -131,3 +131,36 @@ def test_python_binding_validates_tensors():
         _c_scene(sc.with_params(color=torch.zeros(12, 5)))
     with pytest.raises(TypeError):
         _c_scene(sc.with_params(mean=torch.zeros(3, 5, dtype=torch.float64)))
+
+
+def test_loss_entry_points_validate_before_any_launch():
+    """L1 loss and Eq. (2) objective: sizes and pointers are checked on the
+    host (no device pointer is touched when a check fails)."""
+    abi, L = _lib()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced
+    assert L.dgs_l1_scratch_bytes(8, 1280, 720) > 0
+    assert L.dgs_l1_scratch_bytes(-1, 16, 16) == 0 and L.dgs_l1_scratch_bytes(1, 0, 16) == 0
+    assert L.dgs_l1_scratch_bytes(65536, 16, 16) == 0
+    need = L.dgs_l1_scratch_bytes(2, 16, 16)
+    loss = ctypes.c_void_p(1 << 21)
+    # bad sizes, missing targets, missing loss / scratch, misaligned or short scratch
+    assert L.dgs_l1_loss(fake, -1, 16, 16, fake, 1, None, loss, fake, need, None) == 1
+    assert L.dgs_l1_loss(fake, 2, 0, 16, fake, 1, None, loss, fake, need, None) == 1
+    assert L.dgs_l1_loss(fake, 2, 16, 16, None, 1, None, loss, fake, need, None) == 1
+    assert L.dgs_l1_loss(fake, 2, 16, 16, fake, 0, None, loss, fake, need, None) == 1
+    assert L.dgs_l1_loss(fake, 2, 16, 16, fake, 1, None, None, fake, need, None) == 1
+    assert L.dgs_l1_loss(fake, 2, 16, 16, fake, 1, None, loss, None, need, None) == 1
+    assert L.dgs_l1_loss(fake, 2, 16, 16, fake, 1, None, loss, ctypes.c_void_p((1 << 20) + 4), need, None) == 1
+    assert b"aligned" in L.dgs_last_error()
+    assert L.dgs_l1_loss(fake, 2, 16, 16, fake, 1, None, loss, fake, need - 1, None) == 2
+    assert L.dgs_l1_loss_grad(fake, 2, 16, 16, fake, 1, None, None, None, None) == 1
+    assert b"grad" in L.dgs_last_error()
+    # objective: alpha outside (0, 1] and negative weights are refused
+    w = abi.ObjectiveWeights(0.2, 0.3, 0.0, 0.1, 2.0, 0.5)
+    ob = L.dgs_objective_scratch_bytes(2, 16, 16, 0)
+    assert ob > 0
+    assert L.dgs_objective(fake, 2, 16, 16, fake, 1, fake, fake, 1, None, 0, None, 0, None, 0, ctypes.byref(w),
+                           loss, None, None, fake, ob, None) == 1
+    w = abi.ObjectiveWeights(0.2, -0.3, 0.05, 0.1, 2.0, 0.5)
+    assert L.dgs_objective(fake, 2, 16, 16, fake, 1, fake, fake, 1, None, 0, None, 0, None, 0, ctypes.byref(w),
+                           loss, None, None, fake, ob, None) == 1
