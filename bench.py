@@ -185,7 +185,8 @@ def main():
                       "contexts": w.scene.num_contexts, "tile": f"{tw}x{th}",
                       "states_per_group": args.states_per_group, "instances": M},
            "batched": {"bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4),
-                       "timed_as": "hip graph replay" if graph is not None else "eager launches"}}
+                       "timed_as": "hip graph replay" if graph is not None else "eager launches",
+                       "step_ms": distribution([e[0].elapsed_time(e[2]) for e in ev], np)}}
 
     if not args.no_per_state:
         # plain per-state render, synchronized after every state
@@ -239,6 +240,18 @@ def main():
     return 0
 
 
+def distribution(times, np):
+    """Median, mean with its Student-t 95% interval, and percentiles of a
+    list of per-iteration times (ms)."""
+    from scipy import stats
+    t = np.asarray(times, np.float64)
+    n = t.size
+    half = float(stats.t.ppf(0.975, n - 1) * t.std(ddof=1) / np.sqrt(n)) if n > 1 else float("nan")
+    return {"n": int(n), "median": round(float(np.median(t)), 4), "mean": round(float(t.mean()), 4),
+            "ci95_half_width": round(half, 4),
+            "p5_p25_p75_p95": [round(float(np.percentile(t, q)), 4) for q in (5, 25, 75, 95)]}
+
+
 def fwd_bwd(dgs, synth, torch, np, dev, args):
     """Forward + L1 loss + backward to the six parameter tensors on the
     250k-Gaussian 1280x720 8-state workload; the target is the full-delivery
@@ -286,7 +299,8 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
     log(f"[bench] fwd+bwd {name}: median {np.median(times):.3f} ms/iter, loss {float(loss.detach()):.5f}")
     out = {"workload": name, "gaussians": w.scene.n, "width": cam.width, "height": cam.height,
            "states": int(codes.shape[0]), "ms_per_iter": round(float(np.median(times)), 4),
-           "ms_per_iter_all": [round(t, 4) for t in times], "grads_finite": finite}
+           "ms_per_iter_all": [round(t, 4) for t in times], "distribution": distribution(times, np),
+           "grads_finite": finite}
 
     if args.no_refined:
         return out
