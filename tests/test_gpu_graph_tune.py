@@ -44,6 +44,59 @@ def test_graph_replays_equal_eager_every_time(dev_workload):
     scene.opacity_logit.copy_(old)
 
 
+def test_training_step_graph_replays_match_eager(dev_workload):
+    """Forward + L1 + backward captured in one graph (torch whole-step
+    capture through the C ABI): every replay, with eager work of the same
+    renderer and synchronisations in between, reproduces the eager
+    gradients up to the order of the FP32 atomics."""
+    import paper_2606_17212_amd as dgs
+    from paper_2606_17212_amd.render import PARAMS
+    w, scene, cam, codes = dev_workload
+    dev = codes.device
+    r = dgs.Renderer(states_per_group=8)
+    full = torch.full((1, w.scene.num_packets), 4, dtype=torch.uint8, device=dev)
+    target = r.render(scene, cam, full, w.basis, BG)[:1].clone() * 0.9
+    params = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    sc = scene.with_params(**params)
+    l1 = dgs.L1Loss(dev)
+
+    def it():
+        dgs.l1_loss(dgs.render(r, sc, cam, codes, w.basis, BG), target, None, l1).backward()
+
+    it()
+    torch.cuda.synchronize()
+    ref = {k: p.grad.clone() for k, p in params.items()}
+    # the captured step uses its own leaf tensors, never used on the default
+    # stream (a leaf whose gradient node was created on another stream and is
+    # still alive does not capture cleanly)
+    params = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    sc = scene.with_params(**params)
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            for p in params.values():
+                p.grad = None
+            it()
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    for p in params.values():
+        p.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        it()
+    for rep in range(4):
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in PARAMS:
+            nb = float(ref[k].norm())
+            assert nb > 0 and float((params[k].grad - ref[k]).norm()) <= 1e-5 * nb, (rep, k)
+        # eager work on the same renderer (its workspace) between replays
+        r.render(scene, cam, codes[:3].contiguous(), w.basis, BG)
+        r.check()
+    del graph
+
+
 def test_graph_psnr_replays(dev_workload):
     import paper_2606_17212_amd as dgs
     w, scene, cam, codes = dev_workload
