@@ -368,14 +368,40 @@ k_chunk_segsum(const uint32_t *__restrict__ chist, int chunks, int tiles, uint32
   segsum[(int64_t)sg * tiles + t] = s;
 }
 
+// segsum[s][t] <- instances of tile t in segments before s (exclusive
+// prefix over segments).  A workgroup takes 16 tiles; 16 threads per tile
+// split the segments into 16 parts (reads coalesced across the 16 tiles):
+// part totals, their prefix in LDS, then each part rewritten in order.
+constexpr int kScanTiles = 16, kScanParts = kBlock / kScanTiles;
+__global__ void __launch_bounds__(kBlock)
+k_chunk_segscan(uint32_t *__restrict__ segsum, int nseg, int tiles) {
+  __shared__ uint32_t part[kScanParts][kScanTiles + 1];
+  const int tl = threadIdx.x % kScanTiles, pp = threadIdx.x / kScanTiles;
+  const int t = blockIdx.x * kScanTiles + tl;
+  const int per = (nseg + kScanParts - 1) / kScanParts;
+  const int k0 = pp * per, k1 = (k0 + per) < nseg ? (k0 + per) : nseg;
+  uint32_t sum = 0;
+  if (t < tiles)
+    for (int k = k0; k < k1; ++k) sum += segsum[(int64_t)k * tiles + t];
+  part[pp][tl] = sum;
+  __syncthreads();
+  uint32_t run = 0;
+  for (int q = 0; q < pp; ++q) run += part[q][tl];
+  if (t < tiles)
+    for (int k = k0; k < k1; ++k) {
+      const uint32_t v = segsum[(int64_t)k * tiles + t];
+      segsum[(int64_t)k * tiles + t] = run;
+      run += v;
+    }
+}
+
 // chist[c][t] <- ranges[t].x + instances of tile t in chunks before c.
 __global__ void __launch_bounds__(kBlock)
 k_chunk_offsets(uint32_t *__restrict__ chist, const uint32_t *__restrict__ segsum, const uint2 *__restrict__ ranges,
                 int chunks, int tiles) {
   const int t = blockIdx.x * kBlock + threadIdx.x, sg = blockIdx.y;
   if (t >= tiles) return;
-  uint32_t base = ranges[t].x;
-  for (int k = 0; k < sg; ++k) base += segsum[(int64_t)k * tiles + t];
+  uint32_t base = ranges[t].x + segsum[(int64_t)sg * tiles + t];
   const int c0 = sg * kSegChunks, c1 = (c0 + kSegChunks) < chunks ? (c0 + kSegChunks) : chunks;
   for (int c = c0; c < c1; ++c) {
     const uint32_t v = chist[(int64_t)c * tiles + t];
@@ -475,6 +501,7 @@ void launch_chunk_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
   k_chunk_hist<<<chunks, kBlock, sizeof(uint32_t) * (size_t)tiles, st>>>(dkey, dval, rect, n_active, grid_n,
                                                                        tiles_x, tiles, chist);
   k_chunk_segsum<<<tg, kBlock, 0, st>>>(chist, chunks, tiles, segsum);
+  k_chunk_segscan<<<(unsigned)ceil_div(tiles, kScanTiles), kBlock, 0, st>>>(segsum, nseg, tiles);
   k_chunk_offsets<<<tg, kBlock, 0, st>>>(chist, segsum, ranges, chunks, tiles);
   k_chunk_scatter<<<chunks, kBlock, sizeof(uint16_t) * 4 * (size_t)tiles, st>>>(
       dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
