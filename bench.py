@@ -73,8 +73,8 @@ def log(*a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported in this build "
-              "(states shard across GPUs with no exchange in the forward; see DESIGN.md)",
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (delivery states would "
+              "shard across GPUs, each rendering its share with no exchange in the forward)",
               file=sys.stderr)
         return 2
 
