@@ -68,10 +68,11 @@ ObjLayout make_obj_layout(int64_t K, int64_t width, int64_t height, int64_t Q) {
 
 // ------------------------------------------------------------- moments
 // One 16x16 block of one image.  The three channels of the 26x26 apron are
-// read at once (12 contiguous bytes per pixel), the horizontal 11-tap pass
-// of the five window sums runs for all channels with two adjacent output
-// columns per task (12 reads for 22 taps), then the vertical pass, SSIM and
-// the coefficient maps per channel.  Three barriers in all.
+// read at once (12 contiguous bytes per pixel); then per channel the
+// horizontal 11-tap pass of the five window sums (two adjacent output columns
+// per task: 12 reads for 22 taps) and the vertical pass, SSIM and the
+// coefficient maps.  One channel's horizontal sums at a time keep the
+// workgroup at 24.5 KB of LDS (six per CU instead of three).
 constexpr int kObjAW = 16 + 2 * kSsimR, kObjAH = 16 + 2 * kSsimR, kObjA = kObjAW * kObjAH;
 
 // Horizontal 11-tap sums of rows r of `in` (apron layout) for output columns
@@ -92,8 +93,8 @@ __device__ __forceinline__ void hpass2(const float *__restrict__ in, const SsimW
 
 __global__ void __launch_bounds__(kBlock) k_obj_moments(ObjArgs a, SsimWeights W) {
   __shared__ float xs[3][kObjA], ys[3][kObjA];
-  // horizontal sums per channel: x, y, xx, yy, xy over (26 rows x 16 columns)
-  __shared__ float hs[3][5][kObjAH * 16];
+  // horizontal sums of one channel: x, y, xx, yy, xy over (26 rows x 16 columns)
+  __shared__ float hs[5][kObjAH * 16];
   __shared__ float red[4];
   const int blk = blockIdx.x, k = blockIdx.y;
   const int tx = blk % a.bx, ty = blk / a.bx;
@@ -116,50 +117,51 @@ __global__ void __launch_bounds__(kBlock) k_obj_moments(ObjArgs a, SsimWeights W
     ys[0][q] = w0; ys[1][q] = w1; ys[2][q] = w2;
   }
   __syncthreads();
-  for (int task = threadIdx.x; task < 3 * kObjAH * 8; task += kBlock) {
-    const int c = task / (kObjAH * 8), rem = task % (kObjAH * 8), r = rem / 8, cx = (rem % 8) * 2;
-    const float *xr = &xs[c][r * kObjAW + cx], *yr = &ys[c][r * kObjAW + cx];
-    float m0 = 0, m1 = 0, n0 = 0, n1 = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0, s0 = 0, s1 = 0;
-#pragma unroll
-    for (int d = 0; d <= 2 * kSsimR + 1; ++d) {
-      const float xv = xr[d], yv = yr[d];
-      const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
-      if (d <= 2 * kSsimR) {
-        const float wd = W.w[d];
-        m0 = fmaf(wd, xv, m0); n0 = fmaf(wd, yv, n0); p0 = fmaf(wd, xx, p0); q0 = fmaf(wd, yy, q0);
-        s0 = fmaf(wd, xy, s0);
-      }
-      if (d >= 1) {
-        const float wd = W.w[d - 1];
-        m1 = fmaf(wd, xv, m1); n1 = fmaf(wd, yv, n1); p1 = fmaf(wd, xx, p1); q1 = fmaf(wd, yy, q1);
-        s1 = fmaf(wd, xy, s1);
-      }
-    }
-    const int o = r * 16 + cx;
-    hs[c][0][o] = m0; hs[c][0][o + 1] = m1;
-    hs[c][1][o] = n0; hs[c][1][o + 1] = n1;
-    hs[c][2][o] = p0; hs[c][2][o + 1] = p1;
-    hs[c][3][o] = q0; hs[c][3][o + 1] = q1;
-    hs[c][4][o] = s0; hs[c][4][o + 1] = s1;
-  }
-  __syncthreads();
   const int ox = threadIdx.x % 16, oy = threadIdx.x / 16;
   const int px = tx * 16 + ox, py = ty * 16 + oy;
+  const bool inpx = px < a.width && py < a.height;
   float se = 0.0f, ss = 0.0f;
-  if (px < a.width && py < a.height) {
-    float mp[9];
+  float mp[9];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 3; ++c) {
+    for (int task = threadIdx.x; task < kObjAH * 8; task += kBlock) {
+      const int r = task / 8, cx = (task % 8) * 2;
+      const float *xr = &xs[c][r * kObjAW + cx], *yr = &ys[c][r * kObjAW + cx];
+      float m0 = 0, m1 = 0, n0 = 0, n1 = 0, p0 = 0, p1 = 0, q0 = 0, q1 = 0, s0 = 0, s1 = 0;
+#pragma unroll
+      for (int d = 0; d <= 2 * kSsimR + 1; ++d) {
+        const float xv = xr[d], yv = yr[d];
+        const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
+        if (d <= 2 * kSsimR) {
+          const float wd = W.w[d];
+          m0 = fmaf(wd, xv, m0); n0 = fmaf(wd, yv, n0); p0 = fmaf(wd, xx, p0); q0 = fmaf(wd, yy, q0);
+          s0 = fmaf(wd, xy, s0);
+        }
+        if (d >= 1) {
+          const float wd = W.w[d - 1];
+          m1 = fmaf(wd, xv, m1); n1 = fmaf(wd, yv, n1); p1 = fmaf(wd, xx, p1); q1 = fmaf(wd, yy, q1);
+          s1 = fmaf(wd, xy, s1);
+        }
+      }
+      const int o = r * 16 + cx;
+      hs[0][o] = m0; hs[0][o + 1] = m1;
+      hs[1][o] = n0; hs[1][o + 1] = n1;
+      hs[2][o] = p0; hs[2][o + 1] = p1;
+      hs[3][o] = q0; hs[3][o + 1] = q1;
+      hs[4][o] = s0; hs[4][o + 1] = s1;
+    }
+    __syncthreads();
+    if (inpx) {
       float mx = 0, my = 0, exx = 0, eyy = 0, exy = 0;
 #pragma unroll
       for (int d = 0; d <= 2 * kSsimR; ++d) {
         const int q = (oy + d) * 16 + ox;
         const float wd = W.w[d];
-        mx = fmaf(wd, hs[c][0][q], mx);
-        my = fmaf(wd, hs[c][1][q], my);
-        exx = fmaf(wd, hs[c][2][q], exx);
-        eyy = fmaf(wd, hs[c][3][q], eyy);
-        exy = fmaf(wd, hs[c][4][q], exy);
+        mx = fmaf(wd, hs[0][q], mx);
+        my = fmaf(wd, hs[1][q], my);
+        exx = fmaf(wd, hs[2][q], exx);
+        eyy = fmaf(wd, hs[3][q], eyy);
+        exy = fmaf(wd, hs[4][q], exy);
       }
       const int ai = (oy + kSsimR) * kObjAW + ox + kSsimR;
       const float dv = xs[c][ai] - ys[c][ai];
@@ -178,6 +180,9 @@ __global__ void __launch_bounds__(kBlock) k_obj_moments(ObjArgs a, SsimWeights W
       mp[3 * c + 1] = ds_sxx;
       mp[3 * c + 2] = ds_sxy;
     }
+    __syncthreads();  // the next channel overwrites the horizontal sums
+  }
+  if (inpx) {
     float *dst = a.maps + ((int64_t)k * plane + (int64_t)py * a.width + px) * 9;
 #pragma unroll
     for (int j = 0; j < 9; ++j) dst[j] = mp[j];
