@@ -121,10 +121,11 @@ def geometry_f64(scene, cam, basis) -> dict:
 
 def mirror_f32(scene, cam, basis, tile_w: int = 16, tile_h: int = 16) -> dict:
     """FP32 integer decisions: depth z32 (+ its uint32 bits), u, v, a, b, c,
-    tile rectangle [x0, y0, x1, y1) and validity."""
+    the conic scaled for the base-2 exponent (cA, cB, cC: q' = cA dx^2 +
+    cB dx dy + cC dy^2), tile rectangle [x0, y0, x1, y1) and validity."""
     pin = _Pinned(scene, cam)
     n = scene.mean.shape[1]
-    f = np.zeros((6, max(n, 1)), dtype=np.float32)
+    f = np.zeros((9, max(n, 1)), dtype=np.float32)
     r = np.zeros((4, max(n, 1)), dtype=np.int32)
     v = np.zeros(max(n, 1), dtype=np.int32)
     b = _f32(basis) if len(basis) else np.zeros(1, np.float32)
@@ -137,7 +138,7 @@ def mirror_f32(scene, cam, basis, tile_w: int = 16, tile_h: int = 16) -> dict:
     z32 = f[0, :n].copy()
     return dict(z32=z32, zbits=z32.view(np.uint32), u=f[1, :n].copy(), v=f[2, :n].copy(),
                 a=f[3, :n].copy(), b=f[4, :n].copy(), c=f[5, :n].copy(),
-                rect=r[:, :n].copy(), valid=v[:n].astype(bool), tile_w=tile_w, tile_h=tile_h)
+                cA=f[6, :n].copy(), cB=f[7, :n].copy(), cC=f[8, :n].copy(), rect=r[:, :n].copy(), valid=v[:n].astype(bool), tile_w=tile_w, tile_h=tile_h)
 
 
 def tile_lists(mirror: dict, width: int, height: int, present=None):

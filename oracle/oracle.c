@@ -115,12 +115,14 @@ static inline float clampf(float x, float lo, float hi) {
  *   b = ((V00 V10) v0 + (V01 V11) v1) + (V02 V12) v2
  *   c = (((V10 V10) v0 + (V11 V11) v1) + (V12 V12) v2) + 0.3
  *   det = a c - b b
+ *   A = c / det, B = -b / det, C = a / det;
+ *   A' = kA A, B' = kB B, C' = kA C with kA = fl32(-log2(e)/2), kB = fl32(-log2(e))
  *   ex = sqrt(11.1 a), ey = sqrt(11.1 c)
  *   x0 = clamp(floor((u - ex)/TW), 0, tiles_x), x1 = clamp(floor((u + ex)/TW) + 1, 0, tiles_x)
  *   (y likewise with TH, tiles_y); TW, TH powers of two.
  */
 static void mirror_one(const or_scene *s, const or_camera *cam, const float *basis,
-                       int tile_w, int tile_h, int64_t i, float *f6, int32_t *r4,
+                       int tile_w, int tile_h, int64_t i, float *f9, int32_t *r4,
                        int32_t *valid) {
   const int64_t n = s->n;
   float m0 = s->mean[i], m1 = s->mean[n + i], m2 = s->mean[2 * n + i];
@@ -179,9 +181,12 @@ static void mirror_one(const or_scene *s, const or_camera *cam, const float *bas
   float b = ((V[0] * V[3]) * vs[0] + (V[1] * V[4]) * vs[1]) + (V[2] * V[5]) * vs[2];
   float c = (((V[3] * V[3]) * vs[0] + (V[4] * V[4]) * vs[1]) + (V[5] * V[5]) * vs[2]) + 0.3f;
   float det = a * c - b * b;
+  const float kA = -0x1.715476p-1f, kB = -0x1.715476p+0f; /* -log2(e)/2, -log2(e) in FP32 */
+  float cA = c / det, cB = -b / det, cC = a / det;
 
   int ok = (Z > cam->near_z) && (det > 0.0f);
-  f6[0] = Z; f6[1] = u; f6[2] = v; f6[3] = a; f6[4] = b; f6[5] = c;
+  f9[0] = Z; f9[1] = u; f9[2] = v; f9[3] = a; f9[4] = b; f9[5] = c;
+  f9[6] = kA * cA; f9[7] = kB * cB; f9[8] = kA * cC;
   *valid = ok;
   r4[0] = r4[1] = r4[2] = r4[3] = 0;
   if (!ok) return;
@@ -197,16 +202,16 @@ static void mirror_one(const or_scene *s, const or_camera *cam, const float *bas
 }
 
 int or_mirror_f32(const or_scene *s, const or_camera *cam, const float *basis,
-                  int tile_w, int tile_h, float *out_f /*[6][n]*/, int32_t *rect /*[4][n]*/,
+                  int tile_w, int tile_h, float *out_f /*[9][n]*/, int32_t *rect /*[4][n]*/,
                   int32_t *valid /*[n]*/) {
   const int64_t n = s->n;
   if (tile_w <= 0 || tile_h <= 0 || (tile_w & (tile_w - 1)) || (tile_h & (tile_h - 1))) return 1;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    float f6[6];
+    float f9[9];
     int32_t r4[4], ok;
-    mirror_one(s, cam, basis, tile_w, tile_h, i, f6, r4, &ok);
-    for (int k = 0; k < 6; ++k) out_f[k * n + i] = f6[k];
+    mirror_one(s, cam, basis, tile_w, tile_h, i, f9, r4, &ok);
+    for (int k = 0; k < 9; ++k) out_f[k * n + i] = f9[k];
     for (int k = 0; k < 4; ++k) rect[k * n + i] = r4[k];
     valid[i] = ok;
   }
@@ -339,7 +344,9 @@ int or_geometry_f64(const or_scene *s, const or_camera *cam, const float *basis,
 typedef struct {
   uint32_t zbits;
   int32_t id;
-  double alpha;
+  double alpha; /* FP64 alpha (the definition) */
+  double rho;   /* bound on |alpha_32 / alpha - 1| of an FP32 renderer */
+  int amb;      /* an FP32 renderer may take the other side of the 1/255 skip */
 } cand_t;
 
 static int cand_cmp(const void *pa, const void *pb) {
@@ -350,18 +357,57 @@ static int cand_cmp(const void *pa, const void *pb) {
 
 #define ALPHA_MIN (1.0 / 255.0)
 #define T_STOP 1e-4
-#define AMB_REL 1e-3 /* relative window of the FP32/FP64 ambiguity test */
+
+/*
+ * Ambiguity budget: where an FP32 renderer may legitimately take the other
+ * branch of a discrete decision, and by how much its image may then differ.
+ *
+ * The FP32 renderer evaluates, per (Gaussian, pixel), the base-2 exponent
+ *     q' = A' dx^2 + B' dx dy + C' dy^2 + l,   dx = u - (px + 0.5), dy likewise,
+ * from its FP32 record (u, v, A', B', C') -- the values or_mirror_f32 computes,
+ * in the same operation order -- and its FP32 log2-opacity l; it skips the
+ * pair when q' < fl32(log2(1/255)), uses alpha = min(fl32(0.99), 2^q') (the
+ * hardware base-2 exponential), then T alpha and T - T alpha, each rounded
+ * once, and stops when T - T alpha < fl32(1e-4).
+ *
+ * Bounds (EPS = 2^-24, the FP32 unit roundoff):
+ *  - qg = the exponent from the mirror's FP32 record and the FP64 log2(o),
+ *    evaluated in FP64 (exact to ~1e-16).  The renderer's q' differs from qg
+ *    by at most E = EVAL_ROUNDINGS EPS S + DLO: the rounding of dx and of the
+ *    five products / fused adds of the quadratic form, each at most EPS of a
+ *    partial sum bounded by S = |A'| dx^2 + |B' dx dy| + |C'| dy^2 + |l|,
+ *    plus DLO, the error of the record's log2-opacity (hardware exp and log;
+ *    the GPU tests check every record against DLO).
+ *  - skip: the definition skips iff alpha < 1/255; the renderer's decision
+ *    can differ only if qg - E < fl32(log2(1/255)) <= qg + E disagrees with
+ *    it.  A skip that may flip adds 2 T alpha M (with or without the
+ *    Gaussian the colour differs by T alpha (c - colour behind it)) and lets
+ *    T differ by the factor 1 - alpha (relative alpha / (1 - alpha)).
+ *  - alpha: |alpha_32 / alpha - 1| <= rho = (2^(|qg - q64| + E) - 1)(1 + XR) + XR,
+ *    with q64 = log2 of the FP64 alpha and XR = 2^-22 for the hardware 2^x
+ *    (1 ulp, doubled); rho = XR where both sides surely take the 0.99 cap
+ *    (|fl32(0.99) - 0.99| < XR).
+ *  - transmittance: after a composited alpha the relative error of T grows
+ *    multiplicatively by (1 + EPS)(1 + (alpha / (1 - alpha)) ((1 + rho)(1 + EPS) - 1))
+ *    (rounding of T alpha and of T - T alpha, and the alpha error).
+ *  - stop: the definition stops iff T_after < 1e-4; the renderer's T lies in
+ *    T_after (1 +- relT); a stop that may flip adds 2 T_after (1 + relT) M
+ *    (what the rest of the list and the background can contribute).
+ *  M = max |colour| over the pixel's candidates and |background|, + 2^-16 for
+ *  the FP32 colour.
+ */
+#define EPS32 (1.0 / 16777216.0)
+#define EVAL_ROUNDINGS 8.0
+#define DLO (1.0 / 65536.0)
+#define EXP_REL (1.0 / 4194304.0)
 
 /*
  * Render npix pixels (pix_xy = x,y pairs; NULL = every pixel, row-major) for
  * num_states states.  Outputs, indexed [w][k]:
  *   image  [W][npix][3]  composited colour incl. background
  *   tfinal [W][npix]     transmittance after the last composited Gaussian
- *   budget [W][npix]     ambiguity budget: the largest change an FP32
- *                        renderer may legitimately show because an alpha sits
- *                        within AMB_REL of 1/255 (skip may flip: 2 T alpha M)
- *                        or T within the running relative window of 1e-4
- *                        (stop may flip: 2 T M), M = max |colour|, |bg|
+ *   budget [W][npix]     ambiguity budget (above): the largest change an FP32
+ *                        renderer may legitimately show at the pixel
  *   ncomp  [W][npix]     number of composited Gaussians (present pairs)
  */
 int or_render(const or_scene *s, const or_camera *cam, const float *basis, int num_states,
@@ -371,7 +417,7 @@ int or_render(const or_scene *s, const or_camera *cam, const float *basis, int n
   const int64_t n = s->n;
   const int P = s->num_packets;
   double *geo = (double *)malloc(sizeof(double) * G_NF * (size_t)(n > 0 ? n : 1));
-  float *mf = (float *)malloc(sizeof(float) * 6 * (size_t)(n > 0 ? n : 1));
+  float *mf = (float *)malloc(sizeof(float) * 9 * (size_t)(n > 0 ? n : 1));
   int32_t *rect = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(n > 0 ? n : 1));
   int32_t *valid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   if (!geo || !mf || !rect || !valid) {
@@ -383,6 +429,10 @@ int or_render(const or_scene *s, const or_camera *cam, const float *basis, int n
   const int Wd = cam->width;
   double bgd[3] = {bg[0], bg[1], bg[2]};
   double bgmax = fmax(fabs(bgd[0]), fmax(fabs(bgd[1]), fabs(bgd[2])));
+  const double log2e = 1.0 / log(2.0);
+  const double qskip32 = (double)(float)(-log2(255.0)); /* the FP32 renderer's skip threshold */
+  const double tstop32 = (double)1e-4f;                 /* and its stop threshold */
+  const double log2cap32 = log2((double)0.99f);         /* 2^q' above this: alpha_32 = fl32(0.99) */
   int err = 0;
 
 #pragma omp parallel
@@ -405,39 +455,59 @@ int or_render(const or_scene *s, const or_camera *cam, const float *basis, int n
         double dx = geo[G_U * n + i] - cxp, dy = geo[G_V * n + i] - cyp;
         double q = geo[G_CA * n + i] * dx * dx + 2.0 * geo[G_CB * n + i] * dx * dy +
                    geo[G_CC * n + i] * dy * dy;
-        double al = geo[G_O * n + i] * exp(-0.5 * q);
+        double o = geo[G_O * n + i];
+        double al = o * exp(-0.5 * q);
         if (al > 0.99) al = 0.99;
-        if (al < ALPHA_MIN * (1.0 - AMB_REL)) continue;
+        /* the FP32 renderer's exponent, from the mirror's record */
+        double lo = log2(o);
+        double fx = (double)mf[1 * n + i] - cxp, fy = (double)mf[2 * n + i] - cyp;
+        double tA = (double)mf[6 * n + i] * fx * fx, tB = (double)mf[7 * n + i] * fx * fy;
+        double tC = (double)mf[8 * n + i] * fy * fy;
+        double qg = tA + tB + tC + lo;
+        double E = EVAL_ROUNDINGS * EPS32 * (fabs(tA) + fabs(tB) + fabs(tC) + fabs(lo)) + DLO;
+        int skip = al < ALPHA_MIN;
+        int amb = skip ? (qg + E >= qskip32) : (qg - E < qskip32);
+        if (skip && !amb) continue;
+        double q64 = lo - 0.5 * log2e * q; /* log2 of the uncapped FP64 alpha */
         uint32_t zb;
         memcpy(&zb, &mf[i], 4);
         cand[nc].zbits = zb;
         cand[nc].id = (int32_t)i;
         cand[nc].alpha = al;
+        /* both sides surely capped: alpha_32 = fl32(0.99) against 0.99 */
+        int capped = (q64 >= log2(0.99)) && (qg - E - EXP_REL > log2cap32);
+        cand[nc].rho = capped ? EXP_REL : (exp2(fabs(qg - q64) + E) - 1.0) * (1.0 + EXP_REL) + EXP_REL;
+        cand[nc].amb = amb;
         ++nc;
         for (int ch = 0; ch < 3; ++ch) colmax = fmax(colmax, fabs(geo[(G_R + ch) * n + i]));
       }
       qsort(cand, (size_t)nc, sizeof(cand_t), cand_cmp);
+      const double M = colmax + DLO;
       for (int w = 0; w < num_states; ++w) {
         const uint8_t *cw = codes + (int64_t)w * P;
-        double T = 1.0, C[3] = {0.0, 0.0, 0.0}, B = 0.0, rel = AMB_REL;
+        double T = 1.0, C[3] = {0.0, 0.0, 0.0}, B = 0.0, relT = 0.0;
         int32_t cnt = 0;
         for (int64_t j = 0; j < nc; ++j) {
           int32_t i = cand[j].id;
           uint16_t pl = s->packet_layer[i];
           if ((int)(pl & 3u) >= (int)cw[pl >> 2]) continue; /* not delivered */
           double al = cand[j].alpha;
-          int amb = fabs(al - ALPHA_MIN) <= AMB_REL * ALPHA_MIN;
-          if (amb) {
-            B += 2.0 * T * al * colmax;
-            rel += al;
+          double odds = al / (1.0 - al);
+          if (cand[j].amb) {
+            B += 2.0 * T * al * M;
+            relT = (1.0 + relT) * (1.0 + odds) - 1.0;
           }
           if (al < ALPHA_MIN) continue;
           for (int ch = 0; ch < 3; ++ch) C[ch] += T * al * geo[(G_R + ch) * n + i];
           double Ta = T * (1.0 - al);
           ++cnt;
-          if (fabs(Ta - T_STOP) <= rel * T_STOP) B += 2.0 * Ta * colmax;
+          relT = (1.0 + relT) * (1.0 + EPS32) *
+                     (1.0 + odds * ((1.0 + cand[j].rho) * (1.0 + EPS32) - 1.0)) - 1.0;
+          int stop = Ta < T_STOP;
+          int amb_stop = stop ? (Ta * (1.0 + relT) >= tstop32) : (Ta * (1.0 - relT) < tstop32);
+          if (amb_stop) B += 2.0 * Ta * (1.0 + relT) * M;
           T = Ta;
-          if (T < T_STOP) break;
+          if (stop) break;
         }
         for (int ch = 0; ch < 3; ++ch) C[ch] += T * bgd[ch];
         int64_t o = (int64_t)w * npix + k;

@@ -182,6 +182,96 @@ def test_alpha_cap_and_skip():
     assert np.all(r["image"][0] == BG.astype(np.float64)) and np.all(r["ncomp"] == 0)
 
 
+# ------------------------------------------------ ambiguity budget pins
+# The budget marks (state, pixel) pairs where an FP32 renderer may take the
+# other branch of the 1/255 skip or of the T < 1e-4 stop, and bounds the image
+# change: 2 T alpha M for a skip, 2 T_after (1 + relT) M for a stop, M = the
+# largest |colour| or |background| (+ 2^-16).  The skip window is the FP32
+# exponent's error bound: for a Gaussian seen at its own centre (dx = dy = 0)
+# it is 8 2^-24 |log2 o| + 2^-16 in log2 units, i.e. about 1.3e-5 relative in
+# alpha -- so an alpha 2e-6 from 1/255 is ambiguous and one 1e-4 away is not.
+
+def _at_centre(alphas, cols, zs=None):
+    """Gaussians on the optical axis seen at pixel (8, 8), whose centre is the
+    principal point: |dx|, |dy| are rounding-level, so alpha = o to ~1e-7."""
+    cam = centred_camera(16, 16, cx=8.5, cy=8.5)
+    zs = [-0.5 + 0.1 * k for k in range(len(alphas))] if zs is None else zs
+    sc = _axis_scene(zs, alphas, cols)
+    r = oracle.render(sc, cam, BASIS0, np.ones((1, 1), np.uint8), BG, pixels=np.array([[8, 8]]))
+    return sc, r
+
+
+def _m(cols):
+    return max(max(abs(c) for col in cols for c in col), float(np.max(np.abs(BG64)))) + 2.0 ** -16
+
+
+@pytest.mark.parametrize("rel,amb", [(2e-6, True), (-2e-6, True), (1e-4, False), (-1e-4, False),
+                                     (5e-4, False)])
+def test_budget_skip_window(rel, amb):
+    cols = [[0.9, 0.1, 0.3]]
+    sc, r = _at_centre([(1 + rel) / 255.0], cols)
+    a = _o(sc.opacity_logit[0])
+    assert abs(a * 255.0 - 1.0 - rel) < 5e-7  # FP32 logit moves alpha by < 4e-7
+    B = r["budget"][0, 0]
+    if amb:
+        assert B == pytest.approx(2.0 * a * _m(cols), rel=1e-6)
+    else:
+        assert B == 0.0
+    # the definition itself: composited iff alpha >= 1/255
+    assert r["ncomp"][0, 0] == (1 if a >= 1 / 255 else 0)
+
+
+def test_budget_stop_window():
+    cols = [[0.2, 0.4, 0.6], [0.7, 0.1, 0.5], [0.3, 0.3, 0.9]]
+    # two capped alphas leave T = (1 - 0.99)^2 = 1e-4 (+2e-18): either side of the stop
+    sc, r = _at_centre([0.9999, 0.9999], cols[:2])
+    Ta = (1 - 0.99) ** 2
+    assert r["ncomp"][0, 0] == 2 and r["tfinal"][0, 0] == pytest.approx(Ta, rel=1e-12)
+    assert r["budget"][0, 0] == pytest.approx(2.0 * Ta * _m(cols[:2]), rel=1e-3)
+    # T far from 1e-4 after each composited Gaussian: no budget
+    sc, r = _at_centre([0.9999, 0.95, 0.9], cols)
+    assert r["ncomp"][0, 0] == 3 and r["budget"][0, 0] == 0.0
+    sc, r = _at_centre([0.9999, 0.5], cols[:2])
+    assert r["budget"][0, 0] == 0.0
+
+
+def _third_alpha(t1, target):
+    """alpha of a third Gaussian that takes T from t1 * 0.01 to target."""
+    return 1.0 - target / (t1 * (1 - 0.99))
+
+
+def test_budget_earlier_ambiguous_skip_widens_stop_window():
+    """T after three Gaussians lands 0.25% above 1e-4.  Alone, that is outside
+    the stop window (whose width is the alphas' FP32 error, ~1e-3 here); after
+    a Gaussian whose skip may flip (changing T by up to alpha / (1 - alpha) =
+    0.4%) it is inside, and the stop term appears."""
+    cols = [[0.2, 0.4, 0.6], [0.7, 0.1, 0.5], [0.3, 0.3, 0.9]]
+    target = 1e-4 * (1 + 2.5e-3)
+    # ambiguous first alpha (2e-6 above 1/255)
+    a1 = (1 + 2e-6) / 255.0
+    sc, r = _at_centre([a1, 0.9999, _third_alpha(1 - a1, target)], cols)
+    o1 = _o(sc.opacity_logit[0])
+    T = (1 - o1) * (1 - 0.99) * (1 - _o(sc.opacity_logit[2]))
+    assert T == pytest.approx(target, rel=1e-5) and r["ncomp"][0, 0] == 3
+    skip_term = 2.0 * o1 * _m(cols)
+    B = r["budget"][0, 0]
+    assert 2.0 * T * _m(cols) < B - skip_term < 2.02 * T * _m(cols)
+    # the same T after a first alpha that is clearly above 1/255: no budget at all
+    a1 = 1.05 / 255.0
+    sc, r = _at_centre([a1, 0.9999, _third_alpha(1 - a1, target)], cols)
+    T = (1 - _o(sc.opacity_logit[0])) * (1 - 0.99) * (1 - _o(sc.opacity_logit[2]))
+    assert T == pytest.approx(target, rel=1e-5) and r["budget"][0, 0] == 0.0
+
+
+def test_budget_share_on_the_tiny_workload():
+    """On the 4,096-Gaussian 128x128 16-state workload the budget excuses
+    fewer than 0.1% of (state, pixel) pairs, none by more than 0.01."""
+    w = synth.make_workload("g4k_128px_16states", background=BG)
+    B = oracle.render(w.scene, w.camera, w.basis, w.codes, w.background)["budget"]
+    assert 0 < (B > 0).mean() < 1e-3
+    assert B.max() < 1e-2
+
+
 # ------------------------------------------------------ P4-P7 invariants
 
 @pytest.fixture(scope="module")
