@@ -34,6 +34,21 @@ int hip_check(const char *where) {
   return DGS_OK;
 }
 
+// Entry points that copy a header to the host and wait for it cannot be part
+// of a captured graph: they refuse a stream that is being captured (before
+// any launch), instead of leaving the capture invalid.
+int refuse_capture(hipStream_t st, const char *what) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DGS_ERR_HIP, "%s: capture status of the stream: %s", what, hipGetErrorString(e));
+  }
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(DGS_ERR_INVALID_ARG, "%s synchronises with the host and cannot run under graph capture", what);
+  return DGS_OK;
+}
+
 struct Tiling {
   int tw, th, tiles_x, tiles_y, tiles, tile_bits;
 };
@@ -75,6 +90,8 @@ int check_camera(const dgs_camera *cam) {
     if (!isfinite(cam->t_cw[k])) return fail(DGS_ERR_INVALID_ARG, "t_cw not finite");
   if (!isfinite(cam->cx) || !isfinite(cam->cy) || !isfinite(cam->near_z))
     return fail(DGS_ERR_INVALID_ARG, "principal point / near plane not finite");
+  // a non-positive near plane would let depths at or behind the camera through
+  if (!(cam->near_z > 0.0f)) return fail(DGS_ERR_INVALID_ARG, "near_z %g must be positive", (double)cam->near_z);
   return DGS_OK;
 }
 
@@ -403,12 +420,14 @@ int dgs_count_instances(const dgs_scene *scene, const dgs_camera *cam, const dgs
                         const dgs_tuning *tun, void *ws, size_t ws_bytes, int64_t *instances, void *stream) {
   g_err.clear();
   if (!instances) return fail(DGS_ERR_INVALID_ARG, "instances is NULL");
+  if (!states) return fail(DGS_ERR_INVALID_ARG, "states is NULL");
   dgs_states st0 = *states;
   st0.num_states = 0;  // no per-state buffers needed
   Call cl;
   int rc = prepare(scene, cam, &st0, tun, ws, ws_bytes, 0, 0, &cl);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  if ((rc = refuse_capture(st, "dgs_count_instances"))) return rc;
   Header *h = at<Header>(ws, cl.L.header);
   launch_clear_header(h, 0ull, st);
   project_and_count(cl, ws, false, st);
@@ -667,6 +686,8 @@ int dgs_check(void *ws, size_t ws_bytes, int64_t *instances, void *stream) {
   g_err.clear();
   if (!ws || ws_bytes < sizeof(Header)) return fail(DGS_ERR_INVALID_ARG, "workspace missing");
   hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = refuse_capture(st, "dgs_check"))) return rc;
   Header hh;
   if (hipMemcpyAsync(&hh, ws, sizeof(Header), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -700,6 +721,7 @@ int dgs_utility_count(const dgs_scene *scene, const dgs_camera *cam, const dgs_s
                            uws_bytes, 0, &cl, &u);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  if ((rc = refuse_capture(st, "dgs_utility_count"))) return rc;
   utility_setup(cl, ws, u, contexts, group_pl, num_groups, st);
   UtilHeader h;
   if (hipMemcpyAsync(&h, u.hdr, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -754,6 +776,8 @@ int dgs_utility_check(void *uws, size_t uws_bytes, int64_t item_capacity, int64_
   g_err.clear();
   if (!uws || uws_bytes < sizeof(UtilHeader)) return fail(DGS_ERR_INVALID_ARG, "utility workspace missing");
   hipStream_t st = (hipStream_t)stream;
+  int rc0;
+  if ((rc0 = refuse_capture(st, "dgs_utility_check"))) return rc0;
   UtilHeader h;
   if (hipMemcpyAsync(&h, uws, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -941,6 +965,8 @@ int dgs_objective_check(void *scratch, size_t scratch_bytes, void *stream) {
   g_err.clear();
   if (!scratch || scratch_bytes < sizeof(ObjHeader)) return fail(DGS_ERR_INVALID_ARG, "objective scratch missing");
   hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = refuse_capture(st, "dgs_objective_check"))) return rc;
   ObjHeader h;
   if (hipMemcpyAsync(&h, scratch, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)

@@ -104,6 +104,15 @@ def _check_tensor(t, name, dtype, device):
         raise ValueError(f"{name} must be on {device}, got {t.device}")
 
 
+def _refuse_capture(what: str, device=None):
+    """Calls that wait for the device (a header copied to the host, a
+    synchronisation, an allocation-sized plan) cannot be recorded in a HIP
+    graph; refuse them with a clear error while the current stream captures."""
+    if torch.cuda.is_available() and torch.cuda.is_current_stream_capturing():
+        raise RuntimeError(f"{what} synchronises with the host and cannot run while the current stream is "
+                           "being captured into a graph; call it before the capture")
+
+
 def _c_scene(s: GaussianScene, params=None) -> _abi.Scene:
     p = params or {k: getattr(s, k) for k in PARAMS}
     dev = p["mean"].device
@@ -116,6 +125,11 @@ def _c_scene(s: GaussianScene, params=None) -> _abi.Scene:
     for k, shp in shapes.items():
         if tuple(p[k].shape) != shp:
             raise ValueError(f"{k} has shape {tuple(p[k].shape)}, expected {shp}")
+    if s.cluster_affine is not None:
+        _check_tensor(s.cluster_affine, "cluster_affine", torch.float32, dev)
+        if s.cluster_affine.numel() != 12 * s.num_clusters or s.cluster_affine.shape[0] != s.num_clusters:
+            raise ValueError(f"cluster_affine has shape {tuple(s.cluster_affine.shape)}, "
+                             f"expected ({s.num_clusters}, 12) or ({s.num_clusters}, 3, 4)")
     if s.refine is not None:
         _check_tensor(s.refine, "refine", torch.float32, dev)
         shp = (3, 11 + (3 if s.sh_degree == 0 else 12), n)
@@ -178,6 +192,7 @@ class Renderer:
         self.uws = None       # utility workspace
         self.utility_capacity = 0
         self._key = None
+        self.live_captures = 0  # CapturedRender graphs holding pointers into the workspace
 
     # ---------------------------------------------------------------- planning
     def _stream(self):
@@ -185,6 +200,9 @@ class Renderer:
 
     def _ensure_ws(self, nbytes):
         if self.ws is None or self.ws_bytes < nbytes:
+            if self.live_captures:
+                raise RuntimeError(f"the workspace must grow to {int(nbytes)} bytes, but {self.live_captures} "
+                                   "captured graph(s) hold pointers into it; close() them first")
             # 256-byte aligned device buffer (torch's caching allocator aligns to 512)
             self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
             self.ws_bytes = int(nbytes)
@@ -198,6 +216,7 @@ class Renderer:
         return int(b)
 
     def count_instances(self, scene: GaussianScene, camera: Camera, basis, params=None) -> int:
+        _refuse_capture("Renderer.count_instances")
         L = _abi.lib()
         cam = _c_camera(camera)
         self._ensure_ws(self.workspace_bytes(scene, camera, 0, 0))
@@ -210,6 +229,10 @@ class Renderer:
         return int(m.value)
 
     def plan(self, scene: GaussianScene, camera: Camera, basis, max_states: int, params=None) -> int:
+        _refuse_capture("Renderer.plan")
+        if self.live_captures:
+            raise RuntimeError(f"{self.live_captures} captured graph(s) hold pointers into this renderer's "
+                               "workspace and capacity; close() them before planning again")
         m = self.count_instances(scene, camera, basis, params)
         cap = max(int(m * self.slack) + 1024, 1024)
         cap = min(cap, 0xFFFFFFFF)
@@ -226,6 +249,7 @@ class Renderer:
     def sections(self, scene: GaussianScene, camera: Camera, num_states: int) -> dict:
         """Intermediate results of the last render (synchronises): per-record
         data and rectangles, per-tile ranges and the sorted ids."""
+        _refuse_capture("Renderer.sections")
         v = _abi.WorkspaceView()
         _abi.check(_abi.lib().dgs_workspace_sections(
             scene.records, scene.num_packets, ctypes.byref(_c_camera(camera)), ctypes.byref(self.tuning),
@@ -248,6 +272,7 @@ class Renderer:
     def check(self) -> int:
         """Synchronise and return the last binning's instance count; raises
         DgsError on overflow."""
+        _refuse_capture("Renderer.check")
         m = ctypes.c_int64(0)
         _abi.check(_abi.lib().dgs_check(_ptr(self.ws), self.ws_bytes, ctypes.byref(m), self._stream()))
         return int(m.value)
@@ -319,6 +344,7 @@ class Renderer:
     def composite_stats(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis):
         """(alpha evaluations, blends, wave evaluations, wave misses) one
         ``composite`` of ``codes`` performs after the last ``bin`` (synchronises)."""
+        _refuse_capture("Renderer.composite_stats")
         self._codes(codes, scene)
         cnt = torch.zeros(4, dtype=torch.int64, device=self.device)
         _abi.check(_abi.lib().dgs_composite_stats(
@@ -360,6 +386,7 @@ class Renderer:
     def utility_items(self, scene: GaussianScene, camera: Camera, contexts: torch.Tensor,
                       context_group: torch.Tensor, group_pl: torch.Tensor, basis) -> int:
         """Work items ``utility`` needs (synchronises; uses the last ``bin``)."""
+        _refuse_capture("Renderer.utility_items")
         self._utility_args(scene, camera, contexts, context_group, group_pl)
         G, J = int(group_pl.shape[0]), int(contexts.shape[0])
         nbytes = self._ensure_uws(scene, camera, G, J, 0)
@@ -396,6 +423,7 @@ class Renderer:
     def utility_check(self) -> int:
         """Synchronise; work items of the last ``utility``; raises DgsError on
         an invalid group or context or an item overflow."""
+        _refuse_capture("Renderer.utility_check")
         items = ctypes.c_int64(0)
         _abi.check(_abi.lib().dgs_utility_check(_ptr(self.uws), self.uws.numel(), self.utility_capacity,
                                                 ctypes.byref(items), self._stream()))
@@ -462,6 +490,10 @@ class RenderFunction(torch.autograd.Function):
         p = dict(zip(PARAMS, params))
         r = ctx.renderer
         if r.generation != ctx.generation:
+            # another call reused the workspace between this forward and its
+            # backward; rebuilding the lists is a render of its own, which a
+            # captured training step must not hide inside its backward
+            _refuse_capture("a re-render in RenderFunction.backward (the workspace was reused after the forward)")
             r.render(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, params=p)
         g = r.backward(ctx.scene, ctx.camera, ctx.codes, ctx.basis, ctx.background, img, grad_image, params=p)
         out = tuple(g[k] for k in PARAMS) + ((g["refine"],) if len(params) > len(PARAMS) else ())
@@ -596,6 +628,7 @@ class Objective:
 
     def check(self):
         """Synchronise; raises DgsError if the last call met an index out of range."""
+        _refuse_capture("Objective.check")
         with torch.cuda.device(self.device):
             st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
             _abi.check(_abi.lib().dgs_objective_check(_ptr(self.scratch), self.scratch_bytes, st))
@@ -674,6 +707,7 @@ class L1Loss:
 
     def check(self):
         """Synchronise; raises DgsError if the last loss met a target index out of range."""
+        _refuse_capture("L1Loss.check")
         with torch.cuda.device(self.device):
             st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
             _abi.check(_abi.lib().dgs_objective_check(_ptr(self.scratch), self.scratch_bytes, st))
@@ -720,7 +754,8 @@ class CapturedRender:
 
     The scene, codes and reference tensors are read at every replay, so their
     contents may change between replays (not their shapes or addresses).  The
-    renderer must not be re-planned while the graph is alive."""
+    graph holds the renderer's workspace (kept alive here); until ``close()``
+    the renderer refuses to plan again or to replace that workspace."""
 
     def __init__(self, renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis,
                  background=(0, 0, 0), reference: Optional[torch.Tensor] = None):
@@ -750,8 +785,27 @@ class CapturedRender:
         with torch.cuda.graph(self.graph):
             body()
         self.renderer = r
-        self._keep = (scene, codes, reference)
+        # the graph's kernels hold raw pointers into these tensors
+        self._keep = (scene, codes, reference, r.ws, r.uws)
+        r.live_captures += 1
+        self._closed = False
 
     def replay(self) -> torch.Tensor:
+        if self._closed:
+            raise RuntimeError("this CapturedRender was closed")
         self.graph.replay()
         return self.out
+
+    def close(self):
+        """Release the graph and let the renderer plan again."""
+        if not self._closed:
+            self._closed = True
+            self.graph.reset()
+            self._keep = None
+            self.renderer.live_captures -= 1
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass

@@ -5,6 +5,7 @@ arguments before touching the device."""
 import ctypes
 import os
 import re
+from types import SimpleNamespace
 
 import pytest
 
@@ -164,3 +165,80 @@ def test_loss_entry_points_validate_before_any_launch():
     w = abi.ObjectiveWeights(0.2, -0.3, 0.05, 0.1, 2.0, 0.5)
     assert L.dgs_objective(fake, 2, 16, 16, fake, 1, fake, fake, 1, None, 0, None, 0, None, 0, ctypes.byref(w),
                            loss, None, None, fake, ob, None) == 1
+
+
+def test_count_instances_null_states_and_near_plane_rejected():
+    abi, L = _lib()
+    cam = _cam(abi)
+    tun = abi.Tuning(16, 16, 16, 0)
+    st = abi.States()
+    sc = abi.Scene(10, 2, 0, 2, 2, *([4096] * 8))
+    ws = ctypes.c_void_p(1 << 20)
+    m = ctypes.c_int64(0)
+    assert L.dgs_count_instances(ctypes.byref(sc), ctypes.byref(cam), None, ctypes.byref(tun), ws, 1 << 30,
+                                 ctypes.byref(m), None) == 1
+    assert b"states" in L.dgs_last_error()
+    for near in (0.0, -0.5):
+        c = _cam(abi)
+        c.near_z = near
+        assert L.dgs_count_instances(ctypes.byref(sc), ctypes.byref(c), ctypes.byref(st), ctypes.byref(tun), ws,
+                                     1 << 30, ctypes.byref(m), None) == 1
+        assert b"near_z" in L.dgs_last_error()
+        assert L.dgs_workspace_bytes(1000, 4, ctypes.byref(c), ctypes.byref(tun), 16, 0) == 0
+
+
+def _capturing(monkeypatch):
+    import torch
+    monkeypatch.setattr(torch.cuda, "is_available", lambda: True)
+    monkeypatch.setattr(torch.cuda, "is_current_stream_capturing", lambda: True)
+
+
+def test_python_synchronising_calls_refuse_graph_capture(monkeypatch):
+    """Every binding call that waits for the device raises, before any
+    device work, while the current stream is being captured."""
+    import torch
+
+    import paper_2606_17212_amd as dgs
+    from paper_2606_17212_amd.render import PARAMS, RenderFunction
+    _capturing(monkeypatch)
+    r = dgs.Renderer(torch.device("cuda", 0))
+    sc = dgs.GaussianScene(torch.zeros(3, 5), torch.zeros(3, 5), torch.zeros(4, 5), torch.zeros(5),
+                           torch.zeros(3, 5), torch.zeros(6, 5), torch.zeros(5, dtype=torch.int16), 2, 2, 2, 0)
+    cam = dgs.Camera([1, 0, 0, 0, 1, 0, 0, 0, 1], [0, 0, 3], 100.0, 100.0, 32.0, 32.0, 64, 64)
+    codes = torch.zeros(2, 4, dtype=torch.uint8)
+    calls = [lambda: r.plan(sc, cam, [0.5, 0.25], 2), lambda: r.count_instances(sc, cam, [0.5, 0.25]),
+             lambda: r.check(), lambda: r.sections(sc, cam, 2), lambda: r.composite_stats(sc, cam, codes, [0, 0]),
+             lambda: r.utility_items(sc, cam, codes, None, None, [0, 0]), lambda: r.utility_check(),
+             lambda: dgs.Objective(torch.device("cuda", 0)).check(),
+             lambda: dgs.L1Loss(torch.device("cuda", 0)).check()]
+    for f in calls:
+        with pytest.raises(RuntimeError, match="captured"):
+            f()
+
+    # a backward whose forward's lists were overwritten by another render
+    ctx = SimpleNamespace(renderer=r, scene=sc, camera=cam, codes=codes, basis=(0.5, 0.25), background=(0, 0, 0),
+                          generation=r.generation - 1,
+                          saved_tensors=(torch.zeros(2, 64, 64, 3),) + tuple(getattr(sc, k) for k in PARAMS))
+    with pytest.raises(RuntimeError, match="re-render"):
+        RenderFunction.backward(ctx, torch.zeros(2, 64, 64, 3))
+
+
+def test_live_capture_blocks_replanning(monkeypatch):
+    """While a captured graph holds pointers into a renderer's workspace,
+    planning again or growing the workspace raises."""
+    import torch
+
+    import paper_2606_17212_amd as dgs
+    r = dgs.Renderer(torch.device("cuda", 0))
+    r.ws = torch.zeros(1024, dtype=torch.uint8)
+    r.ws_bytes = 1024
+    r.live_captures = 1
+    sc = dgs.GaussianScene(torch.zeros(3, 5), torch.zeros(3, 5), torch.zeros(4, 5), torch.zeros(5),
+                           torch.zeros(3, 5), torch.zeros(6, 5), torch.zeros(5, dtype=torch.int16), 2, 2, 2, 0)
+    cam = dgs.Camera([1, 0, 0, 0, 1, 0, 0, 0, 1], [0, 0, 3], 100.0, 100.0, 32.0, 32.0, 64, 64)
+    with pytest.raises(RuntimeError, match="close"):
+        r.plan(sc, cam, [0.5, 0.25], 4)
+    with pytest.raises(RuntimeError, match="close"):
+        r._ensure_ws(4096)
+    r._ensure_ws(512)  # fits: the buffer is kept
+    assert r.ws_bytes == 1024
