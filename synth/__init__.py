@@ -22,6 +22,7 @@ from .workloads import (  # noqa: F401
     subscene,
     make_workload,
     permute_gaussians,
+    near_identity_affines,
     UTILITY_WORKLOADS,
     UtilityWorkload,
     make_utility_contexts,

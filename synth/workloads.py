@@ -3,7 +3,7 @@
 Every array is drawn from ``numpy.random.default_rng(SeedSequence([2606,
 workload_index, stream]))`` with stream 0 = scene, 1 = delivery states,
 2 = parameter perturbation, 3 = finite-difference subscene, 4 = refinement
-levels.  Values are drawn in
+levels, 5 = cluster affines.  Values are drawn in
 float64 and stored as float32; both the oracle and the GPU path read the
 float32 values.
 
@@ -282,6 +282,18 @@ def perturb_scene(scene: SceneArrays, sigma: float = 0.01, index: int = 0,
     return replace(scene, mean=noisy(scene.mean), log_scale=noisy(scene.log_scale),
                    quat=noisy(scene.quat), opacity_logit=noisy(scene.opacity_logit),
                    color=noisy(scene.color), temporal=noisy(scene.temporal))
+
+
+def near_identity_affines(num_clusters: int, sigma: float = 0.05, index: int = 0,
+                          stream: int = 5) -> np.ndarray:
+    """Per-cluster affines A_c = [I + E | t] ([C][12], row-major 3x4) with E
+    ~ N(0, sigma) and t ~ N(0, 2 sigma): random cluster motions near the
+    identity, for the A_{c,t} term of Eq. (1)."""
+    rng = _rng(index, stream)
+    E = rng.normal(0.0, sigma, size=(num_clusters, 3, 3))
+    t = rng.normal(0.0, 2.0 * sigma, size=(num_clusters, 3, 1))
+    A = np.concatenate([np.eye(3)[None] + E, t], axis=2)
+    return np.ascontiguousarray(A.reshape(num_clusters, 12), dtype=np.float32)
 
 
 def permute_gaussians(scene: SceneArrays, perm: np.ndarray) -> SceneArrays:

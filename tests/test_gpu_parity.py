@@ -2,7 +2,10 @@
 
 Bars: tile rectangles, depth keys and per-tile sorted lists bit-exact with the
 oracle's FP32 mirror; images within 1e-4 absolute of the FP64 oracle plus its
-ambiguity budget (alphas within 0.1% of 1/255, transmittance near 1e-4);
+ambiguity budget (pairs whose FP32 exponent or transmittance may fall on the
+other side of the 1/255 skip or the 1e-4 stop, from the mirror's FP32 records;
+the premises of that bound -- records bit-exact with the mirror, log2-opacity
+within 2^-16 -- are checked here too);
 batched == per-state == any group size == either tile shape, bit for bit.
 """
 
@@ -71,7 +74,7 @@ def test_geometry_keys_rects_and_lists_bit_exact(tiny, tile):
     # FP32 projection against the FP64 definition
     g = oracle.geometry_f64(w.scene, w.camera, w.basis)
     # wave-block reach masks are conservative: a tile's 8x8 block holding a
-    # pixel centre where the Gaussian's FP64 alpha >= (1/255)(1 + 1e-3) has its bit set
+    # pixel centre where the Gaussian's FP64 alpha >= 1/255 has its bit set
     masks = sec["wave_masks"].numpy()[:M].astype(np.int64)
     tile_of = np.repeat(np.arange(ranges.shape[0]), ranges[:, 1] - ranges[:, 0])
     tiles_x = sec["tiles_x"]
@@ -86,10 +89,19 @@ def test_geometry_keys_rects_and_lists_bit_exact(tiny, tile):
                 y = py + dy + 0.5 - g["v"][ids]
                 q = g["conA"][ids] * x * x + 2 * g["conB"][ids] * x * y + g["conC"][ids] * y * y
                 inside = (px + dx < w.camera.width) & (py + dy < w.camera.height)
-                need_any[:, b] |= inside & (g["o"][ids] * np.exp(-0.5 * q) >= (1 / 255) * (1 + 1e-3))
+                need_any[:, b] |= inside & (g["o"][ids] * np.exp(-0.5 * q) >= 1 / 255)
     bits = (masks[:, None] >> np.arange(4)[None, :]) & 1
     assert not np.any(need_any & (bits == 0)), "a reached wave block has no mask bit"
     assert bits.sum() < 4 * M  # and the masks do cull blocks
+    # premises of the oracle's ambiguity budget: the compositing records hold
+    # the mirror's FP32 (u, v) and scaled conic bit for bit, and a log2-opacity
+    # within 2^-16 of the FP64 value
+    r0, r1 = sec["rec0"].numpy(), sec["rec1"].numpy()
+    assert np.array_equal(r0[valid, 0].view(np.uint32), m["u"][valid].view(np.uint32))
+    assert np.array_equal(r0[valid, 1].view(np.uint32), m["v"][valid].view(np.uint32))
+    for j, k in enumerate(("cA", "cB", "cC")):
+        assert np.array_equal(r1[valid, j].view(np.uint32), m[k][valid].view(np.uint32)), k
+    assert np.max(np.abs(r0[valid, 2].astype(np.float64) - np.log2(g["o"][valid]))) <= 2.0 ** -16
     rec0, rec1, rec2 = (sec[k].numpy().astype(np.float64) for k in ("rec0", "rec1", "rec2"))
     assert np.max(np.abs(rec0[valid, 0] - g["u"][valid])) < 2e-4
     assert np.max(np.abs(rec0[valid, 1] - g["v"][valid])) < 2e-4
