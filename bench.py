@@ -30,6 +30,11 @@ PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic FLOPs (an FMA counts 2) per unit of compositing work:
 FLOPS_PER_ALPHA = 14       # dx, dy, quadratic form (8), scale, exp, x opacity, cap
 FLOPS_PER_BLEND = 8        # T*alpha, 3 FMA colour, T - T*alpha
+# Backward compositing, per alpha evaluation: the forward's 14 + dq = dL/dalpha alpha ln2 (2) + the
+# six per-pixel terms of (u, v, A', B', C', log2 o) (16) + the pixel sums of the nine 2D gradients (9)
+FLOPS_BWD_PER_ALPHA = 41
+# per blend: the forward's 8 + g . c (5) + colour-behind update (2) + dL/dalpha (4) + dL/dc (6)
+FLOPS_BWD_PER_BLEND = 25
 LAUNCH = {"auto": None, "grid": False, "persistent": True}
 
 
@@ -50,6 +55,8 @@ def parse():
     ap.add_argument("--no-serial-fwdbwd", action="store_true",
                     help="skip the 2.7M-Gaussian fwd+bwd leg: 32 states batched vs one state per call")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2.7M-Gaussian 256-state leg and the 32,768-state PSNR sweep")
     ap.add_argument("--no-utility", action="store_true")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the leg with attribute refinement levels on the same workload")
@@ -156,6 +163,35 @@ def main():
     value = W * args.steps / (total_ms / 1e3)
     r.check()
     log(f"[bench] batched: {ms_step:.3f} ms/step (bin {bin_ms:.3f}, composite {comp_ms:.3f}) -> {value:.1f} states/s")
+    # two more independent timed repetitions of the same K steps (the paper's
+    # protocol: three repetitions, Student-t interval over them)
+    reps = [value]
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0.record(st)
+        for k in range(args.steps):
+            step()
+        t1.record(st)
+        torch.cuda.synchronize()
+        reps.append(W * args.steps / (t0.elapsed_time(t1) / 1e3))
+    r.check()
+    graph_leg = None
+    if graph is None:
+        # the same step as one captured HIP graph (bin + composite), replayed
+        g = dgs.CapturedRender(r, scene, cam, codes, w.basis, bg)
+        g.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(g.out, img))
+        t0.record(st)
+        for k in range(args.steps):
+            g.replay()
+        t1.record(st)
+        torch.cuda.synchronize()
+        gms = t0.elapsed_time(t1) / args.steps
+        g.close()
+        graph_leg = {"ms_per_step": round(gms, 4), "states_per_s": round(W / (gms / 1e3), 2),
+                     "bit_identical_to_eager": same}
+        log(f"[bench] batched as graph replay: {gms:.3f} ms/step -> {W / (gms / 1e3):.1f} states/s; identical={same}")
 
     # algorithmic work of one composite launch
     alpha_evals, blends, wave_evals, wave_miss = r.composite_stats(scene, cam, codes, w.basis)
@@ -186,7 +222,11 @@ def main():
                       "states_per_group": args.states_per_group, "instances": M},
            "batched": {"bin_ms": round(bin_ms, 4), "composite_ms": round(comp_ms, 4),
                        "timed_as": "hip graph replay" if graph is not None else "eager launches",
-                       "step_ms": distribution([e[0].elapsed_time(e[2]) for e in ev], np)}}
+                       "step_ms": distribution([e[0].elapsed_time(e[2]) for e in ev], np),
+                       "repetitions_states_per_s": [round(x, 2) for x in reps],
+                       "repetitions": distribution(reps, np)}}
+    if graph_leg is not None:
+        out["batched"]["graph"] = graph_leg
 
     if not args.no_per_state:
         # plain per-state render, synchronized after every state
@@ -208,6 +248,9 @@ def main():
         log(f"[bench] per-state: {1e3 * ps_s / W:.3f} ms/state -> {ps_rate:.1f} states/s; identical={same}")
 
     out["roofline"] = roofline
+    roofs = measured_roofs(dgs, torch, np, dev)
+    out["measured_roofs"] = roofs
+    roofline["frac_of_measured_fma"] = round(achieved / roofs["fma_tflops"], 4)
 
     if args.copy_mib > 0:
         # one streaming pass of known size (reads and writes the buffer once),
@@ -221,6 +264,9 @@ def main():
 
     if not args.no_fwdbwd:
         out["fwd_bwd"] = fwd_bwd(dgs, synth, torch, np, dev, args)
+        rb = out["fwd_bwd"].pop("roofline_bwd")
+        rb["frac_of_measured_fma"] = round(rb["achieved"] / roofs["fma_tflops"], 4)
+        out["roofline_bwd"] = rb
         if not args.no_train_step:
             out["train_step"] = train_step(dgs, synth, torch, np, dev, args)
         if not args.no_serial_fwdbwd:
@@ -228,6 +274,14 @@ def main():
 
     if not args.no_refined:
         out["refined"] = refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg)
+
+    if not args.no_large:
+        del r, img
+        torch.cuda.empty_cache()
+        out["large_batched"] = large_batched_leg(args, dgs, synth, torch, np, dev)
+        pw = synth.make_workload("g1m_540p_32768states_psnr")
+        out["psnr_sweep"] = psnr_sweep_leg(args, pw.name, pw, dgs.GaussianScene.from_arrays(pw.scene, dev),
+                                           dgs.Camera.from_arrays(pw.camera), dgs, torch, np, dev, 16, 16, 8, None)
 
     if not args.no_utility:
         out["utility"] = utility_bench(args, dgs, synth, torch, np, dev, tw, th)
@@ -238,6 +292,51 @@ def main():
 
     print(json.dumps(out), flush=True)
     return 0
+
+
+def measured_roofs(dgs, torch, np, dev):
+    """Measured roofs beside the published peaks: a 1 GiB device copy (HBM
+    bytes moved = 2 x 1 GiB) and the issue rates of FP32 FMA (2 FLOPs per
+    instruction and lane, no packed FP32) and of the hardware base-2
+    exponential, each the best of five timed launches."""
+    import ctypes
+    from paper_2606_17212_amd import _abi
+    L = _abi.lib()
+    st = torch.cuda.current_stream(dev)
+    sp = ctypes.c_void_p(st.cuda_stream)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    out = torch.empty(_abi.PROBE_THREADS, dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(f):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0.record(st)
+            f()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    copy_ms = best(lambda: _abi.check(L.dgs_probe_copy(ctypes.c_void_p(src.data_ptr()),
+                                                       ctypes.c_void_p(dst.data_ptr()), nbytes, sp)))
+    assert bool(torch.equal(src[:1024], dst[:1024]))
+    iters = 1 << 14
+    fma_ms = best(lambda: _abi.check(L.dgs_probe_valu(0, iters, ctypes.c_void_p(out.data_ptr()), sp)))
+    exp_ms = best(lambda: _abi.check(L.dgs_probe_valu(1, iters, ctypes.c_void_p(out.data_ptr()), sp)))
+    lanes_steps = _abi.PROBE_THREADS * 8 * iters
+    res = {"copy_gbps": round(2 * nbytes / (copy_ms / 1e3) / 1e9, 1), "hbm_peak_gbps": 8000.0,
+           "fma_tflops": round(2 * lanes_steps / (fma_ms / 1e3) / 1e12, 2),
+           "fma_peak_nonpacked_tflops": round(PEAK_FP32_NONPACKED_TFLOPS, 1), "fp32_peak_tflops": PEAK_FP32_TFLOPS,
+           "exp2_per_s": round(lanes_steps / (exp_ms / 1e3), -9)}
+    log(f"[bench] measured roofs: copy {res['copy_gbps']:.0f} GB/s, FMA {res['fma_tflops']:.1f} TFLOP/s, "
+        f"exp2 {res['exp2_per_s'] / 1e12:.2f} T/s")
+    del src, dst, out
+    return res
 
 
 def distribution(times, np):
@@ -302,6 +401,10 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
            "ms_per_iter_all": [round(t, 4) for t in times], "distribution": distribution(times, np),
            "grads_finite": finite}
 
+    out["roofline_bwd"] = backward_roofline(dgs, torch, np, dev, r, sc, cam, codes, w.basis, bg, target, l1,
+                                            params, iters)
+    out["graph"] = fwd_bwd_graph(dgs, torch, np, dev, r, sc, scene, cam, codes, w.basis, bg, target, l1, params,
+                                 iters)
     if args.no_refined:
         return out
     # the same step with three refinement levels (gradients for base and levels)
@@ -338,13 +441,102 @@ def fwd_bwd(dgs, synth, torch, np, dev, args):
     return out
 
 
+def backward_roofline(dgs, torch, np, dev, r, sc, cam, codes, basis, bg, target, l1, params, iters):
+    """Roofline of the backward: dgs_backward timed alone with HIP events
+    on its stream (the compositing backward, which replays each tile, plus
+    the geometry backward), against the algorithmic FLOPs of the compositing
+    backward: per alpha evaluation (pixel, entry, state group) the forward's
+    14 plus the chain to the splat's nine 2D gradients and their sum over
+    pixels (27), per blend (pixel, state, Gaussian) the forward's 8 plus
+    g . c, the colour-behind update, dL/dalpha and dL/dc (17).  The unit
+    counts are the forward's, which the replay repeats."""
+    with torch.no_grad():
+        img = r.render(sc, cam, codes, basis, bg)
+        gimg = l1.grad(img, target)
+    st = torch.cuda.current_stream(dev)
+    for _ in range(2):
+        r.backward(sc, cam, codes, basis, bg, img, gimg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(iters):
+        e0.record(st)
+        r.backward(sc, cam, codes, basis, bg, img, gimg)
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    r.check()
+    a_ev, bl, _, _ = r.composite_stats(sc, cam, codes, basis)
+    fl = FLOPS_BWD_PER_ALPHA * a_ev + FLOPS_BWD_PER_BLEND * bl
+    ms = float(np.mean(times))
+    ach = fl / (ms / 1e3) / 1e12
+    log(f"[bench] backward: {ms:.3f} ms per dgs_backward, {a_ev} alpha evals, {bl} blends -> {ach:.2f} TFLOP/s")
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": "k_composite_bwd (+ k_geometry_bwd in the timed call)",
+            "peak_nonpacked": round(PEAK_FP32_NONPACKED_TFLOPS, 1),
+            "frac_nonpacked": round(ach / PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "call_ms": round(ms, 4), "alpha_evals": a_ev, "blends": bl, "flops_per_call": fl}
+
+
+def fwd_bwd_graph(dgs, torch, np, dev, r, sc, scene, cam, codes, basis, bg, target, l1, eager_params, iters):
+    """The forward + L1 + backward iteration captured as one HIP graph and
+    replayed.  The captured step owns leaf tensors that were never used on
+    the default stream and is warmed up on the capture's side stream (a leaf
+    whose gradient-accumulation node is bound to the default stream makes
+    autograd synchronise with that stream inside the capture).  Every replay's
+    gradients are compared with the eager iteration's."""
+    from paper_2606_17212_amd.render import PARAMS
+    ref = {k: p.grad.detach().clone() for k, p in eager_params.items()}
+    params = {k: getattr(scene, k).clone().requires_grad_(True) for k in PARAMS}
+    gsc = scene.with_params(**params)
+
+    def it():
+        loss = dgs.l1_loss(dgs.render(r, gsc, cam, codes, basis, bg), target, None, l1)
+        loss.backward()
+
+    side = torch.cuda.Stream(dev)  # default priority
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            for p in params.values():
+                p.grad = None
+            it()
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    for p in params.values():
+        p.grad = None
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        it()
+    st = torch.cuda.current_stream(dev)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times, worst = [], 0.0
+    for _ in range(iters):
+        e0.record(st)
+        graph.replay()
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        worst = max(worst, max(float((params[k].grad - ref[k]).norm() / ref[k].norm().clamp_min(1e-30))
+                               for k in PARAMS))
+    r.check()
+    del graph
+    log(f"[bench] fwd+bwd as one graph replay: median {np.median(times):.3f} ms/iter; "
+        f"max relative gradient difference to eager {worst:.2e}")
+    return {"ms_per_iter": round(float(np.median(times)), 4), "distribution": distribution(times, np),
+            "max_rel_grad_diff_vs_eager": worst}
+
+
 def fwd_bwd_batched_vs_serial(dgs, synth, torch, np, dev, states=32, iters=5, serial_iters=2):
     """Forward + L1 + backward of 32 delivery states of the 2.7M-Gaussian
     1920x1080 recipe in one batched call, against synchronized serial calls
     of the same renderer with one state each (each call projects and bins the
     whole scene, composites its state and runs the backward; gradients
     accumulate over the calls).  The paper reports this speedup for 32
-    batched states on 2.7M primitives (Sec. 10) on other hardware and scenes:
+    batched states on 2.7M primitives (Sec. 6) on other hardware and scenes:
     context, not a target.  The target is the full-delivery render of the
     scene with parameters perturbed by N(0, 0.01)."""
     name = "g2700k_1080p_256states"
@@ -541,18 +733,32 @@ def refined_bench(args, w, r, img, dgs, synth, torch, np, dev, bg):
 
 
 def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
+    """Main mode for the PSNR-sweep workload: the sweep leg as the JSON line."""
+    leg = psnr_sweep_leg(args, args.workload, w, scene, cam, dgs, torch, np, dev, tw, th, args.states_per_group,
+                         LAUNCH[args.launch])
+    out = {"metric": METRIC, "value": leg["value"], "unit": "states/s", "n_gpus": 1, "steps": 1,
+           "warmup": leg["warmup"], "ms_per_step": leg["ms_per_sweep"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "gaussians": scene.n, "width": cam.width, "height": cam.height,
+                      "states": leg["states"], "batch": leg["batch"], "tile": f"{tw}x{th}",
+                      "states_per_group": args.states_per_group}}
+    out.update({k: leg[k] for k in ("batch_latency_ms", "psnr_db", "roofline_composite")})
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def psnr_sweep_leg(args, name, w, scene, cam, dgs, torch, np, dev, tw, th, S, persistent):
     """Utility-style sweep: every delivery state's PSNR against the
     full-delivery render, in batches, binning shared by the whole sweep
-    (one scene, one camera, one time)."""
+    (one scene, one camera, one time), PSNR reduced on the device."""
     import synth
     total, batch = w.total_states, w.batch
-    rec = synth.WORKLOADS[args.workload]
+    rec = synth.WORKLOADS[name]
     kind, lo, hi = rec["masks"]
     codes_all = torch.from_numpy(synth.make_codes(kind, lo, hi, total, w.scene.num_packets, rec["layers"],
                                                   index=w.index)).to(dev)
     bg = tuple(float(x) for x in w.background)
-    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=args.states_per_group, persistent=LAUNCH[args.launch],
-                       lds_batch=args.lds_batch)
+    ren = dgs.Renderer(dev, tile=(tw, th), states_per_group=S, persistent=persistent, lds_batch=args.lds_batch)
     ren.plan(scene, cam, w.basis, batch)
     ref = ren.render(scene, cam, torch.ones_like(codes_all[:1]), w.basis, bg)[0].contiguous()
     psnr = torch.empty(total, dtype=torch.float32, device=dev)
@@ -583,20 +789,91 @@ def psnr_sweep(args, w, scene, cam, dgs, torch, np, dev, tw, th):
     lat = [e[0].elapsed_time(e[1]) for e in ev]
     value = total / (ms / 1e3)
     p = psnr.cpu().numpy()
+    # compositing work of one batch (the first), for the roofline of the PSNR-mode kernel
+    a_ev, bl, _, _ = ren.composite_stats(scene, cam, codes_all[:batch], w.basis)
+    fl = FLOPS_PER_ALPHA * a_ev + FLOPS_PER_BLEND * bl
+    ach = fl / (lat[0] / 1e3) / 1e12
     log(f"[bench] psnr sweep: {total} states in {ms:.1f} ms -> {value:.1f} states/s; batch latency median "
-        f"{np.median(lat):.3f} ms; PSNR median {np.median(p):.2f} dB")
-    out = {"metric": METRIC, "value": round(value, 2), "unit": "states/s", "n_gpus": 1, "steps": 1,
-           "warmup": max(1, args.warmup // 2), "ms_per_step": round(ms, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": args.workload, "gaussians": scene.n, "width": cam.width, "height": cam.height,
-                      "states": total, "batch": batch, "tile": f"{tw}x{th}",
-                      "states_per_group": args.states_per_group},
-           "batch_latency_ms": {"median": round(float(np.median(lat)), 4), "p90": round(float(np.percentile(lat, 90)), 4),
-                                "max": round(float(np.max(lat)), 4)},
-           "psnr_db": {"median": round(float(np.median(p)), 3), "min": round(float(np.min(p)), 3),
-                       "max": round(float(np.max(p)), 3)}}
-    print(json.dumps(out), flush=True)
-    return 0
+        f"{np.median(lat):.3f} ms; PSNR median {np.median(p):.2f} dB; first batch {ach:.2f} TFLOP/s")
+    plan = ren.launch_plan(cam, batch)
+    del ren
+    return {"workload": name, "value": round(value, 2), "unit": "states/s", "states": total, "batch": batch,
+            "gaussians": scene.n, "width": cam.width, "height": cam.height, "tile": f"{tw}x{th}",
+            "launch": plan, "warmup": max(1, args.warmup // 2), "ms_per_sweep": round(ms, 3),
+            "batch_latency_ms": {"median": round(float(np.median(lat)), 4),
+                                 "p90": round(float(np.percentile(lat, 90)), 4), "max": round(float(np.max(lat)), 4),
+                                 "distribution": distribution(lat, np)},
+            "psnr_db": {"median": round(float(np.median(p)), 3), "min": round(float(np.min(p)), 3),
+                        "max": round(float(np.max(p)), 3)},
+            "roofline_composite": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                                   "scope": "first batch of 512 states", "alpha_evals": a_ev, "blends": bl}}
+
+
+def large_batched_leg(args, dgs, synth, torch, np, dev, w=None):
+    """The 2.7M-Gaussian 1920x1080 workload with 256 delivery states of
+    uneven present counts (5% .. 100% of the Gaussians) in one batch:
+    bin + composite per step, compositing in the persistent launch with 16
+    states per group (the autotuner's choice for this workload), three
+    repetitions of the timed steps.  Reports states/s and the HBM rate of
+    the algorithmic bytes model (scene, records, sort and instances once per
+    step; per (tile, state group) the list's values and records; per state
+    its image)."""
+    name = "g2700k_1080p_256states"
+    w = w or synth.make_workload(name)
+    scene = dgs.GaussianScene.from_arrays(w.scene, dev)
+    cam = dgs.Camera.from_arrays(w.camera)
+    codes = torch.from_numpy(w.codes).to(dev)
+    W = int(codes.shape[0])
+    bg = tuple(float(x) for x in w.background)
+    S = 16
+    r = dgs.Renderer(dev, tile=(16, 16), states_per_group=S, persistent=True, lds_batch=256)
+    M = r.plan(scene, cam, w.basis, W)
+    img = torch.empty((W, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        r.bin(scene, cam, w.basis)
+        r.composite(scene, cam, codes, w.basis, bg, out=img)
+    r.check()
+    st = torch.cuda.current_stream(dev)
+    steps = 4
+    reps, bins, comps = [], [], []
+    for _ in range(3):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        for k in range(steps):
+            ev[k][0].record(st)
+            r.bin(scene, cam, w.basis)
+            ev[k][1].record(st)
+            r.composite(scene, cam, codes, w.basis, bg, out=img)
+            ev[k][2].record(st)
+        torch.cuda.synchronize()
+        reps.append(W * steps / (ev[0][0].elapsed_time(ev[-1][2]) / 1e3))
+        bins += [e[0].elapsed_time(e[1]) for e in ev]
+        comps += [e[1].elapsed_time(e[2]) for e in ev]
+    r.check()
+    a_ev, bl, _, _ = r.composite_stats(scene, cam, codes, w.basis)
+    fl = FLOPS_PER_ALPHA * a_ev + FLOPS_PER_BLEND * bl
+    bin_ms, comp_ms = float(np.median(bins)), float(np.median(comps))
+    # algorithmic bytes of one step (the model above): geometry 118 B read + 64 B written per Gaussian,
+    # four 16-B passes of the depth sort, 8 B per instance (scatter write + range walk), per (tile, group)
+    # each list entry's value (4 B) and record (48 B), per state 12 B per pixel of image
+    groups = (W + S - 1) // S
+    nbytes = scene.n * (118 + 64 + 4 * 16) + 8 * M + groups * M * 52 + W * cam.width * cam.height * 12
+    value = float(np.median(reps))
+    ms_step = W / value * 1e3
+    log(f"[bench] {name}: {ms_step:.2f} ms/step (bin {bin_ms:.2f}, composite {comp_ms:.2f}) -> {value:.1f} states/s; "
+        f"model bytes {nbytes / 1e9:.2f} GB -> {nbytes / (ms_step / 1e3) / 1e9:.0f} GB/s")
+    out = {"workload": name, "gaussians": scene.n, "width": cam.width, "height": cam.height, "states": W,
+           "instances": M, "tile": "16x16", "states_per_group": S, "launch": r.launch_plan(cam, W),
+           "value": round(value, 2), "unit": "states/s", "ms_per_step": round(ms_step, 3),
+           "bin_ms": round(bin_ms, 3), "composite_ms": round(comp_ms, 3),
+           "repetitions_states_per_s": [round(x, 2) for x in reps], "repetitions": distribution(reps, np),
+           "hbm_model_bytes_per_step": int(nbytes), "hbm_model_gbps": round(nbytes / (ms_step / 1e3) / 1e9, 1),
+           "composite_achieved_tflops": round(fl / (comp_ms / 1e3) / 1e12, 3),
+           "composite_frac": round(fl / (comp_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
+    del r, img
+    torch.cuda.empty_cache()
+    return out
 
 
 def utility_bench(args, dgs, synth, torch, np, dev, tw, th):

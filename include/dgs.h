@@ -26,6 +26,16 @@
  *    sort keys are reproducible bit for bit; a state's image is bit-identical
  *    whether it is rendered alone (dgs_render_per_state) or batched
  *    (dgs_render), with either tile shape.
+ *  - Graph capture: the calls that synchronise (dgs_count_instances,
+ *    dgs_check, dgs_utility_count, dgs_utility_check, dgs_objective_check)
+ *    return DGS_ERR_INVALID_ARG, before any launch, on a stream that is
+ *    being captured; every other call only enqueues work and may be captured.
+ *
+ * Plan / forward / poll: sizing is dgs_workspace_bytes plus the one
+ * synchronising count dgs_count_instances; the forward is dgs_render (or
+ * dgs_bin followed by any number of dgs_composite calls); dgs_check polls for
+ * overflow and asynchronous errors.  There is no context object: tuning is an
+ * explicit dgs_tuning argument and graph capture belongs to the caller.
  */
 #ifndef DGS_H
 #define DGS_H
@@ -186,10 +196,12 @@ int dgs_count_instances(const dgs_scene *scene, const dgs_camera *cam,
                         size_t ws_bytes, int64_t *instances, void *stream);
 
 /*
- * Batched render (the hot path).  Deformation (Eq. (1)) and projection of all
+ * Batched render (the hot path; Sec. 6: the states of one scene are
+ * rasterised in one call, in FP32).  Deformation (Eq. (1)) and projection of all
  * Gaussians, tile binning and the (tile, depth, index) sort run once; then
  * every state is composited front to back from the shared per-tile lists,
- * skipping Gaussians its codes do not deliver.
+ * skipping Gaussians its codes do not deliver (the cluster-layer masks of
+ * Sec. 4).
  *   image  device [W][height][width][3] FP32, colour + T_final * background
  *   tfinal device [W][height][width] transmittance after the last
  *          composited Gaussian, or NULL
@@ -203,7 +215,8 @@ int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *
                float *image, float *tfinal, void *stream);
 
 /*
- * The two halves of dgs_render.  dgs_bin runs the shared part -- deformation,
+ * The two halves of dgs_render (Sec. 6: one scene and time shared by every
+ * state of the batch).  dgs_bin runs the shared part -- deformation,
  * projection, depth sort, tile binning and the per-tile lists -- for the
  * scene and camera (states->codes is not read; basis is).  dgs_composite then
  * composites every state in `states` from those lists; it may be called any
@@ -254,7 +267,9 @@ int dgs_composite_stats(const dgs_scene *scene, const dgs_camera *cam, const dgs
                         int64_t instance_capacity, unsigned long long *counters, void *stream);
 
 /*
- * Plain per-state render (baseline): for each state in turn, compacts the
+ * Plain per-state render (baseline; with a synchronisation after each call it
+ * is Sec. 6's synchronized serial evaluation, which the paper states batched
+ * evaluation equals bit for bit): for each state in turn, compacts the
  * delivered Gaussians, projects, bins, sorts and composites only them.
  * Same outputs, bit-identical to dgs_render's.  tun->states_per_group is
  * ignored.  instance_capacity from dgs_count_instances covers every state.
@@ -266,6 +281,8 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam,
 
 /*
  * Batched render reduced on device to one PSNR per state against `reference`
+ * (the per-state image-space evaluation behind Sec. 5's utilities and
+ * Sec. 6's utility-state throughput)
  * (device [height][width][3]): PSNR = 10 log10(1 / max(MSE, 1e-10)), MSE over
  * every pixel and channel, accumulated from per-tile FP32 partial sums in
  * FP64.  No image is written.  psnr: device [W] FP32.
@@ -276,7 +293,9 @@ int dgs_render_psnr(const dgs_scene *scene, const dgs_camera *cam, const dgs_sta
                     void *stream);
 
 /*
- * Backward of dgs_render.  Must follow a dgs_render with the same arguments
+ * Backward of dgs_render (Sec. 4 and Sec. 6: training renders and
+ * differentiates the batched states; gradients of Eq. (1)'s parameters,
+ * scale, rotation, opacity and colour).  Must follow a dgs_render with the same arguments
  * and the same, untouched workspace (its sorted lists are reused; per tile the
  * compositing is recomputed front to back, no per-pixel lists are stored).
  *   image      device [W][H][Wd][3]: the forward's output
@@ -542,6 +561,25 @@ int dgs_l1_loss(const float *images, int32_t num_images, int32_t width, int32_t 
 int dgs_l1_loss_grad(const float *images, int32_t num_images, int32_t width, int32_t height, const float *targets,
                      int32_t num_targets, const int32_t *target_of, const float *dloss, float *grad, void *stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Measured roofs (for reporting kernels against the machine as well as
+ * against its published peaks; nothing on the render path uses these).
+ *
+ * dgs_probe_copy: copies `bytes` (a multiple of 16, both pointers 16-byte
+ * aligned device pointers) from src to dst with 16-byte loads and stores;
+ * reads and writes each byte once, so bytes moved = 2 * bytes.
+ * dgs_probe_valu: DGS_PROBE_THREADS threads (8 waves per SIMD on 256 CUs),
+ * each running 8 independent chains of `iterations` (1 .. 2^24) steps:
+ * kind 0 an FP32 fused multiply-add per step (2 FLOPs), kind 1 one hardware
+ * base-2 exponential per step; out: device float [DGS_PROBE_THREADS] (one
+ * value per thread, written so the work is not optimised away).
+ * Both asynchronous on `stream`; DGS_ERR_INVALID_ARG for bad arguments,
+ * DGS_ERR_HIP for a failed launch.
+ */
+#define DGS_PROBE_THREADS 524288
+int dgs_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
+int dgs_probe_valu(int32_t kind, int64_t iterations, float *out, void *stream);
 
 #ifdef __cplusplus
 }

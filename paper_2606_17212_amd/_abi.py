@@ -24,7 +24,9 @@ EXPORTS = (
     "dgs_utility_count", "dgs_utility", "dgs_utility_check", "dgs_distortion_scratch_bytes", "dgs_distortion",
     "dgs_risk_adjusted", "dgs_sample_states", "dgs_objective_scratch_bytes", "dgs_objective",
     "dgs_objective_check", "dgs_l1_scratch_bytes", "dgs_l1_loss", "dgs_l1_loss_grad",
+    "dgs_probe_copy", "dgs_probe_valu",
 )
+PROBE_THREADS = 524288
 
 
 class Scene(ctypes.Structure):
@@ -161,6 +163,10 @@ def lib():
     L.dgs_l1_loss.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, vp, sz, vp]
     L.dgs_l1_loss_grad.restype = ctypes.c_int
     L.dgs_l1_loss_grad.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, vp, vp]
+    L.dgs_probe_copy.restype = ctypes.c_int
+    L.dgs_probe_copy.argtypes = [vp, vp, sz, vp]
+    L.dgs_probe_valu.restype = ctypes.c_int
+    L.dgs_probe_valu.argtypes = [i32, ctypes.c_int64, vp, vp]
     _lib = L
     return L
 

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgs.so")
 SOURCES = ["geometry.hip", "sort.hip", "binning.hip", "composite.hip", "utility.hip", "sampler.hip", "objective.hip",
-           "capi.hip"]
+           "probe.hip", "capi.hip"]
 ARCH = os.environ.get("DGS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
