@@ -215,6 +215,29 @@ int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *
                float *image, float *tfinal, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dgs_render
+ * with its workspace in a static device array of the library instead of a
+ * caller-owned buffer.  Same arguments, outputs and kernels as dgs_render
+ * (the images are bit-identical), without ws / ws_bytes.
+ *   instances  device int64 [1] or NULL: receives the tile instances the
+ *              scene needs (as dgs_check reports them); more than
+ *              instance_capacity means the images are undefined (overflow).
+ * Limit: the call's workspace (dgs_workspace_bytes of the same arguments)
+ * must fit DGS_NOALLOC_SCRATCH_BYTES, else DGS_ERR_WORKSPACE before any HIP
+ * call.  The array is allocated with the library's device code on each GPU
+ * it runs on and held until the process ends; this call allocates and frees
+ * nothing and does not synchronise.  All calls on one GPU share that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (concurrent streams or threads) race and must be serialised by the caller.
+ * dgs_backward and dgs_check cannot name this array.
+ */
+#define DGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int dgs_render_noalloc(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                       const dgs_tuning *tun, int64_t instance_capacity, float *image, float *tfinal,
+                       int64_t *instances, void *stream);
+
+/*
  * The two halves of dgs_render (Sec. 6: one scene and time shared by every
  * state of the batch).  dgs_bin runs the shared part -- deformation,
  * projection, depth sort, tile binning and the per-tile lists -- for the

@@ -24,8 +24,9 @@ EXPORTS = (
     "dgs_utility_count", "dgs_utility", "dgs_utility_check", "dgs_distortion_scratch_bytes", "dgs_distortion",
     "dgs_risk_adjusted", "dgs_sample_states", "dgs_objective_scratch_bytes", "dgs_objective",
     "dgs_objective_check", "dgs_l1_scratch_bytes", "dgs_l1_loss", "dgs_l1_loss_grad",
-    "dgs_probe_copy", "dgs_probe_valu",
+    "dgs_probe_copy", "dgs_probe_valu", "dgs_render_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DGS_NOALLOC_SCRATCH_BYTES
 PROBE_THREADS = 524288
 
 
@@ -115,6 +116,8 @@ def lib():
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = common + [i64, vp, vp, vp]
+    L.dgs_render_noalloc.restype = ctypes.c_int
+    L.dgs_render_noalloc.argtypes = [P(Scene), P(Camera), P(States), P(Tuning), i64, vp, vp, vp, vp]
     L.dgs_composite_launch.restype = ctypes.c_int
     L.dgs_composite_launch.argtypes = [P(Camera), P(Tuning), i32, P(i32), P(i32), P(i64), P(i64), P(i32)]
     L.dgs_bin.restype = ctypes.c_int

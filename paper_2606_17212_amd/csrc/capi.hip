@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/dgs.h"
@@ -533,6 +534,90 @@ int dgs_render(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *
   if (states->num_states == 0) return DGS_OK;
   if ((rc = dgs_bin(scene, cam, states, tun, ws, ws_bytes, cap, stream))) return rc;
   return dgs_composite(scene, cam, states, tun, ws, ws_bytes, cap, image, tfinal, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free render.  The workspace of dgs_render_noalloc is a static
+// device array of fixed size (every GPU the library runs on holds its own
+// copy until the process ends).  In host code `scratch` only names the
+// symbol: its device address comes from hipGetSymbolAddress, looked up once
+// per device on that device's first call and kept in noalloc_ptr.
+constexpr size_t kNoAllocScratchBytes = DGS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+void *noalloc_ptr[kMaxDevices];
+
+// Device address of the current device's scratch (looked up on first use).
+int noalloc_scratch(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DGS_ERR_HIP, "dgs_render_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  }
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(DGS_ERR_UNSUPPORTED, "dgs_render_noalloc: device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(DGS_ERR_HIP, "dgs_render_noalloc: address of the static scratch on device %d: %s", dev,
+                  hipGetErrorString(e));
+    }
+    noalloc_ptr[dev] = p;
+  }
+  *out = noalloc_ptr[dev];
+  return DGS_OK;
+}
+
+__global__ void k_report_instances(const Header *h, int64_t *out) { *out = (int64_t)h->instances; }
+
+}  // namespace
+
+extern "C" {
+
+int dgs_render_noalloc(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,
+                       const dgs_tuning *tun, int64_t cap, float *image, float *tfinal, int64_t *instances,
+                       void *stream) {
+  g_err.clear();
+  // sizes first, on the host: nothing reaches the device for a call that does not fit
+  int rc;
+  if ((rc = check_scene(scene)) || (rc = check_camera(cam))) return rc;
+  const int P = scene->num_clusters * scene->num_contexts;
+  if ((rc = check_states(states, P, 1))) return rc;
+  Tiling t;
+  if ((rc = check_tuning(cam, tun, &t))) return rc;
+  if (cap < 0 || cap > (int64_t)0xFFFFFFFFll)
+    return fail(DGS_ERR_INVALID_ARG, "instance capacity %lld outside 0..2^32-1", (long long)cap);
+  const int records = scene->refine ? 4 * scene->n : scene->n;
+  const size_t need = make_layout(records, P, t.tiles_x, t.tiles_y, states->num_states, cap).total;
+  if (need > kNoAllocScratchBytes)
+    return fail(DGS_ERR_WORKSPACE,
+                "dgs_render_noalloc: this call needs %zu bytes of workspace, the static scratch holds %zu "
+                "(use fewer Gaussians, states, tiles or a smaller instance capacity, or dgs_render)",
+                need, kNoAllocScratchBytes);
+  if (states->num_states > 0 && !image) return fail(DGS_ERR_INVALID_ARG, "image is NULL");
+  if (states->num_states == 0 && !instances) return DGS_OK;
+  void *ws = nullptr;
+  if ((rc = noalloc_scratch(&ws))) return rc;
+  if ((rc = dgs_bin(scene, cam, states, tun, ws, kNoAllocScratchBytes, cap, stream))) return rc;
+  if (states->num_states > 0 &&
+      (rc = dgs_composite(scene, cam, states, tun, ws, kNoAllocScratchBytes, cap, image, tfinal, stream)))
+    return rc;
+  if (instances) {
+    Call cl;
+    if ((rc = prepare(scene, cam, states, tun, ws, kNoAllocScratchBytes, cap, 1, &cl))) return rc;
+    k_report_instances<<<1, 1, 0, (hipStream_t)stream>>>(at<Header>(ws, cl.L.header), instances);
+  }
+  return hip_check("render_noalloc launch");
 }
 
 int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *states,

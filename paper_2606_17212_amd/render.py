@@ -163,6 +163,44 @@ def _c_states(codes: Optional[torch.Tensor], basis, background, num_states=None)
     return st
 
 
+def render_noalloc(scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis, background,
+                   instance_capacity: int, out: torch.Tensor, tfinal: Optional[torch.Tensor] = None,
+                   instances: Optional[torch.Tensor] = None, tile=(16, 16), states_per_group=16,
+                   persistent=None, lds_batch=256) -> torch.Tensor:
+    """``dgs_render_noalloc``: a batched render whose workspace is the
+    library's static device array, for callers that cannot allocate (graph
+    capture, serving loops).  Every output is caller-provided: ``out`` [W, H,
+    Wd, 3] FP32, optional ``tfinal`` [W, H, Wd] FP32 and ``instances`` int64
+    [1] (the tile instances the scene needs; above ``instance_capacity`` the
+    images are undefined).  Raises DgsError (DGS_ERR_WORKSPACE) when the call
+    does not fit the array (``DGS_NOALLOC_SCRATCH_BYTES``).  Calls on one GPU
+    share the array and must not overlap."""
+    dev = out.device
+    _check_tensor(codes, "codes", torch.uint8, dev)
+    if codes.dim() != 2 or codes.shape[1] != scene.num_packets:
+        raise ValueError(f"codes must be [W, {scene.num_packets}]")
+    W = int(codes.shape[0])
+    _check_tensor(out, "out", torch.float32, dev)
+    if tuple(out.shape) != (W, camera.height, camera.width, 3):
+        raise ValueError(f"out has shape {tuple(out.shape)}, expected {(W, camera.height, camera.width, 3)}")
+    if tfinal is not None:
+        _check_tensor(tfinal, "tfinal", torch.float32, dev)
+        if tuple(tfinal.shape) != (W, camera.height, camera.width):
+            raise ValueError(f"tfinal has shape {tuple(tfinal.shape)}, expected {(W, camera.height, camera.width)}")
+    if instances is not None:
+        _check_tensor(instances, "instances", torch.int64, dev)
+        if instances.numel() < 1:
+            raise ValueError("instances needs one element")
+    flags = 0 if persistent is None else (_abi.TUNE_PERSISTENT if persistent else _abi.TUNE_GRID)
+    tun = _abi.Tuning(int(tile[0]), int(tile[1]), int(states_per_group), flags, int(lds_batch))
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _abi.check(_abi.lib().dgs_render_noalloc(
+        ctypes.byref(_c_scene(scene)), ctypes.byref(_c_camera(camera)),
+        ctypes.byref(_c_states(codes, basis, background)), ctypes.byref(tun), int(instance_capacity),
+        _ptr(out), _ptr(tfinal), _ptr(instances), st))
+    return out
+
+
 class Renderer:
     """Owns the device workspace and the launch shape.
 

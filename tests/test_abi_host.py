@@ -242,3 +242,39 @@ def test_live_capture_blocks_replanning(monkeypatch):
         r._ensure_ws(4096)
     r._ensure_ws(512)  # fits: the buffer is kept
     assert r.ws_bytes == 1024
+
+
+def test_noalloc_render_refuses_oversize_and_bad_arguments_before_any_hip_call():
+    """dgs_render_noalloc: a call whose workspace would not fit the static
+    array, and malformed arguments, are refused on the host."""
+    abi, L = _lib()
+    cam = _cam(abi)
+    tun = abi.Tuning(16, 16, 16, 0)
+    st = abi.States()
+    st.num_states = 16
+    st.codes = 4096  # never dereferenced
+    img = ctypes.c_void_p(4096)
+    sc = abi.Scene(4096, 2, 0, 8, 4, *([4096] * 8))
+    need = L.dgs_workspace_bytes(4096, 32, ctypes.byref(cam), ctypes.byref(tun), 16, 200_000)
+    assert 0 < need <= abi.NOALLOC_SCRATCH_BYTES
+    # the instance capacity alone pushes the workspace past the array
+    big = 0xFFFFFFFF
+    assert L.dgs_workspace_bytes(4096, 32, ctypes.byref(cam), ctypes.byref(tun), 16, big) > \
+        abi.NOALLOC_SCRATCH_BYTES
+    assert L.dgs_render_noalloc(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), big,
+                                img, None, None, None) == 2
+    assert b"static scratch" in L.dgs_last_error()
+    # so does a large scene
+    sc_big = abi.Scene(4_000_000, 2, 0, 8, 4, *([4096] * 8))
+    assert L.dgs_render_noalloc(ctypes.byref(sc_big), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun),
+                                1000, img, None, None, None) == 2
+    # missing image, NULL scene, bad capacity, unsupported tile
+    assert L.dgs_render_noalloc(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), 1000,
+                                None, None, None, None) == 1
+    assert L.dgs_render_noalloc(None, ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), 1000, img, None,
+                                None, None) == 1
+    assert L.dgs_render_noalloc(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(tun), -1, img,
+                                None, None, None) == 1
+    t8 = abi.Tuning(8, 8, 16, 0)
+    assert L.dgs_render_noalloc(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(t8), 1000,
+                                img, None, None, None) == 5
