@@ -1,10 +1,13 @@
-// Tile binning: per-Gaussian instance counts in depth order, instance
-// emission, per-tile ranges, the per-(state group, packet, layer) delivery
-// bit table, and the per-state compaction of delivered Gaussians.
+// Tile binning: per-tile ranges from the Gaussians' tile rectangles, the
+// instances of the depth-sorted Gaussians put in (tile, depth, index) order,
+// the per-(state group, packet, layer) delivery bit table, and the per-state
+// compaction of delivered Gaussians.
 //
-// Gaussians are first sorted by (depth bits, index); instances are emitted in
-// that order and then sorted stably by tile id alone, which yields the
-// (tile, depth, index) order with a sort over 12-13 key bits instead of 44-45.
+// Gaussians are first sorted by (depth bits, index).  For tile grids of at
+// most kMaxSupers super-tiles the instances are then placed by a two-level
+// stable scatter (super-tile lists, then tiles); larger grids emit the
+// instances in depth order and sort them stably by tile id alone, a sort over
+// the tile bits instead of tile and depth bits.
 #include <type_traits>
 
 #include "common.h"
@@ -53,13 +56,11 @@ void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect,
 // exponent q' over the block's pixel centres must not fall below log2(1/255)
 // by more than a rounding margin.  Pixels outside reached blocks would all be
 // skipped by the per-pixel test, so the mask never changes a result.
-__device__ inline uint32_t block_reach_mask(const float4 &r0, const float4 &r1, const uint2 &pb, uint32_t tx,
-                                            uint32_t ty, int tile_w, int tile_h) {
+__device__ inline uint32_t block_reach_mask_pre(const float4 &r0, const float4 &r1, const uint2 &pb, float need,
+                                                float ia, float ic, uint32_t tx, uint32_t ty, int tile_w, int tile_h) {
   const int tpx = (int)tx * tile_w, tpy = (int)ty * tile_h;
   const int x0 = (int)(pb.x & 0xFFFFu) - tpx, y0 = (int)(pb.x >> 16) - tpy;
   const int x1 = (int)(pb.y & 0xFFFFu) - tpx, y1 = (int)(pb.y >> 16) - tpy;
-  const float need = kQSkip - 0.01f - r0.z;
-  const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
   const float ftx = (float)tpx + 0.5f, fty = (float)tpy + 0.5f;
   if (box_all_reach(r1.x, r1.y, r1.z, r0.x - (ftx + (float)(tile_w - 1)), r0.x - ftx, r0.y - (fty + (float)(tile_h - 1)),
                     r0.y - fty, need))
@@ -75,8 +76,15 @@ __device__ inline uint32_t block_reach_mask(const float4 &r0, const float4 &r1, 
         mask |= 1u << w;
     }
   }
-  (void)tile_h;
   return mask;
+}
+
+// (need = log2(1/255) - 0.01 - log2 o; ia = -1/(2 A'), ic = -1/(2 C') of the record)
+__device__ inline uint32_t block_reach_mask(const float4 &r0, const float4 &r1, const uint2 &pb, uint32_t tx,
+                                            uint32_t ty, int tile_w, int tile_h) {
+  const float need = kQSkip - 0.01f - r0.z;
+  const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
+  return block_reach_mask_pre(r0, r1, pb, need, ia, ic, tx, ty, tile_w, tile_h);
 }
 
 __device__ inline uint32_t wave_block_mask(uint32_t id, uint32_t tx, uint32_t ty, int tile_w, int tile_h,
@@ -184,13 +192,17 @@ k_tile_prefix(uint32_t *__restrict__ diff, int tiles_x, int tiles_y, uint32_t *_
   }
 }
 
+// h->instances holds the total of the counts; more than the capacity is an
+// overflow, after which the instance arrays are incomplete and every range
+// is empty.
 __global__ void __launch_bounds__(kBlock)
 k_ranges_from_counts(const uint32_t *__restrict__ tcnt, const uint32_t *__restrict__ tstart, int tiles,
-                     const Header *__restrict__ h, uint2 *__restrict__ ranges) {
+                     Header *__restrict__ h, uint2 *__restrict__ ranges) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
+  const bool over = h->overflow || h->instances > h->capacity;
+  if (t == 0 && over) h->overflow = 1u;
   if (t >= tiles) return;
-  // after an overflow the instance arrays are incomplete: every range is empty
-  ranges[t] = h->overflow ? make_uint2(0u, 0u) : make_uint2(tstart[t], tstart[t] + tcnt[t]);
+  ranges[t] = over ? make_uint2(0u, 0u) : make_uint2(tstart[t], tstart[t] + tcnt[t]);
 }
 
 // One workgroup, the whole difference array in LDS: 2D prefix (rows, then
@@ -266,246 +278,485 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
   }
 }
 
-bool tile_ranges_in_lds(int tiles_x, int tiles_y) {
-  return (int64_t)(tiles_x + 1) * (tiles_y + 1) <= kDiffLds && (int64_t)tiles_x * tiles_y <= kChunkTiles;
-}
+bool tile_ranges_in_lds(int tiles_x, int tiles_y) { return (int64_t)(tiles_x + 1) * (tiles_y + 1) <= kDiffLds; }
 
 // ---------------------------------------------------------------------------
-// One-pass stable scatter of the tile instances (used when the tile grid fits
-// LDS).  The depth-sorted Gaussians are cut into chunks of kChunk; one wave
-// per chunk counts the chunk's instances per tile, the counts are turned into
-// each chunk's first slot in every tile's range (ranges[t].x plus the counts
-// of the earlier chunks), and one wave per chunk then walks its Gaussians in
-// depth order writing every instance to its tile's next slot.  Within a tile
-// the instances end up in depth order (chunk by chunk, then in order inside
-// the chunk): the order a stable sort by tile of the depth-ordered emission
-// gives.  The tiles of one Gaussian are distinct, so the per-tile slot
-// counters in LDS need no atomics; successive Gaussians are ordered by the
-// wave's program order.
+// Two-level stable scatter of the tile instances (tile grids of at most
+// kMaxSupers super-tiles of kSuper x kSuper tiles).
+//
+// Level 1 puts every depth-sorted Gaussian into the list of each super-tile
+// its tile rectangle touches, in depth order.  Level 2 walks each super-tile's
+// list in segments of kSegWave entries, one wave per segment, and writes the
+// instances of the super-tile's 64 tiles: per tile, one ballot over the
+// wave's 64 entries ranks the lanes that cover it, and they write
+// consecutive slots of that tile's range with one store.  A tile's run of
+// slots per segment is kSegWave x (the share of the super-tile a Gaussian
+// covers) entries long, where scattering chunks of depth-ordered Gaussians
+// straight to tiles leaves runs of a few entries per tile and partial
+// cache-line writes.  Within a tile the instances end up in depth order: the
+// super-tile lists keep depth order, and segments, rounds of 64 entries and
+// lanes follow it.  Every kernel returns at once after an overflow (the
+// ranges are empty then and the lists would not fit).
 
-// The 64 Gaussians [jb, jb + 64) of a wave, one per lane: id and tile
-// rectangle (zero for culled or missing ones), and the records the reach
-// masks need.
-struct WaveGaussians {
-  uint32_t id, rx, ry;
-  float4 r0, r1;
-  uint2 pb;
-};
+// Super-tile rectangle [sx0, sx1) x [sy0, sy1) of depth-sorted Gaussian j
+// (empty past the active count or when culled).
+__device__ inline void super_rect(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval,
+                                  const uint2 *__restrict__ rect, int j, int nact, uint32_t &id, uint32_t &sx0,
+                                  uint32_t &sy0, uint32_t &nx, uint32_t &area) {
+  id = 0u;
+  sx0 = sy0 = nx = area = 0u;
+  if (j >= nact || dkey[j] == 0xFFFFFFFFu) return;
+  id = dval[j];
+  const uint2 r = rect[id];
+  const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+  if (x1 <= x0 || y1 <= y0) return;
+  sx0 = x0 / kSuper;
+  sy0 = y0 / kSuper;
+  nx = (x1 - 1) / kSuper + 1 - sx0;
+  area = nx * ((y1 - 1) / kSuper + 1 - sy0);
+}
 
-template <bool RECORDS>
-__device__ __forceinline__ WaveGaussians load_wave_gaussians(const uint32_t *__restrict__ dkey,
-                                                             const uint32_t *__restrict__ dval,
-                                                             const uint2 *__restrict__ rect, int j, int j1,
-                                                             const float4 *__restrict__ rec0,
-                                                             const float4 *__restrict__ rec1,
-                                                             const uint2 *__restrict__ pbox) {
-  WaveGaussians q{};
-  if (j < j1 && dkey[j] != 0xFFFFFFFFu) {
-    q.id = dval[j];
-    const uint2 r = rect[q.id];
-    q.rx = r.x;
-    q.ry = r.y;
-    if (RECORDS) {
-      q.r0 = rec0[q.id];
-      q.r1 = rec1[q.id];
-      q.pb = pbox[q.id];
+__device__ inline uint32_t super_at(uint32_t k, uint32_t sx0, uint32_t sy0, uint32_t nx, int supers_x) {
+  const uint32_t dy = k / nx;
+  return (sy0 + dy) * (uint32_t)supers_x + sx0 + (k - dy * nx);
+}
+
+// Per-wave super-tile counts of one round of 64 Gaussians: every lane sets
+// its bit in the wave's word of each super-tile it covers; the lowest
+// covering lane then adds the word's population to cnt and clears the word.
+// (A lane that finds the word already cleared by the lowest one adds zero.)
+// LDS operations of one wave complete in order, so each phase sees the last.
+__device__ inline void super_round_count(unsigned long long *bits, uint32_t *cnt, uint32_t sx0, uint32_t sy0,
+                                         uint32_t nx, uint32_t area, int supers_x) {
+  const unsigned long long me = 1ull << __lane_id(), below = lanemask_lt();
+  for (uint32_t k = 0; k < area; ++k) atomicOr(&bits[super_at(k, sx0, sy0, nx, supers_x)], me);
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t k = 0; k < area; ++k) {
+    const uint32_t s = super_at(k, sx0, sy0, nx, supers_x);
+    const unsigned long long b = bits[s];
+    if ((b & below) == 0ull) {
+      cnt[s] += (uint32_t)__popcll(b);
+      bits[s] = 0ull;
     }
   }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Level 1 counts: instances per (super-tile, chunk of kLevel1Chunk Gaussians);
+// each wave takes four rounds of 64 consecutive Gaussians.
+__global__ void __launch_bounds__(kBlock)
+k_super_count(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
+              const unsigned *__restrict__ n_active, int grid_n, int supers_x, int nsup, int chunks,
+              const Header *__restrict__ h, uint32_t *__restrict__ scnt) {
+  extern __shared__ unsigned long long lds_bits[];  // [4][nsup] words, then [4][nsup] counts
+  if (h->overflow) return;
+  const int w = threadIdx.x >> 6;
+  unsigned long long *bits = lds_bits + w * nsup;
+  uint32_t *cnt_all = reinterpret_cast<uint32_t *>(lds_bits + 4 * nsup), *cnt = cnt_all + w * nsup;
+  for (int s = __lane_id(); s < nsup; s += kWave) {
+    bits[s] = 0ull;
+    cnt[s] = 0u;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int nact = n_active ? (int)*n_active : grid_n;
+  const int jw = blockIdx.x * kLevel1Chunk + w * (kLevel1Chunk / 4);
+  for (int r = 0; r < kLevel1Chunk / 4 / kWave; ++r) {
+    uint32_t id, sx0, sy0, nx, area;
+    super_rect(dkey, dval, rect, jw + r * kWave + __lane_id(), nact, id, sx0, sy0, nx, area);
+    super_round_count(bits, cnt, sx0, sy0, nx, area, supers_x);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < nsup; s += kBlock)
+    scnt[(int64_t)s * chunks + blockIdx.x] =
+        cnt_all[s] + cnt_all[nsup + s] + cnt_all[2 * nsup + s] + cnt_all[3 * nsup + s];
+}
+
+// Level 1: exclusive prefix over chunks of one super-tile's counts (in place)
+// and its list length.  One workgroup per super-tile, a contiguous run of
+// chunks per thread.
+__global__ void __launch_bounds__(kBlock)
+k_super_scan(uint32_t *__restrict__ scnt, int chunks, const Header *__restrict__ h, uint32_t *__restrict__ slen) {
+  __shared__ uint32_t wsum[4];
+  if (h->overflow) return;
+  uint32_t *row = scnt + (int64_t)blockIdx.x * chunks;
+  const int per = (chunks + kBlock - 1) / kBlock;
+  const int c0 = threadIdx.x * per < chunks ? threadIdx.x * per : chunks;
+  const int c1 = c0 + per < chunks ? c0 + per : chunks;
+  uint32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += row[c];
+  const uint32_t incl = wave_incl_scan(sum);
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int k = 0; k < w; ++k) run += wsum[k];
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t v = row[c];
+    row[c] = run;
+    run += v;
+  }
+  if (threadIdx.x == kBlock - 1) slen[blockIdx.x] = run;
+}
+
+// Super-tile tables from the list lengths (one workgroup, in LDS): list start
+// and first level-2 segment of each super-tile, seg[nsup] = segments in all.
+__device__ inline void super_tables(const uint32_t *__restrict__ slen, int nsup, uint32_t *sstart, uint32_t *seg) {
+  __shared__ uint32_t wl[4], wg[4];
+  // each thread owns kMaxSupers / kBlock consecutive super-tiles
+  constexpr int per = kMaxSupers / kBlock;
+  const int s0 = threadIdx.x * per;
+  uint32_t len[per], tl = 0, tg = 0;
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    len[k] = s0 + k < nsup ? slen[s0 + k] : 0u;
+    tl += len[k];
+    tg += (len[k] + kSegWave - 1) / kSegWave;
+  }
+  const uint32_t il = wave_incl_scan(tl), ig = wave_incl_scan(tg);
+  const int w = threadIdx.x >> 6;
+  if (__lane_id() == kWave - 1) {
+    wl[w] = il;
+    wg[w] = ig;
+  }
+  __syncthreads();
+  uint32_t rl = il - tl, rg = ig - tg;
+  for (int k = 0; k < w; ++k) {
+    rl += wl[k];
+    rg += wg[k];
+  }
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    if (s0 + k <= nsup) {
+      sstart[s0 + k] = rl;
+      seg[s0 + k] = rg;
+    }
+    rl += len[k];
+    rg += (len[k] + kSegWave - 1) / kSegWave;
+  }
+  if (threadIdx.x == 0 && nsup == kMaxSupers) {  // the one entry past the last thread's run
+    sstart[kMaxSupers] = wl[0] + wl[1] + wl[2] + wl[3];
+    seg[kMaxSupers] = wg[0] + wg[1] + wg[2] + wg[3];
+  }
+  __syncthreads();
+}
+
+// Level 1 scatter: the same rounds as k_super_count; each wave's first slot
+// per super-tile is the super-tile's list start + the chunk's prefix + the
+// counts of the workgroup's earlier waves, and a covering lane's slot adds
+// the number of lower lanes covering the same super-tile in its round.
+// Workgroup 0 also writes the super-tile tables for level 2:
+// tab[0..] list lengths (already there), tab[K+1..] starts, tab[2K+2..]
+// first segments (K = kMaxSupers).
+__global__ void __launch_bounds__(kBlock)
+k_super_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
+                const unsigned *__restrict__ n_active, int grid_n, int supers_x, int nsup, int chunks,
+                const Header *__restrict__ h, const uint32_t *__restrict__ scnt, uint32_t *__restrict__ tab,
+                uint32_t *__restrict__ list) {
+  extern __shared__ unsigned long long lds_bits[];  // [4][nsup] words, then [4][nsup] counts
+  __shared__ uint32_t sstart[kMaxSupers + 1], seg[kMaxSupers + 1];
+  if (h->overflow) return;
+  super_tables(tab, nsup, sstart, seg);
+  if (blockIdx.x == 0)
+    for (int s = threadIdx.x; s <= nsup; s += kBlock) {
+      tab[kMaxSupers + 1 + s] = sstart[s];
+      tab[2 * (kMaxSupers + 1) + s] = seg[s];
+    }
+  const int w = threadIdx.x >> 6;
+  unsigned long long *bits = lds_bits + w * nsup;
+  uint32_t *cnt_all = reinterpret_cast<uint32_t *>(lds_bits + 4 * nsup), *cnt = cnt_all + w * nsup;
+  for (int s = __lane_id(); s < nsup; s += kWave) {
+    bits[s] = 0ull;
+    cnt[s] = 0u;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int nact = n_active ? (int)*n_active : grid_n;
+  const int jw = blockIdx.x * kLevel1Chunk + w * (kLevel1Chunk / 4);
+  constexpr int rounds = kLevel1Chunk / 4 / kWave;
+  for (int r = 0; r < rounds; ++r) {
+    uint32_t id, sx0, sy0, nx, area;
+    super_rect(dkey, dval, rect, jw + r * kWave + __lane_id(), nact, id, sx0, sy0, nx, area);
+    super_round_count(bits, cnt, sx0, sy0, nx, area, supers_x);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < nsup; s += kBlock) {  // counts -> first slot of each wave
+    const uint32_t a = cnt_all[s], b = cnt_all[nsup + s], c = cnt_all[2 * nsup + s];
+    const uint32_t base = sstart[s] + scnt[(int64_t)s * chunks + blockIdx.x];
+    cnt_all[s] = base;
+    cnt_all[nsup + s] = base + a;
+    cnt_all[2 * nsup + s] = base + a + b;
+    cnt_all[3 * nsup + s] = base + a + b + c;
+  }
+  __syncthreads();
+  const unsigned long long me = 1ull << __lane_id(), below = lanemask_lt();
+  for (int r = 0; r < rounds; ++r) {
+    uint32_t id, sx0, sy0, nx, area;
+    super_rect(dkey, dval, rect, jw + r * kWave + __lane_id(), nact, id, sx0, sy0, nx, area);
+    for (uint32_t k = 0; k < area; ++k) atomicOr(&bits[super_at(k, sx0, sy0, nx, supers_x)], me);
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t k = 0; k < area; ++k) {
+      const uint32_t s = super_at(k, sx0, sy0, nx, supers_x);
+      list[cnt[s] + (uint32_t)__popcll(bits[s] & below)] = id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t k = 0; k < area; ++k) {
+      const uint32_t s = super_at(k, sx0, sy0, nx, supers_x);
+      const unsigned long long b = bits[s];
+      if ((b & below) == 0ull) {
+        cnt[s] += (uint32_t)__popcll(b);
+        bits[s] = 0ull;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Level 2 segment g: super-tile s with seg[s] <= g < seg[s + 1] (segments of
+// empty super-tiles have no width), list entries [e0, e1), tile origin.
+struct SuperSeg {
+  uint32_t e0, e1, tx0, ty0;
+  int s;
+};
+
+__device__ inline SuperSeg find_segment(uint32_t g, const uint32_t *seg, const uint32_t *sstart,
+                                        const uint32_t *slen, int nsup, int supers_x) {
+  int lo = 0, hi = nsup;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (seg[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  SuperSeg q;
+  q.s = lo;
+  q.e0 = sstart[lo] + (g - seg[lo]) * (uint32_t)kSegWave;
+  const uint32_t end = sstart[lo] + slen[lo];
+  q.e1 = q.e0 + kSegWave < end ? q.e0 + kSegWave : end;
+  q.tx0 = (uint32_t)(lo % supers_x) * kSuper;
+  q.ty0 = (uint32_t)(lo / supers_x) * kSuper;
   return q;
 }
 
-// Visits the tiles of the wave's Gaussians g = 0..ng-1 in order, lanes over
-// each rectangle (row-major); f(g, tile, tx, ty) runs once per instance.
-template <typename F>
-__device__ __forceinline__ void for_wave_instances(const WaveGaussians &q, int ng, int tiles_x, F &&f) {
-  for (int g = 0; g < ng; ++g) {
-    const uint32_t gx = __builtin_amdgcn_readlane(q.rx, g), gy = __builtin_amdgcn_readlane(q.ry, g);
-    const uint32_t x0 = gx & 0xFFFFu, y0 = gx >> 16, x1 = gy & 0xFFFFu, y1 = gy >> 16;
-    if (x1 <= x0 || y1 <= y0) continue;  // culled (all zero) or empty
-    const uint32_t nx = x1 - x0, area = nx * (y1 - y0);
-    for (uint32_t k = __lane_id(); k < area; k += kWave) {
-      const uint32_t dy = k / nx, tx = x0 + (k - dy * nx), ty = y0 + dy;
-      f(g, ty * (uint32_t)tiles_x + tx, tx, ty);
+// The tiles of rectangle r inside the super-tile at (tx0, ty0): bit 8 ly + lx.
+__device__ inline unsigned long long local_tiles(uint2 r, uint32_t tx0, uint32_t ty0) {
+  const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+  const uint32_t lx0 = x0 > tx0 ? x0 - tx0 : 0u, ly0 = y0 > ty0 ? y0 - ty0 : 0u;
+  const uint32_t lx1 = x1 > tx0 ? (x1 - tx0 < (uint32_t)kSuper ? x1 - tx0 : (uint32_t)kSuper) : 0u;
+  const uint32_t ly1 = y1 > ty0 ? (y1 - ty0 < (uint32_t)kSuper ? y1 - ty0 : (uint32_t)kSuper) : 0u;
+  if (lx1 <= lx0 || ly1 <= ly0) return 0ull;
+  const unsigned long long row = (unsigned long long)((1u << lx1) - (1u << lx0));
+  const unsigned long long hi = ly1 >= (uint32_t)kSuper ? ~0ull : (1ull << (8u * ly1)) - 1ull;
+  const unsigned long long lo = (1ull << (8u * ly0)) - 1ull;
+  return (row * 0x0101010101010101ull) & hi & ~lo;
+}
+
+__device__ inline void load_super_tables(const uint32_t *__restrict__ tab, int nsup, uint32_t *slen, uint32_t *sstart,
+                                         uint32_t *seg) {
+  for (int s = threadIdx.x; s <= nsup; s += blockDim.x) {
+    slen[s] = s < nsup ? tab[s] : 0u;
+    sstart[s] = tab[kMaxSupers + 1 + s];
+    seg[s] = tab[2 * (kMaxSupers + 1) + s];
+  }
+  __syncthreads();
+}
+
+// Level 2 counts: instances of each of the super-tile's 64 tiles in one
+// segment (one wave per segment, striding over the segments): the covered
+// rectangles go into a per-wave 9x9 difference array, whose 2D prefix gives
+// the counts.
+__global__ void __launch_bounds__(kBlock)
+k_stile_count(const uint32_t *__restrict__ list, const uint2 *__restrict__ rect, const uint32_t *__restrict__ tab,
+              int nsup, int supers_x, const Header *__restrict__ h, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t slen[kMaxSupers + 1], sstart[kMaxSupers + 1], seg[kMaxSupers + 1];
+  __shared__ uint32_t diff[4][(kSuper + 1) * (kSuper + 1)];
+  if (h->overflow) return;
+  load_super_tables(tab, nsup, slen, sstart, seg);
+  const int w = threadIdx.x >> 6, lane = __lane_id();
+  const uint32_t total = seg[nsup];
+  uint32_t *d = diff[w];
+  constexpr int nd = kSuper + 1;
+  for (uint32_t g = blockIdx.x * 4u + (uint32_t)w; g < total; g += gridDim.x * 4u) {
+    const SuperSeg q = find_segment(g, seg, sstart, slen, nsup, supers_x);
+    for (int k = lane; k < nd * nd; k += kWave) d[k] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t e = q.e0 + lane; e < q.e1; e += kWave) {
+      const uint2 r = rect[list[e]];
+      const uint32_t x0 = r.x & 0xFFFFu, y0 = r.x >> 16, x1 = r.y & 0xFFFFu, y1 = r.y >> 16;
+      const uint32_t lx0 = x0 > q.tx0 ? x0 - q.tx0 : 0u, ly0 = y0 > q.ty0 ? y0 - q.ty0 : 0u;
+      const uint32_t lx1 = x1 > q.tx0 ? (x1 - q.tx0 < (uint32_t)kSuper ? x1 - q.tx0 : (uint32_t)kSuper) : 0u;
+      const uint32_t ly1 = y1 > q.ty0 ? (y1 - q.ty0 < (uint32_t)kSuper ? y1 - q.ty0 : (uint32_t)kSuper) : 0u;
+      if (lx1 <= lx0 || ly1 <= ly0) continue;
+      atomicAdd(&d[ly0 * nd + lx0], 1u);
+      atomicAdd(&d[ly0 * nd + lx1], 0xFFFFFFFFu);
+      atomicAdd(&d[ly1 * nd + lx0], 0xFFFFFFFFu);
+      atomicAdd(&d[ly1 * nd + lx1], 1u);
     }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < kSuper) {  // rows
+      uint32_t acc = 0;
+      for (int x = 0; x < kSuper; ++x) {
+        acc += d[lane * nd + x];
+        d[lane * nd + x] = acc;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < kSuper) {  // columns
+      uint32_t acc = 0;
+      for (int y = 0; y < kSuper; ++y) {
+        acc += d[y * nd + lane];
+        d[y * nd + lane] = acc;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    hist[(int64_t)g * 64 + lane] = d[(lane >> 3) * nd + (lane & 7)];
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-__device__ __forceinline__ uint32_t readlane_u(uint32_t v, int g) { return __builtin_amdgcn_readlane(v, g); }
-__device__ __forceinline__ float readlane_f(float v, int g) {
-  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), g));
-}
-
-// Instances per tile of chunk c (kChunk depth-ordered Gaussians, four waves
-// of kWaveGauss), counted with LDS atomics.
-__global__ void __launch_bounds__(kBlock)
-k_chunk_hist(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
-             const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles, uint32_t *__restrict__ chist) {
-  extern __shared__ uint32_t cnt[];
-  const int nact = n_active ? (int)*n_active : grid_n;
-  for (int t = threadIdx.x; t < tiles; t += kBlock) cnt[t] = 0u;
-  __syncthreads();
-  const int jb = blockIdx.x * kChunk + (threadIdx.x >> 6) * kWaveGauss;
-  const int j1 = (jb + kWaveGauss) < nact ? (jb + kWaveGauss) : nact;
-  if (jb < j1) {
-    const WaveGaussians q = load_wave_gaussians<false>(dkey, dval, rect, jb + __lane_id(), j1, nullptr, nullptr,
-                                                       nullptr);
-    const int ng = j1 - jb;
-    for_wave_instances(q, ng, tiles_x, [&](int, uint32_t t, uint32_t, uint32_t) { atomicAdd(&cnt[t], 1u); });
-  }
-  __syncthreads();
-  uint32_t *row = chist + (int64_t)blockIdx.x * tiles;
-  for (int t = threadIdx.x; t < tiles; t += kBlock) row[t] = cnt[t];
-}
-
-// Totals of segments of kSegChunks chunks per tile (thread = tile, y = segment).
-__global__ void __launch_bounds__(kBlock)
-k_chunk_segsum(const uint32_t *__restrict__ chist, int chunks, int tiles, uint32_t *__restrict__ segsum) {
-  const int t = blockIdx.x * kBlock + threadIdx.x, sg = blockIdx.y;
-  if (t >= tiles) return;
-  const int c0 = sg * kSegChunks, c1 = (c0 + kSegChunks) < chunks ? (c0 + kSegChunks) : chunks;
-  uint32_t s = 0;
-  for (int c = c0; c < c1; ++c) s += chist[(int64_t)c * tiles + t];
-  segsum[(int64_t)sg * tiles + t] = s;
-}
-
-// segsum[s][t] <- instances of tile t in segments before s (exclusive
-// prefix over segments).  A workgroup takes 16 tiles; 16 threads per tile
-// split the segments into 16 parts (reads coalesced across the 16 tiles):
-// part totals, their prefix in LDS, then each part rewritten in order.
-constexpr int kScanTiles = 16, kScanParts = kBlock / kScanTiles;
-__global__ void __launch_bounds__(kBlock)
-k_chunk_segscan(uint32_t *__restrict__ segsum, int nseg, int tiles) {
-  __shared__ uint32_t part[kScanParts][kScanTiles + 1];
-  const int tl = threadIdx.x % kScanTiles, pp = threadIdx.x / kScanTiles;
-  const int t = blockIdx.x * kScanTiles + tl;
-  const int per = (nseg + kScanParts - 1) / kScanParts;
-  const int k0 = pp * per, k1 = (k0 + per) < nseg ? (k0 + per) : nseg;
+// Level 2: per super-tile and tile, exclusive prefix over the super-tile's
+// segments of the counts, plus the tile's range start: the first slot of the
+// tile's run in every segment (in place).  One 1024-thread workgroup per
+// super-tile: 16 parts of its segments x 64 tiles.
+__global__ void __launch_bounds__(1024)
+k_stile_scan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tab, int supers_x, int tiles_x, int tiles_y,
+             const uint2 *__restrict__ ranges, const Header *__restrict__ h) {
+  __shared__ uint32_t part[16][64];
+  if (h->overflow) return;
+  const int s = blockIdx.x;
+  const uint32_t g0 = tab[2 * (kMaxSupers + 1) + s], g1 = tab[2 * (kMaxSupers + 1) + s + 1];
+  const int tt = threadIdx.x & 63, pp = threadIdx.x >> 6;
+  const uint32_t per = (g1 - g0 + 15u) / 16u;
+  const uint32_t a = g0 + (uint32_t)pp * per < g1 ? g0 + (uint32_t)pp * per : g1;
+  const uint32_t b = a + per < g1 ? a + per : g1;
   uint32_t sum = 0;
-  if (t < tiles)
-    for (int k = k0; k < k1; ++k) sum += segsum[(int64_t)k * tiles + t];
-  part[pp][tl] = sum;
+  for (uint32_t g = a; g < b; ++g) sum += hist[(int64_t)g * 64 + tt];
+  part[pp][tt] = sum;
   __syncthreads();
-  uint32_t run = 0;
-  for (int q = 0; q < pp; ++q) run += part[q][tl];
-  if (t < tiles)
-    for (int k = k0; k < k1; ++k) {
-      const uint32_t v = segsum[(int64_t)k * tiles + t];
-      segsum[(int64_t)k * tiles + t] = run;
-      run += v;
-    }
-}
-
-// chist[c][t] <- ranges[t].x + instances of tile t in chunks before c.
-__global__ void __launch_bounds__(kBlock)
-k_chunk_offsets(uint32_t *__restrict__ chist, const uint32_t *__restrict__ segsum, const uint2 *__restrict__ ranges,
-                int chunks, int tiles) {
-  const int t = blockIdx.x * kBlock + threadIdx.x, sg = blockIdx.y;
-  if (t >= tiles) return;
-  uint32_t base = ranges[t].x + segsum[(int64_t)sg * tiles + t];
-  const int c0 = sg * kSegChunks, c1 = (c0 + kSegChunks) < chunks ? (c0 + kSegChunks) : chunks;
-  for (int c = c0; c < c1; ++c) {
-    const uint32_t v = chist[(int64_t)c * tiles + t];
-    chist[(int64_t)c * tiles + t] = base;
-    base += v;
+  const int tx = (s % supers_x) * kSuper + (tt & 7), ty = (s / supers_x) * kSuper + (tt >> 3);
+  uint32_t run = (tx < tiles_x && ty < tiles_y) ? ranges[ty * tiles_x + tx].x : 0u;
+  for (int k = 0; k < pp; ++k) run += part[k][tt];
+  for (uint32_t g = a; g < b; ++g) {
+    const uint32_t v = hist[(int64_t)g * 64 + tt];
+    hist[(int64_t)g * 64 + tt] = run;
+    run += v;
   }
 }
 
-// Scatter of chunk c: wave w owns Gaussians [c kChunk + w kWaveGauss, +kWaveGauss).  Its
-// instances of tile t go after the chunk's first slot choff[c][t] and the
-// instances of tile t owned by waves < w.  The four waves' next slots per tile
-// live in LDS as 16-bit counts relative to choff[c][t] (at most kWaveGauss per
-// wave and tile, so the prefix over the waves fits), which is read per
-// instance: half the LDS of absolute 32-bit slots, so twice the resident
-// workgroups (measured faster at 2,500 tiles as well as at 8,160).
-__global__ void __launch_bounds__(kBlock)
-k_chunk_scatter(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
-                const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles, int tile_w, int tile_h,
-                const float4 *__restrict__ rec0, const float4 *__restrict__ rec1, const uint2 *__restrict__ pbox,
-                const uint32_t *__restrict__ choff, const Header *__restrict__ h, uint32_t *__restrict__ tval) {
-  using Slot = uint16_t;
-  extern __shared__ uint32_t lds_raw[];
-  Slot *rel = reinterpret_cast<Slot *>(lds_raw);  // [4][tiles]
-  if (h->overflow) return;  // the ranges are empty; nothing may be written past the capacity
-  const int nact = n_active ? (int)*n_active : grid_n;
-  const int w = threadIdx.x >> 6;
-  for (int t = threadIdx.x; t < 4 * tiles; t += kBlock) rel[t] = 0;
-  __syncthreads();
-  const int jb = blockIdx.x * kChunk + w * kWaveGauss;
-  const int j1 = (jb + kWaveGauss) < nact ? (jb + kWaveGauss) : nact;
-  const int ng = jb < j1 ? j1 - jb : 0;
-  const WaveGaussians q = load_wave_gaussians<true>(dkey, dval, rect, jb + __lane_id(), j1, rec0, rec1, pbox);
-  Slot *mine = rel + w * tiles;
-  // per-wave counts (each Gaussian's tiles are distinct; Gaussians in program order)
-  for_wave_instances(q, ng, tiles_x, [&](int, uint32_t t, uint32_t, uint32_t) { mine[t] = (Slot)(mine[t] + 1); });
-  __syncthreads();
-  const uint32_t *row = choff + (int64_t)blockIdx.x * tiles;
-  for (int t = threadIdx.x; t < tiles; t += kBlock) {  // counts -> first slot of each wave
-    const uint32_t a = rel[t], b = rel[tiles + t], c = rel[2 * tiles + t];
-    rel[t] = 0;
-    rel[tiles + t] = (Slot)a;
-    rel[2 * tiles + t] = (Slot)(a + b);
-    rel[3 * tiles + t] = (Slot)(a + b + c);
+// Level 2 scatter, per segment and round of 64 entries: for each of the 64
+// tiles one ballot over the lanes whose Gaussian covers it ranks the
+// covering lanes; each gets slot base + (covering lanes below), and the
+// tile's base (held by lane tt) advances by the ballot's population.  The
+// (slot, lane, tile) pairs go to a per-wave LDS queue in tile order, and
+// every 64 queued pairs are finished with all lanes busy: the pair's
+// wave-block reach mask (block_reach_mask_pre, from the entry's record staged
+// in LDS) and one store, consecutive lanes of one tile writing consecutive
+// slots.  The queue is drained at the end of each round (the stage is then
+// refilled); it never holds more than 63 + 64 pairs.
+struct StileStage {
+  float u[kWave], v[kWave], A[kWave], B[kWave], C[kWave], need[kWave], ia[kWave], ic[kWave];
+  uint32_t pb0[kWave], pb1[kWave], id[kWave];
+  uint32_t qslot[2 * kWave], qsrc[2 * kWave];
+};
+
+__device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t count, uint32_t tx0, uint32_t ty0,
+                                   int tile_w, int tile_h, uint32_t *__restrict__ out) {
+  const uint32_t lane = __lane_id();
+  if (lane < count) {
+    const uint32_t pos = (head + lane) & (2 * kWave - 1);
+    const uint32_t slot = sg.qslot[pos], src = sg.qsrc[pos];
+    const uint32_t l = src & 63u, tt = src >> 8;
+    const float4 r0 = make_float4(sg.u[l], sg.v[l], 0.0f, 0.0f);
+    const float4 r1 = make_float4(sg.A[l], sg.B[l], sg.C[l], 0.0f);
+    const uint2 pb = make_uint2(sg.pb0[l], sg.pb1[l]);
+    const uint32_t mask = block_reach_mask_pre(r0, r1, pb, sg.need[l], sg.ia[l], sg.ic[l], tx0 + (tt & 7u),
+                                               ty0 + (tt >> 3), tile_w, tile_h);
+    out[slot] = sg.id[l] | (mask << kMaskShift);
   }
-  __syncthreads();
-  // per Gaussian of the wave: the reciprocals of the reach test, once
-  const float ia = -0.5f * __builtin_amdgcn_rcpf(q.r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(q.r1.z);
-  for (int g = 0; g < ng; ++g) {
-    const uint32_t gx = readlane_u(q.rx, g), gy = readlane_u(q.ry, g);
-    const uint32_t x0 = gx & 0xFFFFu, y0 = gx >> 16, x1 = gy & 0xFFFFu, y1 = gy >> 16;
-    if (x1 <= x0 || y1 <= y0) continue;
-    const uint32_t nx = x1 - x0, area = nx * (y1 - y0);
-    const uint32_t id = readlane_u(q.id, g);
-    const float u = readlane_f(q.r0.x, g), v = readlane_f(q.r0.y, g), lo = readlane_f(q.r0.z, g);
-    const float A = readlane_f(q.r1.x, g), B = readlane_f(q.r1.y, g), C = readlane_f(q.r1.z, g);
-    const float gia = readlane_f(ia, g), gic = readlane_f(ic, g);
-    const uint32_t pbx = readlane_u(q.pb.x, g), pby = readlane_u(q.pb.y, g);
-    const float need = kQSkip - 0.01f - lo;
-    for (uint32_t k = __lane_id(); k < area; k += kWave) {
-      const uint32_t dy = k / nx, tx = x0 + (k - dy * nx), ty = y0 + dy;
-      const uint32_t t = ty * (uint32_t)tiles_x + tx;
-      const uint32_t slot = row[t] + (uint32_t)mine[t];
-      mine[t] = (Slot)(mine[t] + 1);
-      // which of the tile's four 8x8 wave blocks the Gaussian reaches (as block_reach_mask)
-      const int tpx = (int)tx * tile_w, tpy = (int)ty * tile_h;
-      const int px0 = (int)(pbx & 0xFFFFu) - tpx, py0 = (int)(pbx >> 16) - tpy;
-      const int px1 = (int)(pby & 0xFFFFu) - tpx, py1 = (int)(pby >> 16) - tpy;
-      // every pixel of the tile reached: all four blocks, no per-block search
-      const float ftx = (float)tpx + 0.5f, fty = (float)tpy + 0.5f;
-      const bool whole = box_all_reach(A, B, C, u - (ftx + (float)(tile_w - 1)), u - ftx,
-                                       v - (fty + (float)(tile_h - 1)), v - fty, need);
-      uint32_t mask = whole ? 0xFu : 0u;
-#pragma unroll
-      for (int wb = 0; wb < 4; ++wb) {
-        if (whole) break;
-        const int bx = wave_block_x0(wb, tile_w), by = wave_block_y0(wb, tile_w);
-        if (px0 < bx + 8 && px1 > bx && py0 < by + 8 && py1 > by) {
-          const float cx0 = (float)(tpx + bx) + 0.5f, cy0 = (float)(tpy + by) + 0.5f;
-          if (box_reaches(A, B, C, gia, gic, u - (cx0 + 7.0f), u - cx0, v - (cy0 + 7.0f), v - cy0, need))
-            mask |= 1u << wb;
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rect, const float4 *__restrict__ rec0,
+                const float4 *__restrict__ rec1, const uint2 *__restrict__ pbox, const uint32_t *__restrict__ tab,
+                int nsup, int supers_x, int tile_w, int tile_h, const Header *__restrict__ h,
+                const uint32_t *__restrict__ hist, uint32_t *__restrict__ out) {
+  __shared__ uint32_t slen[kMaxSupers + 1], sstart[kMaxSupers + 1], seg[kMaxSupers + 1];
+  __shared__ StileStage stage[4];
+  if (h->overflow) return;
+  load_super_tables(tab, nsup, slen, sstart, seg);
+  const int w = threadIdx.x >> 6, lane = __lane_id();
+  StileStage &sg = stage[w];
+  const uint32_t total = seg[nsup];
+  const unsigned long long below = lanemask_lt();
+  for (uint32_t g = blockIdx.x * 4u + (uint32_t)w; g < total; g += gridDim.x * 4u) {
+    const SuperSeg q = find_segment(g, seg, sstart, slen, nsup, supers_x);
+    uint32_t base = hist[(int64_t)g * 64 + lane];  // lane tt: next slot of the segment's run in tile tt
+    for (uint32_t e0 = q.e0; e0 < q.e1; e0 += kWave) {
+      const uint32_t e = e0 + lane;
+      unsigned long long m = 0ull;
+      if (e < q.e1) {
+        const uint32_t id = list[e];
+        m = local_tiles(rect[id], q.tx0, q.ty0);
+        const float4 r0 = rec0[id], r1 = rec1[id];
+        const uint2 pb = pbox[id];
+        sg.u[lane] = r0.x;
+        sg.v[lane] = r0.y;
+        sg.need[lane] = kQSkip - 0.01f - r0.z;
+        sg.A[lane] = r1.x;
+        sg.B[lane] = r1.y;
+        sg.C[lane] = r1.z;
+        sg.ia[lane] = -0.5f * __builtin_amdgcn_rcpf(r1.x);
+        sg.ic[lane] = -0.5f * __builtin_amdgcn_rcpf(r1.z);
+        sg.pb0[lane] = pb.x;
+        sg.pb1[lane] = pb.y;
+        sg.id[lane] = id;
+      }
+      __builtin_amdgcn_wave_barrier();
+      uint32_t head = 0, tail = 0;  // wave-uniform queue positions
+      for (int tt = 0; tt < 64; ++tt) {
+        const bool mine = (m >> tt) & 1ull;
+        const unsigned long long b = __ballot(mine);
+        if (b == 0ull) continue;
+        const uint32_t bt = __builtin_amdgcn_readlane(base, tt);
+        const uint32_t rank = (uint32_t)__popcll(b & below);
+        if (mine) {
+          const uint32_t pos = (tail + rank) & (2 * kWave - 1);
+          sg.qslot[pos] = bt + rank;
+          sg.qsrc[pos] = (uint32_t)lane | ((uint32_t)tt << 8);
+        }
+        const uint32_t nb = (uint32_t)__popcll(b);
+        if (lane == tt) base = bt + nb;
+        tail += nb;
+        __builtin_amdgcn_wave_barrier();
+        if (tail - head >= (uint32_t)kWave) {
+          stile_flush(sg, head, kWave, q.tx0, q.ty0, tile_w, tile_h, out);
+          head += kWave;
         }
       }
-      tval[slot] = id | (mask << kMaskShift);
+      if (tail != head) stile_flush(sg, head, tail - head, q.tx0, q.ty0, tile_w, tile_h, out);
     }
   }
 }
 
-void launch_chunk_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                           int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
                           const float4 *rec1, const uint2 *pbox, const uint2 *ranges, const Header *h,
-                          uint32_t *chist, uint32_t *segsum, uint32_t *tval, hipStream_t st) {
-  const int chunks = (int)ceil_div(grid_n, kChunk);
-  if (chunks <= 0) return;
-  const int tiles = tiles_x * tiles_y;
-  const int nseg = (int)ceil_div(chunks, kSegChunks);
-  const dim3 tg((unsigned)ceil_div(tiles, kBlock), (unsigned)nseg);
-  k_chunk_hist<<<chunks, kBlock, sizeof(uint32_t) * (size_t)tiles, st>>>(dkey, dval, rect, n_active, grid_n,
-                                                                       tiles_x, tiles, chist);
-  k_chunk_segsum<<<tg, kBlock, 0, st>>>(chist, chunks, tiles, segsum);
-  k_chunk_segscan<<<(unsigned)ceil_div(tiles, kScanTiles), kBlock, 0, st>>>(segsum, nseg, tiles);
-  k_chunk_offsets<<<tg, kBlock, 0, st>>>(chist, segsum, ranges, chunks, tiles);
-  k_chunk_scatter<<<chunks, kBlock, sizeof(uint16_t) * 4 * (size_t)tiles, st>>>(
-      dkey, dval, rect, n_active, grid_n, tiles_x, tiles, tile_w, tile_h, rec0, rec1, pbox, chist, h, tval);
-
+                          uint32_t *scnt, uint32_t *tab, uint32_t *list, uint32_t *hist, int64_t cap,
+                          uint32_t *out, hipStream_t st) {
+  if (grid_n <= 0) return;
+  const int supers_x = (tiles_x + kSuper - 1) / kSuper, supers_y = (tiles_y + kSuper - 1) / kSuper;
+  const int nsup = supers_x * supers_y;
+  const int chunks = (int)ceil_div(grid_n, kLevel1Chunk);
+  const size_t lds = (size_t)nsup * 4 * (sizeof(unsigned long long) + sizeof(uint32_t));
+  k_super_count<<<chunks, kBlock, lds, st>>>(dkey, dval, rect, n_active, grid_n, supers_x, nsup, chunks, h, scnt);
+  k_super_scan<<<nsup, kBlock, 0, st>>>(scnt, chunks, h, tab);
+  k_super_scatter<<<chunks, kBlock, lds, st>>>(dkey, dval, rect, n_active, grid_n, supers_x, nsup, chunks, h, scnt,
+                                               tab, list);
+  // level 2 strides over at most cap / kSegWave + nsup segments
+  const int64_t segs = cap / kSegWave + nsup + 1;
+  const int64_t blocks = ceil_div(segs, 4) < 4096 ? ceil_div(segs, 4) : 4096;
+  k_stile_count<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, tab, nsup, supers_x, h, hist);
+  k_stile_scan<<<nsup, 1024, 0, st>>>(hist, tab, supers_x, tiles_x, tiles_y, ranges, h);
+  k_stile_scatter<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, rec0, rec1, pbox, tab, nsup, supers_x, tile_w,
+                                                       tile_h, h, hist, out);
 }
 
 void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
@@ -525,7 +776,7 @@ void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 
     return;
   }
   k_tile_prefix<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, tcnt);
-  launch_scan_u32(tcnt, tstart, tiles, parts, nullptr, st);
+  launch_scan_u32(tcnt, tstart, tiles, parts, &h->instances, st);
   k_ranges_from_counts<<<(unsigned)ceil_div(tiles, kBlock), kBlock, 0, st>>>(tcnt, tstart, tiles, h, ranges);
 }
 

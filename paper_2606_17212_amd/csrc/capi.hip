@@ -210,7 +210,7 @@ void project_and_count(const Call &cl, void *ws, bool list_mode, hipStream_t st)
   launch_radix_sort(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.dkey1),
                     at<uint32_t>(ws, L.dval1), nact, 0, n, 0, 32, at<uint32_t>(ws, L.hist),
                     at<unsigned long long>(ws, L.part), st);
-  if (tile_ranges_in_lds(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
+  if (super_path(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
     // per-tile counts, ranges and the instance count straight from the rectangles
     launch_tile_ranges(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
                        cl.tiling.tiles_x, cl.tiling.tiles_y, h, at<uint32_t>(ws, L.tdiff), at<uint32_t>(ws, L.tcnt),
@@ -236,13 +236,14 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
   Header *h = at<Header>(ws, L.header);
   const int n = cl.records;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
-  if (tile_ranges_in_lds(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
-    // the ranges exist already (project_and_count); one pass puts every instance in place
+  if (super_path(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
+    // the ranges exist already (project_and_count); the two-level scatter puts every instance in place
     uint32_t *out = const_cast<uint32_t *>(sorted_vals(cl, ws));
-    launch_chunk_scatter(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
+    launch_super_scatter(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
                          cl.tiling.tiles_x, cl.tiling.tiles_y, cl.t.tile_w, cl.t.tile_h, at<float4>(ws, L.rec0),
                          at<float4>(ws, L.rec1), at<uint2>(ws, L.pbox), at<uint2>(ws, L.ranges), h,
-                         at<uint32_t>(ws, L.chist), at<uint32_t>(ws, L.segsum), out, st);
+                         at<uint32_t>(ws, L.super_cnt), at<uint32_t>(ws, L.super_tab), at<uint32_t>(ws, L.tkey0),
+                         at<uint32_t>(ws, L.tkey1), cap, out, st);
     return out;
   }
   launch_emit(at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey1),

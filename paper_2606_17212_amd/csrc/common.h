@@ -121,8 +121,8 @@ struct Layout {
   size_t hist;               // u32 radix histograms
   size_t ranges;             // uint2 [tiles]
   size_t tdiff;              // u32 [(tiles_y+1)(tiles_x+1)]: 2D difference array of tile coverage
-  size_t chist;              // u32 [chunks][tiles]: per-chunk instance counts, then first slots
-  size_t segsum;             // u32 [segments][tiles]
+  size_t super_cnt;          // u32 [supers][level-1 chunks]: counts, then first slots (two-level scatter)
+  size_t super_tab;          // u32 [3][kMaxSupers + 1]: list length, list start, first segment per super-tile
   size_t tcnt, tstart;       // u32 [tiles]: instances per tile and their exclusive scan
   size_t grad2d;             // f32 [9][n]
   size_t plhist;             // u32 [P*4]: Gaussians per (packet, layer)
@@ -139,11 +139,17 @@ struct Layout {
 };
 
 constexpr int kDiffLds = 12288;   // tile-coverage entries held in LDS (48 KB): (tiles_x + 1) (tiles_y + 1)
-constexpr int kChunk = 256;       // depth-ordered Gaussians per workgroup of the one-pass instance scatter
-constexpr int kWaveGauss = kChunk / 4;  // of them per wave (at most one per lane)
-static_assert(kWaveGauss <= 64, "one Gaussian per lane");
-constexpr int kChunkTiles = 8192; // tiles whose per-wave 16-bit counts fit one workgroup's LDS (64 KB)
-constexpr int kSegChunks = 32;    // chunks per segment of its offset scan
+// Two-level instance scatter: super-tiles of kSuper x kSuper tiles (one bit
+// per tile in a u64), at most kMaxSupers of them; level 1 takes kLevel1Chunk
+// depth-ordered Gaussians per workgroup, level 2 kSegWave list entries per wave.
+constexpr int kSuper = 8;
+constexpr int kMaxSupers = 1024;
+constexpr int kLevel1Chunk = 1024;
+constexpr int kSegWave = 256;
+inline int64_t supers_of(int64_t tiles_x, int64_t tiles_y) {
+  return ((tiles_x + kSuper - 1) / kSuper) * ((tiles_y + kSuper - 1) / kSuper);
+}
+inline bool super_path(int64_t tiles_x, int64_t tiles_y) { return supers_of(tiles_x, tiles_y) <= kMaxSupers; }
 constexpr int kSortIpt = 16;
 constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per radix workgroup
 constexpr int kScanTile = kBlock * 16;        // 4096 values per scan workgroup
@@ -163,6 +169,7 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   L.sort_blocks = ceil_div(big, kSortTile);
   int64_t hist_entries = 256 * L.sort_blocks;
   int64_t scan_max = hist_entries > nn ? hist_entries : nn;
+  if (tiles > scan_max) scan_max = tiles;  // the scan over tiles of the ranges for large grids
   L.scan_parts = ceil_div(scan_max, kScanTile) + 1;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -179,19 +186,22 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   L.cnt = take(4 * nn);
   L.present = take(4 * nn);
   L.part = take(8 * L.scan_parts);
-  L.tkey0 = take(4 * cc);
-  L.tkey1 = take(4 * cc);
+  L.tkey0 = take(4 * cc);  // two-level scatter: the super-tile lists (at most cap entries)
+  {
+    // two-level scatter: per level-2 segment 64 tile counts, then first slots; a super-tile of
+    // len entries has ceil(len / kSegWave) segments, so at most cap / kSegWave + supers in all
+    const int64_t segs = super_path(tiles_x, tiles_y) ? cc / kSegWave + supers_of(tiles_x, tiles_y) + 1 : 0;
+    L.tkey1 = take(4 * cc > 4 * 64 * segs ? 4 * cc : 4 * 64 * segs);
+  }
   L.tval0 = take(4 * cc);
   L.tval1 = take(4 * cc);
   L.hist = take(4 * hist_entries);
   L.ranges = take(8 * (tiles > 0 ? tiles : 1));
   L.tdiff = take(4 * (tiles_x + 1) * (tiles_y + 1));
   {
-    const int64_t chunks = ceil_div(nn, kChunk), segs = ceil_div(chunks, kSegChunks);
-    // the one-pass scatter's condition
-    const bool lds_grid = (tiles_x + 1) * (tiles_y + 1) <= kDiffLds && tiles <= kChunkTiles;
-    L.chist = take(lds_grid ? 4 * chunks * (tiles > 0 ? tiles : 1) : 4);
-    L.segsum = take(lds_grid ? 4 * segs * (tiles > 0 ? tiles : 1) : 4);
+    const bool sp = super_path(tiles_x, tiles_y);
+    L.super_cnt = take(sp ? 4 * supers_of(tiles_x, tiles_y) * ceil_div(nn, kLevel1Chunk) : 4);
+    L.super_tab = take(4 * 3 * (kMaxSupers + 1));
   }
   L.tcnt = take(4 * (tiles > 0 ? tiles : 1));
   L.tstart = take(4 * (tiles > 0 ? tiles : 1));

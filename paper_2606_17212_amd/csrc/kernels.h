@@ -35,18 +35,21 @@ void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, c
                  hipStream_t st);
 // Per-tile [start, end) of the tile-sorted instances, from the Gaussians'
 // tile rectangles (the same instances emission writes); empty after an overflow.
-// (When the tile grid fits LDS the same launch also writes the instance count
-// to h->instances and sets h->overflow when it exceeds h->capacity.)
+// The same launch writes the instance count to h->instances and sets
+// h->overflow when it exceeds h->capacity.
 void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                         int grid_n, int tiles_x, int tiles_y, Header *h, uint32_t *tdiff, uint32_t *tcnt,
                         uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st);
 bool tile_ranges_in_lds(int tiles_x, int tiles_y);
-// One-pass stable scatter of the instances of the depth-sorted Gaussians into
-// their tiles' ranges (needs the ranges of launch_tile_ranges; grid fits LDS).
-void launch_chunk_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+// Two-level stable scatter of the instances into their tiles' ranges (needs
+// the ranges and the overflow flag of launch_tile_ranges; super_path grids):
+// scnt, tab, list and hist are workspace sections (super_cnt, super_tab, and
+// cap-sized tkey0 / tkey1), out the tile-sorted values.
+void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                           int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
                           const float4 *rec1, const uint2 *pbox, const uint2 *ranges, const Header *h,
-                          uint32_t *chist, uint32_t *segsum, uint32_t *tval, hipStream_t st);
+                          uint32_t *scnt, uint32_t *tab, uint32_t *list, uint32_t *hist, int64_t cap,
+                          uint32_t *out, hipStream_t st);
 void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S, bool exact,
                     uint32_t *visbits, hipStream_t st);
 void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st);

@@ -157,3 +157,48 @@ def test_grid_above_lds_limit_lists_and_pixels(big, tile):
     ps = r.render(s, cam, codes, basis, BG, per_state=True)
     r.check()
     assert torch.equal(ps, img)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8)])
+def test_grid_above_super_tile_limit_lists_and_pixels(tile):
+    """A 4200x4200 camera: more than 1024 super-tiles of 8x8 tiles, so the
+    instances are emitted in depth order and sorted by tile id (the path of
+    very large grids): lists bit-exact, sampled pixels against the oracle,
+    per-state equal to batched."""
+    dgs = _dgs()
+    scene = synth.make_scene(10000, 8, 4, 4, "sh1", index=43)
+    cam_a = synth.ring_camera(4200, 4200)
+    codes_h = synth.make_codes("present_depth", 0.3, 1.0, 4, scene.num_packets, 4, index=43)
+    codes_h[0] = 4
+    basis = synth.temporal_basis(0.5, scene.rank)
+    sx = -(-((cam_a.width + tile[0] - 1) // tile[0]) // 8)
+    sy = -(-((cam_a.height + tile[1] - 1) // tile[1]) // 8)
+    assert sx * sy > 1024
+    dev = torch.device("cuda:0")
+    s = dgs.GaussianScene.from_arrays(scene, dev)
+    cam = dgs.Camera.from_arrays(cam_a)
+    codes = torch.from_numpy(codes_h).to(dev)
+    r = dgs.Renderer(dev, tile=tile, states_per_group=4)
+    print(f"[biggrid] {cam_a.width}x{cam_a.height} tile {tile}: {sx * sy} super-tiles", flush=True)
+    img = r.render(s, cam, codes, basis, BG)
+    M = r.check()
+    sec = r.sections(s, cam, codes.shape[0])
+    m = oracle.mirror_f32(scene, cam_a, basis, *tile)
+    ranges, ids, _ = oracle.tile_lists(m, cam_a.width, cam_a.height)
+    assert M == ids.size and M > 1_000_000
+    granges = sec["ranges"].numpy().astype(np.int64)
+    nonempty = ranges[:, 1] > ranges[:, 0]
+    assert np.array_equal(granges[nonempty], ranges[nonempty])
+    assert np.all(granges[~nonempty, 1] == granges[~nonempty, 0])
+    assert np.array_equal(sec["sorted_ids"].numpy()[:M].astype(np.int64), ids)
+    rng = np.random.default_rng(7)
+    pix = np.stack([rng.integers(0, cam_a.width, 300), rng.integers(0, cam_a.height, 300)], 1)
+    pix = np.concatenate([pix, [[cam_a.width - 1, cam_a.height - 1]]])
+    ref = oracle.render(scene, cam_a, basis, codes_h, BG, pixels=pix)
+    px = torch.from_numpy(pix).to(dev)
+    got = img[:, px[:, 1], px[:, 0], :].cpu().numpy().astype(np.float64)
+    ex = np.abs(got - ref["image"]).max(-1) - ref["budget"]
+    assert ex.max() <= TOL, ex.max()
+    ps = r.render(s, cam, codes, basis, BG, per_state=True)
+    r.check()
+    assert torch.equal(ps, img)
