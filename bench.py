@@ -6,7 +6,7 @@ per-tile lists (dgs_bin), then masked compositing of every delivery state
 (dgs_composite).  Inputs are resident in HBM before timing starts.
 
 Prints ONE JSON line: batched delivery-states/s (value), the plain per-state
-render timed as synchronized serial evaluation, fwd+bwd ms/iter on the
+render timed one state at a time with a synchronisation after each, fwd+bwd ms/iter on the
 250k-Gaussian 720p 8-state training workload, the compositing kernel's
 roofline, and the oracle's CPU rate on a bounded sample.
 """
@@ -533,7 +533,7 @@ def fwd_bwd_graph(dgs, torch, np, dev, r, sc, scene, cam, codes, basis, bg, targ
 
 def fwd_bwd_batched_vs_serial(dgs, synth, torch, np, dev, states=32, iters=5, serial_iters=2):
     """Forward + L1 + backward of 32 delivery states of the 2.7M-Gaussian
-    1920x1080 recipe in one batched call, against synchronized serial calls
+    1920x1080 recipe in one batched call, against serial calls, synchronised after each,
     of the same renderer with one state each (each call projects and bins the
     whole scene, composites its state and runs the backward; gradients
     accumulate over the calls).  The paper reports this speedup for 32
@@ -1028,7 +1028,9 @@ def cpu_baseline(w, np, seconds):
     log(f"[bench] cpu oracle: {k} px x {W} states in {dt:.2f} s on {cores} threads -> {rate:.4g} states/s")
     return {"value": rate, "unit": "states/s", "cores": cores, "kind": "oracle",
             "sample": f"{k} uniformly random pixels of {Wd}x{H}, all {W} states, {dt:.1f} s; "
-                      "rate scaled by (sampled pixels / frame pixels)"}
+                      "rate scaled by (sampled pixels / frame pixels)",
+            "note": "the FP64 oracle as written: every pixel tests every Gaussian (no tiling, no shared "
+                    "binning); a correctness reference timed for context, not a tuned CPU renderer"}
 
 
 if __name__ == "__main__":

@@ -291,8 +291,8 @@ int dgs_composite_stats(const dgs_scene *scene, const dgs_camera *cam, const dgs
 
 /*
  * Plain per-state render (baseline; with a synchronisation after each call it
- * is Sec. 6's synchronized serial evaluation, which the paper states batched
- * evaluation equals bit for bit): for each state in turn, compacts the
+ * is the serial evaluation Sec. 6 compares against, whose results the paper
+ * states batched evaluation reproduces bit for bit): for each state in turn, compacts the
  * delivered Gaussians, projects, bins, sorts and composites only them.
  * Same outputs, bit-identical to dgs_render's.  tun->states_per_group is
  * ignored.  instance_capacity from dgs_count_instances covers every state.
