@@ -646,28 +646,75 @@ k_stile_scan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tab, int 
 // tile's base (held by lane tt) advances by the ballot's population.  The
 // (slot, lane, tile) pairs go to a per-wave LDS queue in tile order, and
 // every 64 queued pairs are finished with all lanes busy: the pair's
-// wave-block reach mask (block_reach_mask_pre, from the entry's record staged
-// in LDS) and one store, consecutive lanes of one tile writing consecutive
-// slots.  The queue is drained at the end of each round (the stage is then
-// refilled); it never holds more than 63 + 64 pairs.
+// wave-block reach mask and one store, consecutive lanes of one tile writing
+// consecutive slots.  The queue is drained at the end of each round (the
+// stage is then refilled); it never holds more than 63 + 64 pairs.
+//
+// Reach masks from band intervals.  A wave block is an 8x8 pixel block whose
+// origin is a multiple of 8 in both tile shapes, so the super-tile's pixel
+// rows fall into tile_h 8-row bands.  When an entry is staged its lane
+// computes, for each band its tiles cover, the range of 8-column blocks whose
+// pixel-centre box meets the Gaussian's reach ellipse {q' >= log2(1/255) -
+// 0.01 - log2 o} -- the criterion block_reach_mask evaluates block by block:
+// a block is reached iff the band meets the ellipse and the block's centre
+// columns meet the band's x-projection of the ellipse.  That projection ends
+// where the ellipse's x-extreme points lie if they fall in the band, else at
+// the band edge nearest to them (the ellipse is convex).  The interval is
+// widened by a margin for the FP32 evaluation, so the masks stay
+// conservative; a pair's mask is then four range tests.
+constexpr int kBandsMax = 16;  // 8-row bands of a super-tile: tile_h of them
+
 struct StileStage {
-  float u[kWave], v[kWave], A[kWave], B[kWave], C[kWave], need[kWave], ia[kWave], ic[kWave];
-  uint32_t pb0[kWave], pb1[kWave], id[kWave];
+  uint32_t id[kWave];
+  uint32_t band[kBandsMax][kWave];  // (lowest + 1) | (highest + 1) << 16 reached block column, local to the super-tile
   uint32_t qslot[2 * kWave], qsrc[2 * kWave];
 };
 
-__device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t count, uint32_t tx0, uint32_t ty0,
-                                   int tile_w, int tile_h, uint32_t *__restrict__ out) {
+// The band ranges of one entry (its lane's column of sg.band) for the local
+// bands [lb0, lb1) of the super-tile whose pixel origin is (sx, sy).
+__device__ inline void stage_bands(StileStage &sg, int lane, float u, float v, float A, float B, float C, float need,
+                                   float sx, float sy, int lb0, int lb1, int ncols) {
+  const float a = -A;  // > 0: the pre-scaled conic is negative definite
+  const float D = 4.0f * A * C - B * B;
+  const bool any = need < 0.0f && D > 0.0f && a > 0.0f;
+  // x- and y-extent of the ellipse, and the y of its rightmost point (the leftmost is its mirror)
+  const float rx = any ? sqrtf(4.0f * C * need / D) : 0.0f;
+  const float ry = any ? sqrtf(4.0f * A * need / D) : 0.0f;
+  const float yext = any ? -B * rx / (2.0f * C) : 0.0f;
+  const float i2a = 0.5f / a;
+  const float marg = 0.01f + 1e-4f * (rx + ry);
+  for (int lb = lb0; lb < lb1; ++lb) {
+    const float yl = sy + (float)(8 * lb) + 0.5f - v, yh = yl + 7.0f;
+    uint32_t packed = 0xFFFFu;  // empty: lowest + 1 above highest + 1
+    if (any && yh >= -ry - marg && yl <= ry + marg) {
+      const float yr = fminf(fmaxf(yext, yl), yh), yq = fminf(fmaxf(-yext, yl), yh);
+      const float dr = fmaxf(B * B * yr * yr + 4.0f * a * (C * yr * yr - need), 0.0f);
+      const float dq = fmaxf(B * B * yq * yq + 4.0f * a * (C * yq * yq - need), 0.0f);
+      const float xr = u + (B * yr + sqrtf(dr)) * i2a + marg;  // x0(y) = B y / (2a), half width sqrt(disc) / (2a)
+      const float xl = u + (B * yq - sqrtf(dq)) * i2a - marg;
+      const float lo = ceilf((xl - 7.5f - sx) * 0.125f), hi = floorf((xr - 0.5f - sx) * 0.125f);
+      const int ilo = (int)fminf(fmaxf(lo, -1.0f), (float)ncols), ihi = (int)fminf(fmaxf(hi, -1.0f), (float)ncols);
+      packed = (uint32_t)(ilo + 1) | ((uint32_t)(ihi + 1) << 16);
+    }
+    sg.band[lb][lane] = packed;
+  }
+}
+
+__device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t count, int tile_w, int tile_h,
+                                   uint32_t *__restrict__ out) {
   const uint32_t lane = __lane_id();
   if (lane < count) {
     const uint32_t pos = (head + lane) & (2 * kWave - 1);
     const uint32_t slot = sg.qslot[pos], src = sg.qsrc[pos];
     const uint32_t l = src & 63u, tt = src >> 8;
-    const float4 r0 = make_float4(sg.u[l], sg.v[l], 0.0f, 0.0f);
-    const float4 r1 = make_float4(sg.A[l], sg.B[l], sg.C[l], 0.0f);
-    const uint2 pb = make_uint2(sg.pb0[l], sg.pb1[l]);
-    const uint32_t mask = block_reach_mask_pre(r0, r1, pb, sg.need[l], sg.ia[l], sg.ic[l], tx0 + (tt & 7u),
-                                               ty0 + (tt >> 3), tile_w, tile_h);
+    const int bx0 = (int)(tt & 7u) * tile_w, by0 = (int)(tt >> 3) * tile_h;  // tile origin in the super-tile
+    uint32_t mask = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t r = sg.band[(by0 + wave_block_y0(w, tile_w)) >> 3][l];
+      const int col = ((bx0 + wave_block_x0(w, tile_w)) >> 3) + 1;
+      if ((int)(r & 0xFFFFu) <= col && col <= (int)(r >> 16)) mask |= 1u << w;
+    }
     out[slot] = sg.id[l] | (mask << kMaskShift);
   }
   __builtin_amdgcn_wave_barrier();
@@ -675,7 +722,7 @@ __device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t
 
 __global__ void __launch_bounds__(kBlock)
 k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rect, const float4 *__restrict__ rec0,
-                const float4 *__restrict__ rec1, const uint2 *__restrict__ pbox, const uint32_t *__restrict__ tab,
+                const float4 *__restrict__ rec1, const uint32_t *__restrict__ tab,
                 int nsup, int supers_x, int tile_w, int tile_h, const Header *__restrict__ h,
                 const uint32_t *__restrict__ hist, uint32_t *__restrict__ out) {
   __shared__ uint32_t slen[kMaxSupers + 1], sstart[kMaxSupers + 1], seg[kMaxSupers + 1];
@@ -685,7 +732,6 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rec
   const int w = threadIdx.x >> 6, lane = __lane_id();
   StileStage &sg = stage[w];
   const uint32_t total = seg[nsup];
-  const unsigned long long below = lanemask_lt();
   for (uint32_t g = blockIdx.x * 4u + (uint32_t)w; g < total; g += gridDim.x * 4u) {
     const SuperSeg q = find_segment(g, seg, sstart, slen, nsup, supers_x);
     uint32_t base = hist[(int64_t)g * 64 + lane];  // lane tt: next slot of the segment's run in tile tt
@@ -694,51 +740,55 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rec
       unsigned long long m = 0ull;
       if (e < q.e1) {
         const uint32_t id = list[e];
-        m = local_tiles(rect[id], q.tx0, q.ty0);
+        const uint2 r = rect[id];
+        m = local_tiles(r, q.tx0, q.ty0);
         const float4 r0 = rec0[id], r1 = rec1[id];
-        const uint2 pb = pbox[id];
-        sg.u[lane] = r0.x;
-        sg.v[lane] = r0.y;
-        sg.need[lane] = kQSkip - 0.01f - r0.z;
-        sg.A[lane] = r1.x;
-        sg.B[lane] = r1.y;
-        sg.C[lane] = r1.z;
-        sg.ia[lane] = -0.5f * __builtin_amdgcn_rcpf(r1.x);
-        sg.ic[lane] = -0.5f * __builtin_amdgcn_rcpf(r1.z);
-        sg.pb0[lane] = pb.x;
-        sg.pb1[lane] = pb.y;
         sg.id[lane] = id;
+        // the entry's tile rows in the super-tile, as 8-row bands
+        const uint32_t y0 = r.x >> 16, y1 = r.y >> 16;
+        const int ly0 = y0 > q.ty0 ? (int)(y0 - q.ty0) : 0;
+        const int ly1 = (int)(y1 - q.ty0) < kSuper ? (int)(y1 - q.ty0) : kSuper;
+        stage_bands(sg, lane, r0.x, r0.y, r1.x, r1.y, r1.z, kQSkip - 0.01f - r0.z, (float)(q.tx0 * (uint32_t)tile_w),
+                    (float)(q.ty0 * (uint32_t)tile_h), ly0 * tile_h / 8, ly1 * tile_h / 8, tile_w);
       }
       __builtin_amdgcn_wave_barrier();
       uint32_t head = 0, tail = 0;  // wave-uniform queue positions
-      for (int tt = 0; tt < 64; ++tt) {
-        const bool mine = (m >> tt) & 1ull;
-        const unsigned long long b = __ballot(mine);
-        if (b == 0ull) continue;
-        const uint32_t bt = __builtin_amdgcn_readlane(base, tt);
-        const uint32_t rank = (uint32_t)__popcll(b & below);
-        if (mine) {
-          const uint32_t pos = (tail + rank) & (2 * kWave - 1);
-          sg.qslot[pos] = bt + rank;
-          sg.qsrc[pos] = (uint32_t)lane | ((uint32_t)tt << 8);
+      // one pass per 32-bit half of the tile mask (tiles 0..31, then 32..63)
+      auto tiles_of = [&](uint32_t word, int tt0) {
+        for (int t = 0; t < 32; ++t) {
+          const int tt = tt0 + t;
+          const bool mine = (word >> t) & 1u;
+          const unsigned long long b = __ballot(mine);
+          if (b == 0ull) continue;
+          const uint32_t bt = __builtin_amdgcn_readlane(base, tt);
+          const uint32_t nb = (uint32_t)__popcll(b);
+          if (mine) {
+            // covering lanes below this one
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+            const uint32_t pos = (tail + rank) & (2 * kWave - 1);
+            sg.qslot[pos] = bt + rank;
+            sg.qsrc[pos] = (uint32_t)lane | ((uint32_t)tt << 8);
+          }
+          base = lane == tt ? bt + nb : base;  // lane tt's base advances past the tile's run
+          tail += nb;
+          __builtin_amdgcn_wave_barrier();
+          if (tail - head >= (uint32_t)kWave) {
+            stile_flush(sg, head, kWave, tile_w, tile_h, out);
+            head += kWave;
+          }
         }
-        const uint32_t nb = (uint32_t)__popcll(b);
-        if (lane == tt) base = bt + nb;
-        tail += nb;
-        __builtin_amdgcn_wave_barrier();
-        if (tail - head >= (uint32_t)kWave) {
-          stile_flush(sg, head, kWave, q.tx0, q.ty0, tile_w, tile_h, out);
-          head += kWave;
-        }
-      }
-      if (tail != head) stile_flush(sg, head, tail - head, q.tx0, q.ty0, tile_w, tile_h, out);
+      };
+      tiles_of((uint32_t)m, 0);
+      tiles_of((uint32_t)(m >> 32), 32);
+      if (tail != head) stile_flush(sg, head, tail - head, tile_w, tile_h, out);
     }
   }
 }
 
 void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                           int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
-                          const float4 *rec1, const uint2 *pbox, const uint2 *ranges, const Header *h,
+                          const float4 *rec1, const uint2 *ranges, const Header *h,
                           uint32_t *scnt, uint32_t *tab, uint32_t *list, uint32_t *hist, int64_t cap,
                           uint32_t *out, hipStream_t st) {
   if (grid_n <= 0) return;
@@ -755,7 +805,7 @@ void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
   const int64_t blocks = ceil_div(segs, 4) < 4096 ? ceil_div(segs, 4) : 4096;
   k_stile_count<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, tab, nsup, supers_x, h, hist);
   k_stile_scan<<<nsup, 1024, 0, st>>>(hist, tab, supers_x, tiles_x, tiles_y, ranges, h);
-  k_stile_scatter<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, rec0, rec1, pbox, tab, nsup, supers_x, tile_w,
+  k_stile_scatter<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, rec0, rec1, tab, nsup, supers_x, tile_w,
                                                        tile_h, h, hist, out);
 }
 

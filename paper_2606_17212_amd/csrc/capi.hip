@@ -241,9 +241,9 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
     uint32_t *out = const_cast<uint32_t *>(sorted_vals(cl, ws));
     launch_super_scatter(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
                          cl.tiling.tiles_x, cl.tiling.tiles_y, cl.t.tile_w, cl.t.tile_h, at<float4>(ws, L.rec0),
-                         at<float4>(ws, L.rec1), at<uint2>(ws, L.pbox), at<uint2>(ws, L.ranges), h,
-                         at<uint32_t>(ws, L.super_cnt), at<uint32_t>(ws, L.super_tab), at<uint32_t>(ws, L.tkey0),
-                         at<uint32_t>(ws, L.tkey1), cap, out, st);
+                         at<float4>(ws, L.rec1), at<uint2>(ws, L.ranges), h, at<uint32_t>(ws, L.super_cnt),
+                         at<uint32_t>(ws, L.super_tab), at<uint32_t>(ws, L.tkey0), at<uint32_t>(ws, L.tkey1), cap,
+                         out, st);
     return out;
   }
   launch_emit(at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), at<uint32_t>(ws, L.dkey1),

@@ -213,9 +213,12 @@ __device__ __forceinline__ void composite_item(const CompositeArgs &a, StageT<B>
         const float4 P0 = rp[j].p0;
         const float2 P1 = rp[j].p1;
         const float q = splat_q(P0, P1, fpx, fpy);
-        if (MODE == 2 && lane == 0) {
-          ++n_wave_alpha;
-          n_wave_miss += __ballot(q >= kQSkip) == 0ull ? 1u : 0u;
+        if (MODE == 2) {  // every lane is active here: the ballot sees the whole wave
+          const bool none = __ballot(q >= kQSkip) == 0ull;
+          if (lane == 0) {
+            ++n_wave_alpha;
+            n_wave_miss += none ? 1u : 0u;
+          }
         }
         if (q < kQSkip) continue;
         const float alpha = alpha_of(q);

@@ -47,7 +47,7 @@ bool tile_ranges_in_lds(int tiles_x, int tiles_y);
 // cap-sized tkey0 / tkey1), out the tile-sorted values.
 void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                           int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
-                          const float4 *rec1, const uint2 *pbox, const uint2 *ranges, const Header *h,
+                          const float4 *rec1, const uint2 *ranges, const Header *h,
                           uint32_t *scnt, uint32_t *tab, uint32_t *list, uint32_t *hist, int64_t cap,
                           uint32_t *out, hipStream_t st);
 void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S, bool exact,
