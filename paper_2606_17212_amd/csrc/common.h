@@ -151,7 +151,17 @@ inline int64_t supers_of(int64_t tiles_x, int64_t tiles_y) {
 }
 inline bool super_path(int64_t tiles_x, int64_t tiles_y) { return supers_of(tiles_x, tiles_y) <= kMaxSupers; }
 constexpr int kSortIpt = 16;
-constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per radix workgroup
+constexpr int kSortTile = kBlock * kSortIpt;  // 4096 keys per radix workgroup (the largest tile)
+// Keys per radix workgroup for a sort of `count` keys: smaller tiles for
+// small sorts, so that up to 256 workgroups share each pass (whose digit
+// offsets the scatter kernel then forms from the raw histograms itself).
+inline int sort_tile_for(int64_t count) {
+  return count <= (int64_t)256 * 1024 ? 1024 : (count <= (int64_t)256 * 2048 ? 2048 : kSortTile);
+}
+inline int64_t sort_blocks_for(int64_t count) {
+  const int64_t c = count > 0 ? count : 1;
+  return (c + sort_tile_for(c) - 1) / sort_tile_for(c);
+}
 constexpr int kScanTile = kBlock * 16;        // 4096 values per scan workgroup
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -166,7 +176,8 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   int64_t nn = n > 0 ? n : 1;
   int64_t cc = cap > 0 ? cap : 1;
   int64_t big = nn > cc ? nn : cc;
-  L.sort_blocks = ceil_div(big, kSortTile);
+  (void)big;
+  L.sort_blocks = sort_blocks_for(nn) > sort_blocks_for(cc) ? sort_blocks_for(nn) : sort_blocks_for(cc);
   int64_t hist_entries = 256 * L.sort_blocks;
   int64_t scan_max = hist_entries > nn ? hist_entries : nn;
   if (tiles > scan_max) scan_max = tiles;  // the scan over tiles of the ranges for large grids

@@ -44,7 +44,7 @@ ObjLayout make_obj_layout(int64_t K, int64_t width, int64_t height, int64_t Q) {
   ObjLayout L{};
   const int64_t blocks = ceil_div(width, 16) * ceil_div(height, 16);
   const int64_t kk = K > 0 ? K : 1, qq = Q > 0 ? Q : 1;
-  const int64_t sort_blocks = ceil_div(2 * qq, kSortTile);
+  const int64_t sort_blocks = sort_blocks_for(2 * qq);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   L.header = take(sizeof(ObjHeader));

@@ -6,9 +6,11 @@
 // its offset.  No workgroup waits on another, so nothing depends on the order
 // or concurrency in which workgroups are dispatched.
 //
-// Radix ranking inside a workgroup: each wave owns a contiguous run of 1024
-// keys and takes them 64 at a time; lanes holding the same digit find each
-// other with one ballot per digit bit, the lane count below gives the rank
+// Radix ranking inside a workgroup: each wave owns a contiguous run of
+// 64 x IPT keys (IPT = 4, 8 or 16 keys per lane, smaller for smaller sorts so
+// that more workgroups share a pass) and takes them 64 at a time; lanes
+// holding the same digit find each other with one ballot per digit bit, the
+// lane count below gives the rank
 // within the round, and a per-(wave, digit) counter in LDS carries the rank
 // across rounds.  No LDS atomics, so heavily skewed digits (the high bytes of
 // depth keys) cost the same as uniform ones.  Keys are then scattered to LDS
@@ -119,6 +121,7 @@ __device__ inline unsigned long long match_digit(uint32_t d, int nbits, unsigned
   return peers;
 }
 
+template <int IPT>
 __global__ void __launch_bounds__(kBlock)
 k_radix_up(const uint32_t *__restrict__ keys, const void *count_dev, int is_u64, int64_t max_count,
            int shift, int nbits, uint32_t *__restrict__ hist, int nblocks) {
@@ -128,17 +131,17 @@ k_radix_up(const uint32_t *__restrict__ keys, const void *count_dev, int is_u64,
   __syncthreads();
   const int64_t n = sort_count(count_dev, is_u64, max_count);
   const uint32_t mask = (1u << nbits) - 1u;
-  const int64_t wbase = (int64_t)blockIdx.x * kSortTile + w * 1024;
+  const int64_t wbase = (int64_t)blockIdx.x * (kBlock * IPT) + w * (kWave * IPT);
   if (wbase < n) {
-    // all sixteen loads in flight before the first digit is ranked
-    uint32_t key[16];
+    // all of the lane's loads in flight before the first digit is ranked
+    uint32_t key[IPT];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < IPT; ++r) {
       const int64_t idx = wbase + r * kWave + lane;
       key[r] = idx < n ? keys[idx] : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < IPT; ++r) {
       const bool valid = wbase + r * kWave + lane < n;
       const uint32_t d = valid ? (key[r] >> shift) & mask : 0u;
       const unsigned long long peers = match_digit(d, nbits, __ballot(valid));
@@ -149,34 +152,36 @@ k_radix_up(const uint32_t *__restrict__ keys, const void *count_dev, int is_u64,
   if (tid <= (int)mask) hist[(int64_t)tid * nblocks + blockIdx.x] = wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
 }
 
+template <int IPT>
 __global__ void __launch_bounds__(kBlock)
 k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, const void *count_dev,
              int is_u64, int64_t max_count, int shift, int nbits, const uint32_t *__restrict__ hist,
              int nblocks, int fused) {
+  constexpr int kTile = kBlock * IPT;
   __shared__ uint32_t wc[4][256];
   __shared__ uint32_t dstart[256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t wsum[4];
-  __shared__ uint32_t skey[kSortTile];
-  __shared__ uint32_t sval[kSortTile];
+  __shared__ uint32_t skey[kTile];
+  __shared__ uint32_t sval[kTile];
   const int64_t n = sort_count(count_dev, is_u64, max_count);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
   if (base >= n) return;  // uniform over the workgroup
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
   wc[0][tid] = 0; wc[1][tid] = 0; wc[2][tid] = 0; wc[3][tid] = 0;
   __syncthreads();
-  uint32_t key[16], val[16], rank[16];
-  const int64_t wbase = base + w * 1024;
+  uint32_t key[IPT], val[IPT], rank[IPT];
+  const int64_t wbase = base + w * (kWave * IPT);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const int64_t idx = wbase + r * kWave + lane;
     key[r] = idx < n ? kin[idx] : 0u;
     val[r] = idx < n ? vin[idx] : 0u;
   }
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const bool valid = wbase + r * kWave + lane < n;
     const uint32_t d = (key[r] >> shift) & mask;
     const unsigned long long peers = match_digit(d, nbits, __ballot(valid));
@@ -226,7 +231,7 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const int64_t idx = wbase + r * kWave + lane;
     if (idx < n) {
       const uint32_t d = (key[r] >> shift) & mask;
@@ -236,7 +241,7 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     }
   }
   __syncthreads();
-  const int cnt = (int)((n - base) < kSortTile ? (n - base) : kSortTile);
+  const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
   for (int k = tid; k < cnt; k += kBlock) {
     const uint32_t kk = skey[k];
     const uint32_t d = (kk >> shift) & mask;
@@ -252,7 +257,8 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
                       int count_is_u64, int64_t max_count, int begin_bit, int end_bit, uint32_t *hist,
                       unsigned long long *parts, hipStream_t st, bool last_pass_keys) {
   if (max_count <= 0) return 0;
-  const int nblocks = (int)ceil_div(max_count, kSortTile);
+  const int tile = sort_tile_for(max_count);
+  const int nblocks = (int)ceil_div(max_count, tile);
   // fewest passes of <= 8 bits, digits as equal as possible (13 bits -> 7 + 6):
   // fewer buckets per pass give longer contiguous runs in the scatter
   const int total_bits = end_bit - begin_bit;
@@ -262,15 +268,27 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
     const int nbits = (total_bits - (shift - begin_bit) + (passes - pass) - 1) / (passes - pass);
     uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
-    k_radix_up<<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist,
-                                           nblocks);
+    if (tile == 1024)
+      k_radix_up<4><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist, nblocks);
+    else if (tile == 2048)
+      k_radix_up<8><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist, nblocks);
+    else
+      k_radix_up<16><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist,
+                                                 nblocks);
     // few blocks: each scatter workgroup forms its digit offsets from the raw
     // histograms itself (no separate scan launches)
     const int fused = nblocks <= kFusedScanBlocks ? 1 : 0;
     if (!fused) launch_scan_u32(hist, hist, (int64_t)(1 << nbits) * nblocks, parts, nullptr, st);
     uint32_t *kwrite = (pass == passes - 1 && !last_pass_keys) ? nullptr : ko;
-    k_radix_down<<<nblocks, kBlock, 0, st>>>(ki, vi, kwrite, vo, count_dev, count_is_u64, max_count, shift,
-                                             nbits, hist, nblocks, fused);
+    if (tile == 1024)
+      k_radix_down<4><<<nblocks, kBlock, 0, st>>>(ki, vi, kwrite, vo, count_dev, count_is_u64, max_count, shift,
+                                                  nbits, hist, nblocks, fused);
+    else if (tile == 2048)
+      k_radix_down<8><<<nblocks, kBlock, 0, st>>>(ki, vi, kwrite, vo, count_dev, count_is_u64, max_count, shift,
+                                                  nbits, hist, nblocks, fused);
+    else
+      k_radix_down<16><<<nblocks, kBlock, 0, st>>>(ki, vi, kwrite, vo, count_dev, count_is_u64, max_count, shift,
+                                                   nbits, hist, nblocks, fused);
     cur ^= 1;
     shift += nbits;
   }
