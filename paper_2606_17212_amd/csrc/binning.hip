@@ -20,15 +20,25 @@ __global__ void __launch_bounds__(kBlock) k_zero_u32(uint32_t *p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
-__global__ void k_clear_header(Header *h, unsigned long long capacity) {
-  h->instances = 0ull;
-  h->capacity = capacity;
-  h->overflow = 0u;
-  h->n_active = 0u;
+// Header reset, and up to two u32 arrays zeroed in the same launch.
+__global__ void __launch_bounds__(kBlock)
+k_clear_header(Header *h, unsigned long long capacity, uint32_t *za, int64_t na, uint32_t *zb, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i == 0) {
+    h->instances = 0ull;
+    h->capacity = capacity;
+    h->overflow = 0u;
+    h->n_active = 0u;
+  }
+  if (i < na) za[i] = 0u;
+  if (i < nb) zb[i] = 0u;
 }
 
-void launch_clear_header(Header *h, unsigned long long capacity, hipStream_t st) {
-  k_clear_header<<<1, 1, 0, st>>>(h, capacity);
+void launch_clear_header(Header *h, unsigned long long capacity, hipStream_t st, uint32_t *za, int64_t na,
+                         uint32_t *zb, int64_t nb) {
+  const int64_t m = na > nb ? na : nb;
+  k_clear_header<<<(unsigned)ceil_div(m > 0 ? m : 1, kBlock), kBlock, 0, st>>>(h, capacity, za, za ? na : 0, zb,
+                                                                                 zb ? nb : 0);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -210,10 +220,11 @@ k_ranges_from_counts(const uint32_t *__restrict__ tcnt, const uint32_t *__restri
 // per tile, all without leaving the workgroup (used when the array fits LDS).
 __global__ void __launch_bounds__(1024)
 k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, Header *__restrict__ h,
-                  uint2 *__restrict__ ranges) {
+                  uint2 *__restrict__ ranges, uint32_t *__restrict__ tile_order) {
   __shared__ uint32_t sd[kDiffLds];
   __shared__ uint32_t wsum[16];
   __shared__ unsigned long long wtot[16];
+  __shared__ uint32_t bcount[33], bstart[33];
   if (threadIdx.x < 16) {
     wsum[threadIdx.x] = 0u;
     wtot[threadIdx.x] = 0ull;
@@ -275,6 +286,27 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
     const uint32_t c = sd[(t / tiles_x) * nx + t % tiles_x];
     ranges[t] = over ? make_uint2(0u, 0u) : make_uint2(start, start + c);
     start += c;
+  }
+  if (!tile_order) return;
+  // tiles by decreasing list length, as k_tile_order (from the counts in LDS)
+  if (tid < 33) bcount[tid] = 0u;
+  __syncthreads();
+  for (int t = tid; t < tiles; t += 1024) {
+    const uint32_t len = over ? 0u : sd[(t / tiles_x) * nx + t % tiles_x];
+    atomicAdd(&bcount[32 - __clz(len)], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int q = 32; q >= 0; --q) {  // heaviest bucket first
+      bstart[q] = acc;
+      acc += bcount[q];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < tiles; t += 1024) {
+    const uint32_t len = over ? 0u : sd[(t / tiles_x) * nx + t % tiles_x];
+    tile_order[atomicAdd(&bstart[32 - __clz(len)], 1u)] = (uint32_t)t;
   }
 }
 
@@ -809,12 +841,13 @@ void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
                                                        tile_h, h, hist, out);
 }
 
-void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+bool launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                         int grid_n, int tiles_x, int tiles_y, Header *h, uint32_t *tdiff, uint32_t *tcnt,
-                        uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st) {
+                        uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st,
+                        bool tdiff_zeroed, uint32_t *tile_order) {
   const int tiles = tiles_x * tiles_y;
   const int64_t ne = (int64_t)(tiles_x + 1) * (tiles_y + 1);
-  k_zero_u32<<<(unsigned)ceil_div(ne, kBlock), kBlock, 0, st>>>(tdiff, ne);
+  if (!tdiff_zeroed) k_zero_u32<<<(unsigned)ceil_div(ne, kBlock), kBlock, 0, st>>>(tdiff, ne);
   if (grid_n > 0) {
     // enough workgroups to cover the machine, few enough to keep the LDS flushes cheap
     const int64_t per = ne <= kDiffLds ? (grid_n / 512 > 1024 ? grid_n / 512 : 1024) : 1024;
@@ -822,12 +855,13 @@ void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 
     k_tile_diff<<<blocks, kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, tiles_x, tiles_y, tdiff);
   }
   if (ne <= kDiffLds) {
-    k_tile_ranges_lds<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, h, ranges);
-    return;
+    k_tile_ranges_lds<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, h, ranges, tile_order);
+    return tile_order != nullptr;
   }
   k_tile_prefix<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, tcnt);
   launch_scan_u32(tcnt, tstart, tiles, parts, &h->instances, st);
   k_ranges_from_counts<<<(unsigned)ceil_div(tiles, kBlock), kBlock, 0, st>>>(tcnt, tstart, tiles, h, ranges);
+  return false;
 }
 
 // visbits[g][p*4 + l], bit s set iff layer l of packet p is delivered in
@@ -862,21 +896,6 @@ void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states,
   if (total <= 0) return;
   k_visbits<<<(unsigned)ceil_div(total, kBlock), kBlock, 0, st>>>(codes, order, num_states, P, S, groups,
                                                                   exact ? 1 : 0, visbits);
-}
-
-// Gaussians per (packet, layer) of the binned scene.
-__global__ void __launch_bounds__(kBlock)
-k_plhist(const uint16_t *__restrict__ packet_layer, int n, int P4, uint32_t *__restrict__ hist) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const int pl = packet_layer[i];
-  if (pl < P4) atomicAdd(hist + pl, 1u);
-}
-
-void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st) {
-  const int P4 = P * 4;
-  k_zero_u32<<<(unsigned)ceil_div(P4, kBlock), kBlock, 0, st>>>(hist, P4);
-  if (n > 0) k_plhist<<<(unsigned)ceil_div(n, kBlock), kBlock, 0, st>>>(packet_layer, n, P4, hist);
 }
 
 // Present count of every state (one workgroup per state) from the

@@ -195,9 +195,21 @@ int prepare(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *sta
   return DGS_OK;
 }
 
-// Projection, depth sort, instance count and offsets.  `list_mode`: only the
-// Gaussians listed in ws.list (count in header.n_active) take part.
-void project_and_count(const Call &cl, void *ws, bool list_mode, hipStream_t st) {
+// Header reset with the zeroing the binning needs (the tile difference array,
+// and the (packet, layer) histogram when `plhist`), in one launch.
+void clear_for_binning(const Call &cl, void *ws, int64_t cap, bool plhist, hipStream_t st) {
+  const Layout &L = cl.L;
+  launch_clear_header(at<Header>(ws, L.header), (unsigned long long)cap, st, at<uint32_t>(ws, L.tdiff),
+                      (int64_t)(cl.tiling.tiles_x + 1) * (cl.tiling.tiles_y + 1),
+                      plhist ? at<uint32_t>(ws, L.plhist) : nullptr, (int64_t)cl.P * 4);
+}
+
+// Projection, depth sort, instance count and offsets, after clear_for_binning.
+// `list_mode`: only the Gaussians listed in ws.list (count in
+// header.n_active) take part.  `plhist`: the projection also counts every
+// Gaussian per (packet, layer).  Returns whether the tile order was written
+// as well (grids whose ranges come from the single-workgroup kernel).
+bool project_and_count(const Call &cl, void *ws, bool list_mode, bool plhist, hipStream_t st) {
   const Layout &L = cl.L;
   Header *h = at<Header>(ws, L.header);
   const int n = cl.records;
@@ -205,23 +217,26 @@ void project_and_count(const Call &cl, void *ws, bool list_mode, hipStream_t st)
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
   launch_geometry(cl.s, cl.c, cl.t, list, nact, n, at<float4>(ws, L.rec0), at<float4>(ws, L.rec1),
                   at<float4>(ws, L.rec2), at<uint2>(ws, L.rect), at<uint2>(ws, L.pbox),
-                  at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), st);
+                  at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), st,
+                  plhist && !list_mode ? at<uint32_t>(ws, L.plhist) : nullptr);
   // depth keys: 32 bits, 4 passes -> result back in dkey0/dval0
   launch_radix_sort(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint32_t>(ws, L.dkey1),
                     at<uint32_t>(ws, L.dval1), nact, 0, n, 0, 32, at<uint32_t>(ws, L.hist),
                     at<unsigned long long>(ws, L.part), st);
   if (super_path(cl.tiling.tiles_x, cl.tiling.tiles_y)) {
     // per-tile counts, ranges and the instance count straight from the rectangles
-    launch_tile_ranges(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
-                       cl.tiling.tiles_x, cl.tiling.tiles_y, h, at<uint32_t>(ws, L.tdiff), at<uint32_t>(ws, L.tcnt),
-                       at<uint32_t>(ws, L.tstart), at<unsigned long long>(ws, L.part), at<uint2>(ws, L.ranges), st);
-    return;
+    return launch_tile_ranges(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
+                              cl.tiling.tiles_x, cl.tiling.tiles_y, h, at<uint32_t>(ws, L.tdiff),
+                              at<uint32_t>(ws, L.tcnt), at<uint32_t>(ws, L.tstart),
+                              at<unsigned long long>(ws, L.part), at<uint2>(ws, L.ranges), st,
+                              /*tdiff_zeroed=*/true, at<uint32_t>(ws, L.tile_order));
   }
   launch_count(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
                at<uint32_t>(ws, L.cnt), st);
   // offsets go to dkey1 (free after the depth sort)
   launch_scan_u32(at<uint32_t>(ws, L.cnt), at<uint32_t>(ws, L.dkey1), n, at<unsigned long long>(ws, L.part),
                   &h->instances, st);
+  return false;
 }
 
 // Buffer holding the tile-sorted values after a binning.
@@ -431,8 +446,8 @@ int dgs_count_instances(const dgs_scene *scene, const dgs_camera *cam, const dgs
   hipStream_t st = (hipStream_t)stream;
   if ((rc = refuse_capture(st, "dgs_count_instances"))) return rc;
   Header *h = at<Header>(ws, cl.L.header);
-  launch_clear_header(h, 0ull, st);
-  project_and_count(cl, ws, false, st);
+  clear_for_binning(cl, ws, 0, false, st);
+  project_and_count(cl, ws, false, false, st);
   if ((rc = hip_check("count_instances launch"))) return rc;
   Header hh;
   if (hipMemcpyAsync(&hh, h, sizeof(Header), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -449,12 +464,10 @@ int dgs_bin(const dgs_scene *scene, const dgs_camera *cam, const dgs_states *sta
   int rc = prepare(scene, cam, states, tun, ws, ws_bytes, cap, 0, &cl);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  Header *h = at<Header>(ws, cl.L.header);
-  launch_clear_header(h, (unsigned long long)cap, st);
-  project_and_count(cl, ws, false, st);
+  clear_for_binning(cl, ws, cap, true, st);
+  const bool ordered = project_and_count(cl, ws, false, true, st);  // also counts the (packet, layer) histogram
   emit_and_sort(cl, ws, false, cap, st);
-  launch_plhist(scene->packet_layer, cl.s.n, cl.P, at<uint32_t>(ws, cl.L.plhist), st);
-  launch_tile_order(at<uint2>(ws, cl.L.ranges), cl.tiling.tiles, at<uint32_t>(ws, cl.L.tile_order), st);
+  if (!ordered) launch_tile_order(at<uint2>(ws, cl.L.ranges), cl.tiling.tiles, at<uint32_t>(ws, cl.L.tile_order), st);
   return hip_check("bin launch");
 }
 
@@ -634,7 +647,7 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
   const int n = cl.s.n;
   Header *h = at<Header>(ws, cl.L.header);
   for (int w = 0; w < W; ++w) {
-    launch_clear_header(h, (unsigned long long)cap, st);
+    clear_for_binning(cl, ws, cap, false, st);
     // compaction of the delivered Gaussians (flags -> scan -> scatter)
     launch_present_flags(states->codes + (int64_t)w * cl.P, scene->packet_layer, n, cl.P,
                          at<uint32_t>(ws, cl.L.cnt), st);
@@ -643,9 +656,10 @@ int dgs_render_per_state(const dgs_scene *scene, const dgs_camera *cam, const dg
     launch_present_scatter(at<uint32_t>(ws, cl.L.cnt), at<uint32_t>(ws, cl.L.dkey1), n,
                            states->codes + (int64_t)w * cl.P, scene->packet_layer, scene->refine != nullptr,
                            at<uint32_t>(ws, cl.L.present), &h->instances, h, st);
-    project_and_count(cl, ws, true, st);
+    const bool ordered = project_and_count(cl, ws, true, false, st);
     const uint32_t *vals = emit_and_sort(cl, ws, true, cap, st);
-    launch_tile_order(at<uint2>(ws, cl.L.ranges), cl.tiling.tiles, at<uint32_t>(ws, cl.L.tile_order), st);
+    if (!ordered)
+      launch_tile_order(at<uint2>(ws, cl.L.ranges), cl.tiling.tiles, at<uint32_t>(ws, cl.L.tile_order), st);
     CompositeArgs a = composite_args(cl, ws, vals, states, nullptr, 1);
     a.image = image;
     a.tfinal = tfinal;

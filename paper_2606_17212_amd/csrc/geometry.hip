@@ -172,13 +172,18 @@ __global__ void __launch_bounds__(kBlock)
 k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ list,
            const unsigned *__restrict__ n_active, float4 *__restrict__ rec0,
            float4 *__restrict__ rec1, float4 *__restrict__ rec2, uint2 *__restrict__ rect,
-           uint2 *__restrict__ pbox, uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval) {
+           uint2 *__restrict__ pbox, uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
+           uint32_t *__restrict__ plhist) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
   const int nact = list ? (int)*n_active : (REFINED ? 4 * s.n : s.n);
   if (j >= nact) return;
   const int v = list ? (int)list[j] : j;
   const int i = REFINED ? (v >> 2) : v;
   const int d = REFINED ? (v & 3) : 0;
+  if (plhist && d == 0) {  // Gaussians per (packet, layer): each Gaussian once
+    const int pl0 = s.packet_layer[i];
+    if (pl0 < 4 * s.num_packets) atomicAdd(plhist + pl0, 1u);
+  }
   Proj p;
   project(s, cam, i, d, p);
   float col[3], dir[3], raw[3];
@@ -439,14 +444,15 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
 
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
-                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st) {
+                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st, uint32_t *plhist) {
   if (grid_n <= 0) return;
+  if (list) plhist = nullptr;  // a list covers a subset: the histogram needs every Gaussian
   if (s.refine)
     k_geometry<true><<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
-                                                                            rec2, rect, pbox, dkey, dval);
+                                                                            rec2, rect, pbox, dkey, dval, plhist);
   else
     k_geometry<false><<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
-                                                                             rec2, rect, pbox, dkey, dval);
+                                                                             rec2, rect, pbox, dkey, dval, plhist);
 }
 
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,

@@ -6,9 +6,12 @@
 namespace dgs {
 
 // geometry.hip
+// plhist (or null): zeroed [P * 4] Gaussian counts per (packet, layer), added
+// to by the same launch (every Gaussian once; not with a list).
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
-                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st);
+                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st,
+                     uint32_t *plhist = nullptr);
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,
                          float *g_ls, float *g_quat, float *g_logit, float *g_color, float *g_temporal,
                          float *g_refine, hipStream_t st);
@@ -26,7 +29,9 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
                       unsigned long long *parts, hipStream_t st, bool last_pass_keys = true);
 
 // binning.hip
-void launch_clear_header(Header *h, unsigned long long capacity, hipStream_t st);
+// Resets the header; also zeroes za[0..na) and zb[0..nb) when given.
+void launch_clear_header(Header *h, unsigned long long capacity, hipStream_t st, uint32_t *za = nullptr,
+                         int64_t na = 0, uint32_t *zb = nullptr, int64_t nb = 0);
 void launch_count(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                   int grid_n, uint32_t *cnt, hipStream_t st);
 void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, const uint32_t *cnt,
@@ -37,9 +42,13 @@ void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, c
 // tile rectangles (the same instances emission writes); empty after an overflow.
 // The same launch writes the instance count to h->instances and sets
 // h->overflow when it exceeds h->capacity.
-void launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
+// tdiff_zeroed: the (tiles_x + 1) (tiles_y + 1) difference array is already
+// zero.  tile_order (or null): when the grid fits LDS the same launch also
+// writes the tiles by decreasing list length; returns whether it did.
+bool launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
                         int grid_n, int tiles_x, int tiles_y, Header *h, uint32_t *tdiff, uint32_t *tcnt,
-                        uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st);
+                        uint32_t *tstart, unsigned long long *parts, uint2 *ranges, hipStream_t st,
+                        bool tdiff_zeroed = false, uint32_t *tile_order = nullptr);
 bool tile_ranges_in_lds(int tiles_x, int tiles_y);
 // Two-level stable scatter of the instances into their tiles' ranges (needs
 // the ranges and the overflow flag of launch_tile_ranges; super_path grids):
@@ -52,7 +61,6 @@ void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
                           uint32_t *out, hipStream_t st);
 void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S, bool exact,
                     uint32_t *visbits, hipStream_t st);
-void launch_plhist(const uint16_t *packet_layer, int n, int P, uint32_t *hist, hipStream_t st);
 constexpr int kMaxOrderedStates = 16384;  // states ranked by present count per composite call
 void launch_state_order(const uint8_t *codes, const uint32_t *hist, int num_states, int P, uint32_t *cnt,
                         uint32_t *order, hipStream_t st);
