@@ -26,8 +26,8 @@ import os
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# sources that define the compositing kernels
-KERNEL_SOURCES = ("csrc/composite.hip", "csrc/common.h", "csrc/kernels.h")
+# sources that define the compositing kernels (forward and backward) and the geometry backward
+KERNEL_SOURCES = ("csrc/composite.hip", "csrc/geometry.hip", "csrc/common.h", "csrc/kernels.h")
 COPY_KERNEL = "neg_kernel"  # the calibration pass of bench.py --copy-mib
 
 
@@ -74,39 +74,47 @@ def kernel_sources_hash(pkg_dir: str = HERE) -> str:
     return h.hexdigest()
 
 
-def traffic_path(root: str, workload: str) -> str:
-    return os.path.join(root, "profiles", f"traffic_k_composite_{workload}.json")
+def traffic_path(root: str, workload: str, tag: str = "k_composite") -> str:
+    return os.path.join(root, "profiles", f"traffic_{tag}_{workload}.json")
 
 
 def traffic_record(fetch_csv: str, write_csv: str, kernel: str, workload: str, copy_bytes: int,
                    command: str) -> dict:
     """Calibrated HBM bytes per launch of ``kernel`` from FETCH_SIZE and
-    WRITE_SIZE counter files of two runs of the same command."""
+    WRITE_SIZE counter files of two runs of the same command.  ``kernel`` may
+    name several kernels joined by '+' (one call that launches each once):
+    their per-dispatch means are added."""
     rec = {"kernel": kernel, "workload": workload, "command": command, "copy_bytes": copy_bytes,
            "sources_sha256": kernel_sources_hash()}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _pmc_rows([path])
-        ks = [v for name, c in rows.items() if kernel in name.replace(" ", "") for v in c.get(counter, [])]
         cp = [v for name, c in rows.items() if COPY_KERNEL in name for v in c.get(counter, [])]
-        if not ks or not cp:
-            raise ValueError(f"{counter}: no dispatches of {kernel!r} or of the copy kernel in {path}")
+        if not cp:
+            raise ValueError(f"{counter}: no dispatches of the copy kernel in {path}")
         copy_kib = sum(cp)  # one call, possibly split over dispatches
         factor = copy_bytes / (copy_kib * 1024.0)
         key = counter.split("_")[0].lower()
-        rec[f"{key}_kib_per_dispatch"] = sum(ks) / len(ks)
-        rec[f"{key}_dispatches"] = len(ks)
+        kib, ndisp = 0.0, []
+        for part in kernel.split("+"):
+            ks = [v for name, c in rows.items() if part in name.replace(" ", "") for v in c.get(counter, [])]
+            if not ks:
+                raise ValueError(f"{counter}: no dispatches of {part!r} in {path}")
+            kib += sum(ks) / len(ks)
+            ndisp.append(len(ks))
+        rec[f"{key}_kib_per_dispatch"] = kib
+        rec[f"{key}_dispatches"] = ndisp[0] if len(ndisp) == 1 else ndisp
         rec[f"{key}_copy_kib"] = copy_kib
         rec[f"{key}_factor"] = factor
-        rec[f"{key}_bytes"] = sum(ks) / len(ks) * 1024.0 * factor
+        rec[f"{key}_bytes"] = kib * 1024.0 * factor
     rec["traffic_bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
     return rec
 
 
-def measured_traffic(kernel: str, workload: str, root: str):
+def measured_traffic(kernel: str, workload: str, root: str, tag: str = "k_composite"):
     """Calibrated HBM bytes per launch of ``kernel`` on ``workload`` from the
     committed counter record, or None if there is none or the kernel's sources
     changed since it was taken."""
-    path = traffic_path(root, workload)
+    path = traffic_path(root, workload, tag)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -133,6 +141,7 @@ def main(argv=None):
     r.add_argument("--copy-bytes", type=int, required=True)
     r.add_argument("--command", required=True)
     r.add_argument("--out", required=True)
+    r.add_argument("--tag", default="k_composite")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(summarize(a.db, a.top))
