@@ -14,6 +14,7 @@ roofline, and the oracle's CPU rate on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -142,6 +143,10 @@ def main():
     for e in [x for row in ev for x in row] + [t_start, t_end]:
         e.record(st)
     torch.cuda.synchronize()
+    # no Python garbage collection inside the timed loops: a full collection can stall the host for
+    # tens of milliseconds, leaving the device idle between launches
+    gc.collect()
+    gc.disable()
     if graph is not None:
         t_start.record(st)
         for k in range(args.steps):
@@ -186,6 +191,7 @@ def main():
         torch.cuda.synchronize()
         reps.append(W * args.steps / (t0.elapsed_time(t1) / 1e3))
     r.check()
+    gc.enable()
     # the headline is the median of the three repetitions (the paper's protocol), robust to a host
     # hiccup in one of them; the first repetition's per-step split is kept beside it
     first_value = value
