@@ -693,16 +693,17 @@ k_stile_scan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tab, int 
 // where the ellipse's x-extreme points lie if they fall in the band, else at
 // the band edge nearest to them (the ellipse is convex).  The interval is
 // widened by a margin for the FP32 evaluation, so the masks stay
-// conservative; a pair's mask is then four range tests.
+// conservative, and kept as a bitmap of the band's tile_w block columns: a
+// pair's four mask bits are then bit fields of one or two bitmaps.
 constexpr int kBandsMax = 16;  // 8-row bands of a super-tile: tile_h of them
 
 struct StileStage {
   uint32_t id[kWave];
-  uint32_t band[kBandsMax][kWave];  // (lowest + 1) | (highest + 1) << 16 reached block column, local to the super-tile
+  uint32_t band[kBandsMax][kWave];  // bit c: 8-column block c of the super-tile is reached in this band
   uint32_t qslot[2 * kWave], qsrc[2 * kWave];
 };
 
-// The band ranges of one entry (its lane's column of sg.band) for the local
+// The band bitmaps of one entry (its lane's column of sg.band) for the local
 // bands [lb0, lb1) of the super-tile whose pixel origin is (sx, sy).
 __device__ inline void stage_bands(StileStage &sg, int lane, float u, float v, float A, float B, float C, float need,
                                    float sx, float sy, int lb0, int lb1, int ncols) {
@@ -717,45 +718,51 @@ __device__ inline void stage_bands(StileStage &sg, int lane, float u, float v, f
   const float marg = 0.01f + 1e-4f * (rx + ry);
   for (int lb = lb0; lb < lb1; ++lb) {
     const float yl = sy + (float)(8 * lb) + 0.5f - v, yh = yl + 7.0f;
-    uint32_t packed = 0xFFFFu;  // empty: lowest + 1 above highest + 1
+    uint32_t bits = 0u;
     if (any && yh >= -ry - marg && yl <= ry + marg) {
       const float yr = fminf(fmaxf(yext, yl), yh), yq = fminf(fmaxf(-yext, yl), yh);
       const float dr = fmaxf(B * B * yr * yr + 4.0f * a * (C * yr * yr - need), 0.0f);
       const float dq = fmaxf(B * B * yq * yq + 4.0f * a * (C * yq * yq - need), 0.0f);
       const float xr = u + (B * yr + sqrtf(dr)) * i2a + marg;  // x0(y) = B y / (2a), half width sqrt(disc) / (2a)
       const float xl = u + (B * yq - sqrtf(dq)) * i2a - marg;
+      // reached block columns [lo, hi] of the band, clipped to the super-tile
       const float lo = ceilf((xl - 7.5f - sx) * 0.125f), hi = floorf((xr - 0.5f - sx) * 0.125f);
-      const int ilo = (int)fminf(fmaxf(lo, -1.0f), (float)ncols), ihi = (int)fminf(fmaxf(hi, -1.0f), (float)ncols);
-      packed = (uint32_t)(ilo + 1) | ((uint32_t)(ihi + 1) << 16);
+      const int ilo = (int)fminf(fmaxf(lo, 0.0f), (float)ncols);
+      const int ihi = (int)fminf(fmaxf(hi, -1.0f), (float)(ncols - 1));
+      if (ihi >= ilo) bits = (0xFFFFFFFFu >> (31 - ihi)) & (0xFFFFFFFFu << ilo);
     }
-    sg.band[lb][lane] = packed;
+    sg.band[lb][lane] = bits;
   }
 }
 
-__device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t count, int tile_w, int tile_h,
-                                   uint32_t *__restrict__ out) {
+// Finishes `count` queued (slot, lane, tile) pairs, one per lane: the pair's
+// wave-block mask and one store.  Wave block w of a tile at (tx, ty) in the
+// super-tile is block column tx * TW / 8 + w % (TW / 8) of band
+// ty * (256 / TW) / 8 + w / (TW / 8).
+template <int TW>
+__device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t count, uint32_t *__restrict__ out) {
   const uint32_t lane = __lane_id();
   if (lane < count) {
     const uint32_t pos = (head + lane) & (2 * kWave - 1);
     const uint32_t slot = sg.qslot[pos], src = sg.qsrc[pos];
     const uint32_t l = src & 63u, tt = src >> 8;
-    const int bx0 = (int)(tt & 7u) * tile_w, by0 = (int)(tt >> 3) * tile_h;  // tile origin in the super-tile
-    uint32_t mask = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t r = sg.band[(by0 + wave_block_y0(w, tile_w)) >> 3][l];
-      const int col = ((bx0 + wave_block_x0(w, tile_w)) >> 3) + 1;
-      if ((int)(r & 0xFFFFu) <= col && col <= (int)(r >> 16)) mask |= 1u << w;
+    const uint32_t tx = tt & 7u, ty = tt >> 3;
+    uint32_t mask;
+    if (TW == 16) {  // 16x16: wave blocks 2 x 2, two bands per tile row
+      const uint32_t r0 = sg.band[2 * ty][l], r1 = sg.band[2 * ty + 1][l];
+      mask = ((r0 >> (2 * tx)) & 3u) | (((r1 >> (2 * tx)) & 3u) << 2);
+    } else {  // 32x8: wave blocks 4 x 1, one band per tile row
+      mask = (sg.band[ty][l] >> (4 * tx)) & 15u;
     }
     out[slot] = sg.id[l] | (mask << kMaskShift);
   }
   __builtin_amdgcn_wave_barrier();
 }
 
+template <int TW>
 __global__ void __launch_bounds__(kBlock)
-k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rect, const float4 *__restrict__ rec0,
-                const float4 *__restrict__ rec1, const uint32_t *__restrict__ tab,
-                int nsup, int supers_x, int tile_w, int tile_h, const Header *__restrict__ h,
+k_stile_scatter(const uint32_t *__restrict__ list, const uint4 *__restrict__ brec, const uint32_t *__restrict__ tab,
+                int nsup, int supers_x, const Header *__restrict__ h,
                 const uint32_t *__restrict__ hist, uint32_t *__restrict__ out) {
   __shared__ uint32_t slen[kMaxSupers + 1], sstart[kMaxSupers + 1], seg[kMaxSupers + 1];
   __shared__ StileStage stage[4];
@@ -763,6 +770,7 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rec
   load_super_tables(tab, nsup, slen, sstart, seg);
   const int w = threadIdx.x >> 6, lane = __lane_id();
   StileStage &sg = stage[w];
+  constexpr int TH = kBlock / TW;
   const uint32_t total = seg[nsup];
   for (uint32_t g = blockIdx.x * 4u + (uint32_t)w; g < total; g += gridDim.x * 4u) {
     const SuperSeg q = find_segment(g, seg, sstart, slen, nsup, supers_x);
@@ -772,16 +780,17 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rec
       unsigned long long m = 0ull;
       if (e < q.e1) {
         const uint32_t id = list[e];
-        const uint2 r = rect[id];
+        const uint4 b0 = brec[2 * (int64_t)id], b1 = brec[2 * (int64_t)id + 1];
+        const uint2 r = make_uint2(b0.x, b0.y);
         m = local_tiles(r, q.tx0, q.ty0);
-        const float4 r0 = rec0[id], r1 = rec1[id];
         sg.id[lane] = id;
         // the entry's tile rows in the super-tile, as 8-row bands
         const uint32_t y0 = r.x >> 16, y1 = r.y >> 16;
         const int ly0 = y0 > q.ty0 ? (int)(y0 - q.ty0) : 0;
         const int ly1 = (int)(y1 - q.ty0) < kSuper ? (int)(y1 - q.ty0) : kSuper;
-        stage_bands(sg, lane, r0.x, r0.y, r1.x, r1.y, r1.z, kQSkip - 0.01f - r0.z, (float)(q.tx0 * (uint32_t)tile_w),
-                    (float)(q.ty0 * (uint32_t)tile_h), ly0 * tile_h / 8, ly1 * tile_h / 8, tile_w);
+        stage_bands(sg, lane, __uint_as_float(b0.z), __uint_as_float(b0.w), __uint_as_float(b1.x),
+                    __uint_as_float(b1.y), __uint_as_float(b1.z), __uint_as_float(b1.w),
+                    (float)(q.tx0 * (uint32_t)TW), (float)(q.ty0 * (uint32_t)TH), ly0 * TH / 8, ly1 * TH / 8, TW);
       }
       __builtin_amdgcn_wave_barrier();
       uint32_t head = 0, tail = 0;  // wave-uniform queue positions
@@ -790,7 +799,7 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rec
         for (int t = 0; t < 32; ++t) {
           const int tt = tt0 + t;
           const bool mine = (word >> t) & 1u;
-          const unsigned long long b = __ballot(mine);
+          const unsigned long long b = __builtin_amdgcn_ballot_w64(mine);
           if (b == 0ull) continue;
           const uint32_t bt = __builtin_amdgcn_readlane(base, tt);
           const uint32_t nb = (uint32_t)__popcll(b);
@@ -806,21 +815,21 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint2 *__restrict__ rec
           tail += nb;
           __builtin_amdgcn_wave_barrier();
           if (tail - head >= (uint32_t)kWave) {
-            stile_flush(sg, head, kWave, tile_w, tile_h, out);
+            stile_flush<TW>(sg, head, kWave, out);
             head += kWave;
           }
         }
       };
       tiles_of((uint32_t)m, 0);
       tiles_of((uint32_t)(m >> 32), 32);
-      if (tail != head) stile_flush(sg, head, tail - head, tile_w, tile_h, out);
+      if (tail != head) stile_flush<TW>(sg, head, tail - head, out);
     }
   }
 }
 
 void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
-                          int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
-                          const float4 *rec1, const uint2 *ranges, const Header *h,
+                          int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const uint4 *brec,
+                          const uint2 *ranges, const Header *h,
                           uint32_t *scnt, uint32_t *tab, uint32_t *list, uint32_t *hist, int64_t cap,
                           uint32_t *out, hipStream_t st) {
   if (grid_n <= 0) return;
@@ -837,8 +846,10 @@ void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
   const int64_t blocks = ceil_div(segs, 4) < 4096 ? ceil_div(segs, 4) : 4096;
   k_stile_count<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, tab, nsup, supers_x, h, hist);
   k_stile_scan<<<nsup, 1024, 0, st>>>(hist, tab, supers_x, tiles_x, tiles_y, ranges, h);
-  k_stile_scatter<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, rec0, rec1, tab, nsup, supers_x, tile_w,
-                                                       tile_h, h, hist, out);
+  if (tile_w == 16)
+    k_stile_scatter<16><<<(unsigned)blocks, kBlock, 0, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
+  else  // 32 x 8, the other tile shape
+    k_stile_scatter<32><<<(unsigned)blocks, kBlock, 0, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
 }
 
 bool launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,

@@ -216,7 +216,7 @@ bool project_and_count(const Call &cl, void *ws, bool list_mode, bool plhist, hi
   const uint32_t *list = list_mode ? at<uint32_t>(ws, L.present) : nullptr;
   const unsigned *nact = list_mode ? &h->n_active : nullptr;
   launch_geometry(cl.s, cl.c, cl.t, list, nact, n, at<float4>(ws, L.rec0), at<float4>(ws, L.rec1),
-                  at<float4>(ws, L.rec2), at<uint2>(ws, L.rect), at<uint2>(ws, L.pbox),
+                  at<float4>(ws, L.rec2), at<uint2>(ws, L.rect), at<uint2>(ws, L.pbox), at<uint4>(ws, L.brec),
                   at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), st,
                   plhist && !list_mode ? at<uint32_t>(ws, L.plhist) : nullptr);
   // depth keys: 32 bits, 4 passes -> result back in dkey0/dval0
@@ -255,8 +255,8 @@ const uint32_t *emit_and_sort(const Call &cl, void *ws, bool list_mode, int64_t 
     // the ranges exist already (project_and_count); the two-level scatter puts every instance in place
     uint32_t *out = const_cast<uint32_t *>(sorted_vals(cl, ws));
     launch_super_scatter(at<uint32_t>(ws, L.dkey0), at<uint32_t>(ws, L.dval0), at<uint2>(ws, L.rect), nact, n,
-                         cl.tiling.tiles_x, cl.tiling.tiles_y, cl.t.tile_w, cl.t.tile_h, at<float4>(ws, L.rec0),
-                         at<float4>(ws, L.rec1), at<uint2>(ws, L.ranges), h, at<uint32_t>(ws, L.super_cnt),
+                         cl.tiling.tiles_x, cl.tiling.tiles_y, cl.t.tile_w, cl.t.tile_h, at<uint4>(ws, L.brec),
+                         at<uint2>(ws, L.ranges), h, at<uint32_t>(ws, L.super_cnt),
                          at<uint32_t>(ws, L.super_tab), at<uint32_t>(ws, L.tkey0), at<uint32_t>(ws, L.tkey1), cap,
                          out, st);
     return out;

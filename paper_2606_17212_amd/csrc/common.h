@@ -113,6 +113,7 @@ struct Layout {
   size_t rec0, rec1, rec2;   // float4 [n] each: (u, v, log2 o, packet_layer bits), (A', B', C', depth), (r, g, b, 0)
   size_t rect;               // uint2 [n]: (x0 | y0 << 16, x1 | y1 << 16) in tiles
   size_t pbox;               // uint2 [n]: the same rectangle in pixels
+  size_t brec;               // uint4 [2n]: (rect, u, v) then (A', B', C', reach bound) -- what level 2 reads per entry
   size_t dkey0, dkey1, dval0, dval1;  // depth sort ping-pong [n]
   size_t cnt;                // u32 [n]: instance counts, then offsets (sorted order)
   size_t present;            // u32 [n]: per-state compaction flags / list
@@ -190,6 +191,7 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   L.rec2 = take(16 * nn);
   L.rect = take(8 * nn);
   L.pbox = take(8 * nn);
+  L.brec = take(32 * nn);
   L.dkey0 = take(4 * nn);
   L.dkey1 = take(4 * nn);
   L.dval0 = take(4 * nn);

@@ -172,8 +172,8 @@ __global__ void __launch_bounds__(kBlock)
 k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ list,
            const unsigned *__restrict__ n_active, float4 *__restrict__ rec0,
            float4 *__restrict__ rec1, float4 *__restrict__ rec2, uint2 *__restrict__ rect,
-           uint2 *__restrict__ pbox, uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
-           uint32_t *__restrict__ plhist) {
+           uint2 *__restrict__ pbox, uint4 *__restrict__ brec, uint32_t *__restrict__ dkey,
+           uint32_t *__restrict__ dval, uint32_t *__restrict__ plhist) {
   const int j = blockIdx.x * kBlock + threadIdx.x;
   const int nact = list ? (int)*n_active : (REFINED ? 4 * s.n : s.n);
   if (j >= nact) return;
@@ -213,11 +213,19 @@ k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ l
     py1 = (uint32_t)clampf(floorf(p.v + ey) + 1.0f, 0.0f, (float)cam.height);
   }
   // conic pre-scaled so that q' = A' dx^2 + B' dx dy + C' dy^2 = -(q/2) log2 e
+  const float cA = kConicA * p.A, cB = kConicB * p.B, cC = kConicA * p.C;
+  const uint2 rt = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
   rec0[v] = make_float4(p.u, p.v, lo, __uint_as_float((uint32_t)pl));
-  rec1[v] = make_float4(kConicA * p.A, kConicB * p.B, kConicA * p.C, p.Z);
+  rec1[v] = make_float4(cA, cB, cC, p.Z);
   rec2[v] = make_float4(col[0], col[1], col[2], 0.0f);
-  rect[v] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+  rect[v] = rt;
   pbox[v] = make_uint2(px0 | (py0 << 16), px1 | (py1 << 16));
+  // what the level-2 instance scatter reads per list entry, in one 32-byte
+  // record: the rectangle, the centre, the conic and the exponent bound of
+  // the reach ellipse, q' >= log2(1/255) - 0.01 - log2 o
+  brec[2 * (int64_t)v] = make_uint4(rt.x, rt.y, __float_as_uint(p.u), __float_as_uint(p.v));
+  brec[2 * (int64_t)v + 1] = make_uint4(__float_as_uint(cA), __float_as_uint(cB), __float_as_uint(cC),
+                                        __float_as_uint(kQSkip - 0.01f - lo));
   const bool nonempty = ok && x1 > x0 && y1 > y0;
   dkey[j] = nonempty ? __float_as_uint(p.Z) : 0xFFFFFFFFu;
   dval[j] = (uint32_t)v;
@@ -444,15 +452,16 @@ k_geometry_bwd(SceneArgs s, CamArgs cam, const float *__restrict__ g2d, float *_
 
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
-                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st, uint32_t *plhist) {
+                     uint2 *rect, uint2 *pbox, uint4 *brec, uint32_t *dkey, uint32_t *dval, hipStream_t st,
+                     uint32_t *plhist) {
   if (grid_n <= 0) return;
   if (list) plhist = nullptr;  // a list covers a subset: the histogram needs every Gaussian
   if (s.refine)
     k_geometry<true><<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
-                                                                            rec2, rect, pbox, dkey, dval, plhist);
+                                                                            rec2, rect, pbox, brec, dkey, dval, plhist);
   else
     k_geometry<false><<<(unsigned)ceil_div(grid_n, kBlock), kBlock, 0, st>>>(s, c, t, list, n_active, rec0, rec1,
-                                                                             rec2, rect, pbox, dkey, dval, plhist);
+                                                                             rec2, rect, pbox, brec, dkey, dval, plhist);
 }
 
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,

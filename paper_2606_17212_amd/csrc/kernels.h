@@ -10,7 +10,7 @@ namespace dgs {
 // to by the same launch (every Gaussian once; not with a list).
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,
-                     uint2 *rect, uint2 *pbox, uint32_t *dkey, uint32_t *dval, hipStream_t st,
+                     uint2 *rect, uint2 *pbox, uint4 *brec, uint32_t *dkey, uint32_t *dval, hipStream_t st,
                      uint32_t *plhist = nullptr);
 void launch_geometry_bwd(const SceneArgs &s, const CamArgs &c, const float *g2d, float *g_mean,
                          float *g_ls, float *g_quat, float *g_logit, float *g_color, float *g_temporal,
@@ -55,8 +55,8 @@ bool tile_ranges_in_lds(int tiles_x, int tiles_y);
 // scnt, tab, list and hist are workspace sections (super_cnt, super_tab, and
 // cap-sized tkey0 / tkey1), out the tile-sorted values.
 void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
-                          int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const float4 *rec0,
-                          const float4 *rec1, const uint2 *ranges, const Header *h,
+                          int grid_n, int tiles_x, int tiles_y, int tile_w, int tile_h, const uint4 *brec,
+                          const uint2 *ranges, const Header *h,
                           uint32_t *scnt, uint32_t *tab, uint32_t *list, uint32_t *hist, int64_t cap,
                           uint32_t *out, hipStream_t st);
 void launch_visbits(const uint8_t *codes, const uint32_t *order, int num_states, int P, int S, bool exact,
