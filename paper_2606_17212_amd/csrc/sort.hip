@@ -121,10 +121,15 @@ __device__ inline unsigned long long match_digit(uint32_t d, int nbits, unsigned
   return peers;
 }
 
+// Per-block digit counts: digit-major (hist[d * nblocks + b], the order a
+// flat scan turns into global offsets) or, for the scatter that forms its
+// offsets itself, block-major (hist[b * 256 + d]: each block's counts one
+// contiguous row, so that the scatter's walk over the blocks reads whole
+// lines).
 template <int IPT>
 __global__ void __launch_bounds__(kBlock)
 k_radix_up(const uint32_t *__restrict__ keys, const void *count_dev, int is_u64, int64_t max_count,
-           int shift, int nbits, uint32_t *__restrict__ hist, int nblocks) {
+           int shift, int nbits, uint32_t *__restrict__ hist, int nblocks, int block_major) {
   __shared__ uint32_t wc[4][256];
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   wc[0][tid] = 0; wc[1][tid] = 0; wc[2][tid] = 0; wc[3][tid] = 0;
@@ -149,7 +154,10 @@ k_radix_up(const uint32_t *__restrict__ keys, const void *count_dev, int is_u64,
     }
   }
   __syncthreads();
-  if (tid <= (int)mask) hist[(int64_t)tid * nblocks + blockIdx.x] = wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+  if (tid <= (int)mask) {
+    const int64_t at = block_major ? (int64_t)blockIdx.x * 256 + tid : (int64_t)tid * nblocks + blockIdx.x;
+    hist[at] = wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+  }
 }
 
 template <int IPT>
@@ -208,15 +216,15 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     if (!fused) gbase[d] = (d <= (int)mask) ? hist[(int64_t)d * nblocks + blockIdx.x] : 0u;
   }
   if (fused) {
-    // global offset of (digit d, this block) from the raw histograms:
-    // sum over all blocks of the lower digits + this digit in earlier blocks
+    // global offset of (digit d, this block) from the raw block-major
+    // histograms: sum over all blocks of the lower digits + this digit in
+    // earlier blocks (the lanes of a wave read consecutive words of a row)
     const int d = tid;
     uint32_t tot = 0, before = 0;
     if (d <= (int)mask) {
-      const uint32_t *row = hist + (int64_t)d * nblocks;
 #pragma unroll 16
       for (int b = 0; b < nblocks; ++b) {
-        const uint32_t c = row[b];
+        const uint32_t c = hist[(int64_t)b * 256 + d];
         tot += c;
         before += b < (int)blockIdx.x ? c : 0u;
       }
@@ -268,16 +276,18 @@ int launch_radix_sort(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, co
     const int nbits = (total_bits - (shift - begin_bit) + (passes - pass) - 1) / (passes - pass);
     uint32_t *ki = cur ? k1 : k0, *vi = cur ? v1 : v0;
     uint32_t *ko = cur ? k0 : k1, *vo = cur ? v0 : v1;
-    if (tile == 1024)
-      k_radix_up<4><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist, nblocks);
-    else if (tile == 2048)
-      k_radix_up<8><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist, nblocks);
-    else
-      k_radix_up<16><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist,
-                                                 nblocks);
     // few blocks: each scatter workgroup forms its digit offsets from the raw
     // histograms itself (no separate scan launches)
     const int fused = nblocks <= kFusedScanBlocks ? 1 : 0;
+    if (tile == 1024)
+      k_radix_up<4><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist, nblocks,
+                                                fused);
+    else if (tile == 2048)
+      k_radix_up<8><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist, nblocks,
+                                                fused);
+    else
+      k_radix_up<16><<<nblocks, kBlock, 0, st>>>(ki, count_dev, count_is_u64, max_count, shift, nbits, hist,
+                                                 nblocks, fused);
     if (!fused) launch_scan_u32(hist, hist, (int64_t)(1 << nbits) * nblocks, parts, nullptr, st);
     uint32_t *kwrite = (pass == passes - 1 && !last_pass_keys) ? nullptr : ko;
     if (tile == 1024)
