@@ -145,7 +145,7 @@ constexpr int kDiffLds = 12288;   // tile-coverage entries held in LDS (48 KB): 
 // depth-ordered Gaussians per workgroup, level 2 kSegWave list entries per wave.
 constexpr int kSuper = 8;
 constexpr int kMaxSupers = 1024;
-constexpr int kLevel1Chunk = 1024;
+constexpr int kLevel1Chunk = 256;
 constexpr int kSegWave = 128;
 inline int64_t supers_of(int64_t tiles_x, int64_t tiles_y) {
   return ((tiles_x + kSuper - 1) / kSuper) * ((tiles_y + kSuper - 1) / kSuper);
