@@ -558,50 +558,44 @@ k_composite_bwd(CompositeBwdArgs a) {
         const float q = splat_q(P0, P1, fpx, fpy);
         const bool hit = q >= kQSkip;
         if (!__ballot(hit)) continue;
-        float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f;
-        float gu = 0.0f, gv = 0.0f, gA = 0.0f, gB = 0.0f, gC = 0.0f, glo = 0.0f;
-        if (hit) {
-          const float alpha = alpha_of(q);
-          const float4 C = st.rec[k].col;
-          // hardware reciprocal (about 1 ulp; 1 - alpha >= 0.01 under the cap)
-          // instead of the IEEE division sequence
-          const float inv1ma = __builtin_amdgcn_rcpf(1.0f - alpha);
-          float d_alpha = 0.0f;
+        // A lane the splat misses (alpha < 1/255) takes alpha = 0 instead of a
+        // branch: then T alpha = 0, every update below leaves T, g . rem and
+        // the colour sums exactly as they are (a live T is >= the stop bound),
+        // and dq = d_alpha x 0 makes every gradient term zero.
+        const float alpha = hit ? alpha_of(q) : 0.0f;
+        const float4 C = st.rec[k].col;
+        // hardware reciprocal (about 1 ulp; 1 - alpha >= 0.01 under the cap)
+        // instead of the IEEE division sequence
+        const float inv1ma = __builtin_amdgcn_rcpf(1.0f - alpha);
+        float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f, d_alpha = 0.0f;
 #pragma unroll
-          for (int s = 0; s < S; ++s) {
-            if (uv & (1u << s)) {
-              const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
-              const float gcol = fmaf(gr[s], C.x, fmaf(gg[s], C.y, gb[s] * C.z));
-              grem[s] = fmaf(-ta, gcol, grem[s]);  // g . rem_k
-              // zero for a stopped state (T and g . rem both cleared at the stop)
-              // and for a lane outside the image (T = -1, g = 0)
-              d_alpha += fmaf(T[s], gcol, -grem[s] * inv1ma);
-              dcr = fmaf(gr[s], ta, dcr);
-              dcg = fmaf(gg[s], ta, dcg);
-              dcb = fmaf(gb[s], ta, dcb);
-              const float Tn = T[s] - ta;
-              const bool stop = Tn < kTStop;
-              // the replay needs T only for T alpha (zero once stopped, as in
-              // the forward's -T_final) and the liveness tests
-              T[s] = stop ? 0.0f : Tn;
-              grem[s] = stop ? 0.0f : grem[s];
-            }
-          }
-          // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap
-          // passes nothing.  dq'/du = 2 A' dx + B' dy and dq'/dv = B' dx + 2 C' dy
-          // are linear in (dx, dy) with entry constants, so the lanes sum
-          // dq dx and dq dy (in the gu, gv slots) and the fold applies A', B', C'.
-          if (alpha < kAlphaMax) {
-            const float dq = d_alpha * alpha * 0.69314718055994531f;
-            const float dx = P0.x - fpx, dy = P0.y - fpy;
-            gu = dq * dx;
-            gv = dq * dy;
-            gA = gu * dx;
-            gB = gu * dy;
-            gC = gv * dy;
-            glo = dq;
+        for (int s = 0; s < S; ++s) {
+          if (uv & (1u << s)) {
+            const float ta = __builtin_amdgcn_fmed3f(T[s] * alpha, 0.0f, 1.0f);
+            const float gcol = fmaf(gr[s], C.x, fmaf(gg[s], C.y, gb[s] * C.z));
+            grem[s] = fmaf(-ta, gcol, grem[s]);  // g . rem_k
+            // zero for a stopped state (T and g . rem both cleared at the stop)
+            // and for a lane outside the image (T = -1, g = 0)
+            d_alpha += fmaf(T[s], gcol, -grem[s] * inv1ma);
+            dcr = fmaf(gr[s], ta, dcr);
+            dcg = fmaf(gg[s], ta, dcg);
+            dcb = fmaf(gb[s], ta, dcb);
+            const float Tn = T[s] - ta;
+            const bool stop = Tn < kTStop;
+            // the replay needs T only for T alpha (zero once stopped, as in
+            // the forward's -T_final) and the liveness tests
+            T[s] = stop ? 0.0f : Tn;
+            grem[s] = stop ? 0.0f : grem[s];
           }
         }
+        // below the cap alpha = 2^q': d alpha / d q' = alpha ln 2; the cap
+        // passes nothing.  dq'/du = 2 A' dx + B' dy and dq'/dv = B' dx + 2 C' dy
+        // are linear in (dx, dy) with entry constants, so the lanes sum
+        // dq dx and dq dy (in the gu, gv slots) and the fold applies A', B', C'.
+        const float dq = alpha < kAlphaMax ? d_alpha * alpha * 0.69314718055994531f : 0.0f;
+        const float dx = P0.x - fpx, dy = P0.y - fpy;
+        const float gu = dq * dx, gv = dq * dy;
+        const float gA = gu * dx, gB = gu * dy, gC = gv * dy, glo = dq;
         // the nine wave sums share their steps: halves, then row pairs fold
         // values into registers that hold four (one per row), then row scans;
         // register q0 ends with rows (gu, gA, gv, gB), q1 with (gC, dcr, glo,
