@@ -918,7 +918,7 @@ k_state_counts(const uint8_t *__restrict__ codes, const uint32_t *__restrict__ h
   uint32_t c = 0;
   for (int p = threadIdx.x; p < P; p += kBlock) {
     const int code = codes[(int64_t)w * P + p];
-    const uint4 h = reinterpret_cast<const uint4 *>(hist)[p];
+    const uint4 h = *reinterpret_cast<const uint4 *>(hist + (int64_t)p * kPlStride);
     c += (code > 0 ? h.x : 0u) + (code > 1 ? h.y : 0u) + (code > 2 ? h.z : 0u) + (code > 3 ? h.w : 0u);
   }
 #pragma unroll

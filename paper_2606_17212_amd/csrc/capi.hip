@@ -201,7 +201,7 @@ void clear_for_binning(const Call &cl, void *ws, int64_t cap, bool plhist, hipSt
   const Layout &L = cl.L;
   launch_clear_header(at<Header>(ws, L.header), (unsigned long long)cap, st, at<uint32_t>(ws, L.tdiff),
                       (int64_t)(cl.tiling.tiles_x + 1) * (cl.tiling.tiles_y + 1),
-                      plhist ? at<uint32_t>(ws, L.plhist) : nullptr, (int64_t)cl.P * 4);
+                      plhist ? at<uint32_t>(ws, L.plhist) : nullptr, (int64_t)cl.P * kPlStride);
 }
 
 // Projection, depth sort, instance count and offsets, after clear_for_binning.

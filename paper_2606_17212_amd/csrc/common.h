@@ -126,7 +126,7 @@ struct Layout {
   size_t super_tab;          // u32 [3][kMaxSupers + 1]: list length, list start, first segment per super-tile
   size_t tcnt, tstart;       // u32 [tiles]: instances per tile and their exclusive scan
   size_t grad2d;             // f32 [9][n]
-  size_t plhist;             // u32 [P*4]: Gaussians per (packet, layer)
+  size_t plhist;             // u32 [P][kPlStride]: Gaussians per (packet, layer), a packet's four layers per row
   size_t tile_order;         // u32 [tiles]: tiles by decreasing list length
   size_t state_cnt;          // u32 [max_states]: present Gaussians per state
   size_t state_order;        // u32 [max_states]: states by increasing present count
@@ -139,6 +139,10 @@ struct Layout {
   int64_t scan_parts;        // entries of the partials buffer
 };
 
+// Row of the (packet, layer) histogram: a packet's four counts at the start
+// of their own 128-byte line, so that the projection's atomic adds spread
+// over as many lines as there are packets.
+constexpr int kPlStride = 32;
 constexpr int kDiffLds = 12288;   // tile-coverage entries held in LDS (48 KB): (tiles_x + 1) (tiles_y + 1)
 // Two-level instance scatter: super-tiles of kSuper x kSuper tiles (one bit
 // per tile in a u64), at most kMaxSupers of them; level 1 takes kLevel1Chunk
@@ -219,7 +223,7 @@ inline Layout make_layout(int64_t n, int64_t P, int64_t tiles_x, int64_t tiles_y
   L.tcnt = take(4 * (tiles > 0 ? tiles : 1));
   L.tstart = take(4 * (tiles > 0 ? tiles : 1));
   L.grad2d = take(4 * 9 * nn);
-  L.plhist = take(4 * P * 4);
+  L.plhist = take(4 * P * kPlStride);
   L.tile_order = take(4 * (tiles > 0 ? tiles : 1));
   L.state_cnt = take(4 * (max_states > 0 ? max_states : 1));
   L.state_order = take(4 * (max_states > 0 ? max_states : 1));

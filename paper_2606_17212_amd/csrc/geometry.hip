@@ -182,7 +182,7 @@ k_geometry(SceneArgs s, CamArgs cam, TileArgs tl, const uint32_t *__restrict__ l
   const int d = REFINED ? (v & 3) : 0;
   if (plhist && d == 0) {  // Gaussians per (packet, layer): each Gaussian once
     const int pl0 = s.packet_layer[i];
-    if (pl0 < 4 * s.num_packets) atomicAdd(plhist + pl0, 1u);
+    if (pl0 < 4 * s.num_packets) atomicAdd(plhist + (pl0 >> 2) * kPlStride + (pl0 & 3), 1u);
   }
   Proj p;
   project(s, cam, i, d, p);

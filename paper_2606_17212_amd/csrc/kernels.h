@@ -6,7 +6,7 @@
 namespace dgs {
 
 // geometry.hip
-// plhist (or null): zeroed [P * 4] Gaussian counts per (packet, layer), added
+// plhist (or null): zeroed [P][kPlStride] Gaussian counts per (packet, layer), added
 // to by the same launch (every Gaussian once; not with a list).
 void launch_geometry(const SceneArgs &s, const CamArgs &c, const TileArgs &t, const uint32_t *list,
                      const unsigned *n_active, int grid_n, float4 *rec0, float4 *rec1, float4 *rec2,

@@ -178,6 +178,30 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
   if (base >= n) return;  // uniform over the workgroup
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
+  if (fused) {
+    // global offset of (digit d, this block) from the raw block-major
+    // histograms: sum over all blocks of the lower digits + this digit in
+    // earlier blocks (the lanes of a wave read consecutive words of a row).
+    // Done first, while the keys do not hold registers yet, so that many of
+    // these loads are in flight at once.
+    const int d = tid;
+    uint32_t tot = 0, before = 0;
+    if (d <= (int)mask) {
+#pragma unroll 16
+      for (int b = 0; b < nblocks; ++b) {
+        const uint32_t c = hist[(int64_t)b * 256 + d];
+        tot += c;
+        before += b < (int)blockIdx.x ? c : 0u;
+      }
+    }
+    const uint32_t incl = wave_incl_scan(tot);
+    __syncthreads();
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    gbase[d] = off + incl - tot + before;
+  }
   wc[0][tid] = 0; wc[1][tid] = 0; wc[2][tid] = 0; wc[3][tid] = 0;
   __syncthreads();
   uint32_t key[IPT], val[IPT], rank[IPT];
@@ -214,28 +238,6 @@ k_radix_down(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     wc[2][d] = ex + c0 + c1;
     wc[3][d] = ex + c0 + c1 + c2;
     if (!fused) gbase[d] = (d <= (int)mask) ? hist[(int64_t)d * nblocks + blockIdx.x] : 0u;
-  }
-  if (fused) {
-    // global offset of (digit d, this block) from the raw block-major
-    // histograms: sum over all blocks of the lower digits + this digit in
-    // earlier blocks (the lanes of a wave read consecutive words of a row)
-    const int d = tid;
-    uint32_t tot = 0, before = 0;
-    if (d <= (int)mask) {
-#pragma unroll 16
-      for (int b = 0; b < nblocks; ++b) {
-        const uint32_t c = hist[(int64_t)b * 256 + d];
-        tot += c;
-        before += b < (int)blockIdx.x ? c : 0u;
-      }
-    }
-    const uint32_t incl = wave_incl_scan(tot);
-    __syncthreads();
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    uint32_t off = 0;
-    for (int k = 0; k < w; ++k) off += wsum[k];
-    gbase[d] = off + incl - tot + before;
   }
   __syncthreads();
 #pragma unroll

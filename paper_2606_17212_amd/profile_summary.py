@@ -23,12 +23,38 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that define the compositing kernels (forward and backward) and the geometry backward
 KERNEL_SOURCES = ("csrc/composite.hip", "csrc/geometry.hip", "csrc/common.h", "csrc/kernels.h")
 COPY_KERNEL = "neg_kernel"  # the calibration pass of bench.py --copy-mib
+
+
+def short_name(name: str) -> str:
+    """A kernel's name without its parameter list; library (torch) kernels
+    shortened to the kernel and the functor or reduction they run."""
+    if name.endswith(")"):
+        depth = 0
+        for i in range(len(name) - 1, -1, -1):
+            if name[i] == ")":
+                depth += 1
+            elif name[i] == "(":
+                depth -= 1
+                if depth == 0:
+                    name = name[:i]
+                    break
+    if "at::native::" in name:
+        base = name.split("<", 1)[0]
+        red = re.search(r"ReduceOp<(\w+)", name)
+        if red:
+            return f"{base}<ReduceOp<{red.group(1)} ...>>"
+        fn = re.search(r"(\w*Functor\w*|\w+_kernel_cuda)", name.split("<", 1)[1] if "<" in name else "")
+        vec = re.match(r"[^<]*<(\d+),", name)
+        parts = ([vec.group(1)] if vec else []) + ([fn.group(1) + " ..."] if fn else [])
+        return f"{base}<{', '.join(parts)}>" if parts else base
+    return name
 
 
 def summarize(db: str, top: int = 25) -> str:
@@ -39,7 +65,8 @@ def summarize(db: str, top: int = 25) -> str:
     total = sum(r[5] for r in rows) or 1
     out = [f"{'share':>7} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10}  kernel"]
     for name, n, avg, mn, mx, tot in rows[:top]:
-        out.append(f"{100.0 * tot / total:6.2f}% {n:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f}  {name}")
+        out.append(f"{100.0 * tot / total:6.2f}% {n:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f}  "
+                   f"{short_name(name)}")
     out.append(f"total GPU kernel time {total / 1e6:.3f} ms over {sum(r[1] for r in rows)} dispatches")
     return "\n".join(out)
 
@@ -60,7 +87,7 @@ def summarize_pmc(csv_paths, match=None) -> str:
     """Per-kernel means of rocprofv3 ``--pmc ... --output-format csv`` files."""
     lines = []
     for name, ctrs in _pmc_rows(csv_paths, match).items():
-        lines.append(name)
+        lines.append(short_name(name))
         for c, v in sorted(ctrs.items()):
             lines.append(f"    {c:24s} mean {sum(v) / len(v):16.1f}   dispatches {len(v)}")
     return "\n".join(lines)
