@@ -567,7 +567,9 @@ k_composite_bwd(CompositeBwdArgs a) {
         // hardware reciprocal (about 1 ulp; 1 - alpha >= 0.01 under the cap)
         // instead of the IEEE division sequence
         const float inv1ma = __builtin_amdgcn_rcpf(1.0f - alpha);
-        float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f, d_alpha = 0.0f;
+        // dL/dalpha = sum over the delivered states of T g . c - (g . rem_k) / (1 - alpha),
+        // kept as the two sums (the second scaled once per entry)
+        float dcr = 0.0f, dcg = 0.0f, dcb = 0.0f, sum_tg = 0.0f, sum_rem = 0.0f;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           if (uv & (1u << s)) {
@@ -576,7 +578,8 @@ k_composite_bwd(CompositeBwdArgs a) {
             grem[s] = fmaf(-ta, gcol, grem[s]);  // g . rem_k
             // zero for a stopped state (T and g . rem both cleared at the stop)
             // and for a lane outside the image (T = -1, g = 0)
-            d_alpha += fmaf(T[s], gcol, -grem[s] * inv1ma);
+            sum_tg = fmaf(T[s], gcol, sum_tg);
+            sum_rem += grem[s];
             dcr = fmaf(gr[s], ta, dcr);
             dcg = fmaf(gg[s], ta, dcg);
             dcb = fmaf(gb[s], ta, dcb);
@@ -592,6 +595,7 @@ k_composite_bwd(CompositeBwdArgs a) {
         // passes nothing.  dq'/du = 2 A' dx + B' dy and dq'/dv = B' dx + 2 C' dy
         // are linear in (dx, dy) with entry constants, so the lanes sum
         // dq dx and dq dy (in the gu, gv slots) and the fold applies A', B', C'.
+        const float d_alpha = fmaf(-sum_rem, inv1ma, sum_tg);
         const float dq = alpha < kAlphaMax ? d_alpha * alpha * 0.69314718055994531f : 0.0f;
         const float dx = P0.x - fpx, dy = P0.y - fpy;
         const float gu = dq * dx, gv = dq * dy;
