@@ -700,7 +700,7 @@ constexpr int kBandsMax = 16;  // 8-row bands of a super-tile: tile_h of them
 struct StileStage {
   uint32_t id[kWave];
   uint32_t band[kBandsMax][kWave];  // bit c: 8-column block c of the super-tile is reached in this band
-  uint32_t qslot[2 * kWave], qsrc[2 * kWave];
+  uint32_t qslot[3 * kWave], qsrc[3 * kWave];  // the queue (2 x 64), then one discard word per lane
 };
 
 // The band bitmaps of one entry (its lane's column of sg.band) for the local
@@ -798,19 +798,18 @@ k_stile_scatter(const uint32_t *__restrict__ list, const uint4 *__restrict__ bre
       auto tiles_of = [&](uint32_t word, int tt0) {
         for (int t = 0; t < 32; ++t) {
           const int tt = tt0 + t;
-          const bool mine = (word >> t) & 1u;
+          const bool mine = __builtin_amdgcn_ubfe(word, (uint32_t)t, 1u) != 0u;
           const unsigned long long b = __builtin_amdgcn_ballot_w64(mine);
           if (b == 0ull) continue;
           const uint32_t bt = __builtin_amdgcn_readlane(base, tt);
           const uint32_t nb = (uint32_t)__popcll(b);
-          if (mine) {
-            // covering lanes below this one
-            const uint32_t rank =
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-            const uint32_t pos = (tail + rank) & (2 * kWave - 1);
-            sg.qslot[pos] = bt + rank;
-            sg.qsrc[pos] = (uint32_t)lane | ((uint32_t)tt << 8);
-          }
+          // a covering lane queues its pair at tail + (covering lanes below
+          // it); the others write their own discard word (no branch)
+          const uint32_t rank =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+          const uint32_t pos = mine ? ((tail + rank) & (2 * kWave - 1)) : 2 * kWave + (uint32_t)lane;
+          sg.qslot[pos] = bt + rank;
+          sg.qsrc[pos] = (uint32_t)lane | ((uint32_t)tt << 8);
           base = lane == tt ? bt + nb : base;  // lane tt's base advances past the tile's run
           tail += nb;
           __builtin_amdgcn_wave_barrier();
