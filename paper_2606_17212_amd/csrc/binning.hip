@@ -375,7 +375,7 @@ __device__ inline void super_round_count(unsigned long long *bits, uint32_t *cnt
 }
 
 // Level 1 counts: instances per (super-tile, chunk of kLevel1Chunk Gaussians);
-// each wave takes four rounds of 64 consecutive Gaussians.
+// each wave takes kLevel1Chunk / 256 rounds of 64 consecutive Gaussians.
 __global__ void __launch_bounds__(kBlock)
 k_super_count(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
               const unsigned *__restrict__ n_active, int grid_n, int supers_x, int nsup, int chunks,
