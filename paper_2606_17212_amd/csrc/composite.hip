@@ -123,11 +123,13 @@ __device__ __forceinline__ void stage_entry(ST &st, int slot, uint32_t val, cons
 }
 
 // Occupancy requested from the register allocator: the state registers
-// (4 per state) dominate, so small groups can keep 8 waves per SIMD; a
+// (4 per state) dominate, so small groups can keep 8 waves per SIMD; 16
+// states ask for 6 (80 registers: a few per-item values then live in scratch
+// outside the entry loop, which costs less than the sixth wave gains); a
 // 512-entry LDS batch (~35 KB) leaves room for 4 workgroups per CU.
 template <int S, int B = kBlock>
 constexpr int waves_per_eu() {
-  constexpr int by_regs = S <= 8 ? 8 : (S <= 16 ? 5 : 2);
+  constexpr int by_regs = S <= 8 ? 8 : (S <= 16 ? 6 : 2);
   constexpr int by_lds = B > kBlock ? 4 : 8;
   return by_regs < by_lds ? by_regs : by_lds;
 }
@@ -639,8 +641,11 @@ k_composite_bwd(CompositeBwdArgs a) {
 // ------------------------------------------------------------------ launchers
 
 // Automatic choice: the persistent launch pays off once the grid would hold
-// many waves of workgroups (per-workgroup launch cost dominates the saving).
+// many waves of workgroups (per-workgroup launch cost dominates the saving),
+// and for groups of 16 or more states (long work items) as soon as there are
+// more items than resident workgroups.
 constexpr int kPersistentItemsPerSlot = 32;
+constexpr int kPersistentMinStates = 16;
 
 // Resident workgroups of the persistent kernel, cached per instantiation
 // (host-side queries only, so a launch can be captured in a graph).
@@ -662,7 +667,8 @@ static CompositePlan plan_fwd_m(int launch, int64_t items) {
   const int64_t resident = resident_slots<S, TW, TH, MODE, B>();
   CompositePlan p;
   p.items = items;
-  p.persistent = launch == 1 || (launch == 0 && items >= kPersistentItemsPerSlot * resident);
+  p.persistent = launch == 1 || (launch == 0 && (items >= kPersistentItemsPerSlot * resident ||
+                                                  (S >= kPersistentMinStates && items > resident)));
   p.workgroups = p.persistent ? (resident < items ? resident : items) : items;
   p.lds_batch = B;
   return p;
