@@ -311,6 +311,48 @@ def test_full_size_250k_800px_sampled_pixels():
     assert torch.equal(ps, img[[0, 17, 63]])
 
 
+def test_full_size_250k_800px_lists_and_masks_32x8():
+    """The same workload binned with 32x8 tiles (the level-2 scatter's other
+    tile width): tile ranges and sorted lists bit-exact at full size, and on a
+    sample of the instances every 8x8 block holding a pixel centre where the
+    Gaussian's FP64 alpha reaches 1/255 has its mask bit."""
+    dgs = _dgs()
+    w = synth.make_workload("g250k_800px_64states", background=BG)
+    scene, cam, codes = on_device(w)
+    r = dgs.Renderer(tile=(32, 8), states_per_group=8)
+    r.render(scene, cam, codes, w.basis, BG)
+    M = r.check()
+    sec = r.sections(scene, cam, codes.shape[0])
+    m = oracle.mirror_f32(w.scene, w.camera, w.basis, 32, 8)
+    ranges, ids, _ = oracle.tile_lists(m, w.camera.width, w.camera.height)
+    assert M == ids.size
+    granges = sec["ranges"].numpy().astype(np.int64)
+    nonempty = ranges[:, 1] > ranges[:, 0]
+    assert np.array_equal(granges[nonempty], ranges[nonempty])
+    assert np.array_equal(sec["sorted_ids"].numpy()[:M].astype(np.int64), ids)
+    g = oracle.geometry_f64(w.scene, w.camera, w.basis)
+    rng = np.random.default_rng(5)
+    pick = rng.choice(M, size=20000, replace=False)
+    sid = ids[pick]
+    masks = sec["wave_masks"].numpy()[:M].astype(np.int64)[pick]
+    tile_of = np.repeat(np.arange(ranges.shape[0]), ranges[:, 1] - ranges[:, 0])[pick]
+    tiles_x = sec["tiles_x"]
+    need = np.zeros((pick.size, 4), bool)
+    for b in range(4):  # 32x8 tiles: four 8x8 blocks side by side
+        px = (tile_of % tiles_x) * 32 + 8 * b
+        py = (tile_of // tiles_x) * 8
+        for dy in range(8):
+            for dx in range(8):
+                x = px + dx + 0.5 - g["u"][sid]
+                y = py + dy + 0.5 - g["v"][sid]
+                q = g["conA"][sid] * x * x + 2 * g["conB"][sid] * x * y + g["conC"][sid] * y * y
+                inside = (px + dx < w.camera.width) & (py + dy < w.camera.height)
+                need[:, b] |= inside & (g["o"][sid] * np.exp(-0.5 * q) >= 1 / 255)
+    bits = (masks[:, None] >> np.arange(4)[None, :]) & 1
+    assert not np.any(need & (bits == 0)), "a reached wave block has no mask bit"
+    assert bits.sum() < 4 * pick.size
+
+
 def test_bin_once_composite_many_and_work_counters(tiny):
     """One binning serves several composite calls (a sweep over state
     batches); the blend counter equals the oracle's composited-pair count up to
