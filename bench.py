@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2.7M-Gaussian 256-state leg and the 32,768-state PSNR sweep")
     ap.add_argument("--no-utility", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batch-size sweep of the headline scene")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the leg with attribute refinement levels on the same workload")
     ap.add_argument("--utility", default="g1m_540p_utility_64groups_16contexts",
@@ -289,6 +290,9 @@ def main():
         out["speedup_batched_vs_per_state"] = round(value / ps_rate, 3)
         log(f"[bench] per-state: {1e3 * ps_s / W:.3f} ms/state -> {ps_rate:.1f} states/s; identical={same}")
 
+    if not args.no_sweep and args.workload == "g250k_800px_64states":
+        out["batch_sweep"] = batch_sweep(args, dgs, synth, torch, np, dev, w, scene, cam, tw, th)
+
     out["roofline"] = roofline
     roofs = measured_roofs(dgs, torch, np, dev)
     out["measured_roofs"] = roofs
@@ -391,6 +395,51 @@ def distribution(times, np):
     return {"n": int(n), "median": round(float(np.median(t)), 4), "mean": round(float(t.mean()), 4),
             "ci95_half_width": round(half, 4),
             "p5_p25_p75_p95": [round(float(np.percentile(t, q)), 4) for q in (5, 25, 75, 95)]}
+
+
+SWEEP_STATES = (1, 2, 4, 8, 16, 32, 64, 128)
+
+
+def batch_sweep(args, dgs, synth, torch, np, dev, w, scene, cam, tw, th):
+    """Throughput against the number of delivery states rendered together
+    (the paper's batch-size sweep, Sec. 9 table, here on this scene): the
+    first W of 128 states drawn with the headline workload's code recipe,
+    binning + compositing per step, default launch choice, the median of
+    three repetitions of the timed steps."""
+    bg = tuple(float(x) for x in w.background)
+    all_codes = torch.from_numpy(synth.make_codes("present_depth", 0.3, 1.0, max(SWEEP_STATES),
+                                                  w.scene.num_packets, 4, index=2, stream=7)).to(dev)
+    points = []
+    for W in SWEEP_STATES:
+        codes = all_codes[:W].contiguous()
+        r = dgs.Renderer(dev, tile=(tw, th), states_per_group=min(args.states_per_group, W),
+                         persistent=LAUNCH[args.launch], lds_batch=args.lds_batch)
+        r.plan(scene, cam, w.basis, W)
+        img = torch.empty((W, cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+        st = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            r.bin(scene, cam, w.basis)
+            r.composite(scene, cam, codes, w.basis, bg, out=img)
+        torch.cuda.synchronize()
+        reps = []
+        for _ in range(3):
+            e0.record(st)
+            for _ in range(args.steps):
+                r.bin(scene, cam, w.basis)
+                r.composite(scene, cam, codes, w.basis, bg, out=img)
+            e1.record(st)
+            torch.cuda.synchronize()
+            reps.append(e0.elapsed_time(e1) / args.steps)
+        r.check()
+        ms = float(np.median(reps))
+        points.append({"states": W, "states_per_s": round(W / (ms / 1e3), 1), "ms_per_step": round(ms, 4)})
+        del r, img
+    log("[bench] batch sweep (states: states/s): " +
+        ", ".join(f"{p['states']}: {p['states_per_s']:.0f}" for p in points))
+    return {"workload": "g250k_800px_64states scene and camera",
+            "codes": "present_depth 0.3-1.0 (the headline recipe), first W of 128 states",
+            "points": points}
 
 
 def fwd_bwd(dgs, synth, torch, np, dev, args):
