@@ -154,14 +154,18 @@ class Autotuner:
                 r.composite(scene, camera, codes, basis, background, out=img)
             st = torch.cuda.current_stream(dev)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(st)
-            for _ in range(reps):
-                r.bin(scene, camera, basis)
-                r.composite(scene, camera, codes, basis, background, out=img)
-            e1.record(st)
+            best = float("inf")
+            for _ in range(3):  # the fastest of three timed blocks: a transient stall cannot pick the winner
+                e0.record(st)
+                for _ in range(reps):
+                    r.bin(scene, camera, basis)
+                    r.composite(scene, camera, codes, basis, background, out=img)
+                e1.record(st)
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1) / reps)
             r.check()
             del r
-            return e0.elapsed_time(e1) / reps
+            return best
 
         res = search(timer, W, tiles, group_sizes, launches, lds_batches)
         self.cache[key] = res.as_dict()
