@@ -143,8 +143,8 @@ typedef struct {
  *   DGS_TUNE_PERSISTENT: one workgroup per resident slot, draining per-XCD
  *     work queues (heavy tiles first, then stealing from other XCDs).
  *   0: automatic - persistent when there are at least 32 work items per
- *     resident slot, or groups of 16 or more states and more work items than
- *     resident slots; else grid.  Setting both bits is DGS_ERR_INVALID_ARG. */
+ *     resident slot, or groups of 16 or more states and at least 4 work items
+ *     per resident slot; else grid.  Setting both bits is DGS_ERR_INVALID_ARG. */
 #define DGS_TUNE_PERSISTENT 1
 #define DGS_TUNE_GRID 2
 typedef struct {

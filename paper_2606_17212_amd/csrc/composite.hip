@@ -642,10 +642,11 @@ k_composite_bwd(CompositeBwdArgs a) {
 
 // Automatic choice: the persistent launch pays off once the grid would hold
 // many waves of workgroups (per-workgroup launch cost dominates the saving),
-// and for groups of 16 or more states (long work items) as soon as there are
-// more items than resident workgroups.
+// and for groups of 16 or more states (long work items) from a few items per
+// resident workgroup on.
 constexpr int kPersistentItemsPerSlot = 32;
 constexpr int kPersistentMinStates = 16;
+constexpr int kPersistentItemsPerSlotLarge = 4;
 
 // Resident workgroups of the persistent kernel, cached per instantiation
 // (host-side queries only, so a launch can be captured in a graph).
@@ -668,7 +669,8 @@ static CompositePlan plan_fwd_m(int launch, int64_t items) {
   CompositePlan p;
   p.items = items;
   p.persistent = launch == 1 || (launch == 0 && (items >= kPersistentItemsPerSlot * resident ||
-                                                  (S >= kPersistentMinStates && items > resident)));
+                                                  (S >= kPersistentMinStates &&
+                                                   items >= kPersistentItemsPerSlotLarge * resident)));
   p.workgroups = p.persistent ? (resident < items ? resident : items) : items;
   p.lds_batch = B;
   return p;
