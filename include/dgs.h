@@ -30,6 +30,13 @@
  *    dgs_check, dgs_utility_count, dgs_utility_check, dgs_objective_check)
  *    return DGS_ERR_INVALID_ARG, before any launch, on a stream that is
  *    being captured; every other call only enqueues work and may be captured.
+ *  - Concurrency: all device state of a call lives in its workspace and its
+ *    outputs (dgs_render_noalloc's in the library's one static array, see
+ *    there).  Calls on different workspaces may run at the same time on
+ *    different streams; calls on one workspace must be ordered by the caller
+ *    (one stream, or events).  Renders of successive batches on two or three
+ *    streams, each with its own workspace, overlap one batch's binning with
+ *    the compositing of the batches before it.
  *
  * Plan / forward / poll: sizing is dgs_workspace_bytes plus the one
  * synchronising count dgs_count_instances; the forward is dgs_render (or

@@ -786,6 +786,63 @@ def render(renderer: Renderer, scene: GaussianScene, camera: Camera, codes: torc
                                 tuple(float(x) for x in background), *params)
 
 
+class StreamPipeline:
+    """Successive renders overlapped on ``depth`` streams.
+
+    Call ``i`` runs the whole path (``bin``, then ``composite``) on stream
+    ``i % depth`` with a renderer, hence a workspace, of its own.  Calls in
+    flight share no device memory apart from their read-only inputs, so the
+    binning of one call (a chain of short launches that leave most of the
+    chip idle) and the last workgroups of its compositing run beside the
+    compositing of the calls before it.  Every call is the full path: the
+    images equal ``Renderer.render``'s bit for bit.
+
+    Each call first waits for the work the caller has queued on its current
+    stream.  The results are ready on the caller's stream after ``join()``;
+    until then a call's inputs must not change and its image must not be
+    read.  The streams have the default priority."""
+
+    def __init__(self, device="cuda", depth: int = 3, **renderer_kwargs):
+        if int(depth) < 1:
+            raise ValueError(f"depth must be at least 1, got {depth}")
+        self.depth = int(depth)
+        self.renderers = [Renderer(device, **renderer_kwargs) for _ in range(self.depth)]
+        self.device = self.renderers[0].device
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(self.depth)]
+        self.calls = 0
+
+    def plan(self, scene: GaussianScene, camera: Camera, basis, max_states: int) -> int:
+        """Plan every renderer (synchronises); returns the instance count."""
+        return [r.plan(scene, camera, basis, max_states) for r in self.renderers][0]
+
+    def render(self, scene: GaussianScene, camera: Camera, codes: torch.Tensor, basis, background=(0, 0, 0),
+               out=None) -> torch.Tensor:
+        """Images [W, H, Wd, 3] of every state in ``codes``, queued on the next stream."""
+        j = self.calls % self.depth
+        self.calls += 1
+        cur = torch.cuda.current_stream(self.device)
+        s = self.streams[j]
+        s.wait_stream(cur)
+        r = self.renderers[j]
+        with torch.cuda.stream(s):
+            r._need_plan(scene, camera, basis, int(codes.shape[0]))
+            r.bin(scene, camera, basis)
+            img = r.composite(scene, camera, codes, basis, background, out=out)
+        if out is None:
+            img.record_stream(cur)  # allocated on s, read later on the caller's stream
+        return img
+
+    def join(self):
+        """Make the caller's current stream wait for every call so far."""
+        cur = torch.cuda.current_stream(self.device)
+        for s in self.streams:
+            cur.wait_stream(s)
+
+    def check(self) -> int:
+        """Synchronise; raise DgsError if any renderer's last binning overflowed."""
+        return max(r.check() for r in self.renderers)
+
+
 class CapturedRender:
     """``bin`` + ``composite`` (or ``composite_psnr``) of fixed tensors captured
     in one HIP graph; ``replay()`` relaunches the whole path with one call.

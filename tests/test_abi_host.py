@@ -278,3 +278,10 @@ def test_noalloc_render_refuses_oversize_and_bad_arguments_before_any_hip_call()
     t8 = abi.Tuning(8, 8, 16, 0)
     assert L.dgs_render_noalloc(ctypes.byref(sc), ctypes.byref(cam), ctypes.byref(st), ctypes.byref(t8), 1000,
                                 img, None, None, None) == 5
+
+
+def test_stream_pipeline_rejects_a_depth_below_one_before_touching_the_device():
+    import paper_2606_17212_amd as dgs
+    for depth in (0, -2):
+        with pytest.raises(ValueError, match="depth"):
+            dgs.StreamPipeline("cuda", depth=depth)
