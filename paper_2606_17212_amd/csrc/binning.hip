@@ -151,12 +151,16 @@ void launch_emit(const uint32_t *dval, const uint2 *rect, const uint32_t *off, c
 // Tile coverage as a 2D difference array: +1 at (x0, y0) and (x1, y1), -1 at
 // (x1, y0) and (x0, y1) of every binned Gaussian's rectangle; its 2D prefix
 // sum is the instance count of each tile.  Workgroups accumulate in LDS when
-// the array fits and flush non-zero entries with one global atomic each.
+// the array fits and flush non-zero entries with one global atomic each.  The
+// LDS array is sized at launch to the tile grid (4 (tiles_x + 1) (tiles_y + 1)
+// bytes, 10.4 KB at 50 x 50 tiles), so that a workgroup fits in the LDS one
+// compositing workgroup leaves when the kernel runs beside a compositing grid
+// on another stream.
 
 __global__ void __launch_bounds__(kBlock)
 k_tile_diff(const uint32_t *__restrict__ dkey, const uint32_t *__restrict__ dval, const uint2 *__restrict__ rect,
             const unsigned *__restrict__ n_active, int grid_n, int tiles_x, int tiles_y, uint32_t *__restrict__ diff) {
-  __shared__ uint32_t sd[kDiffLds];
+  extern __shared__ uint32_t sd[];  // (tiles_x + 1) (tiles_y + 1) entries when they fit kDiffLds, else unused
   const int nx = tiles_x + 1, ne = (tiles_x + 1) * (tiles_y + 1);
   const bool in_lds = ne <= kDiffLds;
   if (in_lds)
@@ -218,22 +222,33 @@ k_ranges_from_counts(const uint32_t *__restrict__ tcnt, const uint32_t *__restri
 // One workgroup, the whole difference array in LDS: 2D prefix (rows, then
 // columns) -> instances per tile, exclusive scan over tiles -> [start, end)
 // per tile, all without leaving the workgroup (used when the array fits LDS).
-__global__ void __launch_bounds__(1024)
+// A workgroup of kBlock threads with the array sized at launch: it takes the
+// place of one compositing workgroup when it runs beside a compositing grid.
+__global__ void __launch_bounds__(kBlock)
 k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, Header *__restrict__ h,
                   uint2 *__restrict__ ranges, uint32_t *__restrict__ tile_order) {
-  __shared__ uint32_t sd[kDiffLds];
-  __shared__ uint32_t wsum[16];
-  __shared__ unsigned long long wtot[16];
+  constexpr int kWaves = kBlock / kWave;
+  extern __shared__ uint32_t sd[];  // (tiles_x + 1) (tiles_y + 1) entries
+  __shared__ uint32_t wsum[kWaves];
+  __shared__ unsigned long long wtot[kWaves];
   __shared__ uint32_t bcount[33], bstart[33];
-  if (threadIdx.x < 16) {
+  if (threadIdx.x < kWaves) {
     wsum[threadIdx.x] = 0u;
     wtot[threadIdx.x] = 0ull;
   }
   const int nx = tiles_x + 1, ne = (tiles_x + 1) * (tiles_y + 1), tiles = tiles_x * tiles_y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int k = tid; k < ne; k += 1024) sd[k] = diff[k];
+  int e = tid;
+  for (; e + 3 * kBlock < ne; e += 4 * kBlock) {  // four reads in flight per thread
+    const uint32_t v0 = diff[e], v1 = diff[e + kBlock], v2 = diff[e + 2 * kBlock], v3 = diff[e + 3 * kBlock];
+    sd[e] = v0;
+    sd[e + kBlock] = v1;
+    sd[e + 2 * kBlock] = v2;
+    sd[e + 3 * kBlock] = v3;
+  }
+  for (; e < ne; e += kBlock) sd[e] = diff[e];
   __syncthreads();
-  for (int y = tid; y < tiles_y; y += 1024) {
+  for (int y = tid; y < tiles_y; y += kBlock) {
     uint32_t acc = 0;
     for (int x = 0; x < tiles_x; ++x) {
       acc += sd[y * nx + x];
@@ -241,7 +256,7 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
     }
   }
   __syncthreads();
-  for (int x = tid; x < tiles_x; x += 1024) {
+  for (int x = tid; x < tiles_x; x += kBlock) {
     uint32_t acc = 0;
     for (int y = 0; y < tiles_y; ++y) {
       acc += sd[y * nx + x];
@@ -251,7 +266,7 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
   __syncthreads();
   // counts of tile t = sd[(t / tiles_x) * nx + t % tiles_x]; each thread scans
   // a contiguous run of tiles, runs are combined by wave and workgroup scans
-  const int per = (tiles + 1023) / 1024;
+  const int per = (tiles + kBlock - 1) / kBlock;
   const int t0 = tid * per;
   uint32_t run = 0;
   unsigned long long run64 = 0;  // the total may exceed 32 bits; the ranges only matter when it does not
@@ -271,7 +286,7 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
   uint32_t off = 0;
   unsigned long long total = 0;
   for (int k = 0; k < w; ++k) off += wsum[k];
-  for (int k = 0; k < 16; ++k) total += wtot[k];
+  for (int k = 0; k < kWaves; ++k) total += wtot[k];
   uint32_t start = off + incl - run;
   // the instance count of this binning; more than the capacity is an
   // overflow, after which every range is empty
@@ -291,7 +306,7 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
   // tiles by decreasing list length, as k_tile_order (from the counts in LDS)
   if (tid < 33) bcount[tid] = 0u;
   __syncthreads();
-  for (int t = tid; t < tiles; t += 1024) {
+  for (int t = tid; t < tiles; t += kBlock) {
     const uint32_t len = over ? 0u : sd[(t / tiles_x) * nx + t % tiles_x];
     atomicAdd(&bcount[32 - __clz(len)], 1u);
   }
@@ -304,7 +319,7 @@ k_tile_ranges_lds(const uint32_t *__restrict__ diff, int tiles_x, int tiles_y, H
     }
   }
   __syncthreads();
-  for (int t = tid; t < tiles; t += 1024) {
+  for (int t = tid; t < tiles; t += kBlock) {
     const uint32_t len = over ? 0u : sd[(t / tiles_x) * nx + t % tiles_x];
     tile_order[atomicAdd(&bstart[32 - __clz(len)], 1u)] = (uint32_t)t;
   }
@@ -645,29 +660,50 @@ k_stile_count(const uint32_t *__restrict__ list, const uint2 *__restrict__ rect,
 
 // Level 2: per super-tile and tile, exclusive prefix over the super-tile's
 // segments of the counts, plus the tile's range start: the first slot of the
-// tile's run in every segment (in place).  One 1024-thread workgroup per
-// super-tile: 16 parts of its segments x 64 tiles.
-__global__ void __launch_bounds__(1024)
+// tile's run in every segment (in place).  One kBlock-thread workgroup per
+// super-tile: 4 parts of its segments x 64 tiles (a workgroup of the size of
+// a compositing one, so that it can start beside a compositing grid).
+__global__ void __launch_bounds__(kBlock)
 k_stile_scan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tab, int supers_x, int tiles_x, int tiles_y,
              const uint2 *__restrict__ ranges, const Header *__restrict__ h) {
-  __shared__ uint32_t part[16][64];
+  constexpr uint32_t kParts = kBlock / 64;
+  __shared__ uint32_t part[kParts][64];
   if (h->overflow) return;
   const int s = blockIdx.x;
   const uint32_t g0 = tab[2 * (kMaxSupers + 1) + s], g1 = tab[2 * (kMaxSupers + 1) + s + 1];
   const int tt = threadIdx.x & 63, pp = threadIdx.x >> 6;
-  const uint32_t per = (g1 - g0 + 15u) / 16u;
+  const uint32_t per = (g1 - g0 + kParts - 1u) / kParts;
   const uint32_t a = g0 + (uint32_t)pp * per < g1 ? g0 + (uint32_t)pp * per : g1;
   const uint32_t b = a + per < g1 ? a + per : g1;
-  uint32_t sum = 0;
-  for (uint32_t g = a; g < b; ++g) sum += hist[(int64_t)g * 64 + tt];
+  // four counts per step, their reads in flight together (a part spans tens of segments)
+  uint32_t *col = hist + tt;
+  uint32_t sum = 0, g = a;
+  for (; g + 4u <= b; g += 4u) {
+    const uint32_t v0 = col[(int64_t)g * 64], v1 = col[(int64_t)(g + 1u) * 64];
+    const uint32_t v2 = col[(int64_t)(g + 2u) * 64], v3 = col[(int64_t)(g + 3u) * 64];
+    sum += (v0 + v1) + (v2 + v3);
+  }
+  for (; g < b; ++g) sum += col[(int64_t)g * 64];
   part[pp][tt] = sum;
   __syncthreads();
   const int tx = (s % supers_x) * kSuper + (tt & 7), ty = (s / supers_x) * kSuper + (tt >> 3);
   uint32_t run = (tx < tiles_x && ty < tiles_y) ? ranges[ty * tiles_x + tx].x : 0u;
-  for (int k = 0; k < pp; ++k) run += part[k][tt];
-  for (uint32_t g = a; g < b; ++g) {
-    const uint32_t v = hist[(int64_t)g * 64 + tt];
-    hist[(int64_t)g * 64 + tt] = run;
+  for (uint32_t k = 0; k < (uint32_t)pp; ++k) run += part[k][tt];
+  for (g = a; g + 4u <= b; g += 4u) {
+    const uint32_t v0 = col[(int64_t)g * 64], v1 = col[(int64_t)(g + 1u) * 64];
+    const uint32_t v2 = col[(int64_t)(g + 2u) * 64], v3 = col[(int64_t)(g + 3u) * 64];
+    col[(int64_t)g * 64] = run;
+    run += v0;
+    col[(int64_t)(g + 1u) * 64] = run;
+    run += v1;
+    col[(int64_t)(g + 2u) * 64] = run;
+    run += v2;
+    col[(int64_t)(g + 3u) * 64] = run;
+    run += v3;
+  }
+  for (; g < b; ++g) {
+    const uint32_t v = col[(int64_t)g * 64];
+    col[(int64_t)g * 64] = run;
     run += v;
   }
 }
@@ -844,7 +880,7 @@ void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
   const int64_t segs = cap / kSegWave + nsup + 1;
   const int64_t blocks = ceil_div(segs, 4) < 4096 ? ceil_div(segs, 4) : 4096;
   k_stile_count<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, tab, nsup, supers_x, h, hist);
-  k_stile_scan<<<nsup, 1024, 0, st>>>(hist, tab, supers_x, tiles_x, tiles_y, ranges, h);
+  k_stile_scan<<<nsup, kBlock, 0, st>>>(hist, tab, supers_x, tiles_x, tiles_y, ranges, h);
   if (tile_w == 16)
     k_stile_scatter<16><<<(unsigned)blocks, kBlock, 0, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
   else  // 32 x 8, the other tile shape
@@ -862,10 +898,12 @@ bool launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 
     // enough workgroups to cover the machine, few enough to keep the LDS flushes cheap
     const int64_t per = ne <= kDiffLds ? (grid_n / 512 > 1024 ? grid_n / 512 : 1024) : 1024;
     const int blocks = (int)ceil_div(grid_n, per);
-    k_tile_diff<<<blocks, kBlock, 0, st>>>(dkey, dval, rect, n_active, grid_n, tiles_x, tiles_y, tdiff);
+    const size_t lds = ne <= kDiffLds ? sizeof(uint32_t) * (size_t)ne : 0;
+    k_tile_diff<<<blocks, kBlock, lds, st>>>(dkey, dval, rect, n_active, grid_n, tiles_x, tiles_y, tdiff);
   }
   if (ne <= kDiffLds) {
-    k_tile_ranges_lds<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, h, ranges, tile_order);
+    k_tile_ranges_lds<<<1, kBlock, sizeof(uint32_t) * (size_t)ne, st>>>(tdiff, tiles_x, tiles_y, h, ranges,
+                                                                         tile_order);
     return tile_order != nullptr;
   }
   k_tile_prefix<<<1, 1024, 0, st>>>(tdiff, tiles_x, tiles_y, tcnt);
@@ -929,7 +967,9 @@ k_state_counts(const uint8_t *__restrict__ codes, const uint32_t *__restrict__ h
 }
 
 // One workgroup: states ordered by increasing present count (ties by index),
-// so that the S states of a group have similar list-walk depths.
+// so that the S states of a group have similar list-walk depths.  Launched
+// with kBlock threads up to kBlock states (the size of a compositing
+// workgroup, so that it can start beside a compositing grid), else 1024.
 __global__ void __launch_bounds__(1024)
 k_state_rank(const uint32_t *__restrict__ cnt_g, int num_states, uint32_t *__restrict__ order) {
   extern __shared__ uint32_t cnt[];
@@ -959,7 +999,8 @@ void launch_state_order(const uint8_t *codes, const uint32_t *hist, int num_stat
     return;
   }
   k_state_counts<<<num_states, kBlock, 0, st>>>(codes, hist, P, cnt);
-  k_state_rank<<<1, 1024, sizeof(uint32_t) * num_states, st>>>(cnt, num_states, order);
+  k_state_rank<<<1, num_states <= kBlock ? kBlock : 1024, sizeof(uint32_t) * num_states, st>>>(cnt, num_states,
+                                                                                               order);
 }
 
 // One workgroup: tiles ordered by decreasing list length, bucketed by
