@@ -731,18 +731,37 @@ k_stile_scan(uint32_t *__restrict__ hist, const uint32_t *__restrict__ tab, int 
 // widened by a margin for the FP32 evaluation, so the masks stay
 // conservative, and kept as a bitmap of the band's tile_w block columns: a
 // pair's four mask bits are then bit fields of one or two bitmaps.
-constexpr int kBandsMax = 16;  // 8-row bands of a super-tile: tile_h of them
+//
+// A super-tile of 8 x 8 tiles of TW x (256 / TW) pixels has 256 / TW * 8 / 8
+// bands of 8 rows and TW 8-column blocks: 16 bands of 16 blocks (16x16
+// tiles) or 8 bands of 32 (32x8), each band's bitmap in a word of its width.
+// The stage then takes 3,840 bytes per wave, so that a workgroup with its
+// super-tile tables fits in the LDS one compositing workgroup leaves (when
+// the kernel runs beside a compositing grid on another stream).
+template <int TW> struct StileBands;
+template <> struct StileBands<16> {
+  static constexpr int kBands = 16;
+  using Word = uint16_t;
+};
+template <> struct StileBands<32> {
+  static constexpr int kBands = 8;
+  using Word = uint32_t;
+};
 
+template <int TW>
 struct StileStage {
   uint32_t id[kWave];
-  uint32_t band[kBandsMax][kWave];  // bit c: 8-column block c of the super-tile is reached in this band
+  // bit c: 8-column block c of the super-tile is reached in this band
+  typename StileBands<TW>::Word band[StileBands<TW>::kBands][kWave];
   uint32_t qslot[3 * kWave], qsrc[3 * kWave];  // the queue (2 x 64), then one discard word per lane
 };
 
 // The band bitmaps of one entry (its lane's column of sg.band) for the local
-// bands [lb0, lb1) of the super-tile whose pixel origin is (sx, sy).
-__device__ inline void stage_bands(StileStage &sg, int lane, float u, float v, float A, float B, float C, float need,
-                                   float sx, float sy, int lb0, int lb1, int ncols) {
+// bands [lb0, lb1) of the super-tile whose pixel origin is (sx, sy); ncols =
+// TW block columns, so a bitmap fits its word.
+template <int TW>
+__device__ inline void stage_bands(StileStage<TW> &sg, int lane, float u, float v, float A, float B, float C,
+                                   float need, float sx, float sy, int lb0, int lb1, int ncols) {
   const float a = -A;  // > 0: the pre-scaled conic is negative definite
   const float D = 4.0f * A * C - B * B;
   const bool any = need < 0.0f && D > 0.0f && a > 0.0f;
@@ -767,7 +786,7 @@ __device__ inline void stage_bands(StileStage &sg, int lane, float u, float v, f
       const int ihi = (int)fminf(fmaxf(hi, -1.0f), (float)(ncols - 1));
       if (ihi >= ilo) bits = (0xFFFFFFFFu >> (31 - ihi)) & (0xFFFFFFFFu << ilo);
     }
-    sg.band[lb][lane] = bits;
+    sg.band[lb][lane] = (typename StileBands<TW>::Word)bits;
   }
 }
 
@@ -776,7 +795,8 @@ __device__ inline void stage_bands(StileStage &sg, int lane, float u, float v, f
 // super-tile is block column tx * TW / 8 + w % (TW / 8) of band
 // ty * (256 / TW) / 8 + w / (TW / 8).
 template <int TW>
-__device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t count, uint32_t *__restrict__ out) {
+__device__ inline void stile_flush(const StileStage<TW> &sg, uint32_t head, uint32_t count,
+                                   uint32_t *__restrict__ out) {
   const uint32_t lane = __lane_id();
   if (lane < count) {
     const uint32_t pos = (head + lane) & (2 * kWave - 1);
@@ -785,10 +805,10 @@ __device__ inline void stile_flush(const StileStage &sg, uint32_t head, uint32_t
     const uint32_t tx = tt & 7u, ty = tt >> 3;
     uint32_t mask;
     if (TW == 16) {  // 16x16: wave blocks 2 x 2, two bands per tile row
-      const uint32_t r0 = sg.band[2 * ty][l], r1 = sg.band[2 * ty + 1][l];
+      const uint32_t r0 = (uint32_t)sg.band[2 * ty][l], r1 = (uint32_t)sg.band[2 * ty + 1][l];
       mask = ((r0 >> (2 * tx)) & 3u) | (((r1 >> (2 * tx)) & 3u) << 2);
     } else {  // 32x8: wave blocks 4 x 1, one band per tile row
-      mask = (sg.band[ty][l] >> (4 * tx)) & 15u;
+      mask = ((uint32_t)sg.band[ty][l] >> (4 * tx)) & 15u;
     }
     out[slot] = sg.id[l] | (mask << kMaskShift);
   }
@@ -800,12 +820,13 @@ __global__ void __launch_bounds__(kBlock)
 k_stile_scatter(const uint32_t *__restrict__ list, const uint4 *__restrict__ brec, const uint32_t *__restrict__ tab,
                 int nsup, int supers_x, const Header *__restrict__ h,
                 const uint32_t *__restrict__ hist, uint32_t *__restrict__ out) {
-  __shared__ uint32_t slen[kMaxSupers + 1], sstart[kMaxSupers + 1], seg[kMaxSupers + 1];
-  __shared__ StileStage stage[4];
+  extern __shared__ uint32_t stab[];  // slen, sstart, seg: nsup + 1 entries each (sized at launch)
+  __shared__ StileStage<TW> stage[4];
   if (h->overflow) return;
+  uint32_t *slen = stab, *sstart = stab + (nsup + 1), *seg = stab + 2 * (nsup + 1);
   load_super_tables(tab, nsup, slen, sstart, seg);
   const int w = threadIdx.x >> 6, lane = __lane_id();
-  StileStage &sg = stage[w];
+  StileStage<TW> &sg = stage[w];
   constexpr int TH = kBlock / TW;
   const uint32_t total = seg[nsup];
   for (uint32_t g = blockIdx.x * 4u + (uint32_t)w; g < total; g += gridDim.x * 4u) {
@@ -881,10 +902,11 @@ void launch_super_scatter(const uint32_t *dkey, const uint32_t *dval, const uint
   const int64_t blocks = ceil_div(segs, 4) < 4096 ? ceil_div(segs, 4) : 4096;
   k_stile_count<<<(unsigned)blocks, kBlock, 0, st>>>(list, rect, tab, nsup, supers_x, h, hist);
   k_stile_scan<<<nsup, kBlock, 0, st>>>(hist, tab, supers_x, tiles_x, tiles_y, ranges, h);
+  const size_t tables = 3 * sizeof(uint32_t) * (size_t)(nsup + 1);
   if (tile_w == 16)
-    k_stile_scatter<16><<<(unsigned)blocks, kBlock, 0, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
+    k_stile_scatter<16><<<(unsigned)blocks, kBlock, tables, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
   else  // 32 x 8, the other tile shape
-    k_stile_scatter<32><<<(unsigned)blocks, kBlock, 0, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
+    k_stile_scatter<32><<<(unsigned)blocks, kBlock, tables, st>>>(list, brec, tab, nsup, supers_x, h, hist, out);
 }
 
 bool launch_tile_ranges(const uint32_t *dkey, const uint32_t *dval, const uint2 *rect, const unsigned *n_active,
