@@ -76,6 +76,9 @@ def parse():
                     help="pick tile shape, states per group, launch and LDS batch by timing")
     ap.add_argument("--lds-batch", type=int, default=256, choices=(128, 256, 512),
                     help="list entries staged in LDS per compositing batch")
+    ap.add_argument("--streams", type=int, default=PIPELINE_DEPTH,
+                    help="streams (each with its own workspace) the timed steps rotate over; 1 times the "
+                         "steps on one stream only")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -203,10 +206,13 @@ def main():
     log(f"[bench] batched, one stream, median of {len(reps)} repetitions: {W / serial_value * 1e3:.3f} ms/step "
         f"-> {serial_value:.1f} states/s")
     # The headline: the same K steps, each the whole path (binning, then compositing), issued round
-    # robin on PIPELINE_DEPTH streams with a renderer (workspace) per stream.  A step's binning, a
+    # robin on --streams streams with a renderer (workspace) per stream.  A step's binning, a
     # chain of short launches that leave most of the chip idle, and the last workgroups of its
     # compositing then run beside the compositing of the steps before it.
-    value, pipe_leg = pipelined(args, dgs, torch, np, dev, st, scene, cam, codes, w.basis, bg, W, tw, th, img)
+    if args.streams > 1:
+        value, pipe_leg = pipelined(args, dgs, torch, np, dev, st, scene, cam, codes, w.basis, bg, W, tw, th, img)
+    else:
+        value, pipe_leg = serial_value, None
     gc.enable()
     ms_step = W / value * 1e3
     graph_leg = None
@@ -267,8 +273,9 @@ def main():
                       "height": cam.height, "states": W, "clusters": w.scene.num_clusters,
                       "contexts": w.scene.num_contexts, "tile": f"{tw}x{th}",
                       "states_per_group": args.states_per_group, "instances": M},
-           "batched": {"timed_as": f"eager launches, steps round robin on {PIPELINE_DEPTH} streams with a "
-                                   "workspace each, median of three repetitions",
+           "batched": {"timed_as": (f"eager launches, steps round robin on {args.streams} streams with a "
+                                    "workspace each, median of three repetitions") if pipe_leg is not None
+                                   else "eager launches on one stream, median of three repetitions",
                        "pipelined": pipe_leg,
                        "serial_states_per_s": round(serial_value, 2),
                        "serial_ms_per_step": round(W / serial_value * 1e3, 4),
@@ -360,17 +367,18 @@ def pipelined(args, dgs, torch, np, dev, st, scene, cam, codes, basis, bg, W, tw
     """K steps on a StreamPipeline, three timed repetitions; returns (median
     states/s, record).  Every step's images are checked against the one-stream
     images ``img`` after the last repetition."""
-    pipe = dgs.StreamPipeline(dev, depth=PIPELINE_DEPTH, tile=(tw, th), states_per_group=args.states_per_group,
+    depth = args.streams
+    pipe = dgs.StreamPipeline(dev, depth=depth, tile=(tw, th), states_per_group=args.states_per_group,
                               persistent=LAUNCH[args.launch], lds_batch=args.lds_batch)
     pipe.plan(scene, cam, basis, W)
-    outs = [torch.empty_like(img) for _ in range(PIPELINE_DEPTH)]
+    outs = [torch.empty_like(img) for _ in range(depth)]
 
     def steps(n):
         for _ in range(n):
-            pipe.render(scene, cam, codes, basis, bg, out=outs[pipe.calls % PIPELINE_DEPTH])
+            pipe.render(scene, cam, codes, basis, bg, out=outs[pipe.calls % depth])
         pipe.join()
 
-    steps(max(args.warmup, PIPELINE_DEPTH))
+    steps(max(args.warmup, depth))
     pipe.check()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = []
@@ -384,9 +392,9 @@ def pipelined(args, dgs, torch, np, dev, st, scene, cam, codes, basis, bg, W, tw
     pipe.check()
     same = all(bool(torch.equal(o, img)) for o in outs)
     value = float(np.median(reps))
-    log(f"[bench] batched, {PIPELINE_DEPTH} streams, median of 3 repetitions: {W / value * 1e3:.3f} ms/step "
+    log(f"[bench] batched, {depth} streams, median of 3 repetitions: {W / value * 1e3:.3f} ms/step "
         f"-> {value:.1f} states/s; identical to one stream={same}")
-    rec = {"streams": PIPELINE_DEPTH, "states_per_s": round(value, 2), "ms_per_step": round(W / value * 1e3, 4),
+    rec = {"streams": depth, "states_per_s": round(value, 2), "ms_per_step": round(W / value * 1e3, 4),
            "repetitions_states_per_s": [round(x, 2) for x in reps], "repetitions": distribution(reps, np),
            "bit_identical_to_one_stream": same}
     del pipe, outs
