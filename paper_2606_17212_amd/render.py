@@ -839,7 +839,10 @@ class StreamPipeline:
             cur.wait_stream(s)
 
     def check(self) -> int:
-        """Synchronise; raise DgsError if any renderer's last binning overflowed."""
+        """Wait for every call so far (``join()``), synchronise, and raise
+        DgsError if any renderer's last binning overflowed; returns the
+        largest instance count."""
+        self.join()
         return max(r.check() for r in self.renderers)
 
 
