@@ -799,8 +799,9 @@ class StreamPipeline:
 
     Each call first waits for the work the caller has queued on its current
     stream.  The results are ready on the caller's stream after ``join()``;
-    until then a call's inputs must not change and its image must not be
-    read.  The streams have the default priority."""
+    until then a call's inputs must not change and its image (a caller's
+    ``out`` buffer included) must not be read or freed.  The streams have the
+    default priority."""
 
     def __init__(self, device="cuda", depth: int = 3, **renderer_kwargs):
         if int(depth) < 1:
