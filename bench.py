@@ -466,7 +466,8 @@ def batch_sweep(args, dgs, synth, torch, np, dev, w, scene, cam, tw, th):
     (the paper's batch-size sweep, Sec. 9 table, here on this scene): the
     first W of 128 states drawn with the headline workload's code recipe,
     binning + compositing per step, default launch choice, the median of
-    three repetitions of the timed steps."""
+    three repetitions of the timed steps, on one stream and (``--streams``
+    above 1) rotating over the headline's streams."""
     bg = tuple(float(x) for x in w.background)
     all_codes = torch.from_numpy(synth.make_codes("present_depth", 0.3, 1.0, max(SWEEP_STATES),
                                                   w.scene.num_packets, 4, index=2, stream=7)).to(dev)
@@ -494,10 +495,42 @@ def batch_sweep(args, dgs, synth, torch, np, dev, w, scene, cam, tw, th):
             reps.append(e0.elapsed_time(e1) / args.steps)
         r.check()
         ms = float(np.median(reps))
-        points.append({"states": W, "states_per_s": round(W / (ms / 1e3), 1), "ms_per_step": round(ms, 4)})
+        point = {"states": W, "states_per_s": round(W / (ms / 1e3), 1), "ms_per_step": round(ms, 4)}
+        if args.streams > 1:
+            # the same steps rotating over the headline's streams, each with a workspace of its own
+            pipe = dgs.StreamPipeline(dev, depth=args.streams, tile=(tw, th),
+                                      states_per_group=min(args.states_per_group, W),
+                                      persistent=LAUNCH[args.launch], lds_batch=args.lds_batch)
+            pipe.plan(scene, cam, w.basis, W)
+            outs = [torch.empty_like(img) for _ in range(args.streams)]
+
+            def steps(n):
+                for _ in range(n):
+                    pipe.render(scene, cam, codes, w.basis, bg, out=outs[pipe.calls % args.streams])
+                pipe.join()
+
+            steps(args.streams)
+            torch.cuda.synchronize()
+            preps = []
+            for _ in range(3):
+                e0.record(st)
+                steps(args.steps)
+                e1.record(st)
+                torch.cuda.synchronize()
+                preps.append(e0.elapsed_time(e1) / args.steps)
+            pipe.check()
+            pms = float(np.median(preps))
+            point.update({"streams": args.streams, "pipelined_states_per_s": round(W / (pms / 1e3), 1),
+                          "pipelined_ms_per_step": round(pms, 4),
+                          "pipelined_bit_identical": all(bool(torch.equal(o, img)) for o in outs)})
+            del pipe, outs
+        points.append(point)
         del r, img
-    log("[bench] batch sweep (states: states/s): " +
+    log("[bench] batch sweep (states: states/s, one stream): " +
         ", ".join(f"{p['states']}: {p['states_per_s']:.0f}" for p in points))
+    if args.streams > 1:
+        log(f"[bench] batch sweep (states: states/s, {args.streams} streams): " +
+            ", ".join(f"{p['states']}: {p['pipelined_states_per_s']:.0f}" for p in points))
     return {"workload": "g250k_800px_64states scene and camera",
             "codes": "present_depth 0.3-1.0 (the headline recipe), first W of 128 states",
             "points": points}
